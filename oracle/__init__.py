@@ -1,0 +1,228 @@
+"""FP64 CPU oracle for synchronous parallel simulated annealing.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg load it; the GPU library never does.  It shares no code with
+the GPU library.  The arithmetic lives in ``sa_oracle.c`` (plain C, FP64); this
+module only marshals arguments through ctypes.
+
+Paper: Ferreiro, Garcia, Lopez-Salas, Vazquez, "An efficient implementation of
+parallel simulated annealing algorithm in GPUs" -- Sec. 2.1 (sequential SA,
+eqs. (4)-(5), Steps 1-5), Sec. 2.2.2 (synchronous multiple Markov chains),
+Sec. 3.3 (synchronous kernel listing), Sec. 4.1 eq. (6) (normalized Schwefel),
+Appendix Tests 1 and 13 (Ackley, Rastrigin).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sa_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
+
+CFLAGS = ["-O2", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+_d = ctypes.c_double
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_i = ctypes.c_int
+_p = ctypes.c_void_p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        L.orc_philox4x32_10.argtypes = [_p, _p, _p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_uniform.argtypes = [_u32]
+        L.orc_uniform.restype = _d
+        L.orc_pick.argtypes = [_u32, _u32]
+        L.orc_pick.restype = _u32
+        L.orc_move_draw.argtypes = [_u64, _u32, _u32, _u32, _u32, _u32, _p, _p, _p, _p]
+        L.orc_move_draw.restype = None
+        L.orc_init_point.argtypes = [_u64, _u32, _u32, _u32, _p, _p, _p]
+        L.orc_init_point.restype = None
+        L.orc_schwefel_term.argtypes = [_d]
+        L.orc_schwefel_term.restype = _d
+        L.orc_rastrigin_term.argtypes = [_d]
+        L.orc_rastrigin_term.restype = _d
+        L.orc_ackley_from_sums.argtypes = [_d, _d, _u32]
+        L.orc_ackley_from_sums.restype = _d
+        L.orc_f.argtypes = [_i, _u32, _p, _p]
+        L.orc_f.restype = _d
+        L.orc_accept.argtypes = [_d, _d, _d]
+        L.orc_accept.restype = _i
+        L.orc_neighbour.argtypes = [_i, _d, _d, _d, _d, _d]
+        L.orc_neighbour.restype = _d
+        L.orc_temperature.argtypes = [_d, _d, _u32]
+        L.orc_temperature.restype = _d
+        L.orc_sa_run.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _i, _u32, _u32,
+                                 _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_sa_run.restype = _i
+        L.orc_replay_level.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _d, _d, _i, _u32, _p, _u32, _u32,
+                                       _p, _p, _p, _p, _p, _p, _p]
+        L.orc_replay_level.restype = _i
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(r: int) -> float:
+    return lib().orc_uniform(r)
+
+
+def pick(r: int, n: int) -> int:
+    return lib().orc_pick(r, n)
+
+
+def move_draw(seed, problem, level, chain, step, n):
+    d = ctypes.c_uint32()
+    u1 = ctypes.c_double()
+    u2 = ctypes.c_double()
+    r3 = ctypes.c_uint32()
+    lib().orc_move_draw(seed, problem, level, chain, step, n, ctypes.byref(d), ctypes.byref(u1),
+                        ctypes.byref(u2), ctypes.byref(r3))
+    return d.value, u1.value, u2.value, r3.value
+
+
+def init_point(seed, problem, chain, lower, upper):
+    lo, hi = _f64(lower), _f64(upper)
+    x = np.zeros(lo.size)
+    lib().orc_init_point(seed, problem, chain, lo.size, _ptr(lo), _ptr(hi), _ptr(x))
+    return x
+
+
+def f(func, x, shift=None):
+    x = _f64(x)
+    s = _f64(shift)
+    return lib().orc_f(func, x.size, _ptr(x), _ptr(s))
+
+
+def schwefel_term(y):
+    return lib().orc_schwefel_term(y)
+
+
+def rastrigin_term(y):
+    return lib().orc_rastrigin_term(y)
+
+
+def ackley_from_sums(s1, s2, n):
+    return lib().orc_ackley_from_sums(s1, s2, n)
+
+
+def accept(df, T, u2) -> bool:
+    return bool(lib().orc_accept(df, T, u2))
+
+
+def neighbour(move_rule, xd, lo, hi, radius_frac, u1):
+    return lib().orc_neighbour(move_rule, xd, lo, hi, radius_frac, u1)
+
+
+def temperature(T0, alpha, level):
+    return lib().orc_temperature(T0, alpha, level)
+
+
+def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
+           move_rule=MOVE_RADIUS, exchange=True, problem=0, level_begin=0, x_start=None, chain_x=None,
+           record=None, keep_x_best=True, final_f=False):
+    """Run levels [level_begin, level_begin+levels) of the multi-chain SA.
+
+    ``record`` = (x_rec, f_rec, rec_level) carried in from an earlier call.
+    Returns a dict of per-level outputs and the record."""
+    lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
+    n = lo.size
+    xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
+    cx = None
+    if not exchange:
+        cx = np.zeros(chains * n) if chain_x is None else _f64(chain_x).copy().reshape(-1)
+    if record is None:
+        x_rec = np.zeros(n)
+        f_rec_io = ctypes.c_double(np.inf)
+        rec_level = ctypes.c_uint32(0)
+    else:
+        x_rec = _f64(record[0]).copy()
+        f_rec_io = ctypes.c_double(record[1])
+        rec_level = ctypes.c_uint32(record[2])
+    win = np.zeros(levels, dtype=np.uint32)
+    f_win = np.zeros(levels)
+    f_best = np.zeros(levels)
+    f_rec = np.zeros(levels)
+    xb = np.zeros(levels * n) if keep_x_best else None
+    acc = np.zeros(levels, dtype=np.uint64)
+    ff = np.zeros(chains) if final_f else None
+    rc = lib().orc_sa_run(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
+                          radius_frac, move_rule, 1 if exchange else 0, level_begin, levels, _ptr(xs), _ptr(cx),
+                          _ptr(x_rec), ctypes.byref(f_rec_io), ctypes.byref(rec_level), _ptr(win), _ptr(f_win),
+                          _ptr(f_best), _ptr(f_rec), _ptr(xb), _ptr(acc), _ptr(ff))
+    if rc != 0:
+        raise RuntimeError(f"orc_sa_run failed: {rc}")
+    out = dict(win_chain=win, f_win=f_win, f_best=f_best, f_rec=f_rec, accepts=acc, x_last=xs,
+               x_rec=x_rec, f_rec_final=f_rec_io.value, rec_level=rec_level.value)
+    if keep_x_best:
+        out["x_best"] = xb.reshape(levels, n)
+    if final_f:
+        out["final_f"] = ff
+    if not exchange:
+        out["chain_x"] = cx.reshape(chains, n)
+    return out
+
+
+def replay_level(func, lower, upper, shift=None, *, seed, steps, T, level, x_start, chain0, nchains,
+                 radius_frac=0.1, move_rule=MOVE_RADIUS, problem=0):
+    """Replay one level for a range of chains from a given start, logging moves."""
+    lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
+    n = lo.size
+    xs = _f64(x_start)
+    m = nchains * steps
+    log_d = np.zeros(m, dtype=np.uint32)
+    log_xold = np.zeros(m)
+    log_xnew = np.zeros(m)
+    log_df = np.zeros(m)
+    log_acc = np.zeros(m, dtype=np.uint8)
+    x_final = np.zeros(nchains * n)
+    f_final = np.zeros(nchains)
+    rc = lib().orc_replay_level(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, steps, T, radius_frac,
+                                move_rule, level, _ptr(xs), chain0, nchains, _ptr(log_d), _ptr(log_xold),
+                                _ptr(log_xnew), _ptr(log_df), _ptr(log_acc), _ptr(x_final), _ptr(f_final))
+    if rc != 0:
+        raise RuntimeError(f"orc_replay_level failed: {rc}")
+    sh = (nchains, steps)
+    return dict(d=log_d.reshape(sh), x_old=log_xold.reshape(sh), x_new=log_xnew.reshape(sh),
+                df=log_df.reshape(sh), acc=log_acc.reshape(sh).astype(bool), x_final=x_final.reshape(nchains, n),
+                f_final=f_final)

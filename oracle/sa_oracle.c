@@ -1,0 +1,420 @@
+/*
+ * FP64 CPU oracle for synchronous parallel simulated annealing.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header or constant table with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * What it follows (Ferreiro, Garcia, Lopez-Salas, Vazquez, "An efficient
+ * implementation of parallel simulated annealing algorithm in GPUs"):
+ *   - the box-constrained problem min f(x), x in I = [l_1,u_1] x ... x [l_n,u_n]
+ *     (Sec. 1, eq. (1));
+ *   - Metropolis acceptance with k_b = 1: a move with energy increment dE is
+ *     taken when dE < 0, otherwise with probability exp(-dE/T)
+ *     (Sec. 2.1, eqs. (4)-(5) and Steps 1-5);
+ *   - geometric cooling T_{k+1} = rho * T_k (Sec. 2.1, Step 5);
+ *   - a neighbour that changes one randomly chosen coordinate, three uniforms
+ *     per move (Sec. 2.1, Step 2 and Step 3);
+ *   - the synchronous multiple-Markov-chain scheme: every chain runs N
+ *     Metropolis steps at a fixed T, the chain with the lowest final cost is
+ *     selected and its state is the start of every chain at the next level
+ *     (Sec. 2.2.2 and the synchronous kernel listing of Sec. 3.3);
+ *   - the asynchronous scheme (no exchange; Sec. 2.2.1) as a switch;
+ *   - the test functions: normalized Schwefel (Sec. 4.1, eq. (6)), Ackley
+ *     (Appendix, Test 1) and Rastrigin (Appendix, Test 13).
+ *
+ * Readings where the paper is silent (all are stated again, with reasons, in
+ * the project design notes):
+ *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
+ *     (seed_lo, seed_hi); move counter = (step, level, chain, tag | problem<<8);
+ *     uniform U = (r >> 8) * 2^-24; coordinate d = (r0 * n) >> 32;
+ *   - neighbour: x'_d = clamp(x_d + rho_d (2U - 1), l_d, u_d),
+ *     rho_d = radius_frac (u_d - l_d); or resampling x'_d = l_d + (u_d - l_d) U;
+ *   - accept iff dE <= 0 or U2 < exp(-dE/T);
+ *   - the level winner is the lowest final cost, ties to the lowest chain;
+ *   - the winner is re-evaluated in full; the record keeps the lowest such
+ *     value (strictly lower replaces);
+ *   - temperatures: T_0 = T0, T_{k+1} = T_k * alpha, repeated FP64 products.
+ *
+ * Cost increments: for a separable cost only the changed coordinate's term is
+ * re-evaluated (the increment is mathematically f(x') - f(x)); for Ackley the
+ * two sums under the exponentials are updated and f is re-formed from them.
+ *
+ * Build: gcc -O2 -shared -fPIC -fno-fast-math -ffp-contract=off -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_SCHWEFEL 0
+#define ORC_RASTRIGIN 1
+#define ORC_ACKLEY 2
+
+#define ORC_TAG_MOVE 0u
+#define ORC_TAG_INIT 1u
+
+#define ORC_MOVE_RADIUS 0
+#define ORC_MOVE_RESAMPLE 1
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon et al., SC'11, Sec. 3 and Table 2).                  */
+/* Round: (hi0,lo0) = M0*c0, (hi1,lo1) = M1*c2,                              */
+/*        c' = (hi1^c1^k0, lo1, hi0^c3^k1, lo0); key += (W0, W1) between      */
+/*        rounds.                                                            */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in [0,1) from the top 24 bits of a 32-bit word. */
+double orc_uniform(uint32_t r) { return (double)(r >> 8) * 0x1p-24; }
+
+/* Coordinate index in [0,n). */
+uint32_t orc_pick(uint32_t r, uint32_t n) { return (uint32_t)(((uint64_t)r * (uint64_t)n) >> 32); }
+
+static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t out[4])
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    orc_philox4x32_10(ctr, key, out);
+}
+
+/* The three uniforms of one move (Sec. 2.1, Step 3): coordinate, change,
+ * acceptance.  r[3] is returned for callers that need a fourth word. */
+void orc_move_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step,
+                   uint32_t n, uint32_t *d, double *u1, double *u2, uint32_t *r3)
+{
+    uint32_t r[4];
+    draw(seed, step, level, chain, ORC_TAG_MOVE | (problem << 8), r);
+    *d = orc_pick(r[0], n);
+    *u1 = orc_uniform(r[1]);
+    *u2 = orc_uniform(r[2]);
+    if (r3) *r3 = r[3];
+}
+
+/* Random start of one chain (Sec. 2.2.2: threads start from a random initial
+ * solution): x_i = l_i + (u_i - l_i) U_i, U_i from counter
+ * (i/4, 0xFFFFFFFF, chain, INIT | problem<<8), word i%4. */
+void orc_init_point(uint64_t seed, uint32_t problem, uint32_t chain, uint32_t n,
+                    const double *lower, const double *upper, double *x)
+{
+    uint32_t r[4];
+    for (uint32_t i = 0; i < n; ++i) {
+        if ((i & 3u) == 0) draw(seed, i >> 2, 0xFFFFFFFFu, chain, ORC_TAG_INIT | (problem << 8), r);
+        double u = orc_uniform(r[i & 3u]);
+        double xi = lower[i] + (upper[i] - lower[i]) * u;
+        if (xi > upper[i]) xi = upper[i];
+        if (xi < lower[i]) xi = lower[i];
+        x[i] = xi;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Test functions, evaluated at y = x - s (s = 0 when no shift is given).     */
+/* ------------------------------------------------------------------------ */
+static const double ORC_PI = 3.14159265358979323846;
+static const double ORC_E = 2.71828182845904523536;
+
+/* One term of the normalized Schwefel function (Sec. 4.1, eq. (6)) before
+ * the -1/n factor is applied: y sin(sqrt|y|). */
+double orc_schwefel_term(double y) { return y * sin(sqrt(fabs(y))); }
+
+/* One term of the Rastrigin sum (Appendix, Test 13): y^2 - 10 cos(2 pi y). */
+double orc_rastrigin_term(double y) { return y * y - 10.0 * cos(2.0 * ORC_PI * y); }
+
+/* Ackley (Appendix, Test 1) from its two sums S1 = sum y^2, S2 = sum cos(2 pi y). */
+double orc_ackley_from_sums(double s1, double s2, uint32_t n)
+{
+    double dn = (double)n;
+    return -20.0 * exp(-0.2 * sqrt(s1 / dn)) - exp(s2 / dn) + 20.0 + ORC_E;
+}
+
+static double shifted(const double *x, const double *s, uint32_t i) { return s ? x[i] - s[i] : x[i]; }
+
+/* Full evaluation, summing the coordinates in order 0..n-1. */
+double orc_f(int func, uint32_t n, const double *x, const double *s)
+{
+    if (func == ORC_SCHWEFEL) {
+        double acc = 0.0;
+        for (uint32_t i = 0; i < n; ++i) acc += orc_schwefel_term(shifted(x, s, i));
+        return -acc / (double)n;
+    }
+    if (func == ORC_RASTRIGIN) {
+        double acc = 0.0;
+        for (uint32_t i = 0; i < n; ++i) acc += orc_rastrigin_term(shifted(x, s, i));
+        return 10.0 * (double)n + acc;
+    }
+    if (func == ORC_ACKLEY) {
+        double s1 = 0.0, s2 = 0.0;
+        for (uint32_t i = 0; i < n; ++i) {
+            double y = shifted(x, s, i);
+            s1 += y * y;
+            s2 += cos(2.0 * ORC_PI * y);
+        }
+        return orc_ackley_from_sums(s1, s2, n);
+    }
+    return NAN;
+}
+
+/* Per-chain cost state: the current cost and, for Ackley, its two sums. */
+typedef struct {
+    double f, s1, s2;
+} orc_cost;
+
+static void cost_full(int func, uint32_t n, const double *x, const double *s, orc_cost *c)
+{
+    c->s1 = 0.0;
+    c->s2 = 0.0;
+    if (func == ORC_ACKLEY) {
+        for (uint32_t i = 0; i < n; ++i) {
+            double y = shifted(x, s, i);
+            c->s1 += y * y;
+            c->s2 += cos(2.0 * ORC_PI * y);
+        }
+        c->f = orc_ackley_from_sums(c->s1, c->s2, n);
+    } else {
+        c->f = orc_f(func, n, x, s);
+    }
+}
+
+/* Cost increment of changing coordinate d from xd to xn, and the new cost
+ * state.  Separable costs: only coordinate d's term is re-evaluated. */
+static double cost_delta(int func, uint32_t n, const orc_cost *c, double xd, double xn, double sd,
+                         orc_cost *out)
+{
+    double y = xd - sd, yn = xn - sd;
+    *out = *c;
+    if (func == ORC_SCHWEFEL) {
+        double df = -(orc_schwefel_term(yn) - orc_schwefel_term(y)) / (double)n;
+        out->f = c->f + df;
+        return df;
+    }
+    if (func == ORC_RASTRIGIN) {
+        double df = orc_rastrigin_term(yn) - orc_rastrigin_term(y);
+        out->f = c->f + df;
+        return df;
+    }
+    /* Ackley */
+    out->s1 = c->s1 + (yn * yn - y * y);
+    out->s2 = c->s2 + (cos(2.0 * ORC_PI * yn) - cos(2.0 * ORC_PI * y));
+    out->f = orc_ackley_from_sums(out->s1, out->s2, n);
+    return out->f - c->f;
+}
+
+/* Metropolis criterion, eq. (5) with k_b = 1. */
+int orc_accept(double df, double T, double u2)
+{
+    if (df <= 0.0) return 1;
+    return u2 < exp(-df / T);
+}
+
+/* Neighbour of coordinate value xd (Sec. 2.1, Step 2). */
+double orc_neighbour(int move_rule, double xd, double lo, double hi, double radius_frac, double u1)
+{
+    double xn;
+    if (move_rule == ORC_MOVE_RESAMPLE) {
+        xn = lo + (hi - lo) * u1;
+    } else {
+        double rho = radius_frac * (hi - lo);
+        xn = xd + rho * (2.0 * u1 - 1.0);
+    }
+    if (xn > hi) xn = hi;
+    if (xn < lo) xn = lo;
+    return xn;
+}
+
+/* Temperature of level k: T0 multiplied by alpha k times, in order. */
+double orc_temperature(double T0, double alpha, uint32_t level)
+{
+    double T = T0;
+    for (uint32_t k = 0; k < level; ++k) T = T * alpha;
+    return T;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One Markov chain at a fixed temperature (Sec. 2.2.2: each thread runs a    */
+/* Metropolis process of length N).  x is updated in place.                   */
+/* Returns the number of accepted moves.                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int func;
+    uint32_t n;
+    const double *lower, *upper, *shift;
+    uint64_t seed;
+    uint32_t problem;
+    uint32_t steps;
+    double radius_frac;
+    int move_rule;
+} orc_problem;
+
+static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, double T, double *x,
+                          orc_cost *c)
+{
+    uint64_t accepted = 0;
+    for (uint32_t step = 0; step < p->steps; ++step) {
+        uint32_t d;
+        double u1, u2;
+        orc_move_draw(p->seed, p->problem, level, chain, step, p->n, &d, &u1, &u2, NULL);
+        double xd = x[d];
+        double xn = orc_neighbour(p->move_rule, xd, p->lower[d], p->upper[d], p->radius_frac, u1);
+        orc_cost cn;
+        double sd = p->shift ? p->shift[d] : 0.0;
+        double df = cost_delta(p->func, p->n, c, xd, xn, sd, &cn);
+        if (orc_accept(df, T, u2)) {
+            x[d] = xn;
+            *c = cn;
+            ++accepted;
+        }
+    }
+    return accepted;
+}
+
+/*
+ * Synchronous (exchange = 1) or asynchronous (exchange = 0) multi-chain SA
+ * over levels [level_begin, level_begin + count).
+ *
+ * Level start: at level 0 every chain starts from its own random point; later,
+ * with exchange, every chain starts from x_start (the previous level's
+ * winner); without exchange, chain p continues from its own state in
+ * `chain_x` (chains * n, in/out; required when exchange = 0).
+ *
+ * Per level k (index k - level_begin into the per-level outputs):
+ *   win_chain[k]  chain with the lowest final cost (ties: lowest index)
+ *   f_win[k]      that chain's final cost as carried incrementally
+ *   f_best[k]     full re-evaluation of the winner's state
+ *   f_rec[k]      lowest f_best so far (record), including rec_in
+ *   x_best[k*n..] winner's state (optional)
+ *   accepts[k]    accepted moves over all chains (optional)
+ * x_rec/f_rec_io/rec_level_io carry the record in and out (f_rec_io = +inf
+ * for a fresh run).  x_start is in/out: the last winner on return.
+ */
+int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+               uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
+               double radius_frac, int move_rule, int exchange, uint32_t level_begin, uint32_t count,
+               double *x_start, double *chain_x, double *x_rec, double *f_rec_io, uint32_t *rec_level_io,
+               uint32_t *win_chain, double *f_win, double *f_best, double *f_rec, double *x_best,
+               uint64_t *accepts, double *final_f)
+{
+    if (n == 0 || chains == 0) return -1;
+    if (!exchange && !chain_x) return -1;
+    if (exchange && level_begin > 0 && !x_start) return -1;
+    orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
+    double *x = (double *)malloc(sizeof(double) * n);
+    double *bx = (double *)malloc(sizeof(double) * n);
+    if (!x || !bx) { free(x); free(bx); return -2; }
+
+    for (uint32_t k = 0; k < count; ++k) {
+        uint32_t level = level_begin + k;
+        double T = orc_temperature(T0, alpha, level);
+        double best_f = INFINITY;
+        uint32_t best_chain = 0;
+        uint64_t acc_total = 0;
+        orc_cost start_cost;
+        if (exchange && level > 0) cost_full(func, n, x_start, shift, &start_cost);
+        for (uint32_t ch = 0; ch < chains; ++ch) {
+            orc_cost c;
+            if (level == 0) {
+                orc_init_point(seed, problem, ch, n, lower, upper, x);
+                cost_full(func, n, x, shift, &c);
+            } else if (exchange) {
+                memcpy(x, x_start, sizeof(double) * n);
+                c = start_cost;
+            } else {
+                memcpy(x, chain_x + (size_t)ch * n, sizeof(double) * n);
+                cost_full(func, n, x, shift, &c);
+            }
+            acc_total += run_chain(&p, level, ch, T, x, &c);
+            if (!exchange) memcpy(chain_x + (size_t)ch * n, x, sizeof(double) * n);
+            if (final_f && k + 1 == count) final_f[ch] = c.f;
+            if (c.f < best_f || ch == 0) {
+                best_f = c.f;
+                best_chain = ch;
+                memcpy(bx, x, sizeof(double) * n);
+            }
+        }
+        double fresh = orc_f(func, n, bx, shift);
+        if (fresh < *f_rec_io) {
+            *f_rec_io = fresh;
+            *rec_level_io = level;
+            memcpy(x_rec, bx, sizeof(double) * n);
+        }
+        if (x_start) memcpy(x_start, bx, sizeof(double) * n);
+        if (win_chain) win_chain[k] = best_chain;
+        if (f_win) f_win[k] = best_f;
+        if (f_best) f_best[k] = fresh;
+        if (f_rec) f_rec[k] = *f_rec_io;
+        if (x_best) memcpy(x_best + (size_t)k * n, bx, sizeof(double) * n);
+        if (accepts) accepts[k] = acc_total;
+    }
+    free(x);
+    free(bx);
+    return 0;
+}
+
+/*
+ * Replay one level for chains [chain0, chain0 + nchains) starting from x_start
+ * (cost state recomputed in full), and log every move:
+ *   log_d[m], log_xold[m], log_xnew[m], log_df[m], log_acc[m]
+ * with m = (chain - chain0) * steps + step.  Final states are written to
+ * x_final (nchains * n) when given.
+ */
+int orc_replay_level(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+                     uint64_t seed, uint32_t problem, uint32_t steps, double T, double radius_frac,
+                     int move_rule, uint32_t level, const double *x_start, uint32_t chain0, uint32_t nchains,
+                     uint32_t *log_d, double *log_xold, double *log_xnew, double *log_df, uint8_t *log_acc,
+                     double *x_final, double *f_final)
+{
+    double *x = (double *)malloc(sizeof(double) * n);
+    if (!x) return -2;
+    for (uint32_t j = 0; j < nchains; ++j) {
+        uint32_t ch = chain0 + j;
+        memcpy(x, x_start, sizeof(double) * n);
+        orc_cost c;
+        cost_full(func, n, x, shift, &c);
+        for (uint32_t step = 0; step < steps; ++step) {
+            uint32_t d;
+            double u1, u2;
+            orc_move_draw(seed, problem, level, ch, step, n, &d, &u1, &u2, NULL);
+            double xd = x[d];
+            double xn = orc_neighbour(move_rule, xd, lower[d], upper[d], radius_frac, u1);
+            orc_cost cn;
+            double df = cost_delta(func, n, &c, xd, xn, shift ? shift[d] : 0.0, &cn);
+            int a = orc_accept(df, T, u2);
+            size_t m = (size_t)j * steps + step;
+            if (log_d) log_d[m] = d;
+            if (log_xold) log_xold[m] = xd;
+            if (log_xnew) log_xnew[m] = xn;
+            if (log_df) log_df[m] = df;
+            if (log_acc) log_acc[m] = (uint8_t)a;
+            if (a) {
+                x[d] = xn;
+                c = cn;
+            }
+        }
+        if (x_final) memcpy(x_final + (size_t)j * n, x, sizeof(double) * n);
+        if (f_final) f_final[j] = c.f;
+    }
+    free(x);
+    return 0;
+}

@@ -1,0 +1,129 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module holds problem definitions and schedules only: boxes, shift vectors
+(drawn with numpy's seeded generator), chain counts and temperature schedules.
+It contains none of the annealing arithmetic and imports neither the GPU
+library nor the oracle.
+
+Workloads (the paper's test functions at the sizes used here):
+  schwefel_n4_fp64       normalized Schwefel (Sec. 4.1, eq. (6)), n=4, box [-500,500]^4,
+                         256 chains, FP64, T0=10, alpha=0.99, 200 levels x 50 steps, seed 0
+  schwefel_n100_fp32     normalized Schwefel, n=100, box [-500,500]^100, 65536 chains, FP32,
+                         T0=10, alpha=0.995, 500 levels x 100 steps, seed 1
+  rastrigin_n512_fp32    Rastrigin (Appendix, Test 13), n=512, box [-5.12,5.12]^512,
+                         shift uniform in the inner 80% of the box, 131072 chains, FP32,
+                         1000 levels x 64 steps
+  ackley_n1024_fp32      Ackley (Appendix, Test 1), n=1024, box [-32.768,32.768]^1024, shift as
+                         above, 131072 chains, FP32, 1000 levels x 64 steps
+Every move uses the radius rule with radius 0.1 (u - l) unless stated.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+FP32, FP64 = 0, 1
+
+# Closed-form minimum of the normalized Schwefel function (Sec. 4.1): the
+# paper prints x_i* = 420.968746 and f* = -418.982887; the digits below solve
+# d/dx [x sin(sqrt x)] = 0 in FP64 (see tests/golden/schwefel_minimum.txt).
+SCHWEFEL_X_STAR = 420.968746359982
+SCHWEFEL_F_STAR = -418.9828872724337
+
+
+@dataclass
+class Workload:
+    name: str
+    func: int
+    n: int
+    lower: np.ndarray
+    upper: np.ndarray
+    shift: Optional[np.ndarray]
+    chains: int
+    levels: int
+    steps: int
+    T0: float
+    alpha: float
+    seed: int
+    precision: int
+    radius_frac: float = 0.1
+    f_star: Optional[float] = None
+    x_star: Optional[np.ndarray] = None
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def moves(self) -> int:
+        return self.chains * self.levels * self.steps
+
+    def with_(self, **kw) -> "Workload":
+        d = dict(self.__dict__)
+        d.update(kw)
+        return Workload(**d)
+
+
+def _box(n, half):
+    return np.full(n, -half), np.full(n, half)
+
+
+def inner_shift(lower, upper, rng):
+    """Shift vector uniform in the inner 80% of the box."""
+    w = upper - lower
+    return rng.uniform(lower + 0.1 * w, upper - 0.1 * w)
+
+
+def schwefel_n4_fp64() -> Workload:
+    lo, hi = _box(4, 500.0)
+    return Workload("schwefel_n4_fp64", SCHWEFEL, 4, lo, hi, None, chains=256, levels=200, steps=50, T0=10.0,
+                    alpha=0.99, seed=0, precision=FP64, f_star=SCHWEFEL_F_STAR,
+                    x_star=np.full(4, SCHWEFEL_X_STAR))
+
+
+def schwefel_n100_fp32() -> Workload:
+    lo, hi = _box(100, 500.0)
+    return Workload("schwefel_n100_fp32", SCHWEFEL, 100, lo, hi, None, chains=65536, levels=500, steps=100,
+                    T0=10.0, alpha=0.995, seed=1, precision=FP32, f_star=SCHWEFEL_F_STAR,
+                    x_star=np.full(100, SCHWEFEL_X_STAR))
+
+
+def rastrigin_n512_fp32(shift_seed: int = 512) -> Workload:
+    lo, hi = _box(512, 5.12)
+    s = inner_shift(lo, hi, np.random.default_rng(shift_seed))
+    return Workload("rastrigin_n512_fp32", RASTRIGIN, 512, lo, hi, s, chains=131072, levels=1000, steps=64,
+                    T0=10.0, alpha=0.99, seed=2, precision=FP32, f_star=0.0, x_star=s.copy())
+
+
+def ackley_n1024_fp32(shift_seed: int = 1024) -> Workload:
+    lo, hi = _box(1024, 32.768)
+    s = inner_shift(lo, hi, np.random.default_rng(shift_seed))
+    return Workload("ackley_n1024_fp32", ACKLEY, 1024, lo, hi, s, chains=131072, levels=1000, steps=64,
+                    T0=10.0, alpha=0.99, seed=3, precision=FP32, f_star=0.0, x_star=s.copy())
+
+
+def random_problem(func: int, n: int, seed: int, shifted: bool = True) -> Workload:
+    """A small random problem of one of the three families, for parity tests:
+    canonical box, optional inner shift, random FP32 schedule."""
+    half = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768}[func]
+    lo, hi = _box(n, half)
+    rng = np.random.default_rng(seed)
+    s = inner_shift(lo, hi, rng) if shifted else None
+    return Workload(f"random_f{func}_n{n}_s{seed}", func, n, lo, hi, s, chains=256, levels=8, steps=32, T0=10.0,
+                    alpha=0.95, seed=seed, precision=FP32)
+
+
+def uneven_box(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Per-coordinate boxes of different widths and centres."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-100.0, 100.0, n)
+    w = rng.uniform(1.0, 400.0, n)
+    return c - w / 2, c + w / 2
+
+
+ALL = {
+    "schwefel_n4_fp64": schwefel_n4_fp64,
+    "schwefel_n100_fp32": schwefel_n100_fp32,
+    "rastrigin_n512_fp32": rastrigin_n512_fp32,
+    "ackley_n1024_fp32": ackley_n1024_fp32,
+}
