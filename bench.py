@@ -1,0 +1,162 @@
+"""Benchmark: SA moves/s on normalized Schwefel n=100 (65536 chains, FP32,
+500 levels x 100 steps, seed 1) on one MI355X.
+
+One step = one whole annealing run (level-0 start, 500 levels, argmin and
+broadcast after each) from a reset context; the inputs are the problem
+definition, already on the device.  Prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-levels L] [--no-cpu] [--probe]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+# Algorithmic VALU work of one FP32 Schwefel move, in full-rate lane-op slots
+# (a quarter-rate instruction costs 4 slots).  The derivation is in the design
+# notes; the per-step part of the counter-based generator is 8 of its 10
+# rounds, because the counter words other than the step are fixed per chain
+# and level.
+SLOTS_PER_MOVE = {
+    "philox_rounds_3_10": 8 * (2 * 4 + 2),  # two 32x32->64 multiplies (quarter rate) + two XOR3 per round
+    "philox_rounds_1_2": 2,                 # step-dependent XORs of the first two rounds
+    "coordinate_pick": 4,                   # high word of r0 * n (quarter rate)
+    "uniforms": 6,                          # two (shift, convert, scale)
+    "neighbour": 4,                         # 2u-1, fma, min, max
+    "increment": 2 * (4 + 1 + 4 + 1) + 2,   # per term: sqrt, scale, sin, product; difference and 1/n
+    "metropolis": 1 + 4 + 3,                # scale, exp2, compares/or
+    "commit_and_address": 3,                # cost update, accept count, LDS address
+}
+SLOTS = sum(SLOTS_PER_MOVE.values())
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz full-rate VALU lane-ops/s.
+PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--cpu-levels", type=int, default=10, help="levels of the workload the CPU oracle times")
+    p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
+    return p.parse_args()
+
+
+def cpu_baseline(wl, levels):
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    oracle.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=wl.chains, steps=wl.steps, T0=wl.T0,
+                  alpha=wl.alpha, levels=levels, radius_frac=wl.radius_frac, keep_x_best=False)
+    dt = time.perf_counter() - t0
+    moves = wl.chains * wl.steps * levels
+    return {"value": moves / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {levels} of {wl.levels} levels, all {wl.chains} chains x {wl.steps} steps, "
+                      f"FP64, single thread, {dt:.1f} s"}
+
+
+def probe_rates():
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_00018_amd", "libsa_peak.so"))
+    lib.sa_peak_probe.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    names = ["fma_f32", "mad_u64_u32", "mul_hi_u32", "xor", "sin_f32", "sqrt_f32", "exp2_f32", "fma_f64"]
+    out = {}
+    blocks, iters = 8192, 2048
+    for k, name in enumerate(names):
+        ms = ctypes.c_float()
+        rc = lib.sa_peak_probe(k, blocks, iters, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"probe {name} failed: {rc}")
+        ops = blocks * 256 * iters * 16
+        out[name] = ops / (ms.value * 1e-3)
+    return {k: float(f"{v:.4g}") for k, v in out.items()}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2408_00018_amd import sa
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    wl = W.schwefel_n100_fp32()
+    sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+                        precision=sa.FP32, graph=True)
+    ann = sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched)
+    stream = ann.stream
+    for _ in range(args.warmup):
+        ann.reset(wl.seed)
+        ann.run()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(args.steps):
+        ann.reset(wl.seed)
+        ann.run()
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    ms_per_step = ms / args.steps
+    moves = wl.moves
+    value = moves / (ms_per_step * 1e-3)
+    x_rec, f_rec, lvl = ann.best()
+    rec = ann.trace()
+    ann.close()
+
+    launches = args.steps * wl.levels
+    avg_launch_s = ms * 1e-3 / launches
+    per_launch = SLOTS * wl.chains * wl.steps
+    achieved = per_launch / avg_launch_s
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_SLOTS_PER_S / 1e12, 3),
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_SLOTS_PER_S, 4), "traffic": None,
+                "kernel": "level_kernel<float,Schwefel>", "slots_per_move": SLOTS,
+                "avg_launch_us": round(avg_launch_s * 1e6, 3)}
+    out = {
+        "metric": "SA moves/s (Schwefel n=100)",
+        "value": float(f"{value:.6g}"),
+        "unit": "moves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "func": "normalized_schwefel", "n": wl.n, "chains": wl.chains,
+                   "levels": wl.levels, "steps": wl.steps, "T0": wl.T0, "alpha": wl.alpha, "seed": wl.seed,
+                   "moves_per_step": moves},
+        "roofline": roofline,
+        "result": {"f_rec": f_rec, "gap_to_f_star": f_rec - W.SCHWEFEL_F_STAR, "rec_level": lvl,
+                   "accept_rate": float(rec["accepts"].sum()) / moves},
+    }
+    if args.probe:
+        out["valu_rates_per_s"] = probe_rates()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

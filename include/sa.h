@@ -1,0 +1,181 @@
+/*
+ * sa.h -- C ABI of the MI355X (gfx950) synchronous parallel simulated
+ * annealing library (libsa_hip.so).
+ *
+ * Method: Ferreiro, Garcia, Lopez-Salas, Vazquez, "An efficient implementation
+ * of parallel simulated annealing algorithm in GPUs".
+ *   - Problem: minimise f over the box I = [l_1,u_1] x ... x [l_n,u_n]
+ *     (Sec. 1, eq. (1)).
+ *   - Each of `chains` Markov chains runs `steps` Metropolis moves at a fixed
+ *     temperature T_k (Sec. 2.1, Steps 2-4; Sec. 2.2.2).  A move changes one
+ *     random coordinate (Step 2) and is accepted when dE <= 0 or
+ *     U < exp(-dE/T) (eq. (5), Step 3).
+ *   - After every level the chain with the lowest final cost is found and its
+ *     state starts every chain at the next level (Sec. 2.2.2, synchronous
+ *     kernel listing of Sec. 3.3).  T_{k+1} = alpha T_k (Sec. 2.1, Step 5).
+ *
+ * Fixed readings (the paper leaves them open):
+ *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed low
+ *     word, seed high word), move counter = (step, level, chain, 0 | problem<<8),
+ *     start counter = (i/4, 0xFFFFFFFF, chain, 1 | problem<<8) for coordinate i.
+ *     Uniform U = (r >> 8) * 2^-24; coordinate d = (r0 * n) >> 32.
+ *   - Move: x'_d = clamp(x_d + rho_d (2 U1 - 1), l_d, u_d) with
+ *     rho_d = radius_frac (u_d - l_d) (SA_MOVE_RADIUS), or
+ *     x'_d = l_d + (u_d - l_d) U1 (SA_MOVE_RESAMPLE).
+ *   - Level 0 starts every chain at its own uniform random point in the box.
+ *   - Winner: lowest final cost, ties to the lowest chain index.  Its state is
+ *     re-evaluated in full (in FP64 arithmetic) and that value starts the next
+ *     level; the record (x_rec, f_rec) keeps the lowest re-evaluated winner.
+ *   - T_k = T0 * alpha * ... * alpha (k products in FP64).
+ *   - FP32 runs keep the box rounded inward to FP32, so every state lies in
+ *     the true box.
+ *
+ * Functions (evaluated at y = x - s, s = shift or 0):
+ *   SA_SCHWEFEL   f = -(1/n) sum y_i sin(sqrt|y_i|)          (Sec. 4.1, eq. (6))
+ *   SA_RASTRIGIN  f = 10 n + sum (y_i^2 - 10 cos(2 pi y_i))  (Appendix, Test 13)
+ *   SA_ACKLEY     f = -20 exp(-0.2 sqrt(sum y^2 / n)) - exp(sum cos(2 pi y)/n)
+ *                     + 20 + e                                (Appendix, Test 1)
+ *
+ * Conventions for every call:
+ *   - Host pointers are read during the call only; the library copies what it
+ *     keeps.  Output pointers are caller-owned host memory.
+ *   - A context is used from one host thread at a time.
+ *   - sa_run only enqueues work on the context's HIP stream.  sa_best,
+ *     sa_trace and sa_move_log synchronise that stream.
+ *   - Errors: a negative sa_status; sa_last_error() describes the last error
+ *     of the calling thread.  No call aborts the process.
+ */
+#ifndef SA_H
+#define SA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SA_ABI_VERSION 1
+
+typedef enum {
+    SA_OK = 0,
+    SA_ERR_INVALID = -1,     /* bad argument */
+    SA_ERR_NOMEM = -2,       /* device or host allocation failed */
+    SA_ERR_DEVICE = -3,      /* a HIP call failed */
+    SA_ERR_STATE = -4,       /* call not valid in the context's state */
+    SA_ERR_UNSUPPORTED = -5  /* valid request this build does not support */
+} sa_status;
+
+typedef enum { SA_SCHWEFEL = 0, SA_RASTRIGIN = 1, SA_ACKLEY = 2 } sa_func;
+typedef enum { SA_FP32 = 0, SA_FP64 = 1 } sa_precision;
+typedef enum { SA_MOVE_RADIUS = 0, SA_MOVE_RESAMPLE = 1 } sa_move;
+
+/* One box-constrained problem.  lower/upper: n host doubles each, finite,
+ * lower[i] < upper[i].  shift: n host doubles or NULL (zero shift). */
+typedef struct {
+    uint32_t func; /* sa_func */
+    uint32_t n;    /* dimension, >= 1 */
+    const double *lower;
+    const double *upper;
+    const double *shift;
+} sa_problem;
+
+/* Annealing schedule and run options. */
+typedef struct {
+    uint64_t seed;      /* Philox key */
+    uint32_t chains;    /* Markov chains, a multiple of 64 */
+    uint32_t levels;    /* temperature levels L */
+    uint32_t steps;     /* Metropolis steps per chain per level (N) */
+    uint32_t precision; /* sa_precision */
+    uint32_t move;      /* sa_move */
+    uint32_t flags;     /* SA_FLAG_* */
+    double T0;          /* T of level 0, > 0 */
+    double alpha;       /* cooling factor, 0 < alpha <= 1 */
+    double radius_frac; /* move radius as a fraction of u_d - l_d, > 0 */
+    /* Move log (verification): moves of chains [0, log_chains) at levels
+     * [log_level, log_level + log_levels) are recorded, together with the
+     * final cost of every chain at those levels.  log_chains = 0: no log. */
+    uint32_t log_chains;
+    uint32_t log_level;
+    uint32_t log_levels;
+    uint32_t reserved;
+} sa_config;
+
+/* Keep the winner state of every level (sa_trace x_best output). */
+#define SA_FLAG_TRACE_X 0x1u
+/* Replay each sa_run from a captured HIP graph instead of eager launches. */
+#define SA_FLAG_GRAPH 0x2u
+
+/* Per-level record returned by sa_trace. */
+typedef struct {
+    uint32_t win_chain; /* chain index of the level winner */
+    uint32_t reserved;
+    double f_win;       /* winner's final cost as carried by its chain */
+    double f_best;      /* full re-evaluation of the winner (FP64 arithmetic) */
+    double f_rec;       /* lowest f_best so far */
+    uint64_t accepts;   /* accepted moves over all chains */
+    uint64_t t_ticks;   /* device constant-clock stamp when the level finished */
+} sa_level;
+
+/* One logged move (sa_move_log).  In FP32 runs the values are the FP32
+ * quantities the device used, widened to double. */
+typedef struct {
+    uint32_t d;      /* coordinate */
+    uint32_t accept; /* 1 if taken */
+    double x_old;    /* x_d before the move */
+    double x_new;    /* proposed x'_d (after clamping) */
+    double df;       /* cost increment the device computed */
+} sa_move_rec;
+
+typedef struct sa_ctx sa_ctx;
+
+/* Bytes of device workspace sa_create needs for this problem and config. */
+sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_t *bytes);
+
+/*
+ * Create a context for one problem on the current HIP device.
+ *   stream:    hipStream_t to enqueue on (NULL = the null stream); not owned.
+ *   workspace: device memory of at least sa_workspace_bytes bytes, 256-byte
+ *              aligned, owned by the caller and kept alive until sa_destroy;
+ *              NULL = the library allocates and frees its own.
+ * The run starts at level 0 with an empty record.  *out is set on success.
+ */
+sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, void *workspace,
+                    size_t ws_bytes, sa_ctx **out);
+
+/* Enqueue the next `levels` levels (0 = all remaining).  SA_ERR_STATE if the
+ * run already finished or `levels` passes cfg->levels. */
+sa_status sa_run(sa_ctx *ctx, uint32_t levels);
+
+/* Restart at level 0 with an empty record and a new seed (enqueued). */
+sa_status sa_reset(sa_ctx *ctx, uint64_t seed);
+
+/* Levels enqueued so far. */
+sa_status sa_levels_done(const sa_ctx *ctx, uint32_t *levels);
+
+/* Record after the enqueued levels (synchronises).  x_out: n doubles;
+ * f_out: f(x_rec) in FP64 arithmetic; level_found: level that set it.
+ * SA_ERR_STATE before the first level has run.  Any output may be NULL. */
+sa_status sa_best(sa_ctx *ctx, double *x_out, double *f_out, uint32_t *level_found);
+
+/* Per-level records of levels [first, first + count) (synchronises).
+ * x_best: count * n doubles or NULL; needs SA_FLAG_TRACE_X. */
+sa_status sa_trace(sa_ctx *ctx, uint32_t first, uint32_t count, sa_level *out, double *x_best);
+
+/* Logged moves (synchronises).  moves: log_levels * log_chains * steps
+ * records, index ((level - log_level) * log_chains + chain) * steps + step;
+ * final_f: log_levels * chains doubles, index (level - log_level) * chains +
+ * chain.  Either may be NULL. */
+sa_status sa_move_log(sa_ctx *ctx, sa_move_rec *moves, double *final_f);
+
+/* Release the context and any memory the library allocated. */
+void sa_destroy(sa_ctx *ctx);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *sa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_H */

@@ -1,0 +1,63 @@
+"""Build the gfx950 HIP library in-tree (hipcc, no JIT cache).
+
+The product is ``paper_2408_00018_amd/libsa_hip.so`` exporting the C ABI of
+``include/sa.h``.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+LIB = os.path.join(PKG, "libsa_hip.so")
+PEAK_LIB = os.path.join(PKG, "libsa_peak.so")
+
+SOURCES = ["sa_kernels.hip", "sa_api.hip"]
+PEAK_SOURCES = ["peak_probe.hip"]
+
+HIPCC_FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # FP64 runs are compared move for move with a plain FP64 evaluation, so no
+    # implicit contraction; FP32 code writes its fused multiply-adds explicitly.
+    "-ffp-contract=off",
+    # Packed FP32 instructions stay off: every VALU op here is scalar FP32/FP64
+    # or integer.
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+]
+
+
+def hipcc() -> str:
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found; the gfx950 library cannot be built")
+
+
+def _compile(sources, out, verbose):
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the library and the issue-rate probe; always rebuilds.
+    Returns the library's path."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(PEAK_SOURCES, PEAK_LIB, verbose)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

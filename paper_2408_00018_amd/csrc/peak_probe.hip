@@ -1,0 +1,122 @@
+// Issue-rate probe for the VALU instruction classes the annealing step uses.
+//
+// Each kernel keeps 16 independent dependency chains per lane and runs `iters`
+// rounds of one operation on each, so the measured rate is the instruction's
+// throughput rather than its latency.  The results are written to `sink` so
+// nothing is optimised away.  Used by the benchmark to check the per-class
+// costs the ALU roofline assumes (full rate vs quarter rate).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace {
+
+constexpr int kChains = 16;
+
+enum Kind : int {
+    kFmaF32 = 0,
+    kMadU64 = 1,
+    kMulHiU32 = 2,
+    kXor3 = 3,
+    kSinF32 = 4,
+    kSqrtF32 = 5,
+    kExp2F32 = 6,
+    kFmaF64 = 7,
+    kNumKinds = 8
+};
+
+__global__ void __launch_bounds__(256) probe_kernel(int kind, int iters, uint32_t *sink)
+{
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t u[kChains];
+    float f[kChains];
+    double g[kChains];
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) {
+        u[i] = tid * 2654435761u + i;
+        f[i] = 0.25f + 1e-3f * (float)((tid + i) & 255);
+        g[i] = 0.25 + 1e-3 * (double)((tid + i) & 255);
+    }
+    const uint32_t k1 = 0xD2511F53u, k2 = 0x9E3779B9u;
+    switch (kind) {
+    case kFmaF32:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) f[i] = fmaf(f[i], 0.999f, 1e-4f);
+        break;
+    case kMadU64:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) {
+                const uint64_t p = (uint64_t)u[i] * k1;
+                u[i] = (uint32_t)(p >> 32) ^ (uint32_t)p;
+            }
+        break;
+    case kMulHiU32:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) u[i] = __umulhi(u[i], k1) + k2;
+        break;
+    case kXor3:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) u[i] = u[i] ^ u[(i + 1) % kChains] ^ (k2 + it);
+        break;
+    case kSinF32:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) f[i] = __builtin_amdgcn_sinf(f[i]);
+        break;
+    case kSqrtF32:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) f[i] = __builtin_amdgcn_sqrtf(f[i]);
+        break;
+    case kExp2F32:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) f[i] = __builtin_amdgcn_exp2f(-f[i]);
+        break;
+    case kFmaF64:
+        for (int it = 0; it < iters; ++it)
+#pragma unroll
+            for (int i = 0; i < kChains; ++i) g[i] = fma(g[i], 0.999, 1e-4);
+        break;
+    default:
+        break;
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) acc ^= u[i] ^ __float_as_uint(f[i]) ^ (uint32_t)__double_as_longlong(g[i]);
+    sink[tid] = acc;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Run `kind` on `blocks` x 256 lanes for `iters` rounds of 16 chains; return
+// the elapsed milliseconds (HIP events on the null stream) in *ms.  The
+// operation count is blocks * 256 * iters * 16 lane-operations.
+int sa_peak_probe(int kind, int blocks, int iters, float *ms)
+{
+    if (kind < 0 || kind >= kNumKinds || blocks <= 0 || iters <= 0 || !ms) return -1;
+    uint32_t *sink = nullptr;
+    if (hipMalloc(&sink, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) return -2;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(256), 0, 0, kind, 1, sink);  // warm-up
+    (void)hipEventRecord(a, 0);
+    hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(256), 0, 0, kind, iters, sink);
+    (void)hipEventRecord(b, 0);
+    hipError_t e = hipEventSynchronize(b);
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(sink);
+    *ms = t;
+    return e == hipSuccess ? 0 : -3;
+}
+
+}  // extern "C"

@@ -1,0 +1,567 @@
+// Host runtime and C ABI (include/sa.h) of the gfx950 annealing library.
+//
+// The host validates the problem, lays out one device workspace, builds the
+// temperature table (T_{k+1} = alpha T_k, Sec. 2.1 Step 5) and enqueues one
+// level kernel per temperature level on the caller's stream -- eagerly, or
+// from a captured HIP graph.  No host work happens between levels: the
+// argmin and the broadcast of the winner run inside the level kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "sa_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sa_status fail(sa_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define SA_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(SA_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// LDS available to one workgroup on gfx950.
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Largest workgroup (4, 2 or 1 waves) that divides `chains` and whose state
+// fits in LDS.  0 if none fits.
+uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, size_t lds_limit)
+{
+    for (uint32_t wg = 256; wg >= 64; wg >>= 1) {
+        if (chains % wg) continue;
+        if (sa::level_lds_bytes(n, wg, real_size, table) <= lds_limit) return wg;
+    }
+    return 0;
+}
+
+struct Layout {
+    size_t table, T, inv_T, x_best, start, slots, slot_x, arrive, x_rec, rec, rec_level, trace, trace_x, log,
+        log_final, total;
+};
+
+struct Plan {
+    bool table = false;
+    uint32_t wg = 0, groups = 0;
+    size_t real = 0;
+    Layout lay{};
+};
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+sa_status validate(const sa_problem *p, const sa_config *c)
+{
+    if (!p || !c) return fail(SA_ERR_INVALID, "null problem or config");
+    if (p->func > SA_ACKLEY) return fail(SA_ERR_INVALID, "unknown function id %u", p->func);
+    if (p->n == 0) return fail(SA_ERR_INVALID, "dimension n must be >= 1");
+    if (!p->lower || !p->upper) return fail(SA_ERR_INVALID, "lower/upper must not be NULL");
+    for (uint32_t i = 0; i < p->n; ++i) {
+        if (!is_finite(p->lower[i]) || !is_finite(p->upper[i]))
+            return fail(SA_ERR_INVALID, "box bound %u is not finite", i);
+        if (!(p->lower[i] < p->upper[i])) return fail(SA_ERR_INVALID, "box %u has lower >= upper", i);
+        if (p->shift && !is_finite(p->shift[i])) return fail(SA_ERR_INVALID, "shift %u is not finite", i);
+    }
+    if (c->chains == 0 || c->chains % 64) return fail(SA_ERR_INVALID, "chains must be a positive multiple of 64");
+    if (c->levels == 0) return fail(SA_ERR_INVALID, "levels must be >= 1");
+    if (c->steps == 0) return fail(SA_ERR_INVALID, "steps must be >= 1");
+    if (c->precision > SA_FP64) return fail(SA_ERR_INVALID, "unknown precision %u", c->precision);
+    if (c->move > SA_MOVE_RESAMPLE) return fail(SA_ERR_INVALID, "unknown move rule %u", c->move);
+    if (!(c->T0 > 0.0) || !is_finite(c->T0)) return fail(SA_ERR_INVALID, "T0 must be finite and > 0");
+    if (!(c->alpha > 0.0 && c->alpha <= 1.0)) return fail(SA_ERR_INVALID, "alpha must be in (0, 1]");
+    if (!(c->radius_frac > 0.0) || !is_finite(c->radius_frac))
+        return fail(SA_ERR_INVALID, "radius_frac must be finite and > 0");
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH)) return fail(SA_ERR_INVALID, "unknown flag bits");
+    if (c->log_chains) {
+        if (c->log_chains > c->chains) return fail(SA_ERR_INVALID, "log_chains exceeds chains");
+        if (c->log_levels == 0 || c->log_level >= c->levels || c->log_levels > c->levels - c->log_level)
+            return fail(SA_ERR_INVALID, "logged level range outside [0, levels)");
+    }
+    return SA_OK;
+}
+
+bool uniform_box(const sa_problem *p)
+{
+    for (uint32_t i = 1; i < p->n; ++i) {
+        if (p->lower[i] != p->lower[0] || p->upper[i] != p->upper[0]) return false;
+        if (p->shift && p->shift[i] != p->shift[0]) return false;
+    }
+    return true;
+}
+
+sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *out)
+{
+    Plan pl;
+    pl.table = !uniform_box(p);
+    pl.real = c->precision == SA_FP64 ? sizeof(double) : sizeof(float);
+    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, lds_limit);
+    if (pl.wg == 0)
+        return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
+    pl.groups = c->chains / pl.wg;
+    const size_t n = p->n, L = c->levels, R = pl.real;
+    Layout &l = pl.lay;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    l.table = take(pl.table ? 4 * n * R : 0);
+    l.T = take(L * sizeof(double));
+    l.inv_T = take(L * sizeof(float));
+    l.x_best = take(n * R);
+    l.start = take(4 * sizeof(double));
+    l.slots = take((size_t)pl.groups * 16);
+    l.slot_x = take((size_t)pl.groups * n * R);
+    l.arrive = take(sizeof(uint32_t));
+    l.x_rec = take(n * R);
+    l.rec = take(2 * sizeof(double));
+    l.rec_level = take(sizeof(uint32_t));
+    l.trace = take(L * sizeof(sa_level));
+    l.trace_x = take((c->flags & SA_FLAG_TRACE_X) ? L * n * R : 0);
+    const size_t log_moves = c->log_chains ? (size_t)c->log_levels * c->log_chains * c->steps : 0;
+    l.log = take(log_moves * sizeof(sa_move_rec));
+    l.log_final = take(c->log_chains ? (size_t)c->log_levels * c->chains * sizeof(double) : 0);
+    l.total = off;
+    *out = pl;
+    return SA_OK;
+}
+
+// Round a box inward to FP32 so every FP32 state lies in the FP64 box.
+float round_up_f(double v)
+{
+    float f = (float)v;
+    if ((double)f < v) f = std::nextafter(f, INFINITY);
+    return f;
+}
+float round_down_f(double v)
+{
+    float f = (float)v;
+    if ((double)f > v) f = std::nextafter(f, -INFINITY);
+    return f;
+}
+
+}  // namespace
+
+struct sa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture = nullptr;
+    sa_problem prob{};
+    sa_config cfg{};
+    std::vector<double> lower, upper, shift;
+    Plan pl;
+    unsigned char *ws = nullptr;
+    bool own_ws = false;
+    uint32_t next_level = 0;
+    uint64_t seed = 0;
+    bool fp64 = false;
+    sa::LevelArgs<float> a32{};
+    sa::LevelArgs<double> a64{};
+    std::map<std::pair<uint32_t, uint32_t>, hipGraphExec_t> graphs;
+    std::map<std::pair<uint32_t, uint32_t>, hipGraph_t> graph_defs;
+};
+
+namespace {
+
+template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
+{
+    const Layout &l = c->pl.lay;
+    unsigned char *w = c->ws;
+    a.n = c->prob.n;
+    a.chains = c->cfg.chains;
+    a.steps = c->cfg.steps;
+    a.move = c->cfg.move;
+    a.problem = 0;
+    a.seed_lo = (uint32_t)c->seed;
+    a.seed_hi = (uint32_t)(c->seed >> 32);
+    a.wg = c->pl.wg;
+    a.table = c->pl.table ? reinterpret_cast<const R *>(w + l.table) : nullptr;
+    a.inv_n = (float)(1.0 / (double)c->prob.n);
+    a.T = reinterpret_cast<const double *>(w + l.T);
+    a.inv_T = reinterpret_cast<const float *>(w + l.inv_T);
+    a.x_best = reinterpret_cast<R *>(w + l.x_best);
+    a.start = reinterpret_cast<double *>(w + l.start);
+    a.slots = reinterpret_cast<sa::Slot<R> *>(w + l.slots);
+    a.slot_x = reinterpret_cast<R *>(w + l.slot_x);
+    a.arrive = reinterpret_cast<uint32_t *>(w + l.arrive);
+    a.x_rec = reinterpret_cast<R *>(w + l.x_rec);
+    a.rec = reinterpret_cast<double *>(w + l.rec);
+    a.rec_level = reinterpret_cast<uint32_t *>(w + l.rec_level);
+    a.trace = reinterpret_cast<sa_level *>(w + l.trace);
+    a.trace_x = (c->cfg.flags & SA_FLAG_TRACE_X) ? reinterpret_cast<R *>(w + l.trace_x) : nullptr;
+    a.log = c->cfg.log_chains ? reinterpret_cast<sa_move_rec *>(w + l.log) : nullptr;
+    a.log_final = c->cfg.log_chains ? reinterpret_cast<double *>(w + l.log_final) : nullptr;
+    a.log_chains = c->cfg.log_chains;
+    a.log_level = c->cfg.log_level;
+    a.log_levels = c->cfg.log_chains ? c->cfg.log_levels : 0;
+}
+
+// Box/shift values of coordinate i in the run's precision: (l, u, rho, s).
+void coord_values(const sa_ctx *c, uint32_t i, double out[4])
+{
+    const double lo = c->lower[i], hi = c->upper[i];
+    const double sh = c->shift.empty() ? 0.0 : c->shift[i];
+    if (c->fp64) {
+        out[0] = lo;
+        out[1] = hi;
+        out[2] = c->cfg.move == SA_MOVE_RADIUS ? c->cfg.radius_frac * (hi - lo) : hi - lo;
+        out[3] = sh;
+    } else {
+        const float l32 = round_up_f(lo), u32 = round_down_f(hi);
+        const double w = (double)u32 - (double)l32;
+        out[0] = l32;
+        out[1] = u32;
+        out[2] = (float)(c->cfg.move == SA_MOVE_RADIUS ? c->cfg.radius_frac * w : w);
+        out[3] = (float)sh;
+    }
+}
+
+sa_status upload_tables(sa_ctx *c)
+{
+    const Layout &l = c->pl.lay;
+    const uint32_t n = c->prob.n, L = c->cfg.levels;
+    std::vector<double> T(L);
+    std::vector<float> inv_T(L);
+    double t = c->cfg.T0;
+    for (uint32_t k = 0; k < L; ++k) {
+        T[k] = t;
+        inv_T[k] = (float)(1.0 / t);
+        t = t * c->cfg.alpha;
+    }
+    SA_HIP(hipMemcpyAsync(c->ws + l.T, T.data(), L * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipMemcpyAsync(c->ws + l.inv_T, inv_T.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    double v[4];
+    if (c->pl.table) {
+        if (c->fp64) {
+            std::vector<double> tab(4 * (size_t)n);
+            for (uint32_t i = 0; i < n; ++i) {
+                coord_values(c, i, v);
+                for (int k = 0; k < 4; ++k) tab[4 * i + k] = v[k];
+            }
+            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+                                  c->stream));
+        } else {
+            std::vector<float> tab(4 * (size_t)n);
+            for (uint32_t i = 0; i < n; ++i) {
+                coord_values(c, i, v);
+                for (int k = 0; k < 4; ++k) tab[4 * i + k] = (float)v[k];
+            }
+            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice,
+                                  c->stream));
+        }
+    }
+    coord_values(c, 0, v);
+    if (c->fp64) {
+        c->a64.lo = v[0];
+        c->a64.hi = v[1];
+        c->a64.rho = v[2];
+        c->a64.sh = v[3];
+    } else {
+        c->a32.lo = (float)v[0];
+        c->a32.hi = (float)v[1];
+        c->a32.rho = (float)v[2];
+        c->a32.sh = (float)v[3];
+    }
+    // The host copies above read pageable memory; finish them before the
+    // vectors go out of scope.
+    SA_HIP(hipStreamSynchronize(c->stream));
+    return SA_OK;
+}
+
+sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t s)
+{
+    const uint32_t lg0 = c->cfg.log_level, lgn = c->cfg.log_chains ? c->cfg.log_levels : 0;
+    for (uint32_t k = first; k < first + count; ++k) {
+        const bool log = lgn && k >= lg0 && k - lg0 < lgn;
+        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, log, c->a64, k, s)
+                               : sa::launch_level_f32(c->prob.func, c->pl.table, log, c->a32, k, s);
+        if (e != hipSuccess) return fail(SA_ERR_DEVICE, "level %u launch: %s", k, hipGetErrorString(e));
+    }
+    return SA_OK;
+}
+
+void drop_graphs(sa_ctx *c)
+{
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
+    for (auto &g : c->graph_defs) (void)hipGraphDestroy(g.second);
+    c->graphs.clear();
+    c->graph_defs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sa_last_error(void) { return g_last_error.c_str(); }
+
+sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_t *bytes)
+{
+    g_last_error.clear();
+    if (!bytes) return fail(SA_ERR_INVALID, "bytes must not be NULL");
+    sa_status st = validate(prob, cfg);
+    if (st != SA_OK) return st;
+    Plan pl;
+    st = plan(prob, cfg, kLdsPerWorkgroup, &pl);
+    if (st != SA_OK) return st;
+    *bytes = pl.lay.total;
+    return SA_OK;
+}
+
+sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, void *workspace, size_t ws_bytes,
+                    sa_ctx **out)
+{
+    g_last_error.clear();
+    if (!out) return fail(SA_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    sa_status st = validate(prob, cfg);
+    if (st != SA_OK) return st;
+
+    int dev = 0;
+    SA_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SA_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SA_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950 only", dev,
+                    prop.gcnArchName);
+    const size_t lds_limit = std::min<size_t>(kLdsPerWorkgroup, prop.sharedMemPerBlock);
+
+    sa_ctx *c = new (std::nothrow) sa_ctx;
+    if (!c) return fail(SA_ERR_NOMEM, "host allocation failed");
+    c->device = dev;
+    c->stream = reinterpret_cast<hipStream_t>(stream);
+    c->cfg = *cfg;
+    c->seed = cfg->seed;
+    c->fp64 = cfg->precision == SA_FP64;
+    c->lower.assign(prob->lower, prob->lower + prob->n);
+    c->upper.assign(prob->upper, prob->upper + prob->n);
+    if (prob->shift) c->shift.assign(prob->shift, prob->shift + prob->n);
+    c->prob = *prob;
+    c->prob.lower = c->lower.data();
+    c->prob.upper = c->upper.data();
+    c->prob.shift = prob->shift ? c->shift.data() : nullptr;
+    if (!c->fp64) {
+        for (uint32_t i = 0; i < prob->n; ++i) {
+            if (!(round_up_f(prob->lower[i]) < round_down_f(prob->upper[i]))) {
+                delete c;
+                return fail(SA_ERR_INVALID, "box %u is empty after rounding inward to FP32", i);
+            }
+        }
+    }
+    st = plan(&c->prob, &c->cfg, lds_limit, &c->pl);
+    if (st != SA_OK) {
+        delete c;
+        return st;
+    }
+    if (workspace) {
+        if (ws_bytes < c->pl.lay.total) {
+            delete c;
+            return fail(SA_ERR_INVALID, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes,
+                        c->pl.lay.total);
+        }
+        if (reinterpret_cast<uintptr_t>(workspace) % kAlign) {
+            delete c;
+            return fail(SA_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+        }
+        c->ws = static_cast<unsigned char *>(workspace);
+    } else {
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&c->ws), c->pl.lay.total);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(SA_ERR_NOMEM, "hipMalloc(%zu): %s", c->pl.lay.total, hipGetErrorString(e));
+        }
+        c->own_ws = true;
+    }
+    if (c->fp64)
+        fill_args<double>(c, c->a64);
+    else
+        fill_args<float>(c, c->a32);
+    st = upload_tables(c);
+    if (st == SA_OK) {
+        hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
+                                        reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level),
+                                        reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.arrive), c->stream);
+        if (e != hipSuccess) st = fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
+    }
+    if (st != SA_OK) {
+        sa_destroy(c);
+        return st;
+    }
+    *out = c;
+    return SA_OK;
+}
+
+sa_status sa_run(sa_ctx *c, uint32_t levels)
+{
+    g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    const uint32_t L = c->cfg.levels;
+    if (c->next_level >= L) return fail(SA_ERR_STATE, "all %u levels have run", L);
+    const uint32_t count = levels ? levels : L - c->next_level;
+    if (count > L - c->next_level)
+        return fail(SA_ERR_STATE, "%u levels requested, %u remain", count, L - c->next_level);
+    const uint32_t first = c->next_level;
+    if (c->cfg.flags & SA_FLAG_GRAPH) {
+        const auto key = std::make_pair(first, count);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (!c->capture) SA_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+            SA_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
+            sa_status st = enqueue_levels(c, first, count, c->capture);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->capture, &g);
+            if (st != SA_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return fail(SA_ERR_DEVICE, "graph capture: %s", hipGetErrorString(e));
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return fail(SA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+            }
+            c->graph_defs[key] = g;
+            it = c->graphs.emplace(key, ge).first;
+        }
+        SA_HIP(hipGraphLaunch(it->second, c->stream));
+    } else {
+        sa_status st = enqueue_levels(c, first, count, c->stream);
+        if (st != SA_OK) return st;
+    }
+    c->next_level = first + count;
+    return SA_OK;
+}
+
+sa_status sa_reset(sa_ctx *c, uint64_t seed)
+{
+    g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (seed != c->seed) {
+        // Captured graphs hold the seed in their kernel arguments.
+        drop_graphs(c);
+        c->seed = seed;
+        c->a32.seed_lo = c->a64.seed_lo = (uint32_t)seed;
+        c->a32.seed_hi = c->a64.seed_hi = (uint32_t)(seed >> 32);
+    }
+    hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
+                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level),
+                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.arrive), c->stream);
+    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
+    c->next_level = 0;
+    return SA_OK;
+}
+
+sa_status sa_levels_done(const sa_ctx *c, uint32_t *levels)
+{
+    if (!c || !levels) return fail(SA_ERR_INVALID, "null argument");
+    *levels = c->next_level;
+    return SA_OK;
+}
+
+sa_status sa_best(sa_ctx *c, double *x_out, double *f_out, uint32_t *level_found)
+{
+    g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (c->next_level == 0) return fail(SA_ERR_STATE, "no level has run");
+    SA_HIP(hipStreamSynchronize(c->stream));
+    const Layout &l = c->pl.lay;
+    const uint32_t n = c->prob.n;
+    double rec[2];
+    uint32_t lvl = 0;
+    SA_HIP(hipMemcpy(rec, c->ws + l.rec, sizeof rec, hipMemcpyDeviceToHost));
+    SA_HIP(hipMemcpy(&lvl, c->ws + l.rec_level, sizeof lvl, hipMemcpyDeviceToHost));
+    if (lvl == 0xFFFFFFFFu) return fail(SA_ERR_STATE, "no record yet");
+    if (x_out) {
+        if (c->fp64) {
+            SA_HIP(hipMemcpy(x_out, c->ws + l.x_rec, n * sizeof(double), hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> x(n);
+            SA_HIP(hipMemcpy(x.data(), c->ws + l.x_rec, n * sizeof(float), hipMemcpyDeviceToHost));
+            for (uint32_t i = 0; i < n; ++i) x_out[i] = x[i];
+        }
+    }
+    if (f_out) *f_out = rec[0];
+    if (level_found) *level_found = lvl;
+    return SA_OK;
+}
+
+sa_status sa_trace(sa_ctx *c, uint32_t first, uint32_t count, sa_level *out, double *x_best)
+{
+    g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (count == 0) return SA_OK;
+    if (first >= c->next_level || count > c->next_level - first)
+        return fail(SA_ERR_STATE, "levels [%u, %u) have not all run (%u done)", first, first + count,
+                    c->next_level);
+    if (x_best && !(c->cfg.flags & SA_FLAG_TRACE_X))
+        return fail(SA_ERR_STATE, "x_best trace needs SA_FLAG_TRACE_X");
+    SA_HIP(hipStreamSynchronize(c->stream));
+    const Layout &l = c->pl.lay;
+    if (out)
+        SA_HIP(hipMemcpy(out, c->ws + l.trace + (size_t)first * sizeof(sa_level), count * sizeof(sa_level),
+                         hipMemcpyDeviceToHost));
+    if (x_best) {
+        const size_t n = c->prob.n, m = n * count;
+        if (c->fp64) {
+            SA_HIP(hipMemcpy(x_best, c->ws + l.trace_x + first * n * sizeof(double), m * sizeof(double),
+                             hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> x(m);
+            SA_HIP(hipMemcpy(x.data(), c->ws + l.trace_x + first * n * sizeof(float), m * sizeof(float),
+                             hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < m; ++i) x_best[i] = x[i];
+        }
+    }
+    return SA_OK;
+}
+
+sa_status sa_move_log(sa_ctx *c, sa_move_rec *moves, double *final_f)
+{
+    g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (!c->cfg.log_chains) return fail(SA_ERR_STATE, "the context was created without a move log");
+    SA_HIP(hipStreamSynchronize(c->stream));
+    const Layout &l = c->pl.lay;
+    if (moves)
+        SA_HIP(hipMemcpy(moves, c->ws + l.log,
+                         (size_t)c->cfg.log_levels * c->cfg.log_chains * c->cfg.steps * sizeof(sa_move_rec),
+                         hipMemcpyDeviceToHost));
+    if (final_f)
+        SA_HIP(hipMemcpy(final_f, c->ws + l.log_final, (size_t)c->cfg.log_levels * c->cfg.chains * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    return SA_OK;
+}
+
+void sa_destroy(sa_ctx *c)
+{
+    if (!c) return;
+    if (c->stream || c->ws) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    if (c->own_ws && c->ws) (void)hipFree(c->ws);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Internal interface between the host runtime (sa_api.hip) and the kernels
+// (sa_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sa.h"
+
+namespace sa {
+
+constexpr int kSchwefel = SA_SCHWEFEL;
+constexpr int kRastrigin = SA_RASTRIGIN;
+constexpr int kAckley = SA_ACKLEY;
+
+// Full evaluation of a state in FP64 arithmetic: the cost and, for Ackley,
+// the two sums under its exponentials.
+struct Full {
+    double f, s1, s2;
+};
+
+// Best chain of a workgroup at the end of a level.
+template <typename R> struct Slot {
+    R f;
+    uint32_t chain;
+    uint32_t accepts;
+};
+
+// Arguments of one level launch.  Device pointers point into the context's
+// workspace.  R is the state precision (float or double).
+template <typename R> struct LevelArgs {
+    uint32_t n, chains, steps, move;
+    uint32_t problem, seed_lo, seed_hi, wg;
+    // Box and shift: either one value for every coordinate (table == nullptr)
+    // or a table of n entries {l, u, rho, s} (rho = u - l for resampling).
+    R lo, hi, rho, sh;
+    const R *table;
+    float inv_n;
+    const double *T;     // T_k, FP64
+    const float *inv_T;  // 1 / T_k rounded to FP32
+    R *x_best;           // n: start state of the level; the winner afterwards
+    double *start;       // {f, S1, S2} of x_best, FP64 arithmetic
+    Slot<R> *slots;      // one per workgroup
+    R *slot_x;           // n per workgroup
+    uint32_t *arrive;    // workgroups finished with the current level
+    R *x_rec;            // n
+    double *rec;         // {f_rec}
+    uint32_t *rec_level;
+    sa_level *trace;     // one per level
+    R *trace_x;          // n per level, or nullptr
+    sa_move_rec *log;    // move log, or nullptr
+    double *log_final;   // per-chain final cost at logged levels
+    uint32_t log_chains, log_level, log_levels;
+};
+
+// Host-side launchers (one level each).  Return the launch status.
+hipError_t launch_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
+                            hipStream_t s);
+hipError_t launch_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
+                            hipStream_t s);
+// Reset the record and the arrival counter (a kernel, so it can be captured).
+hipError_t launch_reset(double *rec, uint32_t *rec_level, uint32_t *arrive, hipStream_t s);
+
+// Dynamic LDS bytes of a level launch.
+size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table);
+
+}  // namespace sa

@@ -1,0 +1,224 @@
+"""ctypes binding of the gfx950 annealing library (``include/sa.h``).
+
+Argument marshalling only: every step of the annealing runs in the library's
+HIP kernels.  PyTorch supplies the device workspace (a uint8 tensor) and the
+HIP stream (the current torch stream).  If the built library is missing, or
+no gfx950 device is present, the calls raise -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
+
+SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+FP32, FP64 = 0, 1
+MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
+FLAG_TRACE_X, FLAG_GRAPH = 0x1, 0x2
+
+SA_OK = 0
+STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ERR_DEVICE", -4: "SA_ERR_STATE",
+                -5: "SA_ERR_UNSUPPORTED"}
+
+EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
+            "sa_move_log", "sa_destroy", "sa_last_error"]
+
+
+class SAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("func", ctypes.c_uint32), ("n", ctypes.c_uint32), ("lower", ctypes.c_void_p),
+                ("upper", ctypes.c_void_p), ("shift", ctypes.c_void_p)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("chains", ctypes.c_uint32), ("levels", ctypes.c_uint32),
+                ("steps", ctypes.c_uint32), ("precision", ctypes.c_uint32), ("move", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("T0", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("radius_frac", ctypes.c_double), ("log_chains", ctypes.c_uint32), ("log_level", ctypes.c_uint32),
+                ("log_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+LEVEL_DTYPE = np.dtype([("win_chain", np.uint32), ("reserved", np.uint32), ("f_win", np.float64),
+                        ("f_best", np.float64), ("f_rec", np.float64), ("accepts", np.uint64),
+                        ("t_ticks", np.uint64)])
+MOVE_DTYPE = np.dtype([("d", np.uint32), ("accept", np.uint32), ("x_old", np.float64), ("x_new", np.float64),
+                       ("df", np.float64)])
+
+_lib = None
+
+
+def load_library():
+    """Load libsa_hip.so (built by ``__graft_entry__.build()``); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+    # torch ships the HIP runtime this process uses; load it first so the
+    # library binds to the same libamdhip64.
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, st = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    L.sa_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config), ctypes.POINTER(ctypes.c_size_t)]
+    L.sa_workspace_bytes.restype = st
+    L.sa_create.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config), vp, vp, ctypes.c_size_t,
+                            ctypes.POINTER(vp)]
+    L.sa_create.restype = st
+    L.sa_run.argtypes = [vp, u32]
+    L.sa_run.restype = st
+    L.sa_reset.argtypes = [vp, u64]
+    L.sa_reset.restype = st
+    L.sa_levels_done.argtypes = [vp, ctypes.POINTER(u32)]
+    L.sa_levels_done.restype = st
+    L.sa_best.argtypes = [vp, vp, vp, vp]
+    L.sa_best.restype = st
+    L.sa_trace.argtypes = [vp, u32, u32, vp, vp]
+    L.sa_trace.restype = st
+    L.sa_move_log.argtypes = [vp, vp, vp]
+    L.sa_move_log.restype = st
+    L.sa_destroy.argtypes = [vp]
+    L.sa_destroy.restype = None
+    L.sa_last_error.argtypes = []
+    L.sa_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != SA_OK:
+        raise SAError(status, load_library().sa_last_error().decode())
+
+
+@dataclass
+class Schedule:
+    """Annealing schedule and options (mirrors ``sa_config``)."""
+    chains: int
+    levels: int
+    steps: int
+    T0: float
+    alpha: float
+    seed: int = 0
+    precision: int = FP32
+    move: int = MOVE_RADIUS
+    radius_frac: float = 0.1
+    trace_x: bool = False
+    graph: bool = False
+    log_chains: int = 0
+    log_level: int = 0
+    log_levels: int = 0
+
+    def to_c(self) -> Config:
+        flags = (FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0)
+        return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
+                      self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels, 0)
+
+
+def _problem_struct(func, lower, upper, shift):
+    lo = np.ascontiguousarray(lower, dtype=np.float64)
+    hi = np.ascontiguousarray(upper, dtype=np.float64)
+    sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
+    p = Problem(func, lo.size, lo.ctypes.data, hi.ctypes.data, None if sh is None else sh.ctypes.data)
+    return p, (lo, hi, sh)
+
+
+def workspace_bytes(func, lower, upper, shift, sched: Schedule) -> int:
+    L = load_library()
+    p, keep = _problem_struct(func, lower, upper, shift)
+    cfg = sched.to_c()
+    nbytes = ctypes.c_size_t()
+    _check(L.sa_workspace_bytes(ctypes.byref(p), ctypes.byref(cfg), ctypes.byref(nbytes)))
+    del keep
+    return nbytes.value
+
+
+class Annealer:
+    """One annealing problem on the current torch CUDA (HIP) device."""
+
+    def __init__(self, func: int, lower, upper, shift=None, *, schedule: Schedule, stream=None,
+                 torch_workspace: bool = True):
+        import torch
+        L = load_library()
+        self.schedule = schedule
+        self.n = int(np.asarray(lower).size)
+        p, keep = _problem_struct(func, lower, upper, shift)
+        cfg = schedule.to_c()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if torch_workspace:
+            nbytes = ctypes.c_size_t()
+            _check(L.sa_workspace_bytes(ctypes.byref(p), ctypes.byref(cfg), ctypes.byref(nbytes)))
+            self._ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+            ws_ptr, ws_bytes = self._ws.data_ptr(), nbytes.value
+        ctx = ctypes.c_void_p()
+        _check(L.sa_create(ctypes.byref(p), ctypes.byref(cfg), ctypes.c_void_p(self._stream.cuda_stream), ws_ptr,
+                           ws_bytes, ctypes.byref(ctx)))
+        del keep
+        self._ctx = ctx
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def run(self, levels: int = 0):
+        _check(load_library().sa_run(self._ctx, levels))
+
+    def reset(self, seed: int):
+        _check(load_library().sa_reset(self._ctx, seed))
+
+    def levels_done(self) -> int:
+        v = ctypes.c_uint32()
+        _check(load_library().sa_levels_done(self._ctx, ctypes.byref(v)))
+        return v.value
+
+    def best(self):
+        x = np.zeros(self.n)
+        f = ctypes.c_double()
+        lvl = ctypes.c_uint32()
+        _check(load_library().sa_best(self._ctx, x.ctypes.data, ctypes.byref(f), ctypes.byref(lvl)))
+        return x, f.value, lvl.value
+
+    def trace(self, first: int = 0, count: Optional[int] = None, with_x: bool = False):
+        if count is None:
+            count = self.levels_done() - first
+        rec = np.zeros(count, dtype=LEVEL_DTYPE)
+        xb = np.zeros((count, self.n)) if with_x else None
+        _check(load_library().sa_trace(self._ctx, first, count, rec.ctypes.data,
+                                       None if xb is None else xb.ctypes.data))
+        return (rec, xb) if with_x else rec
+
+    def move_log(self):
+        s = self.schedule
+        moves = np.zeros((s.log_levels, s.log_chains, s.steps), dtype=MOVE_DTYPE)
+        final_f = np.zeros((s.log_levels, s.chains))
+        _check(load_library().sa_move_log(self._ctx, moves.ctypes.data, final_f.ctypes.data))
+        return moves, final_f
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            load_library().sa_destroy(self._ctx)
+            self._ctx = None
+        self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,132 @@
+"""Shared checks of the GPU path against the FP64 oracle.
+
+The GPU side is reached only through the C ABI binding
+(``paper_2408_00018_amd.sa``); the expected values come only from ``oracle``.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle as O
+
+U32 = 2.0 ** -24  # FP32 unit roundoff
+# Absolute error bound of the FP32 hardware sine/cosine on the arguments used
+# here (|t| <= 64 revolutions), with margin; see the design notes.
+E_TRIG = 2.0 ** -19
+
+
+def f32(v):
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
+def box32(lower, upper):
+    """The FP32 box the library uses: bounds rounded inward."""
+    lo = np.asarray(lower, dtype=np.float64)
+    hi = np.asarray(upper, dtype=np.float64)
+    l32 = lo.astype(np.float32)
+    l32 = np.where(l32.astype(np.float64) < lo, np.nextafter(l32, np.float32(np.inf)), l32)
+    h32 = hi.astype(np.float32)
+    h32 = np.where(h32.astype(np.float64) > hi, np.nextafter(h32, np.float32(-np.inf)), h32)
+    return l32.astype(np.float64), h32.astype(np.float64)
+
+
+def df_floor(func, n, x, xn, d, shift):
+    """Absolute error floor of an FP32 cost increment, from the rounding of its
+    inputs and the hardware transcendental error (the relative 1e-5 is added
+    on top).  x, xn: FP64 copies of the FP32 states before/after the move."""
+    s = 0.0 if shift is None else shift[d]
+    y, yn = x[d] - s, xn[d] - s
+    if func == O.SCHWEFEL:
+        def t(v):
+            a = abs(v)
+            return a * (math.sqrt(a) * 4 * U32 + E_TRIG) + a * 2 * U32
+        return 4.0 * (t(y) + t(yn)) / n
+    if func == O.RASTRIGIN:
+        dl, sg = abs(yn - y), abs(yn + y)
+        ddl = U32 * (abs(y) + abs(yn) + dl)
+        dsg = U32 * (abs(y) + abs(yn) + sg)
+        return 4.0 * (sg * ddl + dl * dsg + dl * sg * 2 * U32 + 20 * (math.pi * (ddl + dsg) + 2 * E_TRIG)
+                      + 40 * U32)
+    # Ackley, increment formed from the two sums (S1 = sum y^2, S2 = sum cos 2 pi y):
+    # errors of dS1 = dl sg and dS2 = -2 sin(pi sg) sin(pi dl), plus the FP32
+    # rounding/drift of the carried sums (<= 64 roundings per level) acting on
+    # e^a = exp(-0.2 sqrt(S1/n)) and e^b = exp(S2/n).
+    ys = x - (0.0 if shift is None else shift)
+    s1 = float(np.dot(ys, ys))
+    s2 = float(np.sum(np.cos(2 * math.pi * ys)))
+    q = math.sqrt(s1 / n)
+    s1n = s1 + (yn * yn - y * y)
+    qn = math.sqrt(max(s1n, 0.0) / n)
+    ea, eb = math.exp(-0.2 * q), math.exp(s2 / n)
+    dl, sg = abs(yn - y), abs(yn + y)
+    ddl = U32 * (abs(y) + abs(yn) + dl)
+    dsg = U32 * (abs(y) + abs(yn) + sg)
+    ds1 = dl * sg
+    e_ds1 = sg * ddl + dl * dsg + U32 * ds1
+    ds2 = 2.0 * abs(math.sin(math.pi * sg) * math.sin(math.pi * dl))
+    e_ds2 = 2.0 * (math.pi * (ddl + dsg) + 2 * E_TRIG) + 3 * U32 * ds2
+    den = max(q + qn, 1e-30)
+    da = 0.2 * (ds1 / n) / den
+    term_a = 20.0 * ea * da * (6.4 * q * U32 + 36 * U32) + 20.0 * ea * 0.2 * e_ds1 / (n * den)
+    term_b = eb * (ds2 / n) * 68 * U32 + eb * e_ds2 / n
+    return 4.0 * (term_a + term_b)
+
+
+def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
+                     final_f, chain_ids, rel=1e-5):
+    """Replay the logged moves of `chain_ids` at one level against the oracle.
+
+    x_start: the level's start state (the previous level's broadcast winner,
+    FP32 values).  Returns statistics; raises AssertionError on a mismatch."""
+    stats = dict(moves=0, max_rel_excess=0.0, decision_mismatch=0, ambiguous=0, max_df_err=0.0)
+    for j, c in enumerate(chain_ids):
+        x = np.array(x_start, dtype=np.float64)
+        f_acc_err = 0.0
+        for s in range(moves.shape[-1]):
+            m = moves[j, s]
+            d_ref, u1, u2, _ = O.move_draw(seed, 0, level, c, s, n)
+            assert int(m["d"]) == d_ref, (level, c, s)
+            assert m["x_old"] == x[d_ref], (level, c, s)
+            xn_ref = O.neighbour(move_rule, float(m["x_old"]), float(lower32[d_ref]), float(upper32[d_ref]),
+                                 radius_frac, u1)
+            rho = radius_frac * (upper32[d_ref] - lower32[d_ref])
+            tol_x = 2.0 ** -23 * (abs(xn_ref) + rho)
+            assert abs(m["x_new"] - xn_ref) <= tol_x, (level, c, s, m["x_new"], xn_ref)
+            assert lower32[d_ref] <= m["x_new"] <= upper32[d_ref]
+            xn = x.copy()
+            xn[d_ref] = m["x_new"]
+            df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
+            floor = df_floor(func, n, x, xn, d_ref, shift32)
+            err = abs(m["df"] - df_ref)
+            tol = rel * abs(df_ref) + floor
+            stats["max_df_err"] = max(stats["max_df_err"], err)
+            stats["max_rel_excess"] = max(stats["max_rel_excess"], err / tol if tol > 0 else 0.0)
+            assert err <= tol, (level, c, s, float(m["df"]), df_ref, floor)
+            # Metropolis decision: equal wherever the oracle's decision cannot
+            # be flipped by an increment error within tolerance.
+            acc_ref = O.accept(df_ref, T, u2)
+            # plus the FP32 rounding of 1/T and of the hardware exp2 (a few ulp)
+            margin = tol + 2.0 ** -18 * T
+            lo_df, hi_df = df_ref - margin, df_ref + margin
+            firm = O.accept(lo_df, T, u2) == O.accept(hi_df, T, u2)
+            if firm:
+                if bool(m["accept"]) != acc_ref:
+                    stats["decision_mismatch"] += 1
+            else:
+                stats["ambiguous"] += 1
+            assert not firm or bool(m["accept"]) == acc_ref, (level, c, s, float(m["df"]), df_ref, u2, T)
+            if m["accept"]:
+                x = xn
+                f_acc_err += tol + 2 * U32 * abs(O.f(func, x, shift32))
+            stats["moves"] += 1
+        f_ref = O.f(func, x, shift32)
+        start_err = 2 * U32 * abs(O.f(func, x_start, shift32)) + 1e-12
+        assert abs(final_f[c] - f_ref) <= f_acc_err + start_err + 2 * U32 * abs(f_ref), (level, c)
+    return stats
+
+
+def lexi_argmin(values):
+    m = np.min(values)
+    return int(np.flatnonzero(values == m)[0])
