@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--cpu-levels", type=int, default=10, help="levels of the workload the CPU oracle times")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
     return p.parse_args()
 
 
@@ -97,6 +99,14 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
     wl = W.schwefel_n100_fp32()
     sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
                         precision=sa.FP32, graph=True)

@@ -28,6 +28,13 @@ constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
 constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
 constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
 
+// Three-input XOR in one VALU instruction: CDNA4's v_bitop3_b32 with truth
+// table 0x96 (A ^ B ^ C).  Left to itself the compiler emits two v_xor_b32.
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t key)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, key, 0x96);
+}
+
 __device__ __forceinline__ Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -36,7 +43,7 @@ __device__ __forceinline__ Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1)
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c.w2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = Ctr{hi1 ^ c.w1 ^ k0, lo1, hi0 ^ c.w3 ^ k1, lo0};
+        c = Ctr{xor3_key(hi1, c.w1, k0), lo1, xor3_key(hi0, c.w3, k1), lo0};
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }

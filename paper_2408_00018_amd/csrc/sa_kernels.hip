@@ -35,7 +35,7 @@ template <> struct Cost<double, kSchwefel> {
         fn = f + df;
         return df;
     }
-    __device__ void commit(float) { f = fn; }
+    __device__ void commit(bool take, float) { f = take ? fn : f; }
 };
 
 template <> struct Cost<double, kRastrigin> {
@@ -47,7 +47,7 @@ template <> struct Cost<double, kRastrigin> {
         fn = f + df;
         return df;
     }
-    __device__ void commit(float) { f = fn; }
+    __device__ void commit(bool take, float) { f = take ? fn : f; }
 };
 
 template <> struct Cost<double, kAckley> {
@@ -65,11 +65,11 @@ template <> struct Cost<double, kAckley> {
         fn = ackley_from_sums_d(s1n, s2n, n);
         return fn - f;
     }
-    __device__ void commit(float)
+    __device__ void commit(bool take, float)
     {
-        f = fn;
-        s1 = s1n;
-        s2 = s2n;
+        f = take ? fn : f;
+        s1 = take ? s1n : s1;
+        s2 = take ? s2n : s2;
     }
 };
 
@@ -88,7 +88,7 @@ template <> struct Cost<float, kSchwefel> {
         df_ = (schwefel_h(y) - schwefel_h(yn)) * inv_n;
         return df_;
     }
-    __device__ void commit(float) { f += df_; }
+    __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
 };
 
 template <> struct Cost<float, kRastrigin> {
@@ -100,7 +100,7 @@ template <> struct Cost<float, kRastrigin> {
         df_ = fmaf(dl, sg, 20.0f * hw_sin_rev(0.5f * dl) * hw_sin_rev(0.5f * sg));
         return df_;
     }
-    __device__ void commit(float) { f += df_; }
+    __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
 };
 
 template <> struct Cost<float, kAckley> {
@@ -129,14 +129,16 @@ template <> struct Cost<float, kAckley> {
         df_ = -20.0f * ea * expm1f(da) - eb * expm1f(ds2 * inv_n);
         return df_;
     }
-    __device__ void commit(float inv_n)
+    __device__ void commit(bool take, float inv_n)
     {
-        f += df_;
-        s1 = s1n_;
-        s2 = s2n_;
-        q = qn_;
-        ea = hw_exp2((-0.2f * kLog2e) * qn_);
-        eb = hw_exp2(kLog2e * (s2n_ * inv_n));
+        if (take) {
+            f += df_;
+            s1 = s1n_;
+            s2 = s2n_;
+            q = qn_;
+            ea = hw_exp2((-0.2f * kLog2e) * qn_);
+            eb = hw_exp2(kLog2e * (s2n_ * inv_n));
+        }
     }
 };
 
@@ -177,15 +179,16 @@ __device__ __forceinline__ Coord<R> coord(const LevelArgs<R> &a, const R *tab, u
     return Coord<R>{a.lo, a.hi, a.rho, a.sh};
 }
 
-// Neighbour of one coordinate (move rule fixed for the run).
-__device__ __forceinline__ float neighbour(uint32_t move, float xd, const Coord<float> &c, float u1)
+// Neighbour of one coordinate: x + rho (2U - 1) (radius rule) or l + (u - l) U
+// (resampling), clamped to [l, u].  FP32 clamps with one v_med3_f32.
+template <int MOVE> __device__ __forceinline__ float neighbour(float xd, const Coord<float> &c, float u1)
 {
-    const float xn = move == SA_MOVE_RADIUS ? fmaf(c.rho, fmaf(2.0f, u1, -1.0f), xd) : fmaf(c.rho, u1, c.lo);
-    return fmaxf(fminf(xn, c.hi), c.lo);
+    const float xn = MOVE == SA_MOVE_RADIUS ? fmaf(c.rho, fmaf(2.0f, u1, -1.0f), xd) : fmaf(c.rho, u1, c.lo);
+    return __builtin_amdgcn_fmed3f(xn, c.lo, c.hi);
 }
-__device__ __forceinline__ double neighbour(uint32_t move, double xd, const Coord<double> &c, double u1)
+template <int MOVE> __device__ __forceinline__ double neighbour(double xd, const Coord<double> &c, double u1)
 {
-    double xn = move == SA_MOVE_RADIUS ? xd + c.rho * (2.0 * u1 - 1.0) : c.lo + c.rho * u1;
+    double xn = MOVE == SA_MOVE_RADIUS ? xd + c.rho * (2.0 * u1 - 1.0) : c.lo + c.rho * u1;
     if (xn > c.hi) xn = c.hi;
     if (xn < c.lo) xn = c.lo;
     return xn;
@@ -241,7 +244,7 @@ template <> __device__ __forceinline__ double widen_inf<double>() { return __bui
 // ---------------------------------------------------------------------------
 // The level kernel.
 // ---------------------------------------------------------------------------
-template <typename R, int F, bool TABLE, bool LOG>
+template <typename R, int F, bool TABLE, bool LOG, int MOVE>
 __global__ void __launch_bounds__(256) level_kernel(const LevelArgs<R> a, const uint32_t level)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -291,14 +294,23 @@ __global__ void __launch_bounds__(256) level_kernel(const LevelArgs<R> a, const 
     const float nl2T = -kLog2e * a.inv_T[level];
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
     const bool logging = LOG && chain < a.log_chains && level >= a.log_level && level - a.log_level < a.log_levels;
+    // Software-pipelined two steps deep: at the top of step s the (old) value
+    // of step s+1's coordinate is read from LDS and step s+2's draws are
+    // computed, so neither the LDS latency nor the generator's dependent
+    // rounds sit on step s's critical path.  If step s+1 picks the coordinate
+    // step s writes, the written value is forwarded.
     uint32_t accepted = 0;
+    const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+    Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
+    Ctr r1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
+    uint32_t d = pick(r.w0, n);
+    uint32_t d1 = pick(r1.w0, n);
+    R xd = xs[__umul24(d, WG) + tid];
     for (uint32_t step = 0; step < a.steps; ++step) {
-        const Ctr r = philox4x32_10(Ctr{step, level, chain, ctr3}, a.seed_lo, a.seed_hi);
-        const uint32_t d = pick(r.w0, n);
-        R *xp = xs + d * WG + tid;
-        const R xd = *xp;
+        const R x1_lds = xs[__umul24(d1, WG) + tid];
+        const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
         const Coord<R> c = coord<R, TABLE>(a, tab, d);
-        const R xn = neighbour(a.move, xd, c, u24<R>(r.w1));
+        const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
         const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
         const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
         if (LOG && logging) {
@@ -310,11 +322,15 @@ __global__ void __launch_bounds__(256) level_kernel(const LevelArgs<R> a, const 
             m.df = (double)df;
             a.log[((size_t)(level - a.log_level) * a.log_chains + chain) * a.steps + step] = m;
         }
-        if (take) {
-            *xp = xn;
-            cost.commit(a.inv_n);
-            ++accepted;
-        }
+        const R xw = take ? xn : xd;
+        xs[__umul24(d, WG) + tid] = xw;
+        cost.commit(take, a.inv_n);
+        accepted += take ? 1u : 0u;
+        xd = d1 == d ? xw : x1_lds;
+        d = d1;
+        r = r1;
+        r1 = r2;
+        d1 = pick(r2.w0, n);
     }
     if (LOG && level >= a.log_level && level - a.log_level < a.log_levels)
         a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
@@ -471,7 +487,12 @@ template <typename R, int F, bool TABLE, bool LOG>
 static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, hipStream_t s)
 {
     const size_t lds = level_lds_bytes(a.n, a.wg, sizeof(R), TABLE);
-    hipLaunchKernelGGL((level_kernel<R, F, TABLE, LOG>), dim3(a.chains / a.wg), dim3(a.wg), lds, s, a, level);
+    if (a.move == SA_MOVE_RADIUS)
+        hipLaunchKernelGGL((level_kernel<R, F, TABLE, LOG, SA_MOVE_RADIUS>), dim3(a.chains / a.wg), dim3(a.wg), lds,
+                           s, a, level);
+    else
+        hipLaunchKernelGGL((level_kernel<R, F, TABLE, LOG, SA_MOVE_RESAMPLE>), dim3(a.chains / a.wg), dim3(a.wg),
+                           lds, s, a, level);
     return hipGetLastError();
 }
 
