@@ -44,6 +44,10 @@
  *     sa_trace and sa_move_log synchronise that stream.
  *   - Errors: a negative sa_status; sa_last_error() describes the last error
  *     of the calling thread.  No call aborts the process.
+ *   - Execution: sa_run enqueues one kernel launch per level and one that
+ *     publishes the last level; each level's launch reduces the previous
+ *     level's per-workgroup candidates to the winner on the device.  There is
+ *     no host work and no grid-wide barrier inside a launch.
  */
 #ifndef SA_H
 #define SA_H
@@ -103,7 +107,8 @@ typedef struct {
 
 /* Keep the winner state of every level (sa_trace x_best output). */
 #define SA_FLAG_TRACE_X 0x1u
-/* Replay each sa_run from a captured HIP graph instead of eager launches. */
+/* Capture the launches of each distinct sa_run (same first level and level
+ * count) into a HIP graph once and replay it. */
 #define SA_FLAG_GRAPH 0x2u
 
 /* Per-level record returned by sa_trace. */

@@ -2,9 +2,10 @@
 //
 // The host validates the problem, lays out one device workspace, builds the
 // temperature table (T_{k+1} = alpha T_k, Sec. 2.1 Step 5) and enqueues one
-// level kernel per temperature level on the caller's stream -- eagerly, or
-// from a captured HIP graph.  No host work happens between levels: the
-// argmin and the broadcast of the winner run inside the level kernel.
+// level kernel per temperature level, plus one finalising kernel per sa_run,
+// on the caller's stream -- eagerly, or from a captured HIP graph.  No host
+// work happens between levels: each level's launch reduces the previous
+// level's candidates to the winner on the device.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <new>
 #include <string>
 #include <utility>
@@ -58,8 +60,7 @@ uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, size
 }
 
 struct Layout {
-    size_t table, T, inv_T, x_best, start, slots, slot_x, arrive, x_rec, rec, rec_level, trace, trace_x, log,
-        log_final, total;
+    size_t table, T, inv_T, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final, total;
 };
 
 struct Plan {
@@ -131,10 +132,9 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.T = take(L * sizeof(double));
     l.inv_T = take(L * sizeof(float));
     l.x_best = take(n * R);
-    l.start = take(4 * sizeof(double));
-    l.slots = take((size_t)pl.groups * 16);
-    l.slot_x = take((size_t)pl.groups * n * R);
-    l.arrive = take(sizeof(uint32_t));
+    // candidates are double-buffered by level parity; at most one per tile
+    l.slots = take(2 * (size_t)pl.groups * sizeof(sa::Slot<double>));
+    l.slot_x = take(2 * (size_t)pl.groups * n * R);
     l.x_rec = take(n * R);
     l.rec = take(2 * sizeof(double));
     l.rec_level = take(sizeof(uint32_t));
@@ -176,11 +176,16 @@ struct sa_ctx {
     bool own_ws = false;
     uint32_t next_level = 0;
     uint64_t seed = 0;
+    uint32_t groups = 0;  // candidates published by the last level enqueued
     bool fp64 = false;
     sa::LevelArgs<float> a32{};
     sa::LevelArgs<double> a64{};
-    std::map<std::pair<uint32_t, uint32_t>, hipGraphExec_t> graphs;
-    std::map<std::pair<uint32_t, uint32_t>, hipGraph_t> graph_defs;
+    struct Graph {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint32_t groups = 0;  // candidates the captured run's last level publishes
+    };
+    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Graph> graphs;
 };
 
 namespace {
@@ -197,15 +202,14 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.seed_lo = (uint32_t)c->seed;
     a.seed_hi = (uint32_t)(c->seed >> 32);
     a.wg = c->pl.wg;
+    a.tiles = c->pl.groups;
     a.table = c->pl.table ? reinterpret_cast<const R *>(w + l.table) : nullptr;
     a.inv_n = (float)(1.0 / (double)c->prob.n);
     a.T = reinterpret_cast<const double *>(w + l.T);
     a.inv_T = reinterpret_cast<const float *>(w + l.inv_T);
     a.x_best = reinterpret_cast<R *>(w + l.x_best);
-    a.start = reinterpret_cast<double *>(w + l.start);
     a.slots = reinterpret_cast<sa::Slot<R> *>(w + l.slots);
     a.slot_x = reinterpret_cast<R *>(w + l.slot_x);
-    a.arrive = reinterpret_cast<uint32_t *>(w + l.arrive);
     a.x_rec = reinterpret_cast<R *>(w + l.x_rec);
     a.rec = reinterpret_cast<double *>(w + l.rec);
     a.rec_level = reinterpret_cast<uint32_t *>(w + l.rec_level);
@@ -290,24 +294,45 @@ sa_status upload_tables(sa_ctx *c)
     return SA_OK;
 }
 
-sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t s)
+// Enqueue levels [first, first + count), one launch each (the logged levels
+// use the logging variant), then the launch that publishes the last level.
+// *groups carries the candidate count of the level before `first` in and
+// that of the last level out.
+sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t s, uint32_t *groups)
 {
-    const uint32_t lg0 = c->cfg.log_level, lgn = c->cfg.log_chains ? c->cfg.log_levels : 0;
+    const uint32_t lg0 = c->cfg.log_level, lg1 = c->cfg.log_chains ? c->cfg.log_level + c->cfg.log_levels : 0;
     for (uint32_t k = first; k < first + count; ++k) {
-        const bool log = lgn && k >= lg0 && k - lg0 < lgn;
-        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, log, c->a64, k, s)
-                               : sa::launch_level_f32(c->prob.func, c->pl.table, log, c->a32, k, s);
+        const bool log = k >= lg0 && k < lg1;
+        uint32_t g = 0;
+        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
+                               : sa::launch_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
         if (e != hipSuccess) return fail(SA_ERR_DEVICE, "level %u launch: %s", k, hipGetErrorString(e));
+        *groups = g;
     }
+    const uint32_t last = first + count - 1;
+    hipError_t e = c->fp64 ? sa::launch_finalize_f64(c->a64, last, *groups, s)
+                           : sa::launch_finalize_f32(c->a32, last, *groups, s);
+    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "finalise launch: %s", hipGetErrorString(e));
     return SA_OK;
 }
 
 void drop_graphs(sa_ctx *c)
 {
-    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.second);
-    for (auto &g : c->graph_defs) (void)hipGraphDestroy(g.second);
+    for (auto &g : c->graphs) {
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+        if (g.second.g) (void)hipGraphDestroy(g.second.g);
+    }
     c->graphs.clear();
-    c->graph_defs.clear();
+}
+
+sa_status enqueue_reset(sa_ctx *c)
+{
+    hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
+                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level), c->stream);
+    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
+    c->groups = 0;
+    c->next_level = 0;
+    return SA_OK;
 }
 
 }  // namespace
@@ -397,13 +422,9 @@ sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, 
         fill_args<double>(c, c->a64);
     else
         fill_args<float>(c, c->a32);
+    c->a32.num_cus = c->a64.num_cus = (uint32_t)prop.multiProcessorCount;
     st = upload_tables(c);
-    if (st == SA_OK) {
-        hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
-                                        reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level),
-                                        reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.arrive), c->stream);
-        if (e != hipSuccess) st = fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
-    }
+    if (st == SA_OK) st = enqueue_reset(c);
     if (st != SA_OK) {
         sa_destroy(c);
         return st;
@@ -423,12 +444,13 @@ sa_status sa_run(sa_ctx *c, uint32_t levels)
         return fail(SA_ERR_STATE, "%u levels requested, %u remain", count, L - c->next_level);
     const uint32_t first = c->next_level;
     if (c->cfg.flags & SA_FLAG_GRAPH) {
-        const auto key = std::make_pair(first, count);
+        const auto key = std::make_tuple(first, count, c->groups);
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             if (!c->capture) SA_HIP(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
             SA_HIP(hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal));
-            sa_status st = enqueue_levels(c, first, count, c->capture);
+            uint32_t groups = c->groups;
+            sa_status st = enqueue_levels(c, first, count, c->capture, &groups);
             hipGraph_t g = nullptr;
             hipError_t e = hipStreamEndCapture(c->capture, &g);
             if (st != SA_OK) {
@@ -442,12 +464,16 @@ sa_status sa_run(sa_ctx *c, uint32_t levels)
                 (void)hipGraphDestroy(g);
                 return fail(SA_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
             }
-            c->graph_defs[key] = g;
-            it = c->graphs.emplace(key, ge).first;
+            sa_ctx::Graph gr;
+            gr.g = g;
+            gr.exec = ge;
+            gr.groups = groups;
+            it = c->graphs.emplace(key, gr).first;
         }
-        SA_HIP(hipGraphLaunch(it->second, c->stream));
+        SA_HIP(hipGraphLaunch(it->second.exec, c->stream));
+        c->groups = it->second.groups;
     } else {
-        sa_status st = enqueue_levels(c, first, count, c->stream);
+        sa_status st = enqueue_levels(c, first, count, c->stream, &c->groups);
         if (st != SA_OK) return st;
     }
     c->next_level = first + count;
@@ -465,12 +491,7 @@ sa_status sa_reset(sa_ctx *c, uint64_t seed)
         c->a32.seed_lo = c->a64.seed_lo = (uint32_t)seed;
         c->a32.seed_hi = c->a64.seed_hi = (uint32_t)(seed >> 32);
     }
-    hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
-                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level),
-                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.arrive), c->stream);
-    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
-    c->next_level = 0;
-    return SA_OK;
+    return enqueue_reset(c);
 }
 
 sa_status sa_levels_done(const sa_ctx *c, uint32_t *levels)

@@ -19,11 +19,15 @@ struct Full {
     double f, s1, s2;
 };
 
-// Best chain of a workgroup at the end of a level.
+// A workgroup's candidate at the end of a level: its best chain's carried
+// cost and index, the workgroup's accepted moves, and the candidate state's
+// full re-evaluation (cost and Ackley's two sums, FP64 arithmetic).
 template <typename R> struct Slot {
     R f;
     uint32_t chain;
     uint32_t accepts;
+    uint32_t pad;
+    double ff, s1, s2;
 };
 
 // Arguments of one level launch.  Device pointers point into the context's
@@ -38,11 +42,11 @@ template <typename R> struct LevelArgs {
     float inv_n;
     const double *T;     // T_k, FP64
     const float *inv_T;  // 1 / T_k rounded to FP32
-    R *x_best;           // n: start state of the level; the winner afterwards
-    double *start;       // {f, S1, S2} of x_best, FP64 arithmetic
-    Slot<R> *slots;      // one per workgroup
-    R *slot_x;           // n per workgroup
-    uint32_t *arrive;    // workgroups finished with the current level
+    uint32_t tiles;      // chains / wg
+    uint32_t num_cus;    // compute units of the device (grid sizing)
+    R *x_best;           // n: winner of the last finished level
+    Slot<R> *slots;      // 2 x tiles candidates (double-buffered by level parity)
+    R *slot_x;           // 2 x tiles x n candidate states
     R *x_rec;            // n
     double *rec;         // {f_rec}
     uint32_t *rec_level;
@@ -53,13 +57,18 @@ template <typename R> struct LevelArgs {
     uint32_t log_chains, log_level, log_levels;
 };
 
-// Host-side launchers (one level each).  Return the launch status.
+// Host-side launchers.  A level launch runs one level and publishes one
+// candidate per workgroup; *groups returns how many (the next level's launch,
+// or the finalising launch, reduces them).
 hipError_t launch_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
-                            hipStream_t s);
+                            uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 hipError_t launch_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
-                            hipStream_t s);
-// Reset the record and the arrival counter (a kernel, so it can be captured).
-hipError_t launch_reset(double *rec, uint32_t *rec_level, uint32_t *arrive, hipStream_t s);
+                            uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+// Publish level `level` (trace entry, record, broadcast state) from its candidates.
+hipError_t launch_finalize_f32(const LevelArgs<float> &a, uint32_t level, uint32_t groups, hipStream_t s);
+hipError_t launch_finalize_f64(const LevelArgs<double> &a, uint32_t level, uint32_t groups, hipStream_t s);
+// Reset the record (a kernel, so it can be captured in a graph).
+hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s);
 
 // Dynamic LDS bytes of a level launch.
 size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table);

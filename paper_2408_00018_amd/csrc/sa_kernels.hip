@@ -1,16 +1,21 @@
 // Level kernel of synchronous parallel simulated annealing for gfx950.
 //
-// One Markov chain per lane.  A workgroup of WG lanes keeps its chains'
+// One Markov chain per lane.  A workgroup of WG lanes keeps a tile of chains'
 // states in LDS as x[d][lane] (coordinate-major), so a per-lane random
 // coordinate d is a bank-conflict-free LDS access.  One launch runs one
 // temperature level (Sec. 2.2.2: every chain runs N Metropolis steps at a
-// fixed T) and ends with the device-wide argmin and broadcast that start the
-// next level: every workgroup publishes its best chain and that chain's
-// state, and the last workgroup to finish picks the global winner,
-// re-evaluates it in full, updates the record and the trace and publishes
-// the winner as the next level's start.
+// fixed T and the lowest final state starts every chain at the next level).
+// Each workgroup runs its tiles of chains, keeps its best chain, re-evaluates
+// that state in full and publishes it as a candidate with plain stores; the
+// kernel boundary makes the candidates visible, and every workgroup of the
+// next level's launch reduces them to the same winner before it starts.
+// There is no cross-workgroup synchronisation inside a launch: on gfx950 a
+// grid-wide barrier (or a last-workgroup hand-off with agent-scope fences)
+// costs several times the ~1.5 us of a graph-replayed launch.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "sa_device.hpp"
 #include "sa_internal.hpp"
@@ -242,293 +247,380 @@ template <> __device__ __forceinline__ float widen_inf<float>() { return __built
 template <> __device__ __forceinline__ double widen_inf<double>() { return __builtin_inf(); }
 
 // ---------------------------------------------------------------------------
-// The level kernel.
+// Full evaluation of a state held in LDS, FP64 arithmetic.  FP64 runs sum in
+// coordinate order on one lane (the order of a plain sequential
+// evaluation); FP32 runs use a fixed parallel order.
 // ---------------------------------------------------------------------------
-template <typename R, int F, bool TABLE, bool LOG, int MOVE>
-__global__ void __launch_bounds__(256) level_kernel(const LevelArgs<R> a, const uint32_t level)
+template <typename R, int F, bool TABLE>
+__device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, double (*part)[2])
 {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ Slot<R> wave_slot[4];
-    __shared__ uint64_t wave_acc[4];
-    __shared__ uint32_t sh_flag;
-    __shared__ double sh_part[4][2];
-
-    const uint32_t WG = a.wg;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
-    const uint32_t nwaves = WG >> 6;
-    const uint32_t chain = blockIdx.x * WG + tid;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
     const uint32_t n = a.n;
-    R *xs = reinterpret_cast<R *>(lds_raw);
-    R *tab = xs + (size_t)n * WG;
-
-    if (TABLE) {
-        for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
+    if (sizeof(R) == sizeof(double)) {
+        if (tid == 0) {
+            FullAcc<F> acc;
+            for (uint32_t i = 0; i < n; ++i) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+            const Full v = acc.finish(n);
+            part[0][0] = v.f;
+            part[0][1] = v.s1;
+            part[1][0] = v.s2;
+        }
         __syncthreads();
+        const Full v{part[0][0], part[0][1], part[1][0]};
+        __syncthreads();
+        return v;
     }
-
-    // ---- level start: own random point at level 0, else the broadcast winner
-    Cost<R, F> cost;
-    if (level == 0) {
-        FullAcc<F> acc;
-        Ctr r{};
-        for (uint32_t i = 0; i < n; ++i) {
-            if ((i & 3u) == 0)
-                r = philox4x32_10(Ctr{i >> 2, kInitLevel, chain, kTagInit | (a.problem << 8)}, a.seed_lo, a.seed_hi);
-            const uint32_t w = (i & 3u) == 0 ? r.w0 : (i & 3u) == 1 ? r.w1 : (i & 3u) == 2 ? r.w2 : r.w3;
-            const Coord<R> c = coord<R, TABLE>(a, tab, i);
-            R xi = c.lo + (c.hi - c.lo) * u24<R>(w);
-            if (xi > c.hi) xi = c.hi;
-            if (xi < c.lo) xi = c.lo;
-            xs[i * WG + tid] = xi;
-            acc.add((double)xi - (double)c.sh);
-        }
-        cost.set(acc.finish(n), n);
-    } else {
-        for (uint32_t i = 0; i < n; ++i) xs[i * WG + tid] = a.x_best[i];
-        cost.set(Full{a.start[0], a.start[1], a.start[2]}, n);
-    }
-
-    // ---- N Metropolis steps at T_level
-    const double T = a.T[level];
-    const float nl2T = -kLog2e * a.inv_T[level];
-    const uint32_t ctr3 = kTagMove | (a.problem << 8);
-    const bool logging = LOG && chain < a.log_chains && level >= a.log_level && level - a.log_level < a.log_levels;
-    // Software-pipelined two steps deep: at the top of step s the (old) value
-    // of step s+1's coordinate is read from LDS and step s+2's draws are
-    // computed, so neither the LDS latency nor the generator's dependent
-    // rounds sit on step s's critical path.  If step s+1 picks the coordinate
-    // step s writes, the written value is forwarded.
-    uint32_t accepted = 0;
-    const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
-    Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
-    Ctr r1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
-    uint32_t d = pick(r.w0, n);
-    uint32_t d1 = pick(r1.w0, n);
-    R xd = xs[__umul24(d, WG) + tid];
-    for (uint32_t step = 0; step < a.steps; ++step) {
-        const R x1_lds = xs[__umul24(d1, WG) + tid];
-        const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
-        const Coord<R> c = coord<R, TABLE>(a, tab, d);
-        const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
-        const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-        const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
-        if (LOG && logging) {
-            sa_move_rec m;
-            m.d = d;
-            m.accept = take ? 1u : 0u;
-            m.x_old = (double)xd;
-            m.x_new = (double)xn;
-            m.df = (double)df;
-            a.log[((size_t)(level - a.log_level) * a.log_chains + chain) * a.steps + step] = m;
-        }
-        const R xw = take ? xn : xd;
-        xs[__umul24(d, WG) + tid] = xw;
-        cost.commit(take, a.inv_n);
-        accepted += take ? 1u : 0u;
-        xd = d1 == d ? xw : x1_lds;
-        d = d1;
-        r = r1;
-        r1 = r2;
-        d1 = pick(r2.w0, n);
-    }
-    if (LOG && level >= a.log_level && level - a.log_level < a.log_levels)
-        a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
-
-    // ---- workgroup argmin of (final cost, chain) and accepted-move count
-    R bf = cost.f;
-    uint32_t bc = chain;
-    wave_best(bf, bc);
-    const uint32_t wacc = wave_sum(accepted);
+    FullAcc<F> acc;
+    for (uint32_t i = tid; i < n; i += blockDim.x) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+    const double pa = wave_sum_d(acc.a), pb = wave_sum_d(acc.b);
     if (lane == 0) {
-        wave_slot[wave] = Slot<R>{bf, bc, wacc};
+        part[wave][0] = pa;
+        part[wave][1] = pb;
     }
     __syncthreads();
-    if (tid == 0) {
-        Slot<R> s = wave_slot[0];
-        for (uint32_t w = 1; w < nwaves; ++w) {
-            best_of(s.f, s.chain, wave_slot[w].f, wave_slot[w].chain);
-            s.accepts += wave_slot[w].accepts;
-        }
-        a.slots[blockIdx.x] = s;
-        sh_flag = s.chain - blockIdx.x * WG;
+    FullAcc<F> tot;
+    for (uint32_t w = 0; w < nwaves; ++w) {
+        tot.a += part[w][0];
+        tot.b += part[w][1];
     }
     __syncthreads();
-    {
-        const uint32_t wl = sh_flag;
-        R *dst = a.slot_x + (size_t)blockIdx.x * n;
-        for (uint32_t i = tid; i < n; i += WG) dst[i] = xs[i * WG + wl];
-    }
-    // Publish the slot, then count this workgroup as arrived.
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (tid == 0) {
-        const uint32_t prev = __hip_atomic_fetch_add(a.arrive, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sh_flag = (prev == gridDim.x - 1) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (sh_flag == 0) return;
+    return tot.finish(n);
+}
 
-    // ---- last workgroup: global winner, broadcast, full re-evaluation, record
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+// ---------------------------------------------------------------------------
+// Reduce the candidates level `lvl` published (`groups` of them) to the
+// level's winner: lowest carried cost, ties to the lowest chain.  Every
+// workgroup that calls this gets the same winner; its state goes to xw and
+// its full re-evaluation to start.  With `publish` the workgroup also writes
+// the level's trace entry, the record and the broadcast state.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t groups, R *xw, double *start,
+                             bool publish, Slot<R> *wave_slot, uint64_t *wave_acc)
+{
+    const uint32_t WG = blockDim.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = WG >> 6;
+    const uint32_t n = a.n;
+    const size_t base = (size_t)(lvl & 1u) * a.tiles;
     R gf = widen_inf<R>();
-    uint32_t gc = 0xFFFFFFFFu;
+    uint32_t gc = 0xFFFFFFFFu, gj = 0;
     uint64_t gacc = 0;
-    for (uint32_t j = tid; j < gridDim.x; j += WG) {
-        const Slot<R> s = a.slots[j];
-        best_of(gf, gc, s.f, s.chain);
+    for (uint32_t j = tid; j < groups; j += WG) {
+        const Slot<R> s = a.slots[base + j];
+        if (s.f < gf || (s.f == gf && s.chain < gc)) {
+            gf = s.f;
+            gc = s.chain;
+            gj = j;
+        }
         gacc += s.accepts;
     }
-    wave_best(gf, gc);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const R f2 = __shfl_xor(gf, off, 64);
+        const uint32_t c2 = __shfl_xor(gc, off, 64);
+        const uint32_t j2 = __shfl_xor(gj, off, 64);
+        if (f2 < gf || (f2 == gf && c2 < gc)) {
+            gf = f2;
+            gc = c2;
+            gj = j2;
+        }
+    }
     gacc = wave_sum(gacc);
     __syncthreads();
     if (lane == 0) {
-        wave_slot[wave] = Slot<R>{gf, gc, 0u};
+        wave_slot[wave] = Slot<R>{gf, gc, gj, 0u, 0.0, 0.0, 0.0};
         wave_acc[wave] = gacc;
     }
     __syncthreads();
     gf = wave_slot[0].f;
     gc = wave_slot[0].chain;
+    gj = wave_slot[0].accepts;
     gacc = wave_acc[0];
     for (uint32_t w = 1; w < nwaves; ++w) {
-        best_of(gf, gc, wave_slot[w].f, wave_slot[w].chain);
+        if (wave_slot[w].f < gf || (wave_slot[w].f == gf && wave_slot[w].chain < gc)) {
+            gf = wave_slot[w].f;
+            gc = wave_slot[w].chain;
+            gj = wave_slot[w].accepts;
+        }
         gacc += wave_acc[w];
     }
-    if (gc >= a.chains) gc = 0;  // only if every final cost were NaN; keeps the index in range
-    const uint32_t wslot = gc / WG;
-    R *xw = xs;  // reuse LDS column 0 as the winner's state
-    __syncthreads();
-    for (uint32_t i = tid; i < n; i += WG) {
-        const R v = a.slot_x[(size_t)wslot * n + i];
-        xw[i] = v;
-        a.x_best[i] = v;
-        if (a.trace_x) a.trace_x[(size_t)level * n + i] = v;
-    }
-    __syncthreads();
-
-    Full fresh;
-    if (sizeof(R) == sizeof(double)) {
-        // FP64 runs: the sequential order of a plain evaluation.
-        if (tid == 0) {
-            FullAcc<F> acc;
-            for (uint32_t i = 0; i < n; ++i) {
-                const Coord<R> c = coord<R, TABLE>(a, tab, i);
-                acc.add((double)xw[i] - (double)c.sh);
-            }
-            fresh = acc.finish(n);
-            sh_part[0][0] = fresh.f;
-            sh_part[0][1] = fresh.s1;
-            sh_part[1][0] = fresh.s2;
-        }
-        __syncthreads();
-        fresh = Full{sh_part[0][0], sh_part[0][1], sh_part[1][0]};
-    } else {
-        // FP32 runs: FP64 arithmetic, fixed parallel order.
-        FullAcc<F> acc;
-        for (uint32_t i = tid; i < n; i += WG) {
-            const Coord<R> c = coord<R, TABLE>(a, tab, i);
-            acc.add((double)xw[i] - (double)c.sh);
-        }
-        const double pa = wave_sum_d(acc.a), pb = wave_sum_d(acc.b);
-        if (lane == 0) {
-            sh_part[wave][0] = pa;
-            sh_part[wave][1] = pb;
-        }
-        __syncthreads();
-        FullAcc<F> tot;
-        for (uint32_t w = 0; w < nwaves; ++w) {
-            tot.a += sh_part[w][0];
-            tot.b += sh_part[w][1];
-        }
-        fresh = tot.finish(n);
-    }
-
-    const bool improved = fresh.f < a.rec[0];
-    if (improved) {
-        for (uint32_t i = tid; i < n; i += WG) a.x_rec[i] = xw[i];
-    }
-    __syncthreads();
+    if (gj >= groups) gj = 0;  // only if every candidate cost were NaN; keeps the index in range
+    const size_t w = base + gj;
+    for (uint32_t i = tid; i < n; i += WG) xw[i] = a.slot_x[w * n + i];
+    const Slot<R> ws = a.slots[w];
     if (tid == 0) {
-        if (improved) {
-            a.rec[0] = fresh.f;
-            *a.rec_level = level;
-        }
-        a.start[0] = fresh.f;
-        a.start[1] = fresh.s1;
-        a.start[2] = fresh.s2;
-        sa_level t;
-        t.win_chain = gc;
-        t.reserved = 0;
-        t.f_win = (double)gf;
-        t.f_best = fresh.f;
-        t.f_rec = improved ? fresh.f : a.rec[0];
-        t.accepts = gacc;
-        t.t_ticks = wall_clock64();
-        a.trace[level] = t;
-        __hip_atomic_store(a.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        start[0] = ws.ff;
+        start[1] = ws.s1;
+        start[2] = ws.s2;
     }
+    if (publish) {
+        const bool improved = ws.ff < a.rec[0];
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += WG) {
+            const R v = a.slot_x[w * n + i];
+            a.x_best[i] = v;
+            if (a.trace_x) a.trace_x[(size_t)lvl * n + i] = v;
+            if (improved) a.x_rec[i] = v;
+        }
+        if (tid == 0) {
+            if (improved) {
+                a.rec[0] = ws.ff;
+                *a.rec_level = lvl;
+            }
+            sa_level t;
+            t.win_chain = gc;
+            t.reserved = 0;
+            t.f_win = (double)gf;
+            t.f_best = ws.ff;
+            t.f_rec = improved ? ws.ff : a.rec[0];
+            t.accepts = gacc;
+            t.t_ticks = wall_clock64();
+            a.trace[lvl] = t;
+        }
+    }
+    __syncthreads();
 }
 
-__global__ void reset_kernel(double *rec, uint32_t *rec_level, uint32_t *arrive)
+// ---------------------------------------------------------------------------
+// The level kernel.  prev_groups: candidates the previous level's launch
+// published (unused at level 0).
+// LDS: xs[n][WG] tile states | xw[n] level start | xb[n] workgroup best |
+//      tab[n][4] per-coordinate box/shift (TABLE only)
+// ---------------------------------------------------------------------------
+template <typename R, int F, bool TABLE, bool LOG, int MOVE>
+__global__ void __launch_bounds__(256)
+    level_kernel(const LevelArgs<R> a, const uint32_t level, const uint32_t prev_groups)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Slot<R> wave_slot[4];
+    __shared__ uint64_t wave_acc[4];
+    __shared__ double sh_part[4][2];
+    __shared__ double sh_start[3];
+
+    const uint32_t WG = blockDim.x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, wave = tid >> 6;
+    const uint32_t nwaves = WG >> 6;
+    const uint32_t G = gridDim.x;
+    const uint32_t n = a.n;
+    R *xs = reinterpret_cast<R *>(lds_raw);
+    R *xw = xs + (size_t)n * WG;
+    R *xb = xw + n;
+    R *tab = xb + n;
+
+    if (TABLE) {
+        for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
+    }
+    if (level > 0) adopt_winner<R>(a, level - 1, prev_groups, xw, sh_start, blockIdx.x == 0, wave_slot, wave_acc);
+    __syncthreads();
+
+    const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
+    const uint32_t ctr3 = kTagMove | (a.problem << 8);
+    const double T = a.T[level];
+    const float nl2T = -kLog2e * a.inv_T[level];
+    const bool log_level = LOG && level >= a.log_level && level - a.log_level < a.log_levels;
+    const Full start{sh_start[0], sh_start[1], sh_start[2]};
+    R wf = widen_inf<R>();
+    uint32_t wc = 0xFFFFFFFFu;
+    uint32_t accepted = 0;
+
+    for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += G) {
+        const uint32_t chain = tile * WG + tid;
+        // ---- tile start: own random point at level 0, else the winner
+        Cost<R, F> cost;
+        if (level == 0) {
+            FullAcc<F> acc;
+            Ctr r{};
+            for (uint32_t i = 0; i < n; ++i) {
+                if ((i & 3u) == 0)
+                    r = philox4x32_10(Ctr{i >> 2, kInitLevel, chain, kTagInit | (a.problem << 8)}, k0, k1);
+                const uint32_t w = (i & 3u) == 0 ? r.w0 : (i & 3u) == 1 ? r.w1 : (i & 3u) == 2 ? r.w2 : r.w3;
+                const Coord<R> c = coord<R, TABLE>(a, tab, i);
+                R xi = c.lo + (c.hi - c.lo) * u24<R>(w);
+                if (xi > c.hi) xi = c.hi;
+                if (xi < c.lo) xi = c.lo;
+                xs[i * WG + tid] = xi;
+                acc.add((double)xi - (double)c.sh);
+            }
+            cost.set(acc.finish(n), n);
+        } else {
+            for (uint32_t i = 0; i < n; ++i) xs[i * WG + tid] = xw[i];
+            cost.set(start, n);
+        }
+
+        // ---- N Metropolis steps, software-pipelined two moves deep: at the
+        // top of move s the (old) value of move s+1's coordinate is read from
+        // LDS and move s+2's draws are computed, so neither the LDS latency
+        // nor the generator's dependent rounds sit on move s's critical path.
+        // If move s+1 picks the coordinate move s writes, the written value is
+        // forwarded.
+        const bool logging = log_level && chain < a.log_chains;
+        Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
+        Ctr r1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
+        uint32_t d = pick(r.w0, n);
+        uint32_t d1 = pick(r1.w0, n);
+        R xd = xs[__umul24(d, WG) + tid];
+        for (uint32_t step = 0; step < a.steps; ++step) {
+            const R x1_lds = xs[__umul24(d1, WG) + tid];
+            const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
+            const Coord<R> c = coord<R, TABLE>(a, tab, d);
+            const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
+            const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
+            const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
+            if (LOG && logging) {
+                sa_move_rec m;
+                m.d = d;
+                m.accept = take ? 1u : 0u;
+                m.x_old = (double)xd;
+                m.x_new = (double)xn;
+                m.df = (double)df;
+                a.log[((size_t)(level - a.log_level) * a.log_chains + chain) * a.steps + step] = m;
+            }
+            const R xwr = take ? xn : xd;
+            xs[__umul24(d, WG) + tid] = xwr;
+            cost.commit(take, a.inv_n);
+            accepted += take ? 1u : 0u;
+            xd = d1 == d ? xwr : x1_lds;
+            d = d1;
+            r = r1;
+            r1 = r2;
+            d1 = pick(r2.w0, n);
+        }
+        if (LOG && log_level) a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
+
+        // ---- tile argmin of (final cost, chain); keep the workgroup's best
+        R bf = cost.f;
+        uint32_t bc = chain;
+        wave_best(bf, bc);
+        if (lane == 0) wave_slot[wave] = Slot<R>{bf, bc, 0u, 0u, 0.0, 0.0, 0.0};
+        __syncthreads();
+        R tf = wave_slot[0].f;
+        uint32_t tc = wave_slot[0].chain;
+        for (uint32_t w = 1; w < nwaves; ++w) best_of(tf, tc, wave_slot[w].f, wave_slot[w].chain);
+        R nf = wf;
+        uint32_t nc = wc;
+        best_of(nf, nc, tf, tc);
+        if (nc != wc) {
+            const uint32_t col = tc - tile * WG;
+            for (uint32_t i = tid; i < n; i += WG) xb[i] = xs[i * WG + col];
+            wf = nf;
+            wc = nc;
+        }
+        __syncthreads();
+    }
+
+    // ---- publish this workgroup's candidate, re-evaluated in full
+    const Full fr = full_eval_wg<R, F, TABLE>(a, tab, xb, sh_part);
+    const uint32_t wacc = wave_sum(accepted);
+    if (lane == 0) wave_acc[wave] = wacc;
+    __syncthreads();
+    const size_t slot = (size_t)(level & 1u) * a.tiles + blockIdx.x;
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t w = 0; w < nwaves; ++w) acc += (uint32_t)wave_acc[w];
+        a.slots[slot] = Slot<R>{wf, wc, acc, 0u, fr.f, fr.s1, fr.s2};
+    }
+    for (uint32_t i = tid; i < n; i += WG) a.slot_x[slot * n + i] = xb[i];
+}
+
+// Close a run of levels: reduce the last level's candidates and publish its
+// trace entry, record and broadcast state.
+template <typename R>
+__global__ void __launch_bounds__(256) finalize_kernel(const LevelArgs<R> a, const uint32_t level,
+                                                        const uint32_t groups)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Slot<R> wave_slot[4];
+    __shared__ uint64_t wave_acc[4];
+    __shared__ double sh_start[3];
+    adopt_winner<R>(a, level, groups, reinterpret_cast<R *>(lds_raw), sh_start, true, wave_slot, wave_acc);
+}
+
+__global__ void reset_kernel(double *rec, uint32_t *rec_level)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         rec[0] = __builtin_inf();
         *rec_level = 0xFFFFFFFFu;
-        *arrive = 0u;
     }
 }
 
 size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table)
 {
-    return ((size_t)n * wg + (table ? 4 * (size_t)n : 0)) * real_size;
+    return ((size_t)n * wg + 2 * (size_t)n + (table ? 4 * (size_t)n : 0)) * real_size;
 }
 
-template <typename R, int F, bool TABLE, bool LOG>
-static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, hipStream_t s)
+template <typename R, int F, bool TABLE, bool LOG, int MOVE>
+static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, uint32_t prev_groups, uint32_t *groups,
+                             hipStream_t s)
 {
+    auto kern = level_kernel<R, F, TABLE, LOG, MOVE>;
     const size_t lds = level_lds_bytes(a.n, a.wg, sizeof(R), TABLE);
-    if (a.move == SA_MOVE_RADIUS)
-        hipLaunchKernelGGL((level_kernel<R, F, TABLE, LOG, SA_MOVE_RADIUS>), dim3(a.chains / a.wg), dim3(a.wg), lds,
-                           s, a, level);
-    else
-        hipLaunchKernelGGL((level_kernel<R, F, TABLE, LOG, SA_MOVE_RESAMPLE>), dim3(a.chains / a.wg), dim3(a.wg),
-                           lds, s, a, level);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)a.wg, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const uint32_t grid = (uint32_t)std::min<uint64_t>((uint64_t)per_cu * a.num_cus, a.tiles);
+    *groups = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(a.wg), lds, s, a, level, prev_groups);
     return hipGetLastError();
 }
 
 template <typename R, int F>
-static hipError_t dispatch_tl(bool table, bool log, const LevelArgs<R> &a, uint32_t level, hipStream_t s)
+static hipError_t dispatch_f(bool table, bool log, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
+                             uint32_t *groups, hipStream_t s)
 {
-    if (table) return log ? launch_one<R, F, true, true>(a, level, s) : launch_one<R, F, true, false>(a, level, s);
-    return log ? launch_one<R, F, false, true>(a, level, s) : launch_one<R, F, false, false>(a, level, s);
+    if (a.move == SA_MOVE_RADIUS) {
+        if (table)
+            return log ? launch_one<R, F, true, true, SA_MOVE_RADIUS>(a, level, prev, groups, s)
+                       : launch_one<R, F, true, false, SA_MOVE_RADIUS>(a, level, prev, groups, s);
+        return log ? launch_one<R, F, false, true, SA_MOVE_RADIUS>(a, level, prev, groups, s)
+                   : launch_one<R, F, false, false, SA_MOVE_RADIUS>(a, level, prev, groups, s);
+    }
+    if (table)
+        return log ? launch_one<R, F, true, true, SA_MOVE_RESAMPLE>(a, level, prev, groups, s)
+                   : launch_one<R, F, true, false, SA_MOVE_RESAMPLE>(a, level, prev, groups, s);
+    return log ? launch_one<R, F, false, true, SA_MOVE_RESAMPLE>(a, level, prev, groups, s)
+               : launch_one<R, F, false, false, SA_MOVE_RESAMPLE>(a, level, prev, groups, s);
 }
 
 template <typename R>
-static hipError_t dispatch(int func, bool table, bool log, const LevelArgs<R> &a, uint32_t level, hipStream_t s)
+static hipError_t dispatch(int func, bool table, bool log, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
+                           uint32_t *groups, hipStream_t s)
 {
     switch (func) {
-    case kSchwefel: return dispatch_tl<R, kSchwefel>(table, log, a, level, s);
-    case kRastrigin: return dispatch_tl<R, kRastrigin>(table, log, a, level, s);
-    case kAckley: return dispatch_tl<R, kAckley>(table, log, a, level, s);
+    case kSchwefel: return dispatch_f<R, kSchwefel>(table, log, a, level, prev, groups, s);
+    case kRastrigin: return dispatch_f<R, kRastrigin>(table, log, a, level, prev, groups, s);
+    case kAckley: return dispatch_f<R, kAckley>(table, log, a, level, prev, groups, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
-                            hipStream_t s)
+                            uint32_t prev_groups, uint32_t *groups, hipStream_t s)
 {
-    return dispatch<float>(func, table, log, a, level, s);
+    return dispatch<float>(func, table, log, a, level, prev_groups, groups, s);
 }
 
 hipError_t launch_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
-                            hipStream_t s)
+                            uint32_t prev_groups, uint32_t *groups, hipStream_t s)
 {
-    return dispatch<double>(func, table, log, a, level, s);
+    return dispatch<double>(func, table, log, a, level, prev_groups, groups, s);
 }
 
-hipError_t launch_reset(double *rec, uint32_t *rec_level, uint32_t *arrive, hipStream_t s)
+hipError_t launch_finalize_f32(const LevelArgs<float> &a, uint32_t level, uint32_t groups, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, rec, rec_level, arrive);
+    hipLaunchKernelGGL(finalize_kernel<float>, dim3(1), dim3(256), a.n * sizeof(float), s, a, level, groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_f64(const LevelArgs<double> &a, uint32_t level, uint32_t groups, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel<double>, dim3(1), dim3(256), a.n * sizeof(double), s, a, level, groups);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s)
+{
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, rec, rec_level);
     return hipGetLastError();
 }
 
