@@ -23,24 +23,53 @@ import numpy as np  # noqa: E402
 
 import workloads as W  # noqa: E402
 
-# Algorithmic VALU work of one FP32 Schwefel move, in full-rate lane-op slots
-# (a quarter-rate instruction costs 4 slots).  The derivation is in the design
-# notes; the per-step part of the counter-based generator is 8 of its 10
-# rounds, because the counter words other than the step are fixed per chain
-# and level.
+# ALU roofline.  Unit: one "slot" = one lane-operation at the FP32 FMA issue
+# rate.  Peak: MI355X FP32 vector 157.3 TFLOP/s = 78.6e12 lane-FMA/s
+# (256 CUs x 4 SIMDs x 32 FP32 lane-ops per clock x 2.4 GHz).  An instruction
+# class that issues r times slower than FMA costs r slots; r comes from the
+# issue-rate probe (libsa_peak.so) at 8 waves per SIMD on MI355X:
+#   v_mad_u64_u32 2.17, v_mul_hi_u32 1.7, v_sin/v_cos/v_sqrt/v_exp_f32 3.15,
+#   FP32 add/mul/fma/med3/cvt, integer shift/xor/bitop3/compare/select 1.
+# Algorithmic work of one FP32 normalized-Schwefel move with the radius rule:
+SLOT_WEIGHT = {"mad_u64": 2.17, "mul_hi": 1.7, "trans": 3.15, "valu": 1.0}
 SLOTS_PER_MOVE = {
-    "philox_rounds_3_10": 8 * (2 * 4 + 2),  # two 32x32->64 multiplies (quarter rate) + two XOR3 per round
-    "philox_rounds_1_2": 2,                 # step-dependent XORs of the first two rounds
-    "coordinate_pick": 4,                   # high word of r0 * n (quarter rate)
-    "uniforms": 6,                          # two (shift, convert, scale)
-    "neighbour": 4,                         # 2u-1, fma, min, max
-    "increment": 2 * (4 + 1 + 4 + 1) + 2,   # per term: sqrt, scale, sin, product; difference and 1/n
-    "metropolis": 1 + 4 + 3,                # scale, exp2, compares/or
-    "commit_and_address": 3,                # cost update, accept count, LDS address
+    # counter-based generator: of Philox4x32-10's ten rounds, rounds 3-10 depend
+    # on the step counter in every word (two 32x32->64 multiplies and two
+    # three-input XORs each); rounds 1-2 leave two step-dependent XORs, the rest
+    # is fixed per chain and level
+    "philox": 16 * SLOT_WEIGHT["mad_u64"] + 16 * 1 + 2 * 1,
+    "coordinate_pick": SLOT_WEIGHT["mul_hi"],                 # high word of r0 * n
+    "uniforms": 2 * 3,                                        # (r >> 8), convert, scale; twice
+    "neighbour": 3,                                           # 2u - 1, fma, clamp (med3)
+    "increment": 2 * (2 * SLOT_WEIGHT["trans"] + 2) + 2,      # per term sqrt, sin, two muls; difference, 1/n
+    "metropolis": 1 + SLOT_WEIGHT["trans"] + 1,               # scale, exp2, compare
+    "commit": 3,                                              # state select, cost select-add, accept count
+    "lds_address": 1,
 }
 SLOTS = sum(SLOTS_PER_MOVE.values())
-# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz full-rate VALU lane-ops/s.
-PEAK_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+PEAK_SLOTS_PER_S = 157.3e12 / 2.0
+
+# HBM traffic of one level launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch), each scaled by the counter's reading for a plain 1 GiB
+# device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
+# profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
+# sources it was measured on (hash below); otherwise reported as null.
+TRAFFIC_MEASURED = {"sources_sha256_16": "1fcb9b05e6b46ecd", "fetch_kib": 143.5145, "fetch_scale": 2.0,
+                    "write_kib": 120.58125, "write_scale": 1.0}
+KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
+                  "paper_2408_00018_amd/csrc/sa_internal.hpp"]
+
+
+def measured_traffic_bytes():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    t = TRAFFIC_MEASURED
+    if h.hexdigest()[:16] != t["sources_sha256_16"]:
+        return None
+    return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
 
 
 def parse():
@@ -83,7 +112,17 @@ def probe_rates():
             raise RuntimeError(f"probe {name} failed: {rc}")
         ops = blocks * 256 * iters * 16
         out[name] = ops / (ms.value * 1e-3)
-    return {k: float(f"{v:.4g}") for k, v in out.items()}
+    rates = {k: float(f"{v:.4g}") for k, v in out.items()}
+    lib.sa_peak_probe_occupancy.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    occ = {}
+    for k, name in ((0, "fma_f32"), (1, "mad_u64_u32"), (4, "sin_f32")):
+        for w in (1, 2, 4, 8):
+            ms = ctypes.c_float()
+            rc = lib.sa_peak_probe_occupancy(k, w, 4096, ctypes.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"occupancy probe {name}/{w} failed: {rc}")
+            occ[f"{name}@{w}w"] = float(f"{256 * 4 * w * 64 * 4096 * 16 / (ms.value * 1e-3):.4g}")
+    return {"rates_many_waves": rates, "by_waves_per_simd": occ}
 
 
 def main():
@@ -138,8 +177,8 @@ def main():
     per_launch = SLOTS * wl.chains * wl.steps
     achieved = per_launch / avg_launch_s
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_SLOTS_PER_S / 1e12, 3),
-                "unit": "Tslot/s", "frac": round(achieved / PEAK_SLOTS_PER_S, 4), "traffic": None,
-                "kernel": "level_kernel<float,Schwefel>", "slots_per_move": SLOTS,
+                "unit": "Tslot/s", "frac": round(achieved / PEAK_SLOTS_PER_S, 4), "traffic": measured_traffic_bytes(),
+                "kernel": "level_kernel<float,Schwefel,uniform box,radius>", "slots_per_move": round(SLOTS, 2),
                 "avg_launch_us": round(avg_launch_s * 1e6, 3)}
     out = {
         "metric": "SA moves/s (Schwefel n=100)",

@@ -26,6 +26,8 @@ enum Kind : int {
 
 __global__ void __launch_bounds__(256) probe_kernel(int kind, int iters, uint32_t *sink)
 {
+    extern __shared__ float lds_pad[];  // sized by the host to cap workgroups per CU
+    if (threadIdx.x == 0 && iters < 0) lds_pad[0] = 0.0f;
     const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t u[kChains];
     float f[kChains];
@@ -108,6 +110,35 @@ int sa_peak_probe(int kind, int blocks, int iters, float *ms)
     hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(256), 0, 0, kind, 1, sink);  // warm-up
     (void)hipEventRecord(a, 0);
     hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(256), 0, 0, kind, iters, sink);
+    (void)hipEventRecord(b, 0);
+    hipError_t e = hipEventSynchronize(b);
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(sink);
+    *ms = t;
+    return e == hipSuccess ? 0 : -3;
+}
+
+// The same operation with one 64-lane workgroup per wave and enough dynamic
+// LDS per workgroup that at most `waves_per_simd` waves share each SIMD of a
+// 256-CU device (160 KiB LDS per CU): shows how many waves a SIMD needs to
+// reach the instruction's issue rate.  Operation count:
+// 256 * 4 * waves_per_simd * 64 * iters * 16.
+int sa_peak_probe_occupancy(int kind, int waves_per_simd, int iters, float *ms)
+{
+    if (kind < 0 || kind >= kNumKinds || waves_per_simd < 1 || waves_per_simd > 8 || iters <= 0 || !ms) return -1;
+    const int blocks = 256 * 4 * waves_per_simd;
+    const size_t lds = (size_t)(160 * 1024) / (4 * (size_t)waves_per_simd) - 1024;
+    uint32_t *sink = nullptr;
+    if (hipMalloc(&sink, (size_t)blocks * 64 * sizeof(uint32_t)) != hipSuccess) return -2;
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(64), lds, 0, kind, 1, sink);
+    (void)hipEventRecord(a, 0);
+    hipLaunchKernelGGL(probe_kernel, dim3(blocks), dim3(64), lds, 0, kind, iters, sink);
     (void)hipEventRecord(b, 0);
     hipError_t e = hipEventSynchronize(b);
     float t = 0.0f;
