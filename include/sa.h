@@ -176,6 +176,80 @@ sa_status sa_move_log(sa_ctx *ctx, sa_move_rec *moves, double *final_f);
 /* Release the context and any memory the library allocated. */
 void sa_destroy(sa_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Batched runs: nprob independent problems (each with its own function,
+ * dimension, box, shift and chain count) advance together, one launch per
+ * level.  Problem p draws its randoms with `problem` = p in the counters
+ * above, so problem p of a batch follows the same trajectory as a
+ * single-problem run of it with problem id p.  Chains of problem p are
+ * numbered 0 .. chains[p]-1.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t seed;
+    uint32_t levels, steps;
+    uint32_t precision; /* sa_precision */
+    uint32_t move;      /* sa_move */
+    uint32_t flags;     /* SA_FLAG_GRAPH, SA_FLAG_TRACE_X */
+    uint32_t waves_per_group; /* 64-chain tiles per workgroup: 1, 2 or 4 (0 = 4) */
+    double T0, alpha, radius_frac;
+    /* Move log of one problem (verification), as in sa_config. */
+    uint32_t log_problem, log_chains, log_level, log_levels;
+} sa_batch_config;
+
+typedef struct sa_batch sa_batch;
+
+/* Workspace bytes for these problems with chains[p] chains each
+ * (multiples of 64, >= 64). */
+sa_status sa_batch_workspace_bytes(const sa_problem *probs, uint32_t nprob, const uint32_t *chains,
+                                   const sa_batch_config *cfg, size_t *bytes);
+
+/* Create a batch (same stream/workspace conventions as sa_create).  probs:
+ * nprob host problems; chains: nprob chain counts (see sa_batch_autotune). */
+sa_status sa_batch_create(const sa_problem *probs, uint32_t nprob, const uint32_t *chains,
+                          const sa_batch_config *cfg, void *stream, void *workspace, size_t ws_bytes,
+                          sa_batch **out);
+
+/* Enqueue the next `levels` levels of every problem (0 = all remaining). */
+sa_status sa_batch_run(sa_batch *b, uint32_t levels);
+
+/* Restart every problem at level 0 with a new seed (enqueued). */
+sa_status sa_batch_reset(sa_batch *b, uint64_t seed);
+
+/* Record of problem p (synchronises), as sa_best. */
+sa_status sa_batch_best(sa_batch *b, uint32_t prob, double *x_out, double *f_out, uint32_t *level_found);
+
+/* Per-level records of problem p, levels [first, first + count) (synchronises).
+ * x_best: count * n_p doubles or NULL; needs SA_FLAG_TRACE_X. */
+sa_status sa_batch_trace(sa_batch *b, uint32_t prob, uint32_t first, uint32_t count, sa_level *out,
+                         double *x_best);
+
+/* Logged moves of cfg->log_problem (synchronises), layout as sa_move_log with
+ * chains = chains[log_problem]. */
+sa_status sa_batch_move_log(sa_batch *b, sa_move_rec *moves, double *final_f);
+
+/* Layout the batch runs with: 64-chain tiles, workgroups per launch, tiles
+ * per workgroup, dynamic LDS bytes per workgroup.  Any output may be NULL. */
+sa_status sa_batch_layout(const sa_batch *b, uint32_t *tiles, uint32_t *groups, uint32_t *waves_per_group,
+                          uint32_t *lds_bytes);
+
+void sa_batch_destroy(sa_batch *b);
+
+/*
+ * Autotuner: pick chains per problem and tiles per workgroup by measurement
+ * on the current device.  Candidates: uniform chain counts 64..1024 and
+ * counts proportional to each problem's dimension (64..1024, multiples of
+ * 64), each with 1, 2 and 4 tiles per workgroup.  Each candidate runs
+ * `trial_levels` levels of cfg's schedule twice (the second timed with HIP
+ * events).  The choice is the candidate with the fewest total chains whose
+ * moves/s is within 5% of the best measured.  Writes nprob chain counts to
+ * chains_out, the tiles per workgroup to *waves_per_group_out and the chosen
+ * candidate's moves/s to *moves_per_s_out (any may be NULL except
+ * chains_out).  Allocates and frees its own device memory.
+ */
+sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_batch_config *cfg, void *stream,
+                            uint32_t trial_levels, uint32_t *chains_out, uint32_t *waves_per_group_out,
+                            double *moves_per_s_out);
+
 /* Description of the calling thread's last error ("" if none). */
 const char *sa_last_error(void);
 

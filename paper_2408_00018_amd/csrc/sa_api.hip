@@ -19,34 +19,19 @@
 #include <utility>
 #include <vector>
 
+#include "sa_host.hpp"
 #include "sa_internal.hpp"
+
+namespace sa {
+thread_local std::string g_last_error;
+}  // namespace sa
 
 namespace {
 
-thread_local std::string g_last_error;
-
-sa_status fail(sa_status st, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_last_error = buf;
-    return st;
-}
-
-#define SA_HIP(call)                                                                              \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
-        if (e_ != hipSuccess) return fail(SA_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-// LDS available to one workgroup on gfx950.
-constexpr size_t kLdsPerWorkgroup = 160 * 1024;
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+using sa::align_up;
+using sa::fail;
+using sa::kAlign;
+using sa::kLdsPerWorkgroup;
 
 // Largest workgroup (4, 2 or 1 waves) that divides `chains` and whose state
 // fits in LDS.  0 if none fits.
@@ -70,29 +55,15 @@ struct Plan {
     Layout lay{};
 };
 
-bool is_finite(double v) { return std::isfinite(v); }
-
 sa_status validate(const sa_problem *p, const sa_config *c)
 {
     if (!p || !c) return fail(SA_ERR_INVALID, "null problem or config");
-    if (p->func > SA_ACKLEY) return fail(SA_ERR_INVALID, "unknown function id %u", p->func);
-    if (p->n == 0) return fail(SA_ERR_INVALID, "dimension n must be >= 1");
-    if (!p->lower || !p->upper) return fail(SA_ERR_INVALID, "lower/upper must not be NULL");
-    for (uint32_t i = 0; i < p->n; ++i) {
-        if (!is_finite(p->lower[i]) || !is_finite(p->upper[i]))
-            return fail(SA_ERR_INVALID, "box bound %u is not finite", i);
-        if (!(p->lower[i] < p->upper[i])) return fail(SA_ERR_INVALID, "box %u has lower >= upper", i);
-        if (p->shift && !is_finite(p->shift[i])) return fail(SA_ERR_INVALID, "shift %u is not finite", i);
-    }
+    if (sa_status st = sa::validate_problem(p, 0); st != SA_OK) return st;
     if (c->chains == 0 || c->chains % 64) return fail(SA_ERR_INVALID, "chains must be a positive multiple of 64");
-    if (c->levels == 0) return fail(SA_ERR_INVALID, "levels must be >= 1");
-    if (c->steps == 0) return fail(SA_ERR_INVALID, "steps must be >= 1");
-    if (c->precision > SA_FP64) return fail(SA_ERR_INVALID, "unknown precision %u", c->precision);
-    if (c->move > SA_MOVE_RESAMPLE) return fail(SA_ERR_INVALID, "unknown move rule %u", c->move);
-    if (!(c->T0 > 0.0) || !is_finite(c->T0)) return fail(SA_ERR_INVALID, "T0 must be finite and > 0");
-    if (!(c->alpha > 0.0 && c->alpha <= 1.0)) return fail(SA_ERR_INVALID, "alpha must be in (0, 1]");
-    if (!(c->radius_frac > 0.0) || !is_finite(c->radius_frac))
-        return fail(SA_ERR_INVALID, "radius_frac must be finite and > 0");
+    if (sa_status st = sa::validate_schedule(c->levels, c->steps, c->precision, c->move, c->T0, c->alpha,
+                                             c->radius_frac);
+        st != SA_OK)
+        return st;
     if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH)) return fail(SA_ERR_INVALID, "unknown flag bits");
     if (c->log_chains) {
         if (c->log_chains > c->chains) return fail(SA_ERR_INVALID, "log_chains exceeds chains");
@@ -146,20 +117,6 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.total = off;
     *out = pl;
     return SA_OK;
-}
-
-// Round a box inward to FP32 so every FP32 state lies in the FP64 box.
-float round_up_f(double v)
-{
-    float f = (float)v;
-    if ((double)f < v) f = std::nextafter(f, INFINITY);
-    return f;
-}
-float round_down_f(double v)
-{
-    float f = (float)v;
-    if ((double)f > v) f = std::nextafter(f, -INFINITY);
-    return f;
 }
 
 }  // namespace
@@ -225,21 +182,8 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
 // Box/shift values of coordinate i in the run's precision: (l, u, rho, s).
 void coord_values(const sa_ctx *c, uint32_t i, double out[4])
 {
-    const double lo = c->lower[i], hi = c->upper[i];
-    const double sh = c->shift.empty() ? 0.0 : c->shift[i];
-    if (c->fp64) {
-        out[0] = lo;
-        out[1] = hi;
-        out[2] = c->cfg.move == SA_MOVE_RADIUS ? c->cfg.radius_frac * (hi - lo) : hi - lo;
-        out[3] = sh;
-    } else {
-        const float l32 = round_up_f(lo), u32 = round_down_f(hi);
-        const double w = (double)u32 - (double)l32;
-        out[0] = l32;
-        out[1] = u32;
-        out[2] = (float)(c->cfg.move == SA_MOVE_RADIUS ? c->cfg.radius_frac * w : w);
-        out[3] = (float)sh;
-    }
+    sa::coord_values(c->lower[i], c->upper[i], c->shift.empty() ? 0.0 : c->shift[i], c->fp64, c->cfg.move,
+                     c->cfg.radius_frac, out);
 }
 
 sa_status upload_tables(sa_ctx *c)
@@ -339,11 +283,11 @@ sa_status enqueue_reset(sa_ctx *c)
 
 extern "C" {
 
-const char *sa_last_error(void) { return g_last_error.c_str(); }
+const char *sa_last_error(void) { return sa::g_last_error.c_str(); }
 
 sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_t *bytes)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!bytes) return fail(SA_ERR_INVALID, "bytes must not be NULL");
     sa_status st = validate(prob, cfg);
     if (st != SA_OK) return st;
@@ -357,7 +301,7 @@ sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_
 sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, void *workspace, size_t ws_bytes,
                     sa_ctx **out)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!out) return fail(SA_ERR_INVALID, "out must not be NULL");
     *out = nullptr;
     sa_status st = validate(prob, cfg);
@@ -388,7 +332,7 @@ sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, 
     c->prob.shift = prob->shift ? c->shift.data() : nullptr;
     if (!c->fp64) {
         for (uint32_t i = 0; i < prob->n; ++i) {
-            if (!(round_up_f(prob->lower[i]) < round_down_f(prob->upper[i]))) {
+            if (!(sa::round_up_f(prob->lower[i]) < sa::round_down_f(prob->upper[i]))) {
                 delete c;
                 return fail(SA_ERR_INVALID, "box %u is empty after rounding inward to FP32", i);
             }
@@ -435,7 +379,7 @@ sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, 
 
 sa_status sa_run(sa_ctx *c, uint32_t levels)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
     const uint32_t L = c->cfg.levels;
     if (c->next_level >= L) return fail(SA_ERR_STATE, "all %u levels have run", L);
@@ -482,7 +426,7 @@ sa_status sa_run(sa_ctx *c, uint32_t levels)
 
 sa_status sa_reset(sa_ctx *c, uint64_t seed)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
     if (seed != c->seed) {
         // Captured graphs hold the seed in their kernel arguments.
@@ -503,7 +447,7 @@ sa_status sa_levels_done(const sa_ctx *c, uint32_t *levels)
 
 sa_status sa_best(sa_ctx *c, double *x_out, double *f_out, uint32_t *level_found)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
     if (c->next_level == 0) return fail(SA_ERR_STATE, "no level has run");
     SA_HIP(hipStreamSynchronize(c->stream));
@@ -530,7 +474,7 @@ sa_status sa_best(sa_ctx *c, double *x_out, double *f_out, uint32_t *level_found
 
 sa_status sa_trace(sa_ctx *c, uint32_t first, uint32_t count, sa_level *out, double *x_best)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
     if (count == 0) return SA_OK;
     if (first >= c->next_level || count > c->next_level - first)
@@ -560,7 +504,7 @@ sa_status sa_trace(sa_ctx *c, uint32_t first, uint32_t count, sa_level *out, dou
 
 sa_status sa_move_log(sa_ctx *c, sa_move_rec *moves, double *final_f)
 {
-    g_last_error.clear();
+    sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
     if (!c->cfg.log_chains) return fail(SA_ERR_STATE, "the context was created without a move log");
     SA_HIP(hipStreamSynchronize(c->stream));

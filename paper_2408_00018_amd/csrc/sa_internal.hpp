@@ -74,3 +74,55 @@ hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s);
 size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table);
 
 }  // namespace sa
+
+namespace sa {
+
+// ---------------------------------------------------------------------------
+// Batched runs: many independent problems, one wave (64 chains) per tile.
+// ---------------------------------------------------------------------------
+struct BatchProblem {
+    uint32_t func, n, chains, first_tile;  // tiles [first_tile, first_tile + chains / 64)
+    uint32_t tab_off;                      // first entry of this problem's {l,u,rho,s} table (entries)
+    uint32_t x_off;                        // first element of this problem's n-vectors
+    float inv_n;
+    uint32_t pad;
+};
+
+template <typename R> struct BatchArgs {
+    uint32_t nprob, ntiles, steps, move;
+    uint32_t seed_lo, seed_hi, waves_per_group, levels;
+    const BatchProblem *probs;  // nprob
+    const uint32_t *tile_prob;  // ntiles: owning problem
+    const uint32_t *tile_xoff;  // ntiles: first element of the tile's candidate state
+    const uint32_t *wg_tile;    // groups x waves_per_group: tile of each wave (~0 = idle)
+    const uint32_t *wg_lds;     // groups x waves_per_group: byte offset of each wave's LDS region
+    const R *table;             // sum_p 4 n_p entries {l, u, rho, s}
+    const double *T;            // levels
+    const float *inv_T;         // levels
+    Slot<R> *slots;             // 2 x ntiles
+    R *slot_x;                  // 2 x sum over tiles of n
+    uint32_t slot_x_stride;     // sum over tiles of n (elements per parity)
+    R *x_best;                  // sum_p n_p
+    R *x_rec;                   // sum_p n_p
+    double *rec;                // nprob
+    uint32_t *rec_level;        // nprob
+    sa_level *trace;            // nprob x levels
+    R *trace_x;                 // levels x n_p per problem (at levels * x_off), or nullptr
+    sa_move_rec *log;           // move log of one problem, or nullptr
+    double *log_final;          // per-chain final cost of that problem at logged levels
+    uint32_t log_problem, log_chains, log_level, log_levels;
+};
+
+// Bytes of LDS one wave of a batched launch needs for dimension n.
+size_t batch_wave_lds_bytes(uint32_t n, size_t real_size);
+
+hipError_t launch_batch_level_f32(const BatchArgs<float> &a, uint32_t groups, size_t lds, bool log, uint32_t level,
+                                  hipStream_t s);
+hipError_t launch_batch_level_f64(const BatchArgs<double> &a, uint32_t groups, size_t lds, bool log, uint32_t level,
+                                  hipStream_t s);
+// max_n: the largest problem dimension (sizes the finalising launch's LDS).
+hipError_t launch_batch_finalize_f32(const BatchArgs<float> &a, uint32_t level, uint32_t max_n, hipStream_t s);
+hipError_t launch_batch_finalize_f64(const BatchArgs<double> &a, uint32_t level, uint32_t max_n, hipStream_t s);
+hipError_t launch_batch_reset(double *rec, uint32_t *rec_level, uint32_t nprob, hipStream_t s);
+
+}  // namespace sa

@@ -19,163 +19,9 @@
 
 #include "sa_device.hpp"
 #include "sa_internal.hpp"
+#include "sa_step.hpp"
 
 namespace sa {
-
-// ---------------------------------------------------------------------------
-// Per-chain cost state.  delta() returns the increment of changing one
-// coordinate from y to yn (shifted coordinates) and stages the new state;
-// commit() installs it when the move is accepted.
-// ---------------------------------------------------------------------------
-template <typename R, int F> struct Cost;
-
-// FP64: the increments are the definitions, evaluated in the same order as a
-// plain FP64 implementation would (the FP64 path is checked move for move).
-template <> struct Cost<double, kSchwefel> {
-    double f, fn;
-    __device__ void set(const Full &v, uint32_t) { f = v.f; }
-    __device__ double delta(double y, double yn, uint32_t n, float)
-    {
-        const double df = -(schwefel_term_d(yn) - schwefel_term_d(y)) / (double)n;
-        fn = f + df;
-        return df;
-    }
-    __device__ void commit(bool take, float) { f = take ? fn : f; }
-};
-
-template <> struct Cost<double, kRastrigin> {
-    double f, fn;
-    __device__ void set(const Full &v, uint32_t) { f = v.f; }
-    __device__ double delta(double y, double yn, uint32_t, float)
-    {
-        const double df = rastrigin_term_d(yn) - rastrigin_term_d(y);
-        fn = f + df;
-        return df;
-    }
-    __device__ void commit(bool take, float) { f = take ? fn : f; }
-};
-
-template <> struct Cost<double, kAckley> {
-    double f, s1, s2, fn, s1n, s2n;
-    __device__ void set(const Full &v, uint32_t)
-    {
-        f = v.f;
-        s1 = v.s1;
-        s2 = v.s2;
-    }
-    __device__ double delta(double y, double yn, uint32_t n, float)
-    {
-        s1n = s1 + (yn * yn - y * y);
-        s2n = s2 + (cos(2.0 * kPi * yn) - cos(2.0 * kPi * y));
-        fn = ackley_from_sums_d(s1n, s2n, n);
-        return fn - f;
-    }
-    __device__ void commit(bool take, float)
-    {
-        f = take ? fn : f;
-        s1 = take ? s1n : s1;
-        s2 = take ? s2n : s2;
-    }
-};
-
-// FP32: cancellation-free increments on the hardware transcendentals.
-//   Schwefel   df = (h(y) - h(y')) / n,  h(y) = y sin(sqrt|y|)
-//   Rastrigin  g(y) = y^2 + 20 sin^2(pi y)  (equal to y^2 - 10 cos 2 pi y + 10)
-//              g(y') - g(y) = dl sg + 20 sin(pi dl) sin(pi sg),  dl = y'-y, sg = y'+y
-//   Ackley     dS1 = dl sg,  dS2 = cos 2pi y' - cos 2pi y = -2 sin(pi sg) sin(pi dl)
-//              df = -20 e^a expm1(a'-a) - e^b expm1(dS2/n)
-//              a = -0.2 sqrt(S1/n), b = S2/n, a'-a = -0.2 (dS1/n) / (sqrt(S1'/n) + sqrt(S1/n))
-template <> struct Cost<float, kSchwefel> {
-    float f, df_;
-    __device__ void set(const Full &v, uint32_t) { f = (float)v.f; }
-    __device__ float delta(float y, float yn, uint32_t, float inv_n)
-    {
-        df_ = (schwefel_h(y) - schwefel_h(yn)) * inv_n;
-        return df_;
-    }
-    __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
-};
-
-template <> struct Cost<float, kRastrigin> {
-    float f, df_;
-    __device__ void set(const Full &v, uint32_t) { f = (float)v.f; }
-    __device__ float delta(float y, float yn, uint32_t, float)
-    {
-        const float dl = yn - y, sg = yn + y;
-        df_ = fmaf(dl, sg, 20.0f * hw_sin_rev(0.5f * dl) * hw_sin_rev(0.5f * sg));
-        return df_;
-    }
-    __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
-};
-
-template <> struct Cost<float, kAckley> {
-    float f, s1, s2, q, ea, eb;  // q = sqrt(S1/n), ea = exp(-0.2 q), eb = exp(S2/n)
-    float df_, s1n_, s2n_, qn_;
-    __device__ void set(const Full &v, uint32_t n)
-    {
-        f = (float)v.f;
-        s1 = (float)v.s1;
-        s2 = (float)v.s2;
-        const double qd = sqrt(v.s1 / (double)n);
-        q = (float)qd;
-        ea = (float)exp(-0.2 * qd);
-        eb = (float)exp(v.s2 / (double)n);
-    }
-    __device__ float delta(float y, float yn, uint32_t, float inv_n)
-    {
-        const float dl = yn - y, sg = yn + y;
-        const float ds1 = dl * sg;
-        const float ds2 = -2.0f * hw_sin_rev(0.5f * sg) * hw_sin_rev(0.5f * dl);
-        s1n_ = fmaxf(s1 + ds1, 0.0f);
-        s2n_ = s2 + ds2;
-        qn_ = hw_sqrt(s1n_ * inv_n);
-        const float den = qn_ + q;
-        const float da = den > 0.0f ? (-0.2f * (ds1 * inv_n)) / den : 0.0f;
-        df_ = -20.0f * ea * expm1f(da) - eb * expm1f(ds2 * inv_n);
-        return df_;
-    }
-    __device__ void commit(bool take, float inv_n)
-    {
-        if (take) {
-            f += df_;
-            s1 = s1n_;
-            s2 = s2n_;
-            q = qn_;
-            ea = hw_exp2((-0.2f * kLog2e) * qn_);
-            eb = hw_exp2(kLog2e * (s2n_ * inv_n));
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
-// Full evaluation in FP64 arithmetic, definition form, coordinates summed in
-// order 0..n-1 (the order of a plain sequential evaluation).
-// ---------------------------------------------------------------------------
-template <int F> struct FullAcc {
-    double a = 0.0, b = 0.0;
-    __device__ void add(double y)
-    {
-        if (F == kSchwefel) {
-            a += schwefel_term_d(y);
-        } else if (F == kRastrigin) {
-            a += rastrigin_term_d(y);
-        } else {
-            a += y * y;
-            b += cos(2.0 * kPi * y);
-        }
-    }
-    __device__ Full finish(uint32_t n) const
-    {
-        if (F == kSchwefel) return Full{-a / (double)n, 0.0, 0.0};
-        if (F == kRastrigin) return Full{10.0 * (double)n + a, 0.0, 0.0};
-        return Full{ackley_from_sums_d(a, b, n), a, b};
-    }
-};
-
-// Per-coordinate parameters {l, u, rho, s}.
-template <typename R> struct Coord {
-    R lo, hi, rho, sh;
-};
 
 template <typename R, bool TABLE>
 __device__ __forceinline__ Coord<R> coord(const LevelArgs<R> &a, const R *tab, uint32_t d)
@@ -183,68 +29,6 @@ __device__ __forceinline__ Coord<R> coord(const LevelArgs<R> &a, const R *tab, u
     if (TABLE) return Coord<R>{tab[4 * d + 0], tab[4 * d + 1], tab[4 * d + 2], tab[4 * d + 3]};
     return Coord<R>{a.lo, a.hi, a.rho, a.sh};
 }
-
-// Neighbour of one coordinate: x + rho (2U - 1) (radius rule) or l + (u - l) U
-// (resampling), clamped to [l, u].  FP32 clamps with one v_med3_f32.
-template <int MOVE> __device__ __forceinline__ float neighbour(float xd, const Coord<float> &c, float u1)
-{
-    const float xn = MOVE == SA_MOVE_RADIUS ? fmaf(c.rho, fmaf(2.0f, u1, -1.0f), xd) : fmaf(c.rho, u1, c.lo);
-    return __builtin_amdgcn_fmed3f(xn, c.lo, c.hi);
-}
-template <int MOVE> __device__ __forceinline__ double neighbour(double xd, const Coord<double> &c, double u1)
-{
-    double xn = MOVE == SA_MOVE_RADIUS ? xd + c.rho * (2.0 * u1 - 1.0) : c.lo + c.rho * u1;
-    if (xn > c.hi) xn = c.hi;
-    if (xn < c.lo) xn = c.lo;
-    return xn;
-}
-
-// Metropolis acceptance (eq. (5), k_b = 1): always downhill, else U < exp(-df/T).
-__device__ __forceinline__ bool metropolis(float df, float u2, double, float neg_log2e_inv_T)
-{
-    return df <= 0.0f || u2 < hw_exp2(df * neg_log2e_inv_T);
-}
-__device__ __forceinline__ bool metropolis(double df, double u2, double T, float)
-{
-    return df <= 0.0 || u2 < exp(-df / T);
-}
-
-// Lexicographic (cost, chain) minimum: ties go to the lower chain index.
-template <typename R> __device__ __forceinline__ void best_of(R &f, uint32_t &c, R f2, uint32_t c2)
-{
-    if (f2 < f || (f2 == f && c2 < c)) {
-        f = f2;
-        c = c2;
-    }
-}
-
-template <typename R> __device__ __forceinline__ void wave_best(R &f, uint32_t &c)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const R f2 = __shfl_xor(f, off, 64);
-        const uint32_t c2 = __shfl_xor(c, off, 64);
-        best_of(f, c, f2, c2);
-    }
-}
-
-template <typename T> __device__ __forceinline__ T wave_sum(T v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <typename R> __device__ __forceinline__ R widen_inf();
-template <> __device__ __forceinline__ float widen_inf<float>() { return __builtin_inff(); }
-template <> __device__ __forceinline__ double widen_inf<double>() { return __builtin_inf(); }
 
 // ---------------------------------------------------------------------------
 // Full evaluation of a state held in LDS, FP64 arithmetic.  FP64 runs sum in
@@ -447,25 +231,10 @@ __global__ void __launch_bounds__(256)
             cost.set(start, n);
         }
 
-        // ---- N Metropolis steps, software-pipelined two moves deep: at the
-        // top of move s the (old) value of move s+1's coordinate is read from
-        // LDS and move s+2's draws are computed, so neither the LDS latency
-        // nor the generator's dependent rounds sit on move s's critical path.
-        // If move s+1 picks the coordinate move s writes, the written value is
-        // forwarded.
+        // ---- N Metropolis steps
         const bool logging = log_level && chain < a.log_chains;
-        Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
-        Ctr r1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
-        uint32_t d = pick(r.w0, n);
-        uint32_t d1 = pick(r1.w0, n);
-        R xd = xs[__umul24(d, WG) + tid];
-        for (uint32_t step = 0; step < a.steps; ++step) {
-            const R x1_lds = xs[__umul24(d1, WG) + tid];
-            const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
-            const Coord<R> c = coord<R, TABLE>(a, tab, d);
-            const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
-            const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-            const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
+        const auto coordf = [&](uint32_t d) { return coord<R, TABLE>(a, tab, d); };
+        const auto logf = [&](uint32_t step, uint32_t d, bool take, R xd, R xn, R df) {
             if (LOG && logging) {
                 sa_move_rec m;
                 m.d = d;
@@ -475,16 +244,9 @@ __global__ void __launch_bounds__(256)
                 m.df = (double)df;
                 a.log[((size_t)(level - a.log_level) * a.log_chains + chain) * a.steps + step] = m;
             }
-            const R xwr = take ? xn : xd;
-            xs[__umul24(d, WG) + tid] = xwr;
-            cost.commit(take, a.inv_n);
-            accepted += take ? 1u : 0u;
-            xd = d1 == d ? xwr : x1_lds;
-            d = d1;
-            r = r1;
-            r1 = r2;
-            d1 = pick(r2.w0, n);
-        }
+        };
+        accepted += run_steps<R, F, MOVE>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3, k0, k1, T,
+                                          nl2T, a.inv_n);
         if (LOG && log_level) a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
 
         // ---- tile argmin of (final cost, chain); keep the workgroup's best

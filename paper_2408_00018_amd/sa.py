@@ -222,3 +222,199 @@ class Annealer:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Batched runs (sa_batch_* in include/sa.h)
+# ---------------------------------------------------------------------------
+EXPORTED_BATCH = ["sa_batch_workspace_bytes", "sa_batch_create", "sa_batch_run", "sa_batch_reset", "sa_batch_best",
+                  "sa_batch_trace", "sa_batch_move_log", "sa_batch_layout", "sa_batch_destroy", "sa_batch_autotune"]
+EXPORTED = EXPORTED + EXPORTED_BATCH
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("levels", ctypes.c_uint32), ("steps", ctypes.c_uint32),
+                ("precision", ctypes.c_uint32), ("move", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("waves_per_group", ctypes.c_uint32), ("T0", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("radius_frac", ctypes.c_double), ("log_problem", ctypes.c_uint32), ("log_chains", ctypes.c_uint32),
+                ("log_level", ctypes.c_uint32), ("log_levels", ctypes.c_uint32)]
+
+
+@dataclass
+class BatchSchedule:
+    """Schedule shared by every problem of a batch (mirrors ``sa_batch_config``)."""
+    levels: int
+    steps: int
+    T0: float
+    alpha: float
+    seed: int = 0
+    precision: int = FP32
+    move: int = MOVE_RADIUS
+    radius_frac: float = 0.1
+    graph: bool = False
+    trace_x: bool = False
+    waves_per_group: int = 0
+    log_problem: int = 0
+    log_chains: int = 0
+    log_level: int = 0
+    log_levels: int = 0
+
+    def to_c(self) -> BatchConfig:
+        flags = (FLAG_GRAPH if self.graph else 0) | (FLAG_TRACE_X if self.trace_x else 0)
+        return BatchConfig(self.seed, self.levels, self.steps, self.precision, self.move, flags,
+                           self.waves_per_group, self.T0, self.alpha,
+                           self.radius_frac, self.log_problem, self.log_chains, self.log_level, self.log_levels)
+
+
+def _bind_batch(L):
+    vp, u32, st = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int
+    P, C = ctypes.POINTER(Problem), ctypes.POINTER(BatchConfig)
+    L.sa_batch_workspace_bytes.argtypes = [P, u32, vp, C, ctypes.POINTER(ctypes.c_size_t)]
+    L.sa_batch_workspace_bytes.restype = st
+    L.sa_batch_create.argtypes = [P, u32, vp, C, vp, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.sa_batch_create.restype = st
+    L.sa_batch_run.argtypes = [vp, u32]
+    L.sa_batch_run.restype = st
+    L.sa_batch_reset.argtypes = [vp, ctypes.c_uint64]
+    L.sa_batch_reset.restype = st
+    L.sa_batch_best.argtypes = [vp, u32, vp, vp, vp]
+    L.sa_batch_best.restype = st
+    L.sa_batch_trace.argtypes = [vp, u32, u32, u32, vp, vp]
+    L.sa_batch_trace.restype = st
+    L.sa_batch_move_log.argtypes = [vp, vp, vp]
+    L.sa_batch_move_log.restype = st
+    L.sa_batch_layout.argtypes = [vp, vp, vp, vp, vp]
+    L.sa_batch_layout.restype = st
+    L.sa_batch_destroy.argtypes = [vp]
+    L.sa_batch_destroy.restype = None
+    L.sa_batch_autotune.argtypes = [P, u32, C, vp, u32, vp, vp, vp]
+    L.sa_batch_autotune.restype = st
+
+
+def _batch_lib():
+    L = load_library()
+    if not getattr(L, "_batch_bound", False):
+        _bind_batch(L)
+        L._batch_bound = True
+    return L
+
+
+def _problem_array(problems):
+    """problems: sequence of (func, lower, upper, shift-or-None)."""
+    arr = (Problem * len(problems))()
+    keep = []
+    for i, (func, lo, hi, sh) in enumerate(problems):
+        p, k = _problem_struct(func, lo, hi, sh)
+        arr[i] = p
+        keep.append(k)
+    return arr, keep
+
+
+def batch_workspace_bytes(problems, chains, sched: BatchSchedule) -> int:
+    L = _batch_lib()
+    arr, keep = _problem_array(problems)
+    ch = np.ascontiguousarray(chains, dtype=np.uint32)
+    cfg = sched.to_c()
+    nbytes = ctypes.c_size_t()
+    _check(L.sa_batch_workspace_bytes(arr, len(problems), ch.ctypes.data, ctypes.byref(cfg), ctypes.byref(nbytes)))
+    del keep
+    return nbytes.value
+
+
+def batch_autotune(problems, sched: BatchSchedule, trial_levels: int = 4, stream=None):
+    """Measure candidate layouts on the device; returns (chains, waves_per_group, moves_per_s)."""
+    import torch
+    L = _batch_lib()
+    arr, keep = _problem_array(problems)
+    cfg = sched.to_c()
+    chains = np.zeros(len(problems), dtype=np.uint32)
+    wpg = ctypes.c_uint32()
+    rate = ctypes.c_double()
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.sa_batch_autotune(arr, len(problems), ctypes.byref(cfg), ctypes.c_void_p(st.cuda_stream), trial_levels,
+                               chains.ctypes.data, ctypes.byref(wpg), ctypes.byref(rate)))
+    del keep
+    return chains, wpg.value, rate.value
+
+
+class BatchAnnealer:
+    """Many independent problems advancing together on the current device."""
+
+    def __init__(self, problems, chains, *, schedule: BatchSchedule, stream=None, torch_workspace: bool = True):
+        import torch
+        L = _batch_lib()
+        self.schedule = schedule
+        self.ns = [int(np.asarray(p[1]).size) for p in problems]
+        self.chains = np.ascontiguousarray(chains, dtype=np.uint32)
+        arr, keep = _problem_array(problems)
+        cfg = schedule.to_c()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        self._ws = None
+        ws_ptr, ws_bytes = None, 0
+        if torch_workspace:
+            nbytes = ctypes.c_size_t()
+            _check(L.sa_batch_workspace_bytes(arr, len(problems), self.chains.ctypes.data, ctypes.byref(cfg),
+                                              ctypes.byref(nbytes)))
+            self._ws = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+            ws_ptr, ws_bytes = self._ws.data_ptr(), nbytes.value
+        h = ctypes.c_void_p()
+        _check(L.sa_batch_create(arr, len(problems), self.chains.ctypes.data, ctypes.byref(cfg),
+                                 ctypes.c_void_p(self._stream.cuda_stream), ws_ptr, ws_bytes, ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    @property
+    def stream(self):
+        return self._stream
+
+    def run(self, levels: int = 0):
+        _check(_batch_lib().sa_batch_run(self._h, levels))
+
+    def reset(self, seed: int):
+        _check(_batch_lib().sa_batch_reset(self._h, seed))
+
+    def best(self, prob: int):
+        x = np.zeros(self.ns[prob])
+        f = ctypes.c_double()
+        lvl = ctypes.c_uint32()
+        _check(_batch_lib().sa_batch_best(self._h, prob, x.ctypes.data, ctypes.byref(f), ctypes.byref(lvl)))
+        return x, f.value, lvl.value
+
+    def trace(self, prob: int, first: int = 0, count: Optional[int] = None, with_x: bool = False):
+        if count is None:
+            count = self.schedule.levels - first
+        rec = np.zeros(count, dtype=LEVEL_DTYPE)
+        xb = np.zeros((count, self.ns[prob])) if with_x else None
+        _check(_batch_lib().sa_batch_trace(self._h, prob, first, count, rec.ctypes.data,
+                                           None if xb is None else xb.ctypes.data))
+        return (rec, xb) if with_x else rec
+
+    def move_log(self):
+        s = self.schedule
+        moves = np.zeros((s.log_levels, s.log_chains, s.steps), dtype=MOVE_DTYPE)
+        final_f = np.zeros((s.log_levels, int(self.chains[s.log_problem])))
+        _check(_batch_lib().sa_batch_move_log(self._h, moves.ctypes.data, final_f.ctypes.data))
+        return moves, final_f
+
+    def layout(self):
+        v = [ctypes.c_uint32() for _ in range(4)]
+        _check(_batch_lib().sa_batch_layout(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(tiles=v[0].value, groups=v[1].value, waves_per_group=v[2].value, lds_bytes=v[3].value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _batch_lib().sa_batch_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -75,7 +75,7 @@ def df_floor(func, n, x, xn, d, shift):
 
 
 def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
-                     final_f, chain_ids, rel=1e-5):
+                     final_f, chain_ids, rel=1e-5, problem=0):
     """Replay the logged moves of `chain_ids` at one level against the oracle.
 
     x_start: the level's start state (the previous level's broadcast winner,
@@ -86,7 +86,7 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
         f_acc_err = 0.0
         for s in range(moves.shape[-1]):
             m = moves[j, s]
-            d_ref, u1, u2, _ = O.move_draw(seed, 0, level, c, s, n)
+            d_ref, u1, u2, _ = O.move_draw(seed, problem, level, c, s, n)
             assert int(m["d"]) == d_ref, (level, c, s)
             assert m["x_old"] == x[d_ref], (level, c, s)
             xn_ref = O.neighbour(move_rule, float(m["x_old"]), float(lower32[d_ref]), float(upper32[d_ref]),
@@ -130,3 +130,71 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
 def lexi_argmin(values):
     m = np.min(values)
     return int(np.flatnonzero(values == m)[0])
+
+
+def fp32_init_state(wl, chain, problem=0):
+    """Level-0 start of one chain as the FP32 path forms it: l + (u - l) U in
+    FP32 arithmetic, from the oracle's Philox draws (start counters)."""
+    lo32, hi32 = box32(wl.lower, wl.upper)
+    x = np.zeros(wl.n, dtype=np.float32)
+    for i in range(wl.n):
+        r = O.philox4x32_10([i >> 2, 0xFFFFFFFF, chain, 1 | (problem << 8)], [wl.seed & 0xFFFFFFFF, wl.seed >> 32])
+        u = np.float32(O.uniform(int(r[i & 3])))
+        v = np.float32(lo32[i]) + (np.float32(hi32[i]) - np.float32(lo32[i])) * u
+        x[i] = min(max(v, np.float32(lo32[i])), np.float32(hi32[i]))
+    # the FP64 start differs from it by at most one FP32 rounding per operation
+    x64 = O.init_point(wl.seed, problem, chain, lo32, hi32)
+    assert np.all(np.abs(x.astype(np.float64) - x64) <= 2.0 ** -22 * (np.abs(x64) + (hi32 - lo32)))
+    return x.astype(np.float64)
+
+
+def check_fp32_run(wl, g, log_level, chain_ids=None, problem=0, move_rule=O.MOVE_RADIUS, say=print):
+    """Per-move replay of a logged FP32 run (moves, final costs, per-level
+    trace and broadcast states in g) against the oracle, plus the level
+    argmin and the full re-evaluation of each broadcast."""
+    lo32, hi32 = box32(wl.lower, wl.upper)
+    sh32 = None if wl.shift is None else f32(wl.shift)
+    moves, final_f = g["moves"], g["final_f"]
+    rec, xb = g["rec"], g["xb"]
+    nlog = moves.shape[0]
+    if chain_ids is None:
+        chain_ids = list(range(moves.shape[1]))
+    totals = dict(moves=0, ambiguous=0, max_rel_excess=0.0)
+    for k in range(nlog):
+        level = log_level + k
+        T = O.temperature(wl.T0, wl.alpha, level)
+        # device-wide argmin of the level: bit-exact on the GPU's own final costs
+        win = lexi_argmin(final_f[k])
+        assert rec["win_chain"][level] == win
+        assert rec["f_win"][level] == final_f[k][win]
+        # broadcast state re-evaluated in full (FP64 on the device)
+        fb = O.f(wl.func, xb[level], sh32)
+        assert abs(rec["f_best"][level] - fb) <= 1e-11 * max(1.0, abs(fb))
+        for c in chain_ids:
+            x_start = fp32_init_state(wl, c, problem) if level == 0 else xb[level - 1]
+            st = check_fp32_level(wl.func, wl.n, lo32, hi32, sh32, wl.seed, level, T, move_rule, wl.radius_frac,
+                                  x_start, moves[k, c:c + 1], final_f[k], [c], problem=problem)
+            totals["moves"] += st["moves"]
+            totals["ambiguous"] += st["ambiguous"]
+            totals["max_rel_excess"] = max(totals["max_rel_excess"], st["max_rel_excess"])
+    say(f"[fp32 parity] {wl.name} problem {problem}: {totals}")
+    return totals
+
+
+def check_record(wl, g):
+    """Record invariants: states in the box, monotone record equal to the
+    running minimum of the re-evaluated winners, x_rec/f_rec consistent."""
+    rec, xb = g["rec"], g["xb"]
+    lo32, hi32 = box32(wl.lower, wl.upper)
+    if wl.precision == 1:
+        lo32, hi32 = np.asarray(wl.lower), np.asarray(wl.upper)
+    assert np.all(xb >= lo32) and np.all(xb <= hi32)
+    assert np.all(np.diff(rec["f_rec"]) <= 0)
+    assert np.array_equal(rec["f_rec"], np.minimum.accumulate(rec["f_best"]))
+    lvl = g["rec_level"]
+    assert np.array_equal(g["x_rec"], xb[lvl])
+    assert g["f_rec"] == rec["f_best"][lvl]
+    sh = None if wl.shift is None else (f32(wl.shift) if wl.precision == 0 else np.asarray(wl.shift))
+    fr = O.f(wl.func, g["x_rec"], sh)
+    assert abs(g["f_rec"] - fr) <= 1e-11 * max(1.0, abs(fr))
+    assert np.all(np.diff(rec["t_ticks"].astype(np.int64)) >= 0)

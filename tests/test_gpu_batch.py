@@ -1,0 +1,153 @@
+"""GPU parity of batched runs (many problems of uneven dimension per launch)
+against the FP64 oracle, run per problem with its problem id in the counters.
+
+FP64 batches must reproduce every problem's oracle trajectory exactly (level
+winners, accepted-move counts, states and costs to 1e-12), whatever the
+packing of tiles into workgroups.  FP32 batches are checked move by move on a
+logged problem, and every problem's record against its definition.  The
+autotuner must return a valid layout that runs.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity_util import check_fp32_run, check_record
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2408_00018_amd import sa
+    sa.load_library()
+    return sa
+
+
+def make_batch(nprob, seed, nmax=24, precision=W.FP64, chains_choices=(64, 128, 192, 320)):
+    """Random problems: function uniform over the three families, n uniform in
+    [1, nmax], shifted boxes (Schwefel: canonical box translated by the shift,
+    so its minimiser stays inside), random chain counts."""
+    rng = np.random.default_rng(seed)
+    probs, chains, wls = [], [], []
+    for p in range(nprob):
+        func = int(rng.integers(0, 3))
+        n = int(rng.integers(1, nmax + 1))
+        half = {W.SCHWEFEL: 500.0, W.RASTRIGIN: 5.12, W.ACKLEY: 32.768}[func]
+        lo, hi = np.full(n, -half), np.full(n, half)
+        s = W.inner_shift(lo, hi, rng)
+        if func == W.SCHWEFEL:
+            lo, hi = lo + s, hi + s
+        c = int(rng.choice(chains_choices))
+        probs.append((func, lo, hi, s))
+        chains.append(c)
+        wls.append(W.Workload(f"batch{seed}_p{p}", func, n, lo, hi, s, chains=c, levels=0, steps=0, T0=0, alpha=0,
+                              seed=0, precision=precision))
+    return probs, chains, wls
+
+
+def run_batch(S, probs, chains, sched, chunks=None):
+    say(f"[gpu batch] nprob={len(probs)} chains={sum(chains)} levels={sched.levels} steps={sched.steps} "
+        f"prec={sched.precision} wpg={sched.waves_per_group} log={sched.log_chains}@p{sched.log_problem}")
+    out = []
+    with S.BatchAnnealer(probs, chains, schedule=sched) as b:
+        for c in (chunks or [0]):
+            b.run(c)
+        lay = b.layout()
+        for p in range(len(probs)):
+            rec, xb = b.trace(p, with_x=True)
+            x_rec, f_rec, lvl = b.best(p)
+            out.append(dict(rec=rec, xb=xb, x_rec=x_rec, f_rec=f_rec, rec_level=lvl))
+        if sched.log_chains:
+            moves, final_f = b.move_log()
+            out[sched.log_problem]["moves"] = moves
+            out[sched.log_problem]["final_f"] = final_f
+    return out, lay
+
+
+@pytest.mark.parametrize("wpg", [1, 2, 4])
+def test_fp64_batch_matches_oracle_per_problem(S, wpg):
+    probs, chains, _ = make_batch(11, seed=5)
+    sched = S.BatchSchedule(levels=7, steps=24, T0=10.0, alpha=0.9, seed=42, precision=S.FP64, trace_x=True,
+                            waves_per_group=wpg)
+    g, lay = run_batch(S, probs, chains, sched)
+    assert lay["tiles"] == sum(chains) // 64
+    for p, (func, lo, hi, s) in enumerate(probs):
+        o = O.sa_run(func, lo, hi, s, seed=42, problem=p, chains=chains[p], steps=24, T0=10.0, alpha=0.9, levels=7)
+        gp = g[p]
+        assert np.array_equal(gp["rec"]["win_chain"], o["win_chain"]), p
+        assert np.array_equal(gp["rec"]["accepts"], o["accepts"]), p
+        np.testing.assert_allclose(gp["xb"], o["x_best"], rtol=1e-12, atol=1e-12)
+        for k in ("f_win", "f_best", "f_rec"):
+            np.testing.assert_allclose(gp["rec"][k], o[k], rtol=1e-12, atol=1e-12)
+        assert gp["rec_level"] == o["rec_level"]
+        np.testing.assert_allclose(gp["x_rec"], o["x_rec"], rtol=1e-12, atol=1e-12)
+
+
+def test_fp64_batch_resume_and_graph(S):
+    probs, chains, _ = make_batch(6, seed=8)
+    kw = dict(levels=6, steps=16, T0=5.0, alpha=0.9, seed=3, precision=S.FP64, trace_x=True)
+    whole, _ = run_batch(S, probs, chains, S.BatchSchedule(**kw))
+    split, _ = run_batch(S, probs, chains, S.BatchSchedule(**kw), chunks=[2, 3, 1])
+    graph, _ = run_batch(S, probs, chains, S.BatchSchedule(graph=True, **kw), chunks=[2, 0])
+    for other in (split, graph):
+        for a, b in zip(whole, other):
+            assert np.array_equal(a["rec"][["win_chain", "accepts", "f_win", "f_best", "f_rec"]],
+                                  b["rec"][["win_chain", "accepts", "f_win", "f_best", "f_rec"]])
+            assert np.array_equal(a["xb"], b["xb"])
+
+
+def test_fp32_batch_per_move_parity(S):
+    probs, chains, wls = make_batch(40, seed=11, nmax=256, precision=W.FP32, chains_choices=(64, 128, 256))
+    q = int(np.argmax([w.n for w in wls]))  # log the largest problem
+    sched = S.BatchSchedule(levels=4, steps=64, T0=10.0, alpha=0.95, seed=9, precision=S.FP32, trace_x=True,
+                            log_problem=q, log_chains=64, log_level=0, log_levels=4)
+    g, lay = run_batch(S, probs, chains, sched)
+    say(f"[gpu batch] layout {lay}")
+    wl = wls[q].with_(levels=4, steps=64, T0=10.0, alpha=0.95, seed=9)
+    check_fp32_run(wl, g[q], 0, chain_ids=list(range(0, 64, 9)), problem=q, say=say)
+    for p, w in enumerate(wls):
+        check_record(w.with_(levels=4, steps=64, T0=10.0, alpha=0.95, seed=9), g[p])
+
+
+def test_fp32_batch_is_layout_invariant(S):
+    """Each tile's arithmetic does not depend on which workgroup it lands in."""
+    probs, chains, _ = make_batch(25, seed=13, nmax=200, precision=W.FP32, chains_choices=(64, 192, 256))
+    base = dict(levels=5, steps=32, T0=10.0, alpha=0.9, seed=1, precision=S.FP32, trace_x=True)
+    runs = [run_batch(S, probs, chains, S.BatchSchedule(waves_per_group=w, **base))[0] for w in (1, 2, 4)]
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a["rec"][["win_chain", "accepts", "f_win", "f_best", "f_rec"]],
+                                  b["rec"][["win_chain", "accepts", "f_win", "f_best", "f_rec"]])
+            assert np.array_equal(a["xb"], b["xb"])
+
+
+def test_autotune_picks_a_valid_layout(S):
+    probs, _, _ = make_batch(64, seed=17, nmax=256, precision=W.FP32)
+    sched = S.BatchSchedule(levels=3, steps=16, T0=10.0, alpha=0.9, seed=0, precision=S.FP32)
+    chains, wpg, rate = S.batch_autotune(probs, sched, trial_levels=2)
+    say(f"[autotune] wpg={wpg} rate={rate:.3e} chains {np.unique(chains)}")
+    assert wpg in (1, 2, 4)
+    assert rate > 0
+    assert np.all(chains % 64 == 0) and np.all(chains >= 64) and np.all(chains <= 1024)
+    sched.waves_per_group = wpg
+    sched.trace_x = True
+    g, _ = run_batch(S, probs, chains, sched)
+    assert all(np.isfinite(x["f_rec"]) for x in g)
+
+
+def test_batch_rejects_oversized_problem(S):
+    lo, hi = np.full(700, -1.0), np.full(700, 1.0)
+    sched = S.BatchSchedule(levels=2, steps=4, T0=1.0, alpha=0.9, precision=S.FP32)
+    with pytest.raises(S.SAError) as e:
+        S.BatchAnnealer([(0, lo, hi, None)], [64], schedule=sched)
+    assert e.value.status == -5

@@ -18,7 +18,8 @@ import pytest
 
 import oracle as O
 import workloads as W
-from parity_util import box32, check_fp32_level, f32, lexi_argmin
+import parity_util
+from parity_util import box32, check_record
 
 pytestmark = pytest.mark.gpu
 
@@ -141,65 +142,8 @@ def test_fp64_resume_and_graph_are_identical(S):
 # --------------------------------------------------------------------------
 
 
-def fp32_init_state(wl, chain):
-    """Level-0 start of one chain as the FP32 path forms it: l + (u - l) U in
-    FP32 arithmetic, from the oracle's Philox draws."""
-    lo32, hi32 = box32(wl.lower, wl.upper)
-    x = np.zeros(wl.n, dtype=np.float32)
-    for i in range(wl.n):
-        r = O.philox4x32_10([i >> 2, 0xFFFFFFFF, chain, 1], [wl.seed & 0xFFFFFFFF, wl.seed >> 32])
-        u = np.float32(O.uniform(int(r[i & 3])))
-        v = np.float32(lo32[i]) + (np.float32(hi32[i]) - np.float32(lo32[i])) * u
-        x[i] = min(max(v, np.float32(lo32[i])), np.float32(hi32[i]))
-    # the FP64 start differs from it by at most one FP32 rounding per operation
-    x64 = O.init_point(wl.seed, 0, chain, lo32, hi32)
-    assert np.all(np.abs(x.astype(np.float64) - x64) <= 2.0 ** -22 * (np.abs(x64) + (hi32 - lo32)))
-    return x.astype(np.float64)
-
-
 def check_fp32_run(S, wl, g, log_level, chain_ids=None):
-    lo32, hi32 = box32(wl.lower, wl.upper)
-    sh32 = None if wl.shift is None else f32(wl.shift)
-    moves, final_f = g["moves"], g["final_f"]
-    rec, xb = g["rec"], g["xb"]
-    nlog = moves.shape[0]
-    if chain_ids is None:
-        chain_ids = list(range(moves.shape[1]))
-    totals = dict(moves=0, ambiguous=0, max_rel_excess=0.0)
-    for k in range(nlog):
-        level = log_level + k
-        T = O.temperature(wl.T0, wl.alpha, level)
-        # device-wide argmin of the level: bit-exact on the GPU's own final costs
-        win = lexi_argmin(final_f[k])
-        assert rec["win_chain"][level] == win
-        assert rec["f_win"][level] == final_f[k][win]
-        # broadcast state re-evaluated in full (FP64 on the device)
-        fb = O.f(wl.func, xb[level], sh32)
-        assert abs(rec["f_best"][level] - fb) <= 1e-11 * max(1.0, abs(fb))
-        for c in chain_ids:
-            x_start = fp32_init_state(wl, c) if level == 0 else xb[level - 1]
-            st = check_fp32_level(wl.func, wl.n, lo32, hi32, sh32, wl.seed, level, T, O.MOVE_RADIUS,
-                                  wl.radius_frac, x_start, moves[k, c:c + 1], final_f[k], [c])
-            totals["moves"] += st["moves"]
-            totals["ambiguous"] += st["ambiguous"]
-            totals["max_rel_excess"] = max(totals["max_rel_excess"], st["max_rel_excess"])
-    say(f"[fp32 parity] {wl.name}: {totals}")
-    return totals
-
-
-def check_record(wl, g):
-    rec, xb = g["rec"], g["xb"]
-    lo32, hi32 = box32(wl.lower, wl.upper)
-    assert np.all(xb >= lo32) and np.all(xb <= hi32)
-    assert np.all(np.diff(rec["f_rec"]) <= 0)
-    assert np.array_equal(rec["f_rec"], np.minimum.accumulate(rec["f_best"]))
-    lvl = g["rec_level"]
-    assert np.array_equal(g["x_rec"], xb[lvl])
-    assert g["f_rec"] == rec["f_best"][lvl]
-    sh32 = None if wl.shift is None else f32(wl.shift)
-    fr = O.f(wl.func, g["x_rec"], sh32)
-    assert abs(g["f_rec"] - fr) <= 1e-11 * max(1.0, abs(fr))
-    assert np.all(np.diff(rec["t_ticks"].astype(np.int64)) >= 0)
+    return parity_util.check_fp32_run(wl, g, log_level, chain_ids=chain_ids, say=say)
 
 
 def test_fp32_schwefel_n100_moves_small(S):
