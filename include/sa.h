@@ -253,6 +253,47 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
 /* Description of the calling thread's last error ("" if none). */
 const char *sa_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Learned proposal network (an extension of the method; not in the paper):
+ * per chosen coordinate, features z = ((x_d - l_d)/(u_d - l_d), ln T, the
+ * chain's last four accepted scaled displacements) -> 128 -> 128 (GELU, tanh
+ * form) -> (mu, s): a Gaussian N(mu, exp(s)^2) over the coordinate's scaled
+ * displacement (x'_d - x_d)/(u_d - l_d).  Parameters: SA_MLP_PARAMS floats,
+ * W1[6][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].  Training
+ * minimises the mean Gaussian negative log-likelihood s + (d - mu)^2 /
+ * (2 exp(2 s)) of captured accepted displacements d with Adam (FP32 master
+ * weights, BF16 weight matrices, BF16 MFMA with FP32 accumulate).
+ * Captured records: 7 floats each, (z[0..5], d).
+ * ------------------------------------------------------------------------ */
+#define SA_MLP_PARAMS 17666
+
+typedef struct sa_mlp sa_mlp;
+
+/* Trainer for minibatches of up to max_batch records (a multiple of 32);
+ * allocates its own device memory; parameters start at zero. */
+sa_status sa_mlp_create(uint32_t max_batch, void *stream, sa_mlp **out);
+
+/* Load host parameters (SA_MLP_PARAMS floats) and reset the optimiser. */
+sa_status sa_mlp_set_params(sa_mlp *m, const float *params);
+
+/* Copy the FP32 master parameters to the host (synchronises). */
+sa_status sa_mlp_get_params(sa_mlp *m, float *params);
+
+/* Gradient of the mean loss over records[idx[0..batch)] (records: device
+ * pointer to nrec x 7 floats; idx: host indices < nrec; batch a multiple of
+ * 32).  Writes SA_MLP_PARAMS floats to the host array grad and the mean loss
+ * to *loss (either may be NULL).  Synchronises. */
+sa_status sa_mlp_grad(sa_mlp *m, const float *records, uint64_t nrec, const uint32_t *idx, uint32_t batch,
+                      float *grad, float *loss);
+
+/* `steps` Adam steps (lr; beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of
+ * `batch` records drawn with replacement by Philox counters under `seed`.
+ * loss_trace: `steps` host floats (each minibatch's mean loss) or NULL. */
+sa_status sa_mlp_train(sa_mlp *m, const float *records, uint64_t nrec, uint32_t batch, uint32_t steps, float lr,
+                       uint64_t seed, float *loss_trace);
+
+void sa_mlp_destroy(sa_mlp *m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,20 @@ def lib():
         L.orc_replay_level.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _d, _d, _i, _u32, _p, _u32, _u32,
                                        _p, _p, _p, _p, _p, _p, _p]
         L.orc_replay_level.restype = _i
+        L.orc_mlp_nparam.argtypes = []
+        L.orc_mlp_nparam.restype = _u32
+        L.orc_gelu.argtypes = [_d]
+        L.orc_gelu.restype = _d
+        L.orc_gelu_grad.argtypes = [_d]
+        L.orc_gelu_grad.restype = _d
+        L.orc_mlp_forward.argtypes = [_p, _p, _p, _p, _p]
+        L.orc_mlp_forward.restype = None
+        L.orc_mlp_loss_grad.argtypes = [_p, _u32, _p, _p, _p]
+        L.orc_mlp_loss_grad.restype = _d
+        L.orc_adam_step.argtypes = [_p, _p, _p, _p, _u32, _u32, _d, _d, _d, _d]
+        L.orc_adam_step.restype = None
+        L.orc_proposal_logpdf.argtypes = [_d, _d, _d]
+        L.orc_proposal_logpdf.restype = _d
         _lib = L
     return _lib
 
@@ -226,3 +240,66 @@ def replay_level(func, lower, upper, shift=None, *, seed, steps, T, level, x_sta
     return dict(d=log_d.reshape(sh), x_old=log_xold.reshape(sh), x_new=log_xnew.reshape(sh),
                 df=log_df.reshape(sh), acc=log_acc.reshape(sh).astype(bool), x_final=x_final.reshape(nchains, n),
                 f_final=f_final)
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal network (FP64 reference)
+# ---------------------------------------------------------------------------
+MLP_HIDDEN = 128
+MLP_INPUTS = 6
+
+
+def mlp_nparam() -> int:
+    return lib().orc_mlp_nparam()
+
+
+def gelu(a: float) -> float:
+    return lib().orc_gelu(a)
+
+
+def gelu_grad(a: float) -> float:
+    return lib().orc_gelu_grad(a)
+
+
+def mlp_forward(params, z):
+    """(mu, s) for one feature vector; also the two pre-activation vectors."""
+    p = _f64(params)
+    zz = _f64(z)
+    out = np.zeros(2)
+    a1 = np.zeros(MLP_HIDDEN)
+    a2 = np.zeros(MLP_HIDDEN)
+    lib().orc_mlp_forward(_ptr(p), _ptr(zz), _ptr(out), _ptr(a1), _ptr(a2))
+    return out, a1, a2
+
+
+def mlp_loss_grad(params, Z, delta, with_grad=True):
+    p = _f64(params)
+    Zc = _f64(Z).reshape(-1, MLP_INPUTS)
+    d = _f64(delta)
+    g = np.zeros(p.size) if with_grad else None
+    loss = lib().orc_mlp_loss_grad(_ptr(p), Zc.shape[0], _ptr(Zc), _ptr(d), _ptr(g))
+    return (loss, g) if with_grad else loss
+
+
+def adam_step(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays."""
+    for a in (params, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.size, t, lr, beta1, beta2, eps)
+
+
+def proposal_logpdf(delta, mu, s):
+    return lib().orc_proposal_logpdf(delta, mu, s)
+
+
+def mlp_unpack(params):
+    """Split the parameter vector into (W1, b1, W2, b2, W3, b3)."""
+    p = _f64(params)
+    H, I = MLP_HIDDEN, MLP_INPUTS
+    sizes = [I * H, H, H * H, H, H * 2, 2]
+    shapes = [(I, H), (H,), (H, H), (H,), (H, 2), (2,)]
+    out, o = [], 0
+    for sz, sh in zip(sizes, shapes):
+        out.append(p[o:o + sz].reshape(sh))
+        o += sz
+    return out

@@ -418,3 +418,151 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
     free(x);
     return 0;
 }
+
+/* ======================================================================== */
+/* Learned proposal (an extension of the method, not in the paper): a small  */
+/* per-coordinate network maps the features of the chosen coordinate to a   */
+/* Gaussian over its scaled displacement.  FP64 reference of its forward     */
+/* pass, negative log-likelihood loss, gradient and Adam step.               */
+/*                                                                          */
+/* Features z (6): z0 = (x_d - l_d)/(u_d - l_d); z1 = ln T; z2..z5 = the     */
+/* chain's last four accepted scaled displacements, most recent first.       */
+/* Network: a1 = z W1 + b1 (6x128), h1 = gelu(a1); a2 = h1 W2 + b2 (128x128), */
+/* h2 = gelu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma.        */
+/* gelu(a) = a/2 (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) (tanh form).      */
+/* Loss of a record (z, delta): s + (delta - mu)^2 / (2 exp(2 s)).           */
+/* Parameter vector order: W1 (row-major, [in][out]), b1, W2, b2, W3, b3.    */
+/* ======================================================================== */
+#define ORC_H 128
+#define ORC_NIN 6
+#define ORC_NPARAM (ORC_NIN * ORC_H + ORC_H + ORC_H * ORC_H + ORC_H + ORC_H * 2 + 2)
+
+uint32_t orc_mlp_nparam(void) { return ORC_NPARAM; }
+
+double orc_gelu(double a)
+{
+    const double c = 0.79788456080286535588; /* sqrt(2/pi) */
+    return 0.5 * a * (1.0 + tanh(c * (a + 0.044715 * a * a * a)));
+}
+
+double orc_gelu_grad(double a)
+{
+    const double c = 0.79788456080286535588;
+    double u = c * (a + 0.044715 * a * a * a);
+    double t = tanh(u);
+    double du = c * (1.0 + 3.0 * 0.044715 * a * a);
+    return 0.5 * (1.0 + t) + 0.5 * a * (1.0 - t * t) * du;
+}
+
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3;
+} orc_mlp;
+
+static orc_mlp mlp_view(const double *p)
+{
+    orc_mlp m;
+    m.W1 = p;
+    m.b1 = m.W1 + ORC_NIN * ORC_H;
+    m.W2 = m.b1 + ORC_H;
+    m.b2 = m.W2 + ORC_H * ORC_H;
+    m.W3 = m.b2 + ORC_H;
+    m.b3 = m.W3 + ORC_H * 2;
+    return m;
+}
+
+/* Forward pass of one feature vector; a1, a2 (pre-activations) optional. */
+void orc_mlp_forward(const double *params, const double *z, double *out2, double *a1_out, double *a2_out)
+{
+    orc_mlp m = mlp_view(params);
+    double a1[ORC_H], h1[ORC_H], a2[ORC_H], h2[ORC_H];
+    for (int j = 0; j < ORC_H; ++j) {
+        double s = m.b1[j];
+        for (int i = 0; i < ORC_NIN; ++i) s += z[i] * m.W1[i * ORC_H + j];
+        a1[j] = s;
+        h1[j] = orc_gelu(s);
+    }
+    for (int j = 0; j < ORC_H; ++j) {
+        double s = m.b2[j];
+        for (int i = 0; i < ORC_H; ++i) s += h1[i] * m.W2[i * ORC_H + j];
+        a2[j] = s;
+        h2[j] = orc_gelu(s);
+    }
+    for (int k = 0; k < 2; ++k) {
+        double s = m.b3[k];
+        for (int i = 0; i < ORC_H; ++i) s += h2[i] * m.W3[i * 2 + k];
+        out2[k] = s;
+    }
+    if (a1_out) memcpy(a1_out, a1, sizeof a1);
+    if (a2_out) memcpy(a2_out, a2, sizeof a2);
+}
+
+/* Mean loss over a batch and its gradient (grad may be NULL). */
+double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, const double *delta, double *grad)
+{
+    orc_mlp m = mlp_view(params);
+    double loss = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * ORC_NPARAM);
+    double *gW1 = grad, *gb1 = grad ? gW1 + ORC_NIN * ORC_H : NULL, *gW2 = grad ? gb1 + ORC_H : NULL;
+    double *gb2 = grad ? gW2 + ORC_H * ORC_H : NULL, *gW3 = grad ? gb2 + ORC_H : NULL;
+    double *gb3 = grad ? gW3 + ORC_H * 2 : NULL;
+    const double inv_b = 1.0 / (double)batch;
+    for (uint32_t r = 0; r < batch; ++r) {
+        const double *z = Z + (size_t)r * ORC_NIN;
+        double a1[ORC_H], a2[ORC_H], h1[ORC_H], h2[ORC_H], o[2];
+        orc_mlp_forward(params, z, o, a1, a2);
+        for (int j = 0; j < ORC_H; ++j) {
+            h1[j] = orc_gelu(a1[j]);
+            h2[j] = orc_gelu(a2[j]);
+        }
+        const double mu = o[0], s = o[1];
+        const double e = delta[r] - mu;
+        const double inv_var = exp(-2.0 * s);
+        loss += (s + 0.5 * e * e * inv_var) * inv_b;
+        if (!grad) continue;
+        const double dmu = -e * inv_var * inv_b;
+        const double ds = (1.0 - e * e * inv_var) * inv_b;
+        double dh2[ORC_H], da2[ORC_H], dh1[ORC_H], da1[ORC_H];
+        gb3[0] += dmu;
+        gb3[1] += ds;
+        for (int i = 0; i < ORC_H; ++i) {
+            gW3[i * 2 + 0] += h2[i] * dmu;
+            gW3[i * 2 + 1] += h2[i] * ds;
+            dh2[i] = m.W3[i * 2 + 0] * dmu + m.W3[i * 2 + 1] * ds;
+            da2[i] = dh2[i] * orc_gelu_grad(a2[i]);
+        }
+        for (int j = 0; j < ORC_H; ++j) gb2[j] += da2[j];
+        for (int i = 0; i < ORC_H; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < ORC_H; ++j) {
+                gW2[i * ORC_H + j] += h1[i] * da2[j];
+                acc += m.W2[i * ORC_H + j] * da2[j];
+            }
+            dh1[i] = acc;
+            da1[i] = dh1[i] * orc_gelu_grad(a1[i]);
+        }
+        for (int j = 0; j < ORC_H; ++j) gb1[j] += da1[j];
+        for (int i = 0; i < ORC_NIN; ++i)
+            for (int j = 0; j < ORC_H; ++j) gW1[i * ORC_H + j] += z[i] * da1[j];
+    }
+    return loss;
+}
+
+/* One Adam step (Kingma & Ba): m, v moments, t = step number (1-based). */
+void orc_adam_step(double *params, const double *grad, double *m, double *v, uint32_t nparam, uint32_t t, double lr,
+                   double beta1, double beta2, double eps)
+{
+    const double c1 = 1.0 - pow(beta1, (double)t), c2 = 1.0 - pow(beta2, (double)t);
+    for (uint32_t i = 0; i < nparam; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * grad[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * grad[i] * grad[i];
+        const double mh = m[i] / c1, vh = v[i] / c2;
+        params[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* Log density of the proposal, in scaled units: ln N(delta; mu, sigma^2). */
+double orc_proposal_logpdf(double delta, double mu, double s)
+{
+    const double e = delta - mu;
+    return -s - 0.5 * e * e * exp(-2.0 * s) - 0.91893853320467274178; /* ln sqrt(2 pi) */
+}

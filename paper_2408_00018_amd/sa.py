@@ -418,3 +418,90 @@ class BatchAnnealer:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Learned proposal network trainer (sa_mlp_* in include/sa.h)
+# ---------------------------------------------------------------------------
+MLP_PARAMS = 17666
+EXPORTED_MLP = ["sa_mlp_create", "sa_mlp_set_params", "sa_mlp_get_params", "sa_mlp_grad", "sa_mlp_train",
+                "sa_mlp_destroy"]
+EXPORTED = EXPORTED + EXPORTED_MLP
+
+
+def _mlp_lib():
+    L = load_library()
+    if not getattr(L, "_mlp_bound", False):
+        vp, u32, u64, st = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        L.sa_mlp_create.argtypes = [u32, vp, ctypes.POINTER(vp)]
+        L.sa_mlp_create.restype = st
+        L.sa_mlp_set_params.argtypes = [vp, vp]
+        L.sa_mlp_set_params.restype = st
+        L.sa_mlp_get_params.argtypes = [vp, vp]
+        L.sa_mlp_get_params.restype = st
+        L.sa_mlp_grad.argtypes = [vp, vp, u64, vp, u32, vp, vp]
+        L.sa_mlp_grad.restype = st
+        L.sa_mlp_train.argtypes = [vp, vp, u64, u32, u32, ctypes.c_float, u64, vp]
+        L.sa_mlp_train.restype = st
+        L.sa_mlp_destroy.argtypes = [vp]
+        L.sa_mlp_destroy.restype = None
+        L._mlp_bound = True
+    return L
+
+
+class MLPTrainer:
+    """Trains the proposal network on captured records (a torch float32 tensor
+    of shape [N, 7] on the device: 6 features, accepted scaled displacement)."""
+
+    def __init__(self, max_batch: int = 4096, stream=None):
+        import torch
+        L = _mlp_lib()
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(L.sa_mlp_create(max_batch, ctypes.c_void_p(self._stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        _check(_mlp_lib().sa_mlp_set_params(self._h, p.ctypes.data))
+
+    def params(self):
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_mlp_lib().sa_mlp_get_params(self._h, p.ctypes.data))
+        return p
+
+    def grad(self, records, idx):
+        """Gradient of the mean loss over records[idx] (idx host indices)."""
+        assert records.is_cuda and records.dtype.is_floating_point and records.shape[1] == 7
+        ix = np.ascontiguousarray(idx, dtype=np.uint32)
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_float()
+        _check(_mlp_lib().sa_mlp_grad(self._h, ctypes.c_void_p(records.data_ptr()), records.shape[0], ix.ctypes.data,
+                                      ix.size, g.ctypes.data, ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, records, batch: int, steps: int, lr: float = 1e-3, seed: int = 0):
+        assert records.is_cuda and records.shape[1] == 7
+        trace = np.zeros(steps, dtype=np.float32)
+        _check(_mlp_lib().sa_mlp_train(self._h, ctypes.c_void_p(records.data_ptr()), records.shape[0], batch, steps,
+                                       lr, seed, trace.ctypes.data))
+        return trace
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _mlp_lib().sa_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bf16_round(a):
+    """Round float32 values to the nearest BF16 (ties to even), as float32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32)
