@@ -110,6 +110,10 @@ typedef struct {
 /* Capture the launches of each distinct sa_run (same first level and level
  * count) into a HIP graph once and replay it. */
 #define SA_FLAG_GRAPH 0x2u
+/* Reserve room for the learned proposal (sa_set_proposal): FP32 and the
+ * radius move only; workgroups are sized so the packed network fits in LDS
+ * beside the chains' states. */
+#define SA_FLAG_LEARNED 0x4u
 
 /* Per-level record returned by sa_trace. */
 typedef struct {
@@ -128,7 +132,9 @@ typedef struct {
     uint32_t d;      /* coordinate */
     uint32_t accept; /* 1 if taken */
     double x_old;    /* x_d before the move */
-    double x_new;    /* proposed x'_d (after clamping) */
+    double x_new;    /* proposed x'_d (after clamping; a learned proposal
+                        outside the box is logged as drawn, with accept 0
+                        and df 0) */
     double df;       /* cost increment the device computed */
 } sa_move_rec;
 
@@ -172,6 +178,45 @@ sa_status sa_trace(sa_ctx *ctx, uint32_t first, uint32_t count, sa_level *out, d
  * final_f: log_levels * chains doubles, index (level - log_level) * chains +
  * chain.  Either may be NULL. */
 sa_status sa_move_log(sa_ctx *ctx, sa_move_rec *moves, double *final_f);
+
+/* Start the run at `level` (1 <= level < cfg->levels) with every chain at x
+ * (n doubles inside the box; FP32 runs round them to FP32, kept inside the
+ * inward-rounded box), instead of the random starts of level 0: the levels
+ * before `level` are skipped and the record starts empty.  Only before the
+ * first sa_run (or after sa_reset, which clears it).  Synchronises. */
+sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
+
+/*
+ * Learned proposal (an extension of the method, not in the paper).  With
+ * params (SA_MLP_PARAMS host floats, the network of sa_mlp_*) every later
+ * move is, with probability eps, the plain radius move with the Metropolis
+ * test, and otherwise a draw from the network's Gaussian over the chosen
+ * coordinate's scaled displacement, dl = mu + exp(s) g (g standard normal by
+ * Box-Muller on the Philox block (step, level, chain, 3 | problem << 8)),
+ * x'_d = x_d + dl (u_d - l_d); a proposal outside [l_d, u_d] is rejected, and
+ * otherwise it is taken iff U < exp(-df/T + ln q(x | x') - ln q(x' | x))
+ * (Metropolis-Hastings with the network evaluated at x_d and at x'_d, both
+ * with the chain's current history).  The plain/learned choice is U(r3) < eps
+ * of the move block.  The history (last four accepted scaled displacements,
+ * most recent first) restarts at zero at every level.  params = NULL returns
+ * to plain moves.  Needs SA_FLAG_LEARNED; SA_ERR_STATE while capturing.
+ * Synchronises.
+ */
+sa_status sa_set_proposal(sa_ctx *ctx, const float *params, float eps);
+
+/* Record every accepted move of the following plain levels into `records`
+ * (device memory, capacity x 7 floats: the six network features at the old
+ * state -- (x_d - l_d)/(u_d - l_d), ln(tau T), the chain's last four accepted
+ * scaled displacements -- and the accepted scaled displacement
+ * (x'_d - x_d)/(u_d - l_d)).  Records go to slots in the order the device
+ * reserves them; once `capacity` are taken, later ones are counted but not
+ * stored.  Resets the count.  records = NULL stops capturing.  SA_ERR_STATE
+ * while a proposal network is set. */
+sa_status sa_capture(sa_ctx *ctx, float *records, uint64_t capacity);
+
+/* Accepted moves the capture has seen since sa_capture (synchronises); the
+ * records stored are min(count, capacity). */
+sa_status sa_capture_count(sa_ctx *ctx, uint64_t *count);
 
 /* Release the context and any memory the library allocated. */
 void sa_destroy(sa_ctx *ctx);
@@ -255,9 +300,10 @@ const char *sa_last_error(void);
 
 /* ------------------------------------------------------------------------
  * Learned proposal network (an extension of the method; not in the paper):
- * per chosen coordinate, features z = ((x_d - l_d)/(u_d - l_d), ln T, the
- * chain's last four accepted scaled displacements) -> 128 -> 128 (GELU, tanh
- * form) -> (mu, s): a Gaussian N(mu, exp(s)^2) over the coordinate's scaled
+ * per chosen coordinate, features z = ((x_d - l_d)/(u_d - l_d), ln(tau T),
+ * the chain's last four accepted scaled displacements, most recent first;
+ * tau = n for Schwefel and Ackley, 1 for Rastrigin) -> 128 (relu) -> 128
+ * (relu) -> (mu, s): a Gaussian N(mu, exp(s)^2) over the coordinate's scaled
  * displacement (x'_d - x_d)/(u_d - l_d).  Parameters: SA_MLP_PARAMS floats,
  * W1[6][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].  Training
  * minimises the mean Gaussian negative log-likelihood s + (d - mu)^2 /
@@ -291,6 +337,14 @@ sa_status sa_mlp_grad(sa_mlp *m, const float *records, uint64_t nrec, const uint
  * loss_trace: `steps` host floats (each minibatch's mean loss) or NULL. */
 sa_status sa_mlp_train(sa_mlp *m, const float *records, uint64_t nrec, uint32_t batch, uint32_t steps, float lr,
                        uint64_t seed, float *loss_trace);
+
+/* Evaluate the network at the current parameters for `rows` feature vectors
+ * Z (device, rows x 6 floats) into out (device, rows x 2 floats: mu, s),
+ * asynchronously on the trainer's stream, with the same BF16-MFMA wave
+ * routine the annealing kernels run: weight matrices and hidden activations
+ * in BF16, features to about 16 bits (BF16 high part plus BF16 remainder),
+ * biases and accumulation in FP32. */
+sa_status sa_mlp_infer(sa_mlp *m, const float *Z, uint32_t rows, float *out);
 
 void sa_mlp_destroy(sa_mlp *m);
 

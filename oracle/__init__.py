@@ -85,10 +85,10 @@ def lib():
         L.orc_replay_level.restype = _i
         L.orc_mlp_nparam.argtypes = []
         L.orc_mlp_nparam.restype = _u32
-        L.orc_gelu.argtypes = [_d]
-        L.orc_gelu.restype = _d
-        L.orc_gelu_grad.argtypes = [_d]
-        L.orc_gelu_grad.restype = _d
+        L.orc_act.argtypes = [_d]
+        L.orc_act.restype = _d
+        L.orc_act_grad.argtypes = [_d]
+        L.orc_act_grad.restype = _d
         L.orc_mlp_forward.argtypes = [_p, _p, _p, _p, _p]
         L.orc_mlp_forward.restype = None
         L.orc_mlp_loss_grad.argtypes = [_p, _u32, _p, _p, _p]
@@ -97,6 +97,13 @@ def lib():
         L.orc_adam_step.restype = None
         L.orc_proposal_logpdf.argtypes = [_d, _d, _d]
         L.orc_proposal_logpdf.restype = _d
+        L.orc_mlp_forward_bound.argtypes = [_p, _p, _p, _p]
+        L.orc_mlp_forward_bound.restype = None
+        L.orc_learn_gauss.argtypes = [_u64, _u32, _u32, _u32, _u32]
+        L.orc_learn_gauss.restype = _d
+        L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
+                                         _p, _d, _p, ctypes.c_uint64, _p]
+        L.orc_sa_run_capture.restype = _i
         _lib = L
     return _lib
 
@@ -253,12 +260,12 @@ def mlp_nparam() -> int:
     return lib().orc_mlp_nparam()
 
 
-def gelu(a: float) -> float:
-    return lib().orc_gelu(a)
+def act(a: float) -> float:
+    return lib().orc_act(a)
 
 
-def gelu_grad(a: float) -> float:
-    return lib().orc_gelu_grad(a)
+def act_grad(a: float) -> float:
+    return lib().orc_act_grad(a)
 
 
 def mlp_forward(params, z):
@@ -303,3 +310,41 @@ def mlp_unpack(params):
         out.append(p[o:o + sz].reshape(sh))
         o += sz
     return out
+
+
+def mlp_forward_bound(params, z):
+    """(mu, s) and the per-output error bound of a BF16-activation evaluation."""
+    p = _f64(params)
+    zz = _f64(z)
+    out = np.zeros(2)
+    bound = np.zeros(2)
+    lib().orc_mlp_forward_bound(_ptr(p), _ptr(zz), _ptr(out), _ptr(bound))
+    return out, bound
+
+
+def learn_gauss(seed, problem, level, chain, step) -> float:
+    """Standard normal draw of a learned move (Box-Muller, Philox tag 3)."""
+    return lib().orc_learn_gauss(seed, problem, level, chain, step)
+
+
+def feature_tau(func, n):
+    """Scale of the temperature feature ln(tau T): n for the objectives
+    normalised by n (Schwefel, Ackley), 1 for Rastrigin."""
+    return 1.0 if func == RASTRIGIN else float(n)
+
+
+def sa_run_capture(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, level_begin=0,
+                   x_start=None, radius_frac=0.1, move_rule=MOVE_RADIUS, problem=0, capacity=1 << 20):
+    """Synchronous run over levels [level_begin, level_begin+levels) that
+    records every accepted move; returns (records float32 [k, 7], count)."""
+    lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
+    n = lo.size
+    xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
+    rec = np.zeros((capacity, 7), dtype=np.float32)
+    cnt = ctypes.c_uint64()
+    rc = lib().orc_sa_run_capture(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
+                                  radius_frac, move_rule, level_begin, levels, _ptr(xs), feature_tau(func, n),
+                                  _ptr(rec), capacity, ctypes.byref(cnt))
+    if rc != 0:
+        raise RuntimeError(f"orc_sa_run_capture failed: {rc}")
+    return rec[:min(cnt.value, capacity)], cnt.value

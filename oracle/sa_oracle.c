@@ -268,10 +268,38 @@ typedef struct {
     int move_rule;
 } orc_problem;
 
+/* Capture sink: while set (orc_sa_run_capture), every accepted move appends
+ * one record -- the learned proposal's features at the old state and the
+ * accepted scaled displacement -- in chain order, then step order. */
+static struct {
+    float *rec;
+    uint64_t capacity, count;
+    double tau;
+} capture_sink;
+
+static void capture_move(const orc_problem *p, double T, uint32_t d, double xd, double xn, double hist[4])
+{
+    const double w = p->upper[d] - p->lower[d];
+    const double dl = (xn - xd) / w;
+    if (capture_sink.count < capture_sink.capacity) {
+        float *r = capture_sink.rec + capture_sink.count * 7;
+        r[0] = (float)((xd - p->lower[d]) / w);
+        r[1] = (float)log(capture_sink.tau * T);
+        for (int k = 0; k < 4; ++k) r[2 + k] = (float)hist[k];
+        r[6] = (float)dl;
+    }
+    capture_sink.count += 1;
+    hist[3] = hist[2];
+    hist[2] = hist[1];
+    hist[1] = hist[0];
+    hist[0] = dl;
+}
+
 static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, double T, double *x,
                           orc_cost *c)
 {
     uint64_t accepted = 0;
+    double hist[4] = {0.0, 0.0, 0.0, 0.0};
     for (uint32_t step = 0; step < p->steps; ++step) {
         uint32_t d;
         double u1, u2;
@@ -282,6 +310,7 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
         double sd = p->shift ? p->shift[d] : 0.0;
         double df = cost_delta(p->func, p->n, c, xd, xn, sd, &cn);
         if (orc_accept(df, T, u2)) {
+            if (capture_sink.rec) capture_move(p, T, d, xd, xn, hist);
             x[d] = xn;
             *c = cn;
             ++accepted;
@@ -373,6 +402,35 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
 }
 
 /*
+ * orc_sa_run that also records every accepted move into rec (capacity x 7
+ * floats: (x_d - l_d)/(u_d - l_d), ln(tau T), the chain's last four accepted
+ * scaled displacements (most recent first, zero at each level start), and
+ * the accepted scaled displacement (x'_d - x_d)/(u_d - l_d)); *count gets the
+ * number of accepted moves (records beyond capacity are dropped).
+ */
+int orc_sa_run_capture(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+                       uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
+                       double radius_frac, int move_rule, uint32_t level_begin, uint32_t count, double *x_start,
+                       double tau, float *rec, uint64_t capacity, uint64_t *n_captured)
+{
+    double *x_rec = (double *)malloc(sizeof(double) * n);
+    double f_rec = INFINITY;
+    uint32_t rec_level = 0;
+    if (!x_rec) return -2;
+    capture_sink.rec = rec;
+    capture_sink.capacity = capacity;
+    capture_sink.count = 0;
+    capture_sink.tau = tau;
+    int rc = orc_sa_run(func, n, lower, upper, shift, seed, problem, chains, steps, T0, alpha, radius_frac, move_rule,
+                        1, level_begin, count, x_start, NULL, x_rec, &f_rec, &rec_level, NULL, NULL, NULL, NULL, NULL,
+                        NULL, NULL);
+    *n_captured = capture_sink.count;
+    capture_sink.rec = NULL;
+    free(x_rec);
+    return rc;
+}
+
+/*
  * Replay one level for chains [chain0, chain0 + nchains) starting from x_start
  * (cost state recomputed in full), and log every move:
  *   log_d[m], log_xold[m], log_xnew[m], log_df[m], log_acc[m]
@@ -425,11 +483,12 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 /* Gaussian over its scaled displacement.  FP64 reference of its forward     */
 /* pass, negative log-likelihood loss, gradient and Adam step.               */
 /*                                                                          */
-/* Features z (6): z0 = (x_d - l_d)/(u_d - l_d); z1 = ln T; z2..z5 = the     */
-/* chain's last four accepted scaled displacements, most recent first.       */
-/* Network: a1 = z W1 + b1 (6x128), h1 = gelu(a1); a2 = h1 W2 + b2 (128x128), */
-/* h2 = gelu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma.        */
-/* gelu(a) = a/2 (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) (tanh form).      */
+/* Features z (6): z0 = (x_d - l_d)/(u_d - l_d); z1 = ln(tau T), tau = n    */
+/* for the objectives normalised by n (Schwefel, Ackley: a one-coordinate    */
+/* change moves f by O(1/n)) and 1 for Rastrigin; z2..z5 = the chain's last  */
+/* four accepted scaled displacements, most recent first.                    */
+/* Network: a1 = z W1 + b1 (6x128), h1 = relu(a1); a2 = h1 W2 + b2 (128x128), */
+/* h2 = relu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma.        */
 /* Loss of a record (z, delta): s + (delta - mu)^2 / (2 exp(2 s)).           */
 /* Parameter vector order: W1 (row-major, [in][out]), b1, W2, b2, W3, b3.    */
 /* ======================================================================== */
@@ -439,20 +498,10 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 
 uint32_t orc_mlp_nparam(void) { return ORC_NPARAM; }
 
-double orc_gelu(double a)
-{
-    const double c = 0.79788456080286535588; /* sqrt(2/pi) */
-    return 0.5 * a * (1.0 + tanh(c * (a + 0.044715 * a * a * a)));
-}
+double orc_act(double a) { return a > 0.0 ? a : 0.0; }
 
-double orc_gelu_grad(double a)
-{
-    const double c = 0.79788456080286535588;
-    double u = c * (a + 0.044715 * a * a * a);
-    double t = tanh(u);
-    double du = c * (1.0 + 3.0 * 0.044715 * a * a);
-    return 0.5 * (1.0 + t) + 0.5 * a * (1.0 - t * t) * du;
-}
+/* Derivative of relu, taken as 0 at a = 0. */
+double orc_act_grad(double a) { return a > 0.0 ? 1.0 : 0.0; }
 
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3;
@@ -479,13 +528,13 @@ void orc_mlp_forward(const double *params, const double *z, double *out2, double
         double s = m.b1[j];
         for (int i = 0; i < ORC_NIN; ++i) s += z[i] * m.W1[i * ORC_H + j];
         a1[j] = s;
-        h1[j] = orc_gelu(s);
+        h1[j] = orc_act(s);
     }
     for (int j = 0; j < ORC_H; ++j) {
         double s = m.b2[j];
         for (int i = 0; i < ORC_H; ++i) s += h1[i] * m.W2[i * ORC_H + j];
         a2[j] = s;
-        h2[j] = orc_gelu(s);
+        h2[j] = orc_act(s);
     }
     for (int k = 0; k < 2; ++k) {
         double s = m.b3[k];
@@ -511,8 +560,8 @@ double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, 
         double a1[ORC_H], a2[ORC_H], h1[ORC_H], h2[ORC_H], o[2];
         orc_mlp_forward(params, z, o, a1, a2);
         for (int j = 0; j < ORC_H; ++j) {
-            h1[j] = orc_gelu(a1[j]);
-            h2[j] = orc_gelu(a2[j]);
+            h1[j] = orc_act(a1[j]);
+            h2[j] = orc_act(a2[j]);
         }
         const double mu = o[0], s = o[1];
         const double e = delta[r] - mu;
@@ -528,7 +577,7 @@ double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, 
             gW3[i * 2 + 0] += h2[i] * dmu;
             gW3[i * 2 + 1] += h2[i] * ds;
             dh2[i] = m.W3[i * 2 + 0] * dmu + m.W3[i * 2 + 1] * ds;
-            da2[i] = dh2[i] * orc_gelu_grad(a2[i]);
+            da2[i] = dh2[i] * orc_act_grad(a2[i]);
         }
         for (int j = 0; j < ORC_H; ++j) gb2[j] += da2[j];
         for (int i = 0; i < ORC_H; ++i) {
@@ -538,7 +587,7 @@ double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, 
                 acc += m.W2[i * ORC_H + j] * da2[j];
             }
             dh1[i] = acc;
-            da1[i] = dh1[i] * orc_gelu_grad(a1[i]);
+            da1[i] = dh1[i] * orc_act_grad(a1[i]);
         }
         for (int j = 0; j < ORC_H; ++j) gb1[j] += da1[j];
         for (int i = 0; i < ORC_NIN; ++i)
@@ -558,6 +607,46 @@ void orc_adam_step(double *params, const double *grad, double *m, double *v, uin
         const double mh = m[i] / c1, vh = v[i] / c2;
         params[i] -= lr * mh / (sqrt(vh) + eps);
     }
+}
+
+/* Forward pass plus, per output, a first-order bound on how far an
+ * evaluation may land from it when it rounds each hidden activation to BF16
+ * (relative error at most u = 2^-9) and computes everything else in FP32:
+ * relu is 1-Lipschitz, so a rounding of h1_i moves a2_j by at most
+ * u |W2_ij h1_i|, and o_k moves by at most
+ *   u sum_j |W3_jk| (|h2_j| + sum_i |W2_ij| |h1_i|),
+ * doubled here to cover second-order terms, FP32 accumulation and the
+ * ~2^-17 rounding of the features. */
+void orc_mlp_forward_bound(const double *params, const double *z, double *out2, double *bound2)
+{
+    orc_mlp m = mlp_view(params);
+    double a1[ORC_H], a2[ORC_H];
+    orc_mlp_forward(params, z, out2, a1, a2);
+    double prop[ORC_H]; /* sum_i |W2_ij| |h1_i| */
+    for (int j = 0; j < ORC_H; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < ORC_H; ++i) t += fabs(m.W2[i * ORC_H + j]) * fabs(orc_act(a1[i]));
+        prop[j] = t;
+    }
+    const double u = ldexp(1.0, -9);
+    for (int k = 0; k < 2; ++k) {
+        double t = 0.0;
+        for (int j = 0; j < ORC_H; ++j) t += fabs(m.W3[j * 2 + k]) * (fabs(orc_act(a2[j])) + prop[j]);
+        bound2[k] = 2.0 * u * t;
+    }
+}
+
+/* Standard normal draw of a learned move: Box-Muller on the first two words
+ * (U0, U1) of the Philox block (step, level, chain, 3 | problem << 8):
+ * g = sqrt(-2 ln(1 - U0)) cos(2 pi U1). */
+double orc_learn_gauss(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
+{
+    const uint32_t ctr[4] = {step, level, chain, 3u | (problem << 8)};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t r[4];
+    orc_philox4x32_10(ctr, key, r);
+    const double u0 = orc_uniform(r[0]), u1 = orc_uniform(r[1]);
+    return sqrt(-2.0 * log(1.0 - u0)) * cos(2.0 * ORC_PI * u1);
 }
 
 /* Log density of the proposal, in scaled units: ln N(delta; mu, sigma^2). */

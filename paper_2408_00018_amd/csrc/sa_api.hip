@@ -8,6 +8,7 @@
 // level's candidates to the winner on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -21,6 +22,7 @@
 
 #include "sa_host.hpp"
 #include "sa_internal.hpp"
+#include "sa_mlp_net.hpp"
 
 namespace sa {
 thread_local std::string g_last_error;
@@ -34,18 +36,21 @@ using sa::kAlign;
 using sa::kLdsPerWorkgroup;
 
 // Largest workgroup (4, 2 or 1 waves) that divides `chains` and whose state
-// fits in LDS.  0 if none fits.
-uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, size_t lds_limit)
+// (and, for learned runs, the packed network) fits in LDS.  0 if none fits.
+uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, bool learn, size_t lds_limit)
 {
     for (uint32_t wg = 256; wg >= 64; wg >>= 1) {
         if (chains % wg) continue;
-        if (sa::level_lds_bytes(n, wg, real_size, table) <= lds_limit) return wg;
+        if (sa::level_lds_bytes(n, wg, real_size, table, learn) <= lds_limit) return wg;
     }
     return 0;
 }
 
+constexpr uint32_t kNoStart = 0xFFFFFFFFu;
+
 struct Layout {
-    size_t table, T, inv_T, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final, total;
+    size_t table, T, inv_T, featT, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final;
+    size_t x_start, theta, net, cap_count, total;
 };
 
 struct Plan {
@@ -64,7 +69,10 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH)) return fail(SA_ERR_INVALID, "unknown flag bits");
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED))
+        return fail(SA_ERR_INVALID, "unknown flag bits");
+    if ((c->flags & SA_FLAG_LEARNED) && (c->precision != SA_FP32 || c->move != SA_MOVE_RADIUS))
+        return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs in FP32 with the radius move as its plain part");
     if (c->log_chains) {
         if (c->log_chains > c->chains) return fail(SA_ERR_INVALID, "log_chains exceeds chains");
         if (c->log_levels == 0 || c->log_level >= c->levels || c->log_levels > c->levels - c->log_level)
@@ -87,7 +95,8 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     Plan pl;
     pl.table = !uniform_box(p);
     pl.real = c->precision == SA_FP64 ? sizeof(double) : sizeof(float);
-    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, lds_limit);
+    const bool learn = (c->flags & SA_FLAG_LEARNED) != 0;
+    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, lds_limit);
     if (pl.wg == 0)
         return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
     pl.groups = c->chains / pl.wg;
@@ -102,6 +111,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.table = take(pl.table ? 4 * n * R : 0);
     l.T = take(L * sizeof(double));
     l.inv_T = take(L * sizeof(float));
+    l.featT = take(L * sizeof(float));
     l.x_best = take(n * R);
     // candidates are double-buffered by level parity; at most one per tile
     l.slots = take(2 * (size_t)pl.groups * sizeof(sa::Slot<double>));
@@ -114,6 +124,10 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     const size_t log_moves = c->log_chains ? (size_t)c->log_levels * c->log_chains * c->steps : 0;
     l.log = take(log_moves * sizeof(sa_move_rec));
     l.log_final = take(c->log_chains ? (size_t)c->log_levels * c->chains * sizeof(double) : 0);
+    l.x_start = take(n * R);
+    l.theta = take(learn ? sa::mlp::kNumParams * sizeof(float) : 0);
+    l.net = take(learn ? sa::mlp::kNetBytes : 0);
+    l.cap_count = take(sizeof(unsigned long long));
     l.total = off;
     *out = pl;
     return SA_OK;
@@ -134,7 +148,10 @@ struct sa_ctx {
     uint32_t next_level = 0;
     uint64_t seed = 0;
     uint32_t groups = 0;  // candidates published by the last level enqueued
+    uint32_t first_level = 0;  // first level of the current run (the start level, or 0)
     bool fp64 = false;
+    bool learned = false;  // a proposal network is set
+    bool capturing = false;  // accepted moves are being recorded
     sa::LevelArgs<float> a32{};
     sa::LevelArgs<double> a64{};
     struct Graph {
@@ -177,7 +194,19 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.log_chains = c->cfg.log_chains;
     a.log_level = c->cfg.log_level;
     a.log_levels = c->cfg.log_chains ? c->cfg.log_levels : 0;
+    a.x_start = reinterpret_cast<const R *>(w + l.x_start);
+    a.start_level = kNoStart;
+    a.featT = reinterpret_cast<const float *>(w + l.featT);
+    a.net = (c->cfg.flags & SA_FLAG_LEARNED) ? w + l.net : nullptr;
+    a.eps = 1.0f;
+    a.cap_rec = nullptr;
+    a.cap_count = reinterpret_cast<unsigned long long *>(w + l.cap_count);
+    a.cap_capacity = 0;
 }
+
+// Temperature feature of the proposal network: ln(tau T), tau = n for the
+// objectives normalised by n (Schwefel, Ackley), 1 for Rastrigin.
+double feature_tau(const sa_problem &p) { return p.func == SA_RASTRIGIN ? 1.0 : (double)p.n; }
 
 // Box/shift values of coordinate i in the run's precision: (l, u, rho, s).
 void coord_values(const sa_ctx *c, uint32_t i, double out[4])
@@ -191,15 +220,18 @@ sa_status upload_tables(sa_ctx *c)
     const Layout &l = c->pl.lay;
     const uint32_t n = c->prob.n, L = c->cfg.levels;
     std::vector<double> T(L);
-    std::vector<float> inv_T(L);
+    std::vector<float> inv_T(L), featT(L);
+    const double tau = feature_tau(c->prob);
     double t = c->cfg.T0;
     for (uint32_t k = 0; k < L; ++k) {
         T[k] = t;
         inv_T[k] = (float)(1.0 / t);
+        featT[k] = (float)std::log(tau * t);
         t = t * c->cfg.alpha;
     }
     SA_HIP(hipMemcpyAsync(c->ws + l.T, T.data(), L * sizeof(double), hipMemcpyHostToDevice, c->stream));
     SA_HIP(hipMemcpyAsync(c->ws + l.inv_T, inv_T.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipMemcpyAsync(c->ws + l.featT, featT.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
     double v[4];
     if (c->pl.table) {
         if (c->fp64) {
@@ -247,9 +279,11 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
     const uint32_t lg0 = c->cfg.log_level, lg1 = c->cfg.log_chains ? c->cfg.log_level + c->cfg.log_levels : 0;
     for (uint32_t k = first; k < first + count; ++k) {
         const bool log = k >= lg0 && k < lg1;
+        const int mode = c->learned ? (log ? sa::kModeLearnLog : sa::kModeLearn)
+                                    : (log ? sa::kModeLog : (c->capturing ? sa::kModeCapture : sa::kModePlain));
         uint32_t g = 0;
-        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
-                               : sa::launch_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
+        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, mode, c->a64, k, *groups, &g, s)
+                               : sa::launch_level_f32(c->prob.func, c->pl.table, mode, c->a32, k, *groups, &g, s);
         if (e != hipSuccess) return fail(SA_ERR_DEVICE, "level %u launch: %s", k, hipGetErrorString(e));
         *groups = g;
     }
@@ -276,6 +310,11 @@ sa_status enqueue_reset(sa_ctx *c)
     if (e != hipSuccess) return fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
     c->groups = 0;
     c->next_level = 0;
+    c->first_level = 0;
+    if (c->a32.start_level != kNoStart || c->a64.start_level != kNoStart) {
+        drop_graphs(c);  // captured launches hold the start level
+        c->a32.start_level = c->a64.start_level = kNoStart;
+    }
     return SA_OK;
 }
 
@@ -480,6 +519,8 @@ sa_status sa_trace(sa_ctx *c, uint32_t first, uint32_t count, sa_level *out, dou
     if (first >= c->next_level || count > c->next_level - first)
         return fail(SA_ERR_STATE, "levels [%u, %u) have not all run (%u done)", first, first + count,
                     c->next_level);
+    if (first < c->first_level)
+        return fail(SA_ERR_STATE, "the run started at level %u; level %u has no trace", c->first_level, first);
     if (x_best && !(c->cfg.flags & SA_FLAG_TRACE_X))
         return fail(SA_ERR_STATE, "x_best trace needs SA_FLAG_TRACE_X");
     SA_HIP(hipStreamSynchronize(c->stream));
@@ -516,6 +557,91 @@ sa_status sa_move_log(sa_ctx *c, sa_move_rec *moves, double *final_f)
     if (final_f)
         SA_HIP(hipMemcpy(final_f, c->ws + l.log_final, (size_t)c->cfg.log_levels * c->cfg.chains * sizeof(double),
                          hipMemcpyDeviceToHost));
+    return SA_OK;
+}
+
+sa_status sa_set_start(sa_ctx *c, uint32_t level, const double *x)
+{
+    sa::g_last_error.clear();
+    if (!c || !x) return fail(SA_ERR_INVALID, "null argument");
+    if (c->next_level != 0) return fail(SA_ERR_STATE, "a start state is set before the first level (after sa_reset)");
+    if (level == 0 || level >= c->cfg.levels)
+        return fail(SA_ERR_INVALID, "start level must be in [1, %u)", c->cfg.levels);
+    const uint32_t n = c->prob.n;
+    for (uint32_t i = 0; i < n; ++i)
+        if (!(x[i] >= c->lower[i] && x[i] <= c->upper[i]))
+            return fail(SA_ERR_INVALID, "start coordinate %u lies outside the box", i);
+    const Layout &l = c->pl.lay;
+    if (c->fp64) {
+        SA_HIP(hipMemcpyAsync(c->ws + l.x_start, x, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    } else {
+        std::vector<float> xf(n);
+        for (uint32_t i = 0; i < n; ++i) {
+            // the FP32 box is the FP64 box rounded inward
+            const float lo = sa::round_up_f(c->lower[i]), hi = sa::round_down_f(c->upper[i]);
+            xf[i] = std::min(std::max((float)x[i], lo), hi);
+        }
+        SA_HIP(hipMemcpyAsync(c->ws + l.x_start, xf.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    }
+    SA_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->a32.start_level = c->a64.start_level = level;
+    c->next_level = c->first_level = level;
+    c->groups = 0;
+    return SA_OK;
+}
+
+sa_status sa_set_proposal(sa_ctx *c, const float *params, float eps)
+{
+    sa::g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (!(c->cfg.flags & SA_FLAG_LEARNED)) return fail(SA_ERR_STATE, "the context was created without SA_FLAG_LEARNED");
+    if (!params) {
+        if (c->learned) drop_graphs(c);
+        c->learned = false;
+        return SA_OK;
+    }
+    if (!(eps >= 0.0f && eps <= 1.0f)) return fail(SA_ERR_INVALID, "eps must lie in [0, 1]");
+    if (c->capturing) return fail(SA_ERR_STATE, "capture records plain runs; stop it (sa_capture(NULL)) first");
+    for (uint32_t i = 0; i < sa::mlp::kNumParams; ++i)
+        if (!std::isfinite(params[i])) return fail(SA_ERR_INVALID, "parameter %u is not finite", i);
+    const Layout &l = c->pl.lay;
+    float *theta = reinterpret_cast<float *>(c->ws + l.theta);
+    SA_HIP(hipMemcpyAsync(theta, params, sa::mlp::kNumParams * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    hipError_t e = sa::launch_pack_net(theta, c->ws + l.net, c->stream);
+    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "pack launch: %s", hipGetErrorString(e));
+    SA_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->a32.eps = eps;
+    c->learned = true;
+    return SA_OK;
+}
+
+sa_status sa_capture(sa_ctx *c, float *records, uint64_t capacity)
+{
+    sa::g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (records && capacity == 0) return fail(SA_ERR_INVALID, "capacity must be positive");
+    if (records && reinterpret_cast<uintptr_t>(records) % sizeof(float))
+        return fail(SA_ERR_INVALID, "records must be float-aligned");
+    if (records && c->learned) return fail(SA_ERR_STATE, "capture records plain runs; clear the proposal first");
+    drop_graphs(c);
+    c->a32.cap_rec = records;
+    c->a64.cap_rec = records;
+    c->a32.cap_capacity = c->a64.cap_capacity = records ? capacity : 0;
+    c->capturing = records != nullptr;
+    SA_HIP(hipMemsetAsync(c->ws + c->pl.lay.cap_count, 0, sizeof(unsigned long long), c->stream));
+    return SA_OK;
+}
+
+sa_status sa_capture_count(sa_ctx *c, uint64_t *count)
+{
+    sa::g_last_error.clear();
+    if (!c || !count) return fail(SA_ERR_INVALID, "null argument");
+    SA_HIP(hipStreamSynchronize(c->stream));
+    unsigned long long v = 0;
+    SA_HIP(hipMemcpy(&v, c->ws + c->pl.lay.cap_count, sizeof v, hipMemcpyDeviceToHost));
+    *count = v;
     return SA_OK;
 }
 

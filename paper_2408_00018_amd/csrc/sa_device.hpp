@@ -52,6 +52,7 @@ __device__ __forceinline__ Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1)
 
 constexpr uint32_t kTagMove = 0u;
 constexpr uint32_t kTagInit = 1u;
+constexpr uint32_t kTagLearn = 3u;  // Gaussian draws of the learned proposal
 constexpr uint32_t kInitLevel = 0xFFFFFFFFu;
 
 // Uniform in [0,1) from the top 24 bits (exact in FP32 and FP64).
@@ -71,11 +72,13 @@ __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrt
 // sin(2 pi t) and cos(2 pi t): the hardware instructions take revolutions.
 __device__ __forceinline__ float hw_sin_rev(float t) { return __builtin_amdgcn_sinf(t); }
 __device__ __forceinline__ float hw_cos_rev(float t) { return __builtin_amdgcn_cosf(t); }
-// 2^t
+// 2^t and log2(t)
 __device__ __forceinline__ float hw_exp2(float t) { return __builtin_amdgcn_exp2f(t); }
+__device__ __forceinline__ float hw_log2(float t) { return __builtin_amdgcn_logf(t); }
 
 constexpr float kInv2Pi = 0.159154943091895335768883763372514362f;
 constexpr float kLog2e = 1.44269504088896340735992468100189214f;
+constexpr float kLn2 = 0.693147180559945309417232121458176568f;
 constexpr double kPi = 3.14159265358979323846;
 constexpr double kE = 2.71828182845904523536;
 

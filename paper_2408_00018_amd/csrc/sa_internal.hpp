@@ -55,14 +55,34 @@ template <typename R> struct LevelArgs {
     sa_move_rec *log;    // move log, or nullptr
     double *log_final;   // per-chain final cost at logged levels
     uint32_t log_chains, log_level, log_levels;
+    // Start state: at level start_level (>= 1; ~0 = none) every chain starts
+    // from x_start instead of the previous level's winner.
+    const R *x_start;
+    uint32_t start_level;
+    // Learned proposal and capture of accepted moves.
+    const float *featT;         // per level: ln(tau T_k), the network's temperature feature
+    const unsigned char *net;   // packed network (global memory), learned modes
+    float eps;                  // probability of a plain move in the learned mixture
+    float *cap_rec;             // captured records, 7 floats each
+    unsigned long long *cap_count;  // accepted moves seen by the capture
+    uint64_t cap_capacity;      // records cap_rec holds
+};
+
+// What a level launch does besides the plain steps.
+enum LevelMode : int {
+    kModePlain = 0,
+    kModeLog = 1,       // log every move of the logged chains
+    kModeCapture = 2,   // record every accepted move (features, scaled displacement)
+    kModeLearn = 3,     // learned-proposal mixture (FP32, radius moves)
+    kModeLearnLog = 4,  // learned mixture with the move log
 };
 
 // Host-side launchers.  A level launch runs one level and publishes one
 // candidate per workgroup; *groups returns how many (the next level's launch,
 // or the finalising launch, reduces them).
-hipError_t launch_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
+hipError_t launch_level_f32(int func, bool table, int mode, const LevelArgs<float> &a, uint32_t level,
                             uint32_t prev_groups, uint32_t *groups, hipStream_t s);
-hipError_t launch_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
+hipError_t launch_level_f64(int func, bool table, int mode, const LevelArgs<double> &a, uint32_t level,
                             uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 // Publish level `level` (trace entry, record, broadcast state) from its candidates.
 hipError_t launch_finalize_f32(const LevelArgs<float> &a, uint32_t level, uint32_t groups, hipStream_t s);
@@ -70,8 +90,8 @@ hipError_t launch_finalize_f64(const LevelArgs<double> &a, uint32_t level, uint3
 // Reset the record (a kernel, so it can be captured in a graph).
 hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s);
 
-// Dynamic LDS bytes of a level launch.
-size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table);
+// Dynamic LDS bytes of a level launch (learn: the packed network as well).
+size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn);
 
 }  // namespace sa
 

@@ -166,14 +166,17 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
 
 // ---------------------------------------------------------------------------
 // The level kernel.  prev_groups: candidates the previous level's launch
-// published (unused at level 0).
-// LDS: xs[n][WG] tile states | xw[n] level start | xb[n] workgroup best |
-//      tab[n][4] per-coordinate box/shift (TABLE only)
+// published (unused at level 0 and at the start level).
+// LDS: [net (learned modes)] | xs[n][WG] tile states | xw[n] level start |
+//      xb[n] workgroup best | tab[n][4] per-coordinate box/shift (TABLE only)
 // ---------------------------------------------------------------------------
-template <typename R, int F, bool TABLE, bool LOG, int MOVE>
+template <typename R, int F, bool TABLE, int MODE, int MOVE>
 __global__ void __launch_bounds__(256)
     level_kernel(const LevelArgs<R> a, const uint32_t level, const uint32_t prev_groups)
 {
+    constexpr bool LOG = MODE == kModeLog || MODE == kModeLearnLog;
+    constexpr bool LEARN = MODE == kModeLearn || MODE == kModeLearnLog;
+    constexpr bool CAPTURE = MODE == kModeCapture;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Slot<R> wave_slot[4];
     __shared__ uint64_t wave_acc[4];
@@ -186,21 +189,35 @@ __global__ void __launch_bounds__(256)
     const uint32_t nwaves = WG >> 6;
     const uint32_t G = gridDim.x;
     const uint32_t n = a.n;
-    R *xs = reinterpret_cast<R *>(lds_raw);
+    unsigned char *net_lds = lds_raw;
+    R *xs = reinterpret_cast<R *>(lds_raw + (LEARN ? mlp::kNetBytes : 0u));
     R *xw = xs + (size_t)n * WG;
     R *xb = xw + n;
     R *tab = xb + n;
 
+    if (LEARN) mlp::stage_net(net_lds, a.net);
     if (TABLE) {
         for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
     }
-    if (level > 0) adopt_winner<R>(a, level - 1, prev_groups, xw, sh_start, blockIdx.x == 0, wave_slot, wave_acc);
+    if (level == a.start_level) {
+        for (uint32_t i = tid; i < n; i += WG) xw[i] = a.x_start[i];
+        __syncthreads();
+        const Full v = full_eval_wg<R, F, TABLE>(a, tab, xw, sh_part);
+        if (tid == 0) {
+            sh_start[0] = v.f;
+            sh_start[1] = v.s1;
+            sh_start[2] = v.s2;
+        }
+    } else if (level > 0) {
+        adopt_winner<R>(a, level - 1, prev_groups, xw, sh_start, blockIdx.x == 0, wave_slot, wave_acc);
+    }
     __syncthreads();
 
     const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
     const double T = a.T[level];
     const float nl2T = -kLog2e * a.inv_T[level];
+    const float featT = (LEARN || CAPTURE) ? a.featT[level] : 0.0f;
     const bool log_level = LOG && level >= a.log_level && level - a.log_level < a.log_levels;
     const Full start{sh_start[0], sh_start[1], sh_start[2]};
     R wf = widen_inf<R>();
@@ -209,7 +226,7 @@ __global__ void __launch_bounds__(256)
 
     for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += G) {
         const uint32_t chain = tile * WG + tid;
-        // ---- tile start: own random point at level 0, else the winner
+        // ---- tile start: own random point at level 0, else the level's start state
         Cost<R, F> cost;
         if (level == 0) {
             FullAcc<F> acc;
@@ -231,7 +248,7 @@ __global__ void __launch_bounds__(256)
             cost.set(start, n);
         }
 
-        // ---- N Metropolis steps
+        // ---- N steps
         const bool logging = log_level && chain < a.log_chains;
         const auto coordf = [&](uint32_t d) { return coord<R, TABLE>(a, tab, d); };
         const auto logf = [&](uint32_t step, uint32_t d, bool take, R xd, R xn, R df) {
@@ -245,8 +262,54 @@ __global__ void __launch_bounds__(256)
                 a.log[((size_t)(level - a.log_level) * a.log_chains + chain) * a.steps + step] = m;
             }
         };
-        accepted += run_steps<R, F, MOVE>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3, k0, k1, T,
-                                          nl2T, a.inv_n);
+        R hist[4] = {R(0), R(0), R(0), R(0)};  // last four accepted scaled displacements
+        if constexpr (LEARN) {
+            float h[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            accepted += run_learned_steps<F>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3,
+                                             kTagLearn | (a.problem << 8), k0, k1, nl2T, a.inv_n, featT, a.eps,
+                                             net_lds, h);
+        } else if constexpr (CAPTURE) {
+            // Record (features at x, scaled displacement) of every accepted move;
+            // one counter update per wave and step.
+            const auto capf = [&](uint32_t, uint32_t d, bool take, R xd, R xn, R) {
+                const Coord<R> c = coordf(d);
+                const R w = c.hi - c.lo;
+                const R z0 = (xd - c.lo) / w;
+                const R dl = (xn - xd) / w;
+                const uint64_t mask = __ballot(take);
+                if (mask) {
+                    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1u;
+                    unsigned long long base = 0;
+                    if (lane == leader) base = atomicAdd(a.cap_count, (unsigned long long)__popcll(mask));
+                    const uint32_t lo = __shfl((uint32_t)base, (int)leader, 64);
+                    const uint32_t hi = __shfl((uint32_t)(base >> 32), (int)leader, 64);
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    const uint64_t slot = (((uint64_t)hi << 32) | lo) + rank;
+                    if (take && slot < a.cap_capacity) {
+                        float *rec = a.cap_rec + slot * 7u;
+                        rec[0] = (float)z0;
+                        rec[1] = featT;
+                        rec[2] = (float)hist[0];
+                        rec[3] = (float)hist[1];
+                        rec[4] = (float)hist[2];
+                        rec[5] = (float)hist[3];
+                        rec[6] = (float)dl;
+                    }
+                }
+                if (take) {
+                    hist[3] = hist[2];
+                    hist[2] = hist[1];
+                    hist[1] = hist[0];
+                    hist[0] = dl;
+                }
+            };
+            accepted += run_steps<R, F, MOVE>(xs, WG, tid, cost, coordf, capf, n, a.steps, level, chain, ctr3, k0,
+                                              k1, T, nl2T, a.inv_n);
+        } else {
+            accepted += run_steps<R, F, MOVE>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3, k0,
+                                              k1, T, nl2T, a.inv_n);
+        }
         if (LOG && log_level) a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
 
         // ---- tile argmin of (final cost, chain); keep the workgroup's best
@@ -305,17 +368,19 @@ __global__ void reset_kernel(double *rec, uint32_t *rec_level)
     }
 }
 
-size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table)
+size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn)
 {
-    return ((size_t)n * wg + 2 * (size_t)n + (table ? 4 * (size_t)n : 0)) * real_size;
+    return ((size_t)n * wg + 2 * (size_t)n + (table ? 4 * (size_t)n : 0)) * real_size +
+           (learn ? (size_t)mlp::kNetBytes : 0);
 }
 
-template <typename R, int F, bool TABLE, bool LOG, int MOVE>
+template <typename R, int F, bool TABLE, int MODE, int MOVE>
 static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, uint32_t prev_groups, uint32_t *groups,
                              hipStream_t s)
 {
-    auto kern = level_kernel<R, F, TABLE, LOG, MOVE>;
-    const size_t lds = level_lds_bytes(a.n, a.wg, sizeof(R), TABLE);
+    auto kern = level_kernel<R, F, TABLE, MODE, MOVE>;
+    const size_t lds =
+        level_lds_bytes(a.n, a.wg, sizeof(R), TABLE, MODE == kModeLearn || MODE == kModeLearnLog);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)a.wg, lds);
     if (e != hipSuccess) return e;
@@ -326,46 +391,56 @@ static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, uint32_t pre
     return hipGetLastError();
 }
 
+template <typename R, int F, bool TABLE, int MOVE>
+static hipError_t launch_mode(int mode, const LevelArgs<R> &a, uint32_t level, uint32_t prev, uint32_t *groups,
+                              hipStream_t s)
+{
+    switch (mode) {
+    case kModePlain: return launch_one<R, F, TABLE, kModePlain, MOVE>(a, level, prev, groups, s);
+    case kModeLog: return launch_one<R, F, TABLE, kModeLog, MOVE>(a, level, prev, groups, s);
+    case kModeCapture: return launch_one<R, F, TABLE, kModeCapture, MOVE>(a, level, prev, groups, s);
+    default: break;
+    }
+    if constexpr (sizeof(R) == sizeof(float) && MOVE == SA_MOVE_RADIUS) {
+        if (mode == kModeLearn) return launch_one<R, F, TABLE, kModeLearn, MOVE>(a, level, prev, groups, s);
+        if (mode == kModeLearnLog) return launch_one<R, F, TABLE, kModeLearnLog, MOVE>(a, level, prev, groups, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <typename R, int F>
-static hipError_t dispatch_f(bool table, bool log, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
+static hipError_t dispatch_f(bool table, int mode, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
                              uint32_t *groups, hipStream_t s)
 {
-    if (a.move == SA_MOVE_RADIUS) {
-        if (table)
-            return log ? launch_one<R, F, true, true, SA_MOVE_RADIUS>(a, level, prev, groups, s)
-                       : launch_one<R, F, true, false, SA_MOVE_RADIUS>(a, level, prev, groups, s);
-        return log ? launch_one<R, F, false, true, SA_MOVE_RADIUS>(a, level, prev, groups, s)
-                   : launch_one<R, F, false, false, SA_MOVE_RADIUS>(a, level, prev, groups, s);
-    }
-    if (table)
-        return log ? launch_one<R, F, true, true, SA_MOVE_RESAMPLE>(a, level, prev, groups, s)
-                   : launch_one<R, F, true, false, SA_MOVE_RESAMPLE>(a, level, prev, groups, s);
-    return log ? launch_one<R, F, false, true, SA_MOVE_RESAMPLE>(a, level, prev, groups, s)
-               : launch_one<R, F, false, false, SA_MOVE_RESAMPLE>(a, level, prev, groups, s);
+    if (a.move == SA_MOVE_RADIUS)
+        return table ? launch_mode<R, F, true, SA_MOVE_RADIUS>(mode, a, level, prev, groups, s)
+                     : launch_mode<R, F, false, SA_MOVE_RADIUS>(mode, a, level, prev, groups, s);
+    return table ? launch_mode<R, F, true, SA_MOVE_RESAMPLE>(mode, a, level, prev, groups, s)
+                 : launch_mode<R, F, false, SA_MOVE_RESAMPLE>(mode, a, level, prev, groups, s);
 }
 
 template <typename R>
-static hipError_t dispatch(int func, bool table, bool log, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
+static hipError_t dispatch(int func, bool table, int mode, const LevelArgs<R> &a, uint32_t level, uint32_t prev,
                            uint32_t *groups, hipStream_t s)
 {
     switch (func) {
-    case kSchwefel: return dispatch_f<R, kSchwefel>(table, log, a, level, prev, groups, s);
-    case kRastrigin: return dispatch_f<R, kRastrigin>(table, log, a, level, prev, groups, s);
-    case kAckley: return dispatch_f<R, kAckley>(table, log, a, level, prev, groups, s);
+    case kSchwefel: return dispatch_f<R, kSchwefel>(table, mode, a, level, prev, groups, s);
+    case kRastrigin: return dispatch_f<R, kRastrigin>(table, mode, a, level, prev, groups, s);
+    case kAckley: return dispatch_f<R, kAckley>(table, mode, a, level, prev, groups, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
+hipError_t launch_level_f32(int func, bool table, int mode, const LevelArgs<float> &a, uint32_t level,
                             uint32_t prev_groups, uint32_t *groups, hipStream_t s)
 {
-    return dispatch<float>(func, table, log, a, level, prev_groups, groups, s);
+    return dispatch<float>(func, table, mode, a, level, prev_groups, groups, s);
 }
 
-hipError_t launch_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
+hipError_t launch_level_f64(int func, bool table, int mode, const LevelArgs<double> &a, uint32_t level,
                             uint32_t prev_groups, uint32_t *groups, hipStream_t s)
 {
-    return dispatch<double>(func, table, log, a, level, prev_groups, groups, s);
+    return dispatch<double>(func, table, mode, a, level, prev_groups, groups, s);
 }
 
 hipError_t launch_finalize_f32(const LevelArgs<float> &a, uint32_t level, uint32_t groups, hipStream_t s)

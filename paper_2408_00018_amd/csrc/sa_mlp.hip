@@ -1,8 +1,8 @@
 // Training of the learned proposal network on gfx950 (sa_mlp_* in
 // include/sa.h).
 //
-// Network (per chosen coordinate): z (6 features) -> 128 (GELU, tanh form)
-// -> 128 (GELU) -> 2 outputs (mean and log standard deviation of a Gaussian
+// Network (per chosen coordinate): z (6 features) -> 128 (relu) -> 128
+// (relu) -> 2 outputs (mean and log standard deviation of a Gaussian
 // over the coordinate's scaled displacement); loss = Gaussian negative
 // log-likelihood of accepted displacements.  Master parameters and Adam
 // moments are FP32; the three weight matrices are used in BF16.  The
@@ -19,6 +19,7 @@
 #include "sa_device.hpp"
 #include "sa_host.hpp"
 #include "sa_mlp_common.hpp"
+#include "sa_mlp_net.hpp"
 
 using sa::fail;
 
@@ -26,22 +27,20 @@ namespace {
 
 using namespace sa::mlp;
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ __bf16 bf16_of_bits(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
 
 // k index of element i (0..7) of lane l in a 16x16x32 MFMA operand.
 __device__ __forceinline__ int mfma_k(int lane, int i) { return (lane >> 4) * 8 + i; }
 
-enum Epilogue { kEpiStore = 0, kEpiBiasGelu = 1, kEpiGeluBwd = 2 };
+enum Epilogue { kEpiStore = 0, kEpiBiasAct = 1, kEpiActBwd = 2 };
 
 // C(m, n) = sum_k A(m, k) B(k, n) with A(m,k) = A[m*am + k*ak] and
 // B(k,n) = B[k*bk + n*bn] (BF16 bits), FP32 accumulate; one wave per 16x16
 // tile; M, N multiples of 16, K a multiple of 32.  Epilogues:
 //   kEpiStore     C = acc
-//   kEpiBiasGelu  C = acc + bias[n] (pre-activation), H = gelu(C)
-//   kEpiGeluBwd   C = acc * gelu'(aux(m, n))
+//   kEpiBiasAct  C = acc + bias[n] (pre-activation), H = act(C)
+//   kEpiActBwd   C = acc * relu'(aux(m, n))
 template <int EPI>
 __global__ void __launch_bounds__(256)
     gemm_bf16(int M, int N, int K, const uint16_t *A, int am, int ak, const uint16_t *B, int bk, int bn, float *C,
@@ -68,11 +67,11 @@ __global__ void __launch_bounds__(256)
     for (int j = 0; j < 4; ++j) {
         const int r = (tm << 4) + (lane >> 4) * 4 + j, c = (tn << 4) + (lane & 15);
         float v = acc[j];
-        if (EPI == kEpiBiasGelu) {
+        if (EPI == kEpiBiasAct) {
             v += bias[c];
-            H[(size_t)r * ldc + c] = gelu(v);
+            H[(size_t)r * ldc + c] = bf16_bits_to_f32(f32_to_bf16_bits(act(v)));
         }
-        if (EPI == kEpiGeluBwd) v *= gelu_grad(aux[(size_t)r * ldc + c]);
+        if (EPI == kEpiActBwd) v *= act_grad(aux[(size_t)r * ldc + c]);
         C[(size_t)r * ldc + c] = v;
     }
 }
@@ -88,7 +87,7 @@ __global__ void sample_index(uint32_t *idx, uint32_t batch, uint64_t nrec, uint3
     idx[r] = (uint32_t)__umul64hi(wide, nrec);
 }
 
-// Layer 1 (VALU): gather the minibatch, a1 = z W1 + b1, h1 = gelu(a1) in BF16.
+// Layer 1 (VALU): gather the minibatch, a1 = z W1 + b1, h1 = act(a1) in BF16.
 __global__ void layer1_forward(const float *records, const uint32_t *idx, uint32_t batch, const uint16_t *W1b,
                                const float *b1, float *Z, float *delta, float *A1, uint16_t *H1b)
 {
@@ -100,7 +99,7 @@ __global__ void layer1_forward(const float *records, const uint32_t *idx, uint32
 #pragma unroll
     for (int i = 0; i < kInputs; ++i) a = fmaf(rec[i], bf16_bits_to_f32(W1b[i * kHidden + j]), a);
     A1[(size_t)r * kHidden + j] = a;
-    H1b[(size_t)r * kHidden + j] = f32_to_bf16_bits(gelu(a));
+    H1b[(size_t)r * kHidden + j] = f32_to_bf16_bits(act(a));
     if (j < kInputs) Z[(size_t)r * kInputs + j] = rec[j];
     if (j == kInputs) delta[r] = rec[kInputs];
 }
@@ -136,7 +135,7 @@ __global__ void __launch_bounds__(256) layer3_loss(const float *H2, const float 
     }
     for (uint32_t j = lane; j < kHidden; j += 64) {
         const float dh = bf16_bits_to_f32(W3b[2 * j + 0]) * dmu + bf16_bits_to_f32(W3b[2 * j + 1]) * ds;
-        const float da = dh * gelu_grad(A2[(size_t)r * kHidden + j]);
+        const float da = dh * act_grad(A2[(size_t)r * kHidden + j]);
         dA2[(size_t)r * kHidden + j] = da;
         dA2b[(size_t)r * kHidden + j] = f32_to_bf16_bits(da);
     }
@@ -206,7 +205,51 @@ __global__ void adam_update(float *theta, const float *g, float *m, float *v, fl
     else if (i >= kOffW3 && i < kOffB3) W3b[i - kOffW3] = b;
 }
 
+// Pack theta into MFMA fragment order (one thread per fragment lane) and copy
+// the biases.
+__global__ void pack_net(const float *theta, unsigned char *net)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 44 * 64) {
+        const uint32_t frag = t >> 6, lane = t & 63;
+        uint16_t *dst = reinterpret_cast<uint16_t *>(net + frag * kFrag + 16 * lane);
+#pragma unroll
+        for (uint32_t i = 0; i < 8; ++i) dst[i] = pack_element(theta, frag, lane, i);
+    }
+    float *b = reinterpret_cast<float *>(net + kNetB1);
+    if (t < 2 * kHidden) b[t] = t < kHidden ? theta[kOffB1 + t] : theta[kOffB2 + t - kHidden];
+    if (t < 4) reinterpret_cast<float *>(net + kNetB3)[t] = t < 2 ? theta[kOffB3 + t] : 0.0f;
+}
+
+// (mu, s) for `rows` feature vectors Z[rows][6], one chain per lane as in the
+// annealing kernels.
+__global__ void __launch_bounds__(256) infer_rows(const unsigned char *net, const float *Z, uint32_t rows, float *out)
+{
+    __shared__ __align__(16) unsigned char lds[kNetBytes];
+    stage_net(lds, net);
+    __syncthreads();
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = r < rows;
+    float z[kInputs];
+#pragma unroll
+    for (int i = 0; i < kInputs; ++i) z[i] = live ? Z[(size_t)r * kInputs + i] : 0.0f;
+    float mu, s;
+    net_forward(lds, z, mu, s);
+    if (live) {
+        out[2 * (size_t)r + 0] = mu;
+        out[2 * (size_t)r + 1] = s;
+    }
+}
+
 }  // namespace
+
+namespace sa {
+hipError_t launch_pack_net(const float *theta, unsigned char *net, hipStream_t s)
+{
+    hipLaunchKernelGGL(pack_net, dim3(11), dim3(256), 0, s, theta, net);
+    return hipGetLastError();
+}
+}  // namespace sa
 
 struct sa_mlp {
     hipStream_t stream = nullptr;
@@ -215,6 +258,7 @@ struct sa_mlp {
     float *theta, *g, *m, *v, *Z, *delta, *A1, *A2, *H2, *dA2, *dA1, *loss_r, *dO, *loss;
     uint16_t *W1b, *W2b, *W3b, *H1b, *dA2b;
     uint32_t *idx;
+    unsigned char *net;  // packed copy for inference
     uint32_t t = 0;  // Adam steps taken
 };
 
@@ -231,7 +275,7 @@ sa_status mlp_alloc(sa_mlp *p)
         {(void **)&p->dA2, B * H * 4},        {(void **)&p->dA1, B * H * 4},     {(void **)&p->loss_r, B * 4},
         {(void **)&p->dO, B * 2 * 4},         {(void **)&p->loss, 4},            {(void **)&p->W1b, kInputs * H * 2},
         {(void **)&p->W2b, H * H * 2},        {(void **)&p->W3b, H * 2 * 2},     {(void **)&p->H1b, B * H * 2},
-        {(void **)&p->dA2b, B * H * 2},       {(void **)&p->idx, B * 4}};
+        {(void **)&p->dA2b, B * H * 2},       {(void **)&p->idx, B * 4},         {(void **)&p->net, kNetBytes}};
     std::vector<size_t> at;
     for (auto &q : parts) {
         at.push_back(off);
@@ -252,9 +296,9 @@ sa_status mlp_grad_pass(sa_mlp *p, const float *records, uint32_t batch)
     const float inv_b = 1.0f / (float)batch;
     hipLaunchKernelGGL(layer1_forward, dim3((batch * kHidden + 255) / 256), blk, 0, p->stream, records, p->idx,
                        batch, p->W1b, p->theta + kOffB1, p->Z, p->delta, p->A1, p->H1b);
-    // a2 = h1 W2 + b2, h2 = gelu(a2)
+    // a2 = h1 W2 + b2, h2 = act(a2)
     const int tiles_bh = (int)(batch / 16) * (kHidden / 16);
-    hipLaunchKernelGGL((gemm_bf16<kEpiBiasGelu>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
+    hipLaunchKernelGGL((gemm_bf16<kEpiBiasAct>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
                        kHidden, p->H1b, kHidden, 1, p->W2b, kHidden, 1, p->A2, kHidden, p->theta + kOffB2,
                        (const float *)nullptr, p->H2);
     hipLaunchKernelGGL(layer3_loss, dim3((batch + 3) / 4), blk, 0, p->stream, p->H2, p->A2, p->W3b,
@@ -263,8 +307,8 @@ sa_status mlp_grad_pass(sa_mlp *p, const float *records, uint32_t batch)
     hipLaunchKernelGGL((gemm_bf16<kEpiStore>), dim3((64 + 3) / 4), blk, 0, p->stream, kHidden, kHidden, (int)batch,
                        p->H1b, 1, kHidden, p->dA2b, kHidden, 1, p->g + kOffW2, kHidden, (const float *)nullptr,
                        (const float *)nullptr, (float *)nullptr);
-    // da1 = (da2 W2^T) * gelu'(a1)
-    hipLaunchKernelGGL((gemm_bf16<kEpiGeluBwd>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
+    // da1 = (da2 W2^T) * relu'(a1)
+    hipLaunchKernelGGL((gemm_bf16<kEpiActBwd>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
                        kHidden, p->dA2b, kHidden, 1, p->W2b, 1, kHidden, p->dA1, kHidden, (const float *)nullptr,
                        p->A1, (float *)nullptr);
     const uint32_t nsmall = kOffB1 + 4 * kHidden + 2;
@@ -369,6 +413,18 @@ sa_status sa_mlp_train(sa_mlp *p, const float *records, uint64_t nrec, uint32_t 
     }
     SA_HIP(hipStreamSynchronize(p->stream));
     if (loss_trace) std::memcpy(loss_trace, trace.data(), steps * sizeof(float));
+    return SA_OK;
+}
+
+sa_status sa_mlp_infer(sa_mlp *p, const float *Z, uint32_t rows, float *out)
+{
+    sa::g_last_error.clear();
+    if (!p || !Z || !out) return fail(SA_ERR_INVALID, "null argument");
+    if (rows == 0) return SA_OK;
+    hipError_t e = sa::launch_pack_net(p->theta, p->net, p->stream);
+    if (e != hipSuccess) return fail(SA_ERR_DEVICE, "pack launch: %s", hipGetErrorString(e));
+    hipLaunchKernelGGL(infer_rows, dim3((rows + 255) / 256), dim3(256), 0, p->stream, p->net, Z, rows, out);
+    SA_HIP(hipGetLastError());
     return SA_OK;
 }
 

@@ -23,22 +23,10 @@ constexpr uint32_t kOffB3 = kOffW3 + kHidden * 2;
 constexpr uint32_t kNumParams = kOffB3 + 2;
 static_assert(kNumParams == 17666, "parameter count");
 
-// GELU, tanh form: a/2 (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))), with
-// tanh(u) = 1 - 2 / (exp(2u) + 1).
-__host__ __device__ __forceinline__ float gelu(float a)
-{
-    const float u = 0.7978845608028654f * fmaf(0.044715f * a, a * a, a);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * u) + 1.0f);
-    return 0.5f * a * (1.0f + t);
-}
+// Hidden activation: relu, with derivative 0 at 0.
+__host__ __device__ __forceinline__ float act(float a) { return fmaxf(a, 0.0f); }
 
-__host__ __device__ __forceinline__ float gelu_grad(float a)
-{
-    const float u = 0.7978845608028654f * fmaf(0.044715f * a, a * a, a);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * u) + 1.0f);
-    const float du = 0.7978845608028654f * fmaf(3.0f * 0.044715f, a * a, 1.0f);
-    return 0.5f * (1.0f + t) + 0.5f * a * (1.0f - t * t) * du;
-}
+__host__ __device__ __forceinline__ float act_grad(float a) { return a > 0.0f ? 1.0f : 0.0f; }
 
 // FP32 <-> BF16 (round to nearest even; NaN stays NaN).
 __host__ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)

@@ -8,6 +8,7 @@
 
 #include "sa_device.hpp"
 #include "sa_internal.hpp"
+#include "sa_mlp_net.hpp"
 
 namespace sa {
 
@@ -268,6 +269,78 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
         r = r1;
         r1 = r2;
         d1 = pick(r2.w0, n);
+    }
+    return accepted;
+}
+
+// ---------------------------------------------------------------------------
+// N steps of the learned-proposal mixture, FP32 (an extension of the method,
+// not in the paper).  Per move, with the move draws r (the plain method's
+// counters) and the learned draws q (tag kTagLearn, same step/level/chain):
+//   d from r0; a plain move with probability eps (U(r3) < eps): the radius
+//   neighbour from r1 and the Metropolis test on r2, as in run_steps;
+//   otherwise the network gives (mu, s) at the features of x_d, the scaled
+//   displacement is dl = mu + e^s g with g = sqrt(-2 ln(1 - U(q0)))
+//   cos(2 pi U(q1)) (Box-Muller), x'_d = x_d + dl (u_d - l_d); a proposal
+//   outside [l_d, u_d] is rejected; otherwise the network is evaluated again
+//   at x'_d (same history) and the move is taken iff
+//       U(r2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
+//   (Metropolis-Hastings: each component is reversible on its own, so the
+//   state-independent mixture is too).
+// h holds the chain's last four accepted scaled displacements (most recent
+// first); every accepted move, plain or learned, pushes (x'_d - x_d)/(u_d - l_d).
+// All lanes of the wave run every step (the network runs on wave-wide MFMA).
+// ---------------------------------------------------------------------------
+template <int F, typename CoordFn, typename LogFn>
+__device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride, uint32_t lane_off,
+                                                      Cost<float, F> &cost, const CoordFn &coordf, const LogFn &logf,
+                                                      uint32_t n, uint32_t steps, uint32_t level, uint32_t chain,
+                                                      uint32_t ctr_move, uint32_t ctr_learn, uint32_t k0, uint32_t k1,
+                                                      float nl2T, float inv_n, float featT, float eps,
+                                                      const unsigned char *net, float (&h)[4])
+{
+    uint32_t accepted = 0;
+    for (uint32_t step = 0; step < steps; ++step) {
+        const Ctr r = philox4x32_10(Ctr{step, level, chain, ctr_move}, k0, k1);
+        const Ctr q = philox4x32_10(Ctr{step, level, chain, ctr_learn}, k0, k1);
+        const uint32_t d = pick(r.w0, n);
+        const Coord<float> c = coordf(d);
+        const uint32_t at = __umul24(d, stride) + lane_off;
+        const float xd = xs[at];
+        const float w = c.hi - c.lo;
+        const float inv_w = 1.0f / w;
+        const bool plain = u24f(r.w3) < eps;
+
+        float z[mlp::kInputs] = {(xd - c.lo) * inv_w, featT, h[0], h[1], h[2], h[3]};
+        float mu, s;
+        mlp::net_forward(net, z, mu, s);
+        const float gz = hw_sqrt(-2.0f * kLn2 * hw_log2(1.0f - u24f(q.w0))) * hw_cos_rev(u24f(q.w1));
+        const float dl = fmaf(hw_exp2(kLog2e * s), gz, mu);
+        const float xl = fmaf(dl, w, xd);
+        const bool inbox = xl >= c.lo && xl <= c.hi;
+        z[0] = inbox ? (xl - c.lo) * inv_w : 0.5f;
+        float mu2, s2;
+        mlp::net_forward(net, z, mu2, s2);
+        // ln q(x | x') - ln q(x' | x); the forward standardised residual is gz
+        const float e2 = (dl + mu2) * hw_exp2(-kLog2e * s2);
+        const float lq = (s - s2) + 0.5f * (gz * gz - e2 * e2);
+
+        const float xp = neighbour<SA_MOVE_RADIUS>(xd, c, u24f(r.w1));
+        const float xn = plain ? xp : xl;
+        const bool valid = plain || inbox;
+        const float df = cost.delta(xd - c.sh, (valid ? xn : xd) - c.sh, n, inv_n);
+        const float u2 = u24f(r.w2);
+        const bool take = plain ? metropolis(df, u2, 0.0, nl2T) : (inbox && u2 < hw_exp2(fmaf(df, nl2T, kLog2e * lq)));
+        logf(step, d, take, xd, xn, df);
+        xs[at] = take ? xn : xd;
+        cost.commit(take, inv_n);
+        if (take) {
+            h[3] = h[2];
+            h[2] = h[1];
+            h[1] = h[0];
+            h[0] = (xn - xd) * inv_w;
+        }
+        accepted += take ? 1u : 0u;
     }
     return accepted;
 }

@@ -20,14 +20,15 @@ LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
-FLAG_TRACE_X, FLAG_GRAPH = 0x1, 0x2
+FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED = 0x1, 0x2, 0x4
 
 SA_OK = 0
 STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ERR_DEVICE", -4: "SA_ERR_STATE",
                 -5: "SA_ERR_UNSUPPORTED"}
 
 EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
-            "sa_move_log", "sa_destroy", "sa_last_error"]
+            "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_destroy",
+            "sa_last_error"]
 
 
 class SAError(RuntimeError):
@@ -87,6 +88,14 @@ def load_library():
     L.sa_trace.restype = st
     L.sa_move_log.argtypes = [vp, vp, vp]
     L.sa_move_log.restype = st
+    L.sa_set_start.argtypes = [vp, u32, vp]
+    L.sa_set_start.restype = st
+    L.sa_set_proposal.argtypes = [vp, vp, ctypes.c_float]
+    L.sa_set_proposal.restype = st
+    L.sa_capture.argtypes = [vp, vp, u64]
+    L.sa_capture.restype = st
+    L.sa_capture_count.argtypes = [vp, ctypes.POINTER(u64)]
+    L.sa_capture_count.restype = st
     L.sa_destroy.argtypes = [vp]
     L.sa_destroy.restype = None
     L.sa_last_error.argtypes = []
@@ -114,12 +123,14 @@ class Schedule:
     radius_frac: float = 0.1
     trace_x: bool = False
     graph: bool = False
+    learned: bool = False  # reserve room for a learned proposal (sa_set_proposal)
     log_chains: int = 0
     log_level: int = 0
     log_levels: int = 0
 
     def to_c(self) -> Config:
-        flags = (FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0)
+        flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
+                 (FLAG_LEARNED if self.learned else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
                       self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels, 0)
 
@@ -197,6 +208,38 @@ class Annealer:
         _check(load_library().sa_trace(self._ctx, first, count, rec.ctypes.data,
                                        None if xb is None else xb.ctypes.data))
         return (rec, xb) if with_x else rec
+
+    def set_start(self, level: int, x):
+        """Start the run at ``level`` with every chain at ``x`` (before the first run)."""
+        xx = np.ascontiguousarray(x, dtype=np.float64)
+        assert xx.size == self.n
+        _check(load_library().sa_set_start(self._ctx, level, xx.ctypes.data))
+
+    def set_proposal(self, params, eps: float = 0.1):
+        """Use the learned proposal with network ``params`` (None: plain moves)."""
+        if params is None:
+            _check(load_library().sa_set_proposal(self._ctx, None, 0.0))
+            return
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        _check(load_library().sa_set_proposal(self._ctx, p.ctypes.data, eps))
+
+    def capture(self, records):
+        """Record accepted moves of later plain levels into ``records`` (a
+        float32 CUDA tensor of shape [capacity, 7]); None stops capturing."""
+        if records is None:
+            _check(load_library().sa_capture(self._ctx, None, 0))
+            self._cap = None
+            return
+        assert records.is_cuda and records.dtype.is_floating_point and records.element_size() == 4
+        assert records.dim() == 2 and records.shape[1] == 7 and records.is_contiguous()
+        self._cap = records
+        _check(load_library().sa_capture(self._ctx, ctypes.c_void_p(records.data_ptr()), records.shape[0]))
+
+    def capture_count(self) -> int:
+        v = ctypes.c_uint64()
+        _check(load_library().sa_capture_count(self._ctx, ctypes.byref(v)))
+        return v.value
 
     def move_log(self):
         s = self.schedule
@@ -425,7 +468,7 @@ class BatchAnnealer:
 # ---------------------------------------------------------------------------
 MLP_PARAMS = 17666
 EXPORTED_MLP = ["sa_mlp_create", "sa_mlp_set_params", "sa_mlp_get_params", "sa_mlp_grad", "sa_mlp_train",
-                "sa_mlp_destroy"]
+                "sa_mlp_infer", "sa_mlp_destroy"]
 EXPORTED = EXPORTED + EXPORTED_MLP
 
 
@@ -443,6 +486,8 @@ def _mlp_lib():
         L.sa_mlp_grad.restype = st
         L.sa_mlp_train.argtypes = [vp, vp, u64, u32, u32, ctypes.c_float, u64, vp]
         L.sa_mlp_train.restype = st
+        L.sa_mlp_infer.argtypes = [vp, vp, u32, vp]
+        L.sa_mlp_infer.restype = st
         L.sa_mlp_destroy.argtypes = [vp]
         L.sa_mlp_destroy.restype = None
         L._mlp_bound = True
@@ -487,6 +532,19 @@ class MLPTrainer:
         _check(_mlp_lib().sa_mlp_train(self._h, ctypes.c_void_p(records.data_ptr()), records.shape[0], batch, steps,
                                        lr, seed, trace.ctypes.data))
         return trace
+
+    def infer(self, Z):
+        """(mu, s) at the current parameters for the rows of Z (a float32 CUDA
+        tensor [rows, 6]); returns a float32 CUDA tensor [rows, 2]."""
+        import torch
+        assert Z.is_cuda and Z.dtype == torch.float32 and Z.dim() == 2 and Z.shape[1] == 6
+        Zc = Z.contiguous()
+        out = torch.empty((Zc.shape[0], 2), dtype=torch.float32, device=Zc.device)
+        self._stream.wait_stream(torch.cuda.current_stream())
+        _check(_mlp_lib().sa_mlp_infer(self._h, ctypes.c_void_p(Zc.data_ptr()), Zc.shape[0],
+                                       ctypes.c_void_p(out.data_ptr())))
+        self._stream.synchronize()
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

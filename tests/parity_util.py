@@ -198,3 +198,115 @@ def check_record(wl, g):
     fr = O.f(wl.func, g["x_rec"], sh)
     assert abs(g["f_rec"] - fr) <= 1e-11 * max(1.0, abs(fr))
     assert np.all(np.diff(rec["t_ticks"].astype(np.int64)) >= 0)
+
+
+def learned_params(seed, scale=0.1, mu0=0.0, sigma0=0.05):
+    """A proposal network for parity tests: random weights, output biases that
+    centre the proposal at mu0 with scale sigma0 (so most proposals land in
+    the box and the Metropolis-Hastings branch is exercised)."""
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, scale, O.mlp_nparam())
+    p[-2], p[-1] = mu0, math.log(sigma0)
+    return p.astype(np.float32)
+
+
+def bf16_matrices(params):
+    """Parameters as the device uses them: the three weight matrices rounded
+    to BF16 (ties to even), biases FP32; returned in float64."""
+    p = np.asarray(params, dtype=np.float32).copy()
+    H, I = O.MLP_HIDDEN, O.MLP_INPUTS
+    for a, b in ((0, I * H), (I * H + H, I * H + H + H * H), (I * H + 2 * H + H * H, I * H + 2 * H + H * H + 2 * H)):
+        u = p[a:b].view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+        p[a:b] = u.astype(np.uint32).view(np.float32)
+    return p.astype(np.float64)
+
+
+def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, featT, eps32, params64, radius_frac,
+                        x_start, moves, final_f, chain_ids, problem=0):
+    """Replay the logged moves of a learned-mixture level against the oracle.
+
+    Each move: the coordinate and the plain/learned choice are bit-exact; a
+    plain move is checked as in check_fp32_level; a learned move's proposal
+    must equal the oracle's mu + e^s g within the network's BF16 error bound,
+    a proposal outside the box must be rejected with df = 0, and an in-box
+    decision must equal the oracle's Metropolis-Hastings decision wherever the
+    bounds cannot flip it.  The chain state follows the GPU's own accepted
+    moves.  Returns statistics."""
+    stats = dict(moves=0, learned=0, outside=0, ambiguous=0, max_dl_excess=0.0, max_rel_excess=0.0)
+    for j, c in enumerate(chain_ids):
+        x = np.array(x_start, dtype=np.float64)
+        h = [0.0, 0.0, 0.0, 0.0]
+        f_acc_err = 0.0
+        for s in range(moves.shape[-1]):
+            m = moves[j, s]
+            d, u1, u2, r3 = O.move_draw(seed, problem, level, c, s, n)
+            assert int(m["d"]) == d, (level, c, s)
+            assert m["x_old"] == x[d], (level, c, s)
+            lo, hi = float(lower32[d]), float(upper32[d])
+            w = hi - lo
+            plain = O.uniform(r3) < eps32
+            xn = x.copy()
+            xn[d] = m["x_new"]
+            if plain:
+                xn_ref = O.neighbour(O.MOVE_RADIUS, float(m["x_old"]), lo, hi, radius_frac, u1)
+                assert abs(m["x_new"] - xn_ref) <= 2.0 ** -23 * (abs(xn_ref) + radius_frac * w), (level, c, s)
+                df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
+                tol = 1e-5 * abs(df_ref) + df_floor(func, n, x, xn, d, shift32)
+                assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
+                margin = tol + 2.0 ** -18 * T
+                firm = O.accept(df_ref - margin, T, u2) == O.accept(df_ref + margin, T, u2)
+                if firm:
+                    assert bool(m["accept"]) == O.accept(df_ref, T, u2), (level, c, s)
+                else:
+                    stats["ambiguous"] += 1
+            else:
+                stats["learned"] += 1
+                x_old = float(m["x_old"])
+                z = [(x_old - lo) / w, featT] + h
+                (mu, sl), (bmu, bs) = O.mlp_forward_bound(params64, z)
+                g = O.learn_gauss(seed, problem, level, c, s)
+                sig = math.exp(sl)
+                dl_ref = mu + sig * g
+                dl_gpu = (float(m["x_new"]) - x_old) / w
+                # network bound, the FP32 rounding of the sampled displacement
+                # and of x' = x + dl w (relative to the box width), and the
+                # hardware log/sqrt/cos/exp2 error of g and e^s (a few ulp)
+                tol_dl = bmu + sig * abs(g) * (math.expm1(bs) + 2.0 ** -18) + sig * 2.0 ** -18 * (1 + abs(g)) \
+                    + 4 * U32 * (abs(dl_ref) + (abs(x_old) + abs(float(m["x_new"]))) / w)
+                err = abs(dl_gpu - dl_ref)
+                stats["max_dl_excess"] = max(stats["max_dl_excess"], err / tol_dl)
+                assert err <= tol_dl, (level, c, s, dl_gpu, dl_ref, tol_dl)
+                inside = lo <= m["x_new"] <= hi
+                if not inside:
+                    stats["outside"] += 1
+                    assert m["accept"] == 0 and m["df"] == 0.0, (level, c, s)
+                else:
+                    z2 = [(float(m["x_new"]) - lo) / w, featT] + h
+                    (mu2, s2), (bmu2, bs2) = O.mlp_forward_bound(params64, z2)
+                    df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
+                    tol = 1e-5 * abs(df_ref) + df_floor(func, n, x, xn, d, shift32)
+                    assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
+                    stats["max_rel_excess"] = max(stats["max_rel_excess"], abs(m["df"] - df_ref) / tol)
+                    lq = O.proposal_logpdf(-dl_gpu, mu2, s2) - O.proposal_logpdf(dl_gpu, mu, sl)
+                    # first-order sensitivity of lq to the network outputs
+                    e1 = (dl_gpu - mu) * math.exp(-sl)
+                    e2 = (-dl_gpu - mu2) * math.exp(-s2)
+                    tol_lq = (abs(e1) * math.exp(-sl) * bmu + abs(1 - e1 * e1) * bs
+                              + abs(e2) * math.exp(-s2) * bmu2 + abs(1 - e2 * e2) * bs2)
+                    r = -df_ref / T + lq
+                    tol_r = 2 * tol_lq + tol / T + 2.0 ** -16 * (1 + abs(r))
+                    lu = math.log(u2) if u2 > 0 else -math.inf
+                    if abs(lu - r) > tol_r:
+                        assert bool(m["accept"]) == (lu < r), (level, c, s, lu, r, tol_r)
+                    else:
+                        stats["ambiguous"] += 1
+            if m["accept"]:
+                h = [(float(m["x_new"]) - float(m["x_old"])) / w] + h[:3]
+                x = xn
+                f_acc_err += tol + 2 * U32 * abs(O.f(func, x, shift32))
+            stats["moves"] += 1
+        f_ref = O.f(func, x, shift32)
+        start_err = 2 * U32 * abs(O.f(func, x_start, shift32)) + 1e-12
+        assert abs(final_f[c] - f_ref) <= f_acc_err + start_err + 2 * U32 * abs(f_ref), (level, c, final_f[c], f_ref)
+    return stats

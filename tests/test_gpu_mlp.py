@@ -55,19 +55,26 @@ def test_gradient_matches_oracle(S, batch):
         q[sl] = S.bf16_round(p[sl]).astype(np.float64)
     sel = rec[idx].astype(np.float64)
     lref, gref = O.mlp_loss_grad(q, sel[:, :6], sel[:, 6])
+    # The device rounds hidden activations (and the layer-2 gradient) to BF16,
+    # unit roundoff u = 2^-9, so each gradient term carries a relative error of
+    # a few u; a relu unit whose pre-activation lies within rounding distance of
+    # 0 can switch sides, which moves single entries of small batches far more
+    # than their norm.  Hence normwise bounds per parameter block (8u) and a
+    # median elementwise bound (2u) rather than an elementwise maximum.
+    u = 2.0 ** -9
     assert abs(loss - lref) <= 2e-3 * max(1.0, abs(lref)), (loss, lref)
     cos = float(np.dot(g, gref) / (np.linalg.norm(g) * np.linalg.norm(gref)))
     big = np.abs(gref) > 1e-2 * np.max(np.abs(gref))
     rel = np.abs(g[big] - gref[big]) / np.abs(gref[big])
-    say(f"[gpu mlp] batch={batch} loss {loss:.6f} vs {lref:.6f} cosine {cos:.6f} max rel (|g|>1% max) "
-        f"{rel.max():.3e} median {np.median(rel):.3e}")
-    assert cos >= 0.999
-    for name, sl in (("W1", w1), ("W2", w2), ("W3", w3)):
-        a, b = g[sl], gref[sl]
-        c = float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
-        assert c >= 0.995, (name, c)
-    assert rel.max() <= 5e-2
-    assert np.median(rel) <= 5e-3
+    blocks = {"W1": w1, "b1": slice(I * H, I * H + H), "W2": w2, "b2": slice(I * H + H + H * H, I * H + 2 * H + H * H),
+              "W3": w3, "b3": slice(w3.stop, w3.stop + 2)}
+    normwise = {k: float(np.linalg.norm(g[sl] - gref[sl]) / np.linalg.norm(gref[sl])) for k, sl in blocks.items()}
+    say(f"[gpu mlp] batch={batch} loss {loss:.6f} vs {lref:.6f} cosine {cos:.6f} median rel {np.median(rel):.3e} "
+        f"normwise {{{', '.join(f'{k}: {v:.2e}' for k, v in normwise.items())}}}")
+    assert cos >= 0.9999
+    for k, v in normwise.items():
+        assert v <= 8 * u, (k, v)
+    assert np.median(rel) <= 2 * u
 
 
 def test_training_reduces_loss_and_learns_scale(S):
