@@ -140,7 +140,8 @@ def test_capture_fp32_invariants_and_capacity(S):
     assert set(np.unique(r[:, 1])) <= featT
     assert np.all(np.abs(r[:, 6]) <= 0.1 * (1 + 1e-6))  # radius 0.1 (u - l)
     assert np.all(np.abs(r[:, 2:6]) <= 0.1 * (1 + 1e-6))
-    assert np.all(r[:, 6] != 0)
+    # a zero displacement is a radius move clamped back onto the box edge it started on
+    assert np.all((r[:, 6] != 0) | (r[:, 0] == 0) | (r[:, 0] == 1))
     # a smaller buffer: every slot written, the count still complete
     small = 1000
     got2, count2, _ = capture_run(S, wl, capacity=small, precision=S.FP32, **kw)
