@@ -5,7 +5,12 @@ One step = one whole annealing run (level-0 start, 500 levels, argmin and
 broadcast after each) from a reset context; the inputs are the problem
 definition, already on the device.  Prints one JSON line.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-levels L] [--no-cpu] [--probe]
+Also reported (unless --no-ttt): time to |f - f*| < 1e-4 on the same
+problem, plain radius moves against the learned proposal (network trained on
+the GPU from accepted moves of plain runs), on the schedule extended to 4000
+levels, from random starts and from a final-approach start.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-levels L] [--no-cpu] [--probe] [--no-ttt]
 """
 from __future__ import annotations
 
@@ -80,6 +85,8 @@ def parse():
     p.add_argument("--cpu-levels", type=int, default=10, help="levels of the workload the CPU oracle times")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
+    p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
+    p.add_argument("--ttt-seeds", type=int, default=1, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
     return p.parse_args()
@@ -123,6 +130,56 @@ def probe_rates():
                 raise RuntimeError(f"occupancy probe {name}/{w} failed: {rc}")
             occ[f"{name}@{w}w"] = float(f"{256 * 4 * w * 64 * 4096 * 16 / (ms.value * 1e-3):.4g}")
     return {"rates_many_waves": rates, "by_waves_per_simd": occ}
+
+
+def time_to_target_report(wl, seeds):
+    """Learned vs plain proposal: time until the record is within 1e-4 of f*.
+
+    Collection: plain runs (4096 chains, 100 steps, T0 10, alpha 0.995, 4000
+    levels, seed 1001) capture accepted moves at every 8th level (at most
+    20000 per level).  Training: 3000 Adam steps, minibatch 4096, lr 1e-3.
+    Arms, on 65536 chains x 100 steps, T_k = 10 * 0.995^k up to k = 3999:
+    'full' starts at level 0 from random points; 'final_approach' starts at
+    level 1000 (T = 0.067) with every chain at x* + U(-50, 50) per coordinate.
+    """
+    import torch
+    from paper_2408_00018_amd import learned as Lp
+    from paper_2408_00018_amd import sa
+    levels = 4000
+    out = {"target": 1e-4, "f_star": W.SCHWEFEL_F_STAR, "levels_cap": levels}
+    t0 = time.perf_counter()
+    col = sa.Schedule(chains=4096, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
+                      precision=sa.FP32)
+    rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=8, per_level=20000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    params, trace = Lp.train(rec, steps=3000, batch=4096, lr=1e-3, seed=0)
+    t2 = time.perf_counter()
+    out["collect"] = {"records": int(rec.shape[0]), "seconds": round(t1 - t0, 3)}
+    out["train"] = {"steps": 3000, "batch": 4096, "loss_first": float(trace[:20].mean()),
+                    "loss_last": float(trace[-50:].mean()), "seconds": round(t2 - t1, 3)}
+    del rec
+    rng = np.random.default_rng(7)
+    x0 = np.clip(W.SCHWEFEL_X_STAR + rng.uniform(-50, 50, wl.n), -500, 500)
+    for regime, start in (("full", 0), ("final_approach", 1000)):
+        res = {}
+        for arm, p in (("plain", None), ("learned", params)):
+            runs = []
+            for seed in range(1, seeds + 1):
+                sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
+                                    seed=seed, precision=sa.FP32)
+                r = Lp.time_to_target(wl.func, wl.lower, wl.upper, wl.shift, sched, W.SCHWEFEL_F_STAR, 1e-4,
+                                      params=p, eps=0.1, start_level=start, x_start=x0 if start else None)
+                runs.append({"seed": seed, "hit": r.hit, "level": r.level, "seconds": r.seconds,
+                             "levels_run": r.levels_run, "ms_per_level": round(r.ms_per_level, 4),
+                             "final_gap": r.final_gap})
+                print(f"[ttt] {regime} {arm} seed {seed}: {runs[-1]}", file=sys.stderr, flush=True)
+            res[arm] = runs
+        hits = {a: [r["seconds"] for r in res[a] if r["hit"]] for a in res}
+        if hits["plain"] and hits["learned"]:
+            res["speedup_median"] = float(np.median(hits["plain"]) / np.median(hits["learned"]))
+        out[regime] = res
+    return out
 
 
 def main():
@@ -204,6 +261,11 @@ def main():
         out["valu_rates_per_s"] = probe_rates()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
+    if not args.no_ttt:
+        try:
+            out["time_to_target"] = time_to_target_report(wl, args.ttt_seeds)
+        except Exception as e:  # the throughput line is printed regardless
+            out["time_to_target"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out), flush=True)
 
 

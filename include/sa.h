@@ -206,8 +206,9 @@ sa_status sa_set_proposal(sa_ctx *ctx, const float *params, float eps);
 
 /* Record every accepted move of the following plain levels into `records`
  * (device memory, capacity x 7 floats: the six network features at the old
- * state -- (x_d - l_d)/(u_d - l_d), ln(tau T), the chain's last four accepted
- * scaled displacements -- and the accepted scaled displacement
+ * state -- (x_d - l_d)/(u_d - l_d), ln(tau T), the history features of the
+ * chain's last four accepted scaled displacements -- and the accepted scaled
+ * displacement
  * (x'_d - x_d)/(u_d - l_d)).  Records go to slots in the order the device
  * reserves them; once `capacity` are taken, later ones are counted but not
  * stored.  Resets the count.  records = NULL stops capturing.  SA_ERR_STATE
@@ -301,8 +302,9 @@ const char *sa_last_error(void);
 /* ------------------------------------------------------------------------
  * Learned proposal network (an extension of the method; not in the paper):
  * per chosen coordinate, features z = ((x_d - l_d)/(u_d - l_d), ln(tau T),
- * the chain's last four accepted scaled displacements, most recent first;
- * tau = n for Schwefel and Ackley, 1 for Rastrigin) -> 128 (relu) -> 128
+ * the chain's last four accepted scaled displacements h, most recent first,
+ * each as sign(h) ln(1 + 2^24 |h|) / 16; tau = n for Schwefel and Ackley, 1
+ * for Rastrigin) -> 128 (relu) -> 128
  * (relu) -> (mu, s): a Gaussian N(mu, exp(s)^2) over the coordinate's scaled
  * displacement (x'_d - x_d)/(u_d - l_d).  Parameters: SA_MLP_PARAMS floats,
  * W1[6][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].  Training

@@ -97,6 +97,8 @@ def lib():
         L.orc_adam_step.restype = None
         L.orc_proposal_logpdf.argtypes = [_d, _d, _d]
         L.orc_proposal_logpdf.restype = _d
+        L.orc_hist_feature.argtypes = [_d]
+        L.orc_hist_feature.restype = _d
         L.orc_mlp_forward_bound.argtypes = [_p, _p, _p, _p]
         L.orc_mlp_forward_bound.restype = None
         L.orc_learn_gauss.argtypes = [_u64, _u32, _u32, _u32, _u32]
@@ -320,6 +322,11 @@ def mlp_forward_bound(params, z):
     bound = np.zeros(2)
     lib().orc_mlp_forward_bound(_ptr(p), _ptr(zz), _ptr(out), _ptr(bound))
     return out, bound
+
+
+def hist_feature(h: float) -> float:
+    """History feature of a scaled displacement: sign(h) ln(1 + 2^24 |h|) / 16."""
+    return lib().orc_hist_feature(h)
 
 
 def learn_gauss(seed, problem, level, chain, step) -> float:

@@ -277,6 +277,9 @@ static struct {
     double tau;
 } capture_sink;
 
+/* History feature of the learned proposal's input: sign(h) ln(1 + 2^24 |h|) / 16. */
+double orc_hist_feature(double h) { return copysign(log(1.0 + ldexp(fabs(h), 24)) / 16.0, h); }
+
 static void capture_move(const orc_problem *p, double T, uint32_t d, double xd, double xn, double hist[4])
 {
     const double w = p->upper[d] - p->lower[d];
@@ -285,7 +288,7 @@ static void capture_move(const orc_problem *p, double T, uint32_t d, double xd, 
         float *r = capture_sink.rec + capture_sink.count * 7;
         r[0] = (float)((xd - p->lower[d]) / w);
         r[1] = (float)log(capture_sink.tau * T);
-        for (int k = 0; k < 4; ++k) r[2 + k] = (float)hist[k];
+        for (int k = 0; k < 4; ++k) r[2 + k] = (float)orc_hist_feature(hist[k]);
         r[6] = (float)dl;
     }
     capture_sink.count += 1;
@@ -486,7 +489,8 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 /* Features z (6): z0 = (x_d - l_d)/(u_d - l_d); z1 = ln(tau T), tau = n    */
 /* for the objectives normalised by n (Schwefel, Ackley: a one-coordinate    */
 /* change moves f by O(1/n)) and 1 for Rastrigin; z2..z5 = the chain's last  */
-/* four accepted scaled displacements, most recent first.                    */
+/* four accepted scaled displacements h, most recent first, each as          */
+/* sign(h) ln(1 + 2^24 |h|) / 16 (orc_hist_feature).                         */
 /* Network: a1 = z W1 + b1 (6x128), h1 = relu(a1); a2 = h1 W2 + b2 (128x128), */
 /* h2 = relu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma.        */
 /* Loss of a record (z, delta): s + (delta - mu)^2 / (2 exp(2 s)).           */

@@ -30,6 +30,10 @@ HIPCC_FLAGS = [
     # Packed FP32 instructions stay off: every VALU op here is scalar FP32/FP64
     # or integer.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # Matrix-core results stay in ordinary VGPRs, where the relu/BF16 packing
+    # that follows each product reads them, instead of accumulation registers
+    # that need a v_accvgpr_read per value.
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
 ]
 

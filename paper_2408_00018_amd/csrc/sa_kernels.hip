@@ -290,10 +290,10 @@ __global__ void __launch_bounds__(256)
                         float *rec = a.cap_rec + slot * 7u;
                         rec[0] = (float)z0;
                         rec[1] = featT;
-                        rec[2] = (float)hist[0];
-                        rec[3] = (float)hist[1];
-                        rec[4] = (float)hist[2];
-                        rec[5] = (float)hist[3];
+                        rec[2] = (float)hist_feature(hist[0]);
+                        rec[3] = (float)hist_feature(hist[1]);
+                        rec[4] = (float)hist_feature(hist[2]);
+                        rec[5] = (float)hist_feature(hist[3]);
                         rec[6] = (float)dl;
                     }
                 }

@@ -78,12 +78,25 @@ __device__ __forceinline__ floatx4 f4_at(const unsigned char *net, uint32_t off)
 
 __device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
 
-// relu as a signed-integer max of the bit pattern (negative floats, -0
-// included, have the sign bit set): one v_max_i32, where fmaxf would first
-// canonicalise its operand.
-__device__ __forceinline__ float relu(float v)
+typedef short short2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values as a word of two BF16 (one v_cvt_pk_bf16_f32, round to
+// nearest even), relu applied as a signed 16-bit integer max of the bit
+// patterns (one v_pk_max_i16; a negative value, -0 included, has the sign bit
+// set, and rounding keeps the sign, so relu(bf16(a)) = bf16(relu(a))).
+__device__ __forceinline__ uint32_t relu_pack(float a, float b)
 {
-    return __builtin_bit_cast(float, max(__builtin_bit_cast(int, v), 0));
+    const bf16x2 h = __builtin_convertvector(float2v{a, b}, bf16x2);
+    const short2v m = __builtin_elementwise_max(__builtin_bit_cast(short2v, h), short2v{0, 0});
+    return __builtin_bit_cast(uint32_t, m);
+}
+
+__device__ __forceinline__ bf16x8 words(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
+{
+    return __builtin_bit_cast(bf16x8, u32x4{w0, w1, w2, w3});
 }
 
 // (mu, s) of this lane's feature vector z[0..5].  Every lane of the wave must
@@ -108,8 +121,9 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
         }
     }
 
-    // Layer 1 -> layer-2 B operands h1[ct][kb].
-    bf16x8 h1[4][4];
+    // Layer 1 -> layer-2 B operands: word (rt & 1) * 2 + j / 2 of h1[ct][rt / 2]
+    // holds rows 4g + j, j + 1 of row tile rt.
+    uint32_t h1[4][4][4];
 #pragma unroll
     for (int rt = 0; rt < 8; ++rt) {
         const bf16x8 a = frag_at(net, kNetL1 + rt * kFrag, lane);
@@ -117,13 +131,13 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
             const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1[ct], bias, 0, 0, 0);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) h1[ct][rt >> 1][(rt & 1) * 4 + j] = to_bf16(relu(acc[j]));
+            h1[ct][rt >> 1][(rt & 1) * 2 + 0] = relu_pack(acc[0], acc[1]);
+            h1[ct][rt >> 1][(rt & 1) * 2 + 1] = relu_pack(acc[2], acc[3]);
         }
     }
 
-    // Layer 2 -> layer-3 B operands h2[ct][kb].
-    bf16x8 h2[4][4];
+    // Layer 2 -> layer-3 B operands h2[ct][kb], same packing.
+    uint32_t h2[4][4][4];
 #pragma unroll
     for (int rt = 0; rt < 8; ++rt) {
         const floatx4 bias = f4_at(net, kNetB2 + 4 * (16 * rt + 4 * g));
@@ -133,12 +147,14 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
             const bf16x8 a = frag_at(net, kNetL2 + (rt * 4 + kb) * kFrag, lane);
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct)
-                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h1[ct][kb], acc[ct], 0, 0, 0);
+                acc[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a, words(h1[ct][kb][0], h1[ct][kb][1], h1[ct][kb][2], h1[ct][kb][3]), acc[ct], 0, 0, 0);
         }
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) h2[ct][rt >> 1][(rt & 1) * 4 + j] = to_bf16(relu(acc[ct][j]));
+        for (int ct = 0; ct < 4; ++ct) {
+            h2[ct][rt >> 1][(rt & 1) * 2 + 0] = relu_pack(acc[ct][0], acc[ct][1]);
+            h2[ct][rt >> 1][(rt & 1) * 2 + 1] = relu_pack(acc[ct][2], acc[ct][3]);
+        }
     }
 
     // Layer 3: rows 0 and 1 of the single row tile are mu and s.
@@ -149,7 +165,9 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
     for (int kb = 0; kb < 4; ++kb) {
         const bf16x8 a = frag_at(net, kNetL3 + kb * kFrag, lane);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) o[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, h2[ct][kb], o[ct], 0, 0, 0);
+        for (int ct = 0; ct < 4; ++ct)
+            o[ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a, words(h2[ct][kb][0], h2[ct][kb][1], h2[ct][kb][2], h2[ct][kb][3]), o[ct], 0, 0, 0);
     }
 
     // Lane c's outputs sit in lane c % 16 of column tile c / 16.

@@ -225,6 +225,15 @@ __device__ __forceinline__ double wave_sum_d(double v)
     return v;
 }
 
+// History feature of the learned proposal: a scaled displacement h enters the
+// network as sign(h) ln(1 + 2^24 |h|) / 16 (a signed log magnitude, so a step
+// size proportional to recent accepted steps is a linear map of it).
+__device__ __forceinline__ float hist_feature(float h)
+{
+    return copysignf(hw_log2(fmaf(0x1p24f, fabsf(h), 1.0f)) * (kLn2 / 16.0f), h);
+}
+__device__ __forceinline__ double hist_feature(double h) { return copysign(log(1.0 + 0x1p24 * fabs(h)) / 16.0, h); }
+
 template <typename R> __device__ __forceinline__ R widen_inf();
 template <> __device__ __forceinline__ float widen_inf<float>() { return __builtin_inff(); }
 template <> __device__ __forceinline__ double widen_inf<double>() { return __builtin_inf(); }
@@ -287,8 +296,9 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
 //       U(r2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
 //   (Metropolis-Hastings: each component is reversible on its own, so the
 //   state-independent mixture is too).
-// h holds the chain's last four accepted scaled displacements (most recent
-// first); every accepted move, plain or learned, pushes (x'_d - x_d)/(u_d - l_d).
+// h holds the history features of the chain's last four accepted scaled
+// displacements (most recent first); every accepted move, plain or learned,
+// pushes hist_feature((x'_d - x_d)/(u_d - l_d)).
 // All lanes of the wave run every step (the network runs on wave-wide MFMA).
 // ---------------------------------------------------------------------------
 template <int F, typename CoordFn, typename LogFn>
@@ -338,7 +348,7 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
             h[3] = h[2];
             h[2] = h[1];
             h[1] = h[0];
-            h[0] = (xn - xd) * inv_w;
+            h[0] = hist_feature((xn - xd) * inv_w);
         }
         accepted += take ? 1u : 0u;
     }

@@ -263,7 +263,8 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
             else:
                 stats["learned"] += 1
                 x_old = float(m["x_old"])
-                z = [(x_old - lo) / w, featT] + h
+                hf = [O.hist_feature(v) for v in h]
+                z = [(x_old - lo) / w, featT] + hf
                 (mu, sl), (bmu, bs) = O.mlp_forward_bound(params64, z)
                 g = O.learn_gauss(seed, problem, level, c, s)
                 sig = math.exp(sl)
@@ -282,7 +283,7 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                     stats["outside"] += 1
                     assert m["accept"] == 0 and m["df"] == 0.0, (level, c, s)
                 else:
-                    z2 = [(float(m["x_new"]) - lo) / w, featT] + h
+                    z2 = [(float(m["x_new"]) - lo) / w, featT] + hf
                     (mu2, s2), (bmu2, bs2) = O.mlp_forward_bound(params64, z2)
                     df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
                     tol = 1e-5 * abs(df_ref) + df_floor(func, n, x, xn, d, shift32)

@@ -147,3 +147,79 @@ def test_training_reduces_loss_on_synthetic_data():
     s_lo = O.mlp_forward(p, [0.25, 0, 0, 0, 0, 0])[0][1]
     s_hi = O.mlp_forward(p, [0.75, 0, 0, 0, 0, 0])[0][1]
     assert s_hi - s_lo > 1.0  # ln(0.1 / 0.01) = 2.3
+
+
+def test_learn_gauss_is_standard_normal_and_follows_its_counters():
+    """Box-Muller draws of learned moves: a standard normal sample (KS test),
+    different counters give independent draws, and each draw is the
+    Box-Muller transform of the two uniforms of its Philox block."""
+    from scipy import stats
+    g = np.array([O.learn_gauss(5, 0, lv, ch, st) for lv in range(4) for ch in range(50) for st in range(100)])
+    assert stats.kstest(g, "norm").pvalue > 1e-3
+    assert abs(g.mean()) < 0.03 and abs(g.std() - 1.0) < 0.03
+    r = O.philox4x32_10([7, 3, 11, 3], [5, 0])
+    u0, u1 = O.uniform(int(r[0])), O.uniform(int(r[1]))
+    # the transform's radius and angle, recovered independently: g^2 is the
+    # chi-square radius times cos^2 of the angle
+    assert abs(O.learn_gauss(5, 0, 3, 11, 7) ** 2 - (-2 * math.log(1 - u0)) * math.cos(2 * math.pi * u1) ** 2) < 1e-12
+    # problem id in the counter's top bits changes the stream
+    assert O.learn_gauss(5, 1, 3, 11, 7) != O.learn_gauss(5, 0, 3, 11, 7)
+
+
+def _bf16(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_forward_bound_covers_bf16_activations():
+    """The first-order bound holds for an evaluation that rounds every hidden
+    activation to BF16, is not vacuous, and is zero for a zero network."""
+    rng = np.random.default_rng(3)
+    worst, ratios = 0.0, []
+    for t in range(200):
+        p = random_params(100 + t, scale=rng.choice([0.05, 0.1, 0.3]))
+        z = rng.normal(0, 1, 6)
+        out, bound = O.mlp_forward_bound(p, z)
+        W1, b1, W2, b2, W3, b3 = O.mlp_unpack(p)
+        h1 = _bf16(np.maximum(z @ W1 + b1, 0))
+        h2 = _bf16(np.maximum(h1 @ W2 + b2, 0))
+        o = h2 @ W3 + b3
+        e = np.abs(o - out)
+        assert np.all(e <= bound)
+        worst = max(worst, float(np.max(e / bound)))
+        ratios.append(np.max(bound / (np.abs(out) + 1e-12)))
+    assert worst > 1e-3          # the bound is of the right order, not vacuous
+    assert np.median(ratios) < 1.0
+    out, bound = O.mlp_forward_bound(np.zeros(O.mlp_nparam()), np.ones(6))
+    assert np.all(bound == 0)
+
+
+def test_capture_records_match_the_replayed_moves():
+    """Records of a capture run equal what the replay log of the same levels
+    implies: features at the old state, history of the last four accepted
+    scaled displacements (reset at each level), the accepted displacement;
+    their number is the run's accepted-move count."""
+    lo, hi = np.full(3, -500.0), np.full(3, 500.0)
+    kw = dict(seed=9, chains=8, steps=30, T0=20.0, alpha=0.8)
+    run = O.sa_run(O.SCHWEFEL, lo, hi, levels=3, level_begin=0, **kw)
+    rec, count = O.sa_run_capture(O.SCHWEFEL, lo, hi, levels=3, capacity=4096, **kw)
+    assert count == int(run["accepts"].sum()) == rec.shape[0]
+    expect = []
+    # levels 1 and 2 start from the previous winner; replay them
+    for level in (1, 2):
+        T = O.temperature(kw["T0"], kw["alpha"], level)
+        logs = O.replay_level(O.SCHWEFEL, lo, hi, None, seed=9, steps=30, T=T, level=level,
+                              x_start=run["x_best"][level - 1], chain0=0, nchains=8)
+        for c in range(8):
+            h = [0.0] * 4
+            for s in range(30):
+                if logs["acc"][c, s]:
+                    d = logs["d"][c, s]
+                    w = hi[d] - lo[d]
+                    dl = (logs["x_new"][c, s] - logs["x_old"][c, s]) / w
+                    feats = [math.copysign(math.log1p(2.0 ** 24 * abs(v)) / 16, v) for v in h]
+                    expect.append([(logs["x_old"][c, s] - lo[d]) / w, math.log(3 * T)] + feats + [dl])
+                    h = [dl] + h[:3]
+    got_late = rec[-len(expect):]
+    assert np.array_equal(got_late, np.array(expect, dtype=np.float32))
