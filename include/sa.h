@@ -114,6 +114,12 @@ typedef struct {
  * radius move only; workgroups are sized so the packed network fits in LDS
  * beside the chains' states. */
 #define SA_FLAG_LEARNED 0x4u
+/* Keep chain states as one shared level-start state per workgroup plus a
+ * per-chain table of the coordinates changed this level (chosen anyway when
+ * the dense per-chain state leaves fewer than two waves per CU, e.g. n >= 512
+ * in FP32).  Plain and logged moves only (not with SA_FLAG_LEARNED or
+ * sa_capture); results are identical to the dense layout. */
+#define SA_FLAG_OVERLAY 0x8u
 
 /* Per-level record returned by sa_trace. */
 typedef struct {
@@ -218,6 +224,11 @@ sa_status sa_capture(sa_ctx *ctx, float *records, uint64_t capacity);
 /* Accepted moves the capture has seen since sa_capture (synchronises); the
  * records stored are min(count, capacity). */
 sa_status sa_capture_count(sa_ctx *ctx, uint64_t *count);
+
+/* Layout the context launches with: lanes per workgroup, overlay table slots
+ * per chain (0 = dense per-chain state), and chain tiles (chains / workgroup).
+ * Any output may be NULL. */
+sa_status sa_layout(const sa_ctx *ctx, uint32_t *workgroup, uint32_t *overlay_slots, uint32_t *tiles);
 
 /* Release the context and any memory the library allocated. */
 void sa_destroy(sa_ctx *ctx);

@@ -46,6 +46,30 @@ uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, bool
     return 0;
 }
 
+// Overlay layout: the largest workgroup (4, 2 or 1 waves) dividing `chains`
+// whose tables hold at least 1.25 N + 1 slots per chain (probe lengths stay
+// short), with up to 2N slots.  Coordinates are 16-bit keys.
+bool pick_overlay(uint32_t n, uint32_t chains, uint32_t steps, size_t real_size, bool table, size_t lds_limit,
+                  uint32_t *wg_out, uint32_t *slots_out)
+{
+    if (n >= 0xFFFFu) return false;
+    const uint32_t want = std::max<uint32_t>(32u, (2 * steps + 7) / 8 * 8);
+    const uint32_t need = (steps + steps / 4 + 8) / 8 * 8;
+    for (uint32_t wg = 256; wg >= 64; wg >>= 1) {
+        if (chains % wg) continue;
+        const size_t fixed = sa::overlay_lds_bytes(n, wg, 0, real_size, table);
+        if (fixed >= lds_limit) continue;
+        size_t slots = (lds_limit - fixed) / ((size_t)wg * (real_size + 2)) / 8 * 8;
+        slots = std::min<size_t>(slots, want);
+        if (slots >= need && slots > steps) {
+            *wg_out = wg;
+            *slots_out = (uint32_t)slots;
+            return true;
+        }
+    }
+    return false;
+}
+
 constexpr uint32_t kNoStart = 0xFFFFFFFFu;
 
 struct Layout {
@@ -55,6 +79,8 @@ struct Layout {
 
 struct Plan {
     bool table = false;
+    bool overlay = false;
+    uint32_t ov_slots = 0;
     uint32_t wg = 0, groups = 0;
     size_t real = 0;
     Layout lay{};
@@ -69,8 +95,10 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED))
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY))
         return fail(SA_ERR_INVALID, "unknown flag bits");
+    if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
+        return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs on the dense state layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->precision != SA_FP32 || c->move != SA_MOVE_RADIUS))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs in FP32 with the radius move as its plain part");
     if (c->log_chains) {
@@ -97,6 +125,15 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     pl.real = c->precision == SA_FP64 ? sizeof(double) : sizeof(float);
     const bool learn = (c->flags & SA_FLAG_LEARNED) != 0;
     pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, lds_limit);
+    // Dense state unless it leaves fewer than two waves per CU (or the overlay
+    // is asked for): then a shared level-start state plus per-chain tables.
+    const size_t dense_waves =
+        pl.wg ? (lds_limit / sa::level_lds_bytes(p->n, pl.wg, pl.real, pl.table, learn)) * (pl.wg / 64) : 0;
+    if (!learn && ((c->flags & SA_FLAG_OVERLAY) || dense_waves < 2)) {
+        if (!pick_overlay(p->n, c->chains, c->steps, pl.real, pl.table, lds_limit, &pl.wg, &pl.ov_slots))
+            return fail(SA_ERR_UNSUPPORTED, "n=%u with %u steps fits neither state layout in LDS", p->n, c->steps);
+        pl.overlay = true;
+    }
     if (pl.wg == 0)
         return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
     pl.groups = c->chains / pl.wg;
@@ -177,6 +214,7 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.seed_hi = (uint32_t)(c->seed >> 32);
     a.wg = c->pl.wg;
     a.tiles = c->pl.groups;
+    a.ov_slots = c->pl.overlay ? c->pl.ov_slots : 0;
     a.table = c->pl.table ? reinterpret_cast<const R *>(w + l.table) : nullptr;
     a.inv_n = (float)(1.0 / (double)c->prob.n);
     a.T = reinterpret_cast<const double *>(w + l.T);
@@ -282,8 +320,13 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
         const int mode = c->learned ? (log ? sa::kModeLearnLog : sa::kModeLearn)
                                     : (log ? sa::kModeLog : (c->capturing ? sa::kModeCapture : sa::kModePlain));
         uint32_t g = 0;
-        hipError_t e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, mode, c->a64, k, *groups, &g, s)
-                               : sa::launch_level_f32(c->prob.func, c->pl.table, mode, c->a32, k, *groups, &g, s);
+        hipError_t e;
+        if (c->pl.overlay)
+            e = c->fp64 ? sa::launch_overlay_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
+                        : sa::launch_overlay_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
+        else
+            e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, mode, c->a64, k, *groups, &g, s)
+                        : sa::launch_level_f32(c->prob.func, c->pl.table, mode, c->a32, k, *groups, &g, s);
         if (e != hipSuccess) return fail(SA_ERR_DEVICE, "level %u launch: %s", k, hipGetErrorString(e));
         *groups = g;
     }
@@ -560,6 +603,15 @@ sa_status sa_move_log(sa_ctx *c, sa_move_rec *moves, double *final_f)
     return SA_OK;
 }
 
+sa_status sa_layout(const sa_ctx *c, uint32_t *workgroup, uint32_t *overlay_slots, uint32_t *tiles)
+{
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (workgroup) *workgroup = c->pl.wg;
+    if (overlay_slots) *overlay_slots = c->pl.overlay ? c->pl.ov_slots : 0;
+    if (tiles) *tiles = c->pl.groups;
+    return SA_OK;
+}
+
 sa_status sa_set_start(sa_ctx *c, uint32_t level, const double *x)
 {
     sa::g_last_error.clear();
@@ -625,6 +677,7 @@ sa_status sa_capture(sa_ctx *c, float *records, uint64_t capacity)
     if (records && reinterpret_cast<uintptr_t>(records) % sizeof(float))
         return fail(SA_ERR_INVALID, "records must be float-aligned");
     if (records && c->learned) return fail(SA_ERR_STATE, "capture records plain runs; clear the proposal first");
+    if (records && c->pl.overlay) return fail(SA_ERR_UNSUPPORTED, "capture runs on the dense state layout");
     drop_graphs(c);
     c->a32.cap_rec = records;
     c->a64.cap_rec = records;

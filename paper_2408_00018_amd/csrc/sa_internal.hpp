@@ -44,6 +44,7 @@ template <typename R> struct LevelArgs {
     const float *inv_T;  // 1 / T_k rounded to FP32
     uint32_t tiles;      // chains / wg
     uint32_t num_cus;    // compute units of the device (grid sizing)
+    uint32_t ov_slots;   // overlay layout: table slots per chain (0: dense layout)
     R *x_best;           // n: winner of the last finished level
     Slot<R> *slots;      // 2 x tiles candidates (double-buffered by level parity)
     R *slot_x;           // 2 x tiles x n candidate states
@@ -92,6 +93,13 @@ hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s);
 
 // Dynamic LDS bytes of a level launch (learn: the packed network as well).
 size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn);
+
+// Level launches on the base-plus-overlay state (plain and logged moves).
+hipError_t launch_overlay_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
+                                    uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+hipError_t launch_overlay_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
+                                    uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+size_t overlay_lds_bytes(uint32_t n, uint32_t wg, uint32_t slots, size_t real_size, bool table);
 
 }  // namespace sa
 

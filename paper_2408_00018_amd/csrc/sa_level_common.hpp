@@ -1,0 +1,157 @@
+// Level-boundary pieces shared by the level kernels (dense and overlay state
+// layouts): per-coordinate parameters, the workgroup's full evaluation of a
+// state in LDS, and the reduction of the previous level's candidates to the
+// winner every chain starts from (Sec. 2.2.2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sa_device.hpp"
+#include "sa_internal.hpp"
+#include "sa_step.hpp"
+
+namespace sa {
+
+template <typename R, bool TABLE>
+__device__ __forceinline__ Coord<R> coord(const LevelArgs<R> &a, const R *tab, uint32_t d)
+{
+    if (TABLE) return Coord<R>{tab[4 * d + 0], tab[4 * d + 1], tab[4 * d + 2], tab[4 * d + 3]};
+    return Coord<R>{a.lo, a.hi, a.rho, a.sh};
+}
+
+// ---------------------------------------------------------------------------
+// Full evaluation of a state held in LDS, FP64 arithmetic.  FP64 runs sum in
+// coordinate order on one lane (the order of a plain sequential
+// evaluation); FP32 runs use a fixed parallel order.
+// ---------------------------------------------------------------------------
+template <typename R, int F, bool TABLE>
+__device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, double (*part)[2])
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    const uint32_t n = a.n;
+    if (sizeof(R) == sizeof(double)) {
+        if (tid == 0) {
+            FullAcc<F> acc;
+            for (uint32_t i = 0; i < n; ++i) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+            const Full v = acc.finish(n);
+            part[0][0] = v.f;
+            part[0][1] = v.s1;
+            part[1][0] = v.s2;
+        }
+        __syncthreads();
+        const Full v{part[0][0], part[0][1], part[1][0]};
+        __syncthreads();
+        return v;
+    }
+    FullAcc<F> acc;
+    for (uint32_t i = tid; i < n; i += blockDim.x) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+    const double pa = wave_sum_d(acc.a), pb = wave_sum_d(acc.b);
+    if (lane == 0) {
+        part[wave][0] = pa;
+        part[wave][1] = pb;
+    }
+    __syncthreads();
+    FullAcc<F> tot;
+    for (uint32_t w = 0; w < nwaves; ++w) {
+        tot.a += part[w][0];
+        tot.b += part[w][1];
+    }
+    __syncthreads();
+    return tot.finish(n);
+}
+
+// ---------------------------------------------------------------------------
+// Reduce the candidates level `lvl` published (`groups` of them) to the
+// level's winner: lowest carried cost, ties to the lowest chain.  Every
+// workgroup that calls this gets the same winner; its state goes to xw and
+// its full re-evaluation to start.  With `publish` the workgroup also writes
+// the level's trace entry, the record and the broadcast state.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t groups, R *xw, double *start,
+                             bool publish, Slot<R> *wave_slot, uint64_t *wave_acc)
+{
+    const uint32_t WG = blockDim.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = WG >> 6;
+    const uint32_t n = a.n;
+    const size_t base = (size_t)(lvl & 1u) * a.tiles;
+    R gf = widen_inf<R>();
+    uint32_t gc = 0xFFFFFFFFu, gj = 0;
+    uint64_t gacc = 0;
+    for (uint32_t j = tid; j < groups; j += WG) {
+        const Slot<R> s = a.slots[base + j];
+        if (s.f < gf || (s.f == gf && s.chain < gc)) {
+            gf = s.f;
+            gc = s.chain;
+            gj = j;
+        }
+        gacc += s.accepts;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const R f2 = __shfl_xor(gf, off, 64);
+        const uint32_t c2 = __shfl_xor(gc, off, 64);
+        const uint32_t j2 = __shfl_xor(gj, off, 64);
+        if (f2 < gf || (f2 == gf && c2 < gc)) {
+            gf = f2;
+            gc = c2;
+            gj = j2;
+        }
+    }
+    gacc = wave_sum(gacc);
+    __syncthreads();
+    if (lane == 0) {
+        wave_slot[wave] = Slot<R>{gf, gc, gj, 0u, 0.0, 0.0, 0.0};
+        wave_acc[wave] = gacc;
+    }
+    __syncthreads();
+    gf = wave_slot[0].f;
+    gc = wave_slot[0].chain;
+    gj = wave_slot[0].accepts;
+    gacc = wave_acc[0];
+    for (uint32_t w = 1; w < nwaves; ++w) {
+        if (wave_slot[w].f < gf || (wave_slot[w].f == gf && wave_slot[w].chain < gc)) {
+            gf = wave_slot[w].f;
+            gc = wave_slot[w].chain;
+            gj = wave_slot[w].accepts;
+        }
+        gacc += wave_acc[w];
+    }
+    if (gj >= groups) gj = 0;  // only if every candidate cost were NaN; keeps the index in range
+    const size_t w = base + gj;
+    for (uint32_t i = tid; i < n; i += WG) xw[i] = a.slot_x[w * n + i];
+    const Slot<R> ws = a.slots[w];
+    if (tid == 0) {
+        start[0] = ws.ff;
+        start[1] = ws.s1;
+        start[2] = ws.s2;
+    }
+    if (publish) {
+        const bool improved = ws.ff < a.rec[0];
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += WG) {
+            const R v = a.slot_x[w * n + i];
+            a.x_best[i] = v;
+            if (a.trace_x) a.trace_x[(size_t)lvl * n + i] = v;
+            if (improved) a.x_rec[i] = v;
+        }
+        if (tid == 0) {
+            if (improved) {
+                a.rec[0] = ws.ff;
+                *a.rec_level = lvl;
+            }
+            sa_level t;
+            t.win_chain = gc;
+            t.reserved = 0;
+            t.f_win = (double)gf;
+            t.f_best = ws.ff;
+            t.f_rec = improved ? ws.ff : a.rec[0];
+            t.accepts = gacc;
+            t.t_ticks = wall_clock64();
+            a.trace[lvl] = t;
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace sa

@@ -20,15 +20,15 @@ LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
-FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED = 0x1, 0x2, 0x4
+FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8
 
 SA_OK = 0
 STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ERR_DEVICE", -4: "SA_ERR_STATE",
                 -5: "SA_ERR_UNSUPPORTED"}
 
 EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
-            "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_destroy",
-            "sa_last_error"]
+            "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_layout",
+            "sa_destroy", "sa_last_error"]
 
 
 class SAError(RuntimeError):
@@ -96,6 +96,8 @@ def load_library():
     L.sa_capture.restype = st
     L.sa_capture_count.argtypes = [vp, ctypes.POINTER(u64)]
     L.sa_capture_count.restype = st
+    L.sa_layout.argtypes = [vp, vp, vp, vp]
+    L.sa_layout.restype = st
     L.sa_destroy.argtypes = [vp]
     L.sa_destroy.restype = None
     L.sa_last_error.argtypes = []
@@ -124,13 +126,14 @@ class Schedule:
     trace_x: bool = False
     graph: bool = False
     learned: bool = False  # reserve room for a learned proposal (sa_set_proposal)
+    overlay: bool = False  # force the base-plus-overlay state layout
     log_chains: int = 0
     log_level: int = 0
     log_levels: int = 0
 
     def to_c(self) -> Config:
         flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
-                 (FLAG_LEARNED if self.learned else 0))
+                 (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
                       self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels, 0)
 
@@ -235,6 +238,12 @@ class Annealer:
         assert records.dim() == 2 and records.shape[1] == 7 and records.is_contiguous()
         self._cap = records
         _check(load_library().sa_capture(self._ctx, ctypes.c_void_p(records.data_ptr()), records.shape[0]))
+
+    def layout(self):
+        """(lanes per workgroup, overlay slots per chain or 0, tiles)."""
+        v = [ctypes.c_uint32() for _ in range(3)]
+        _check(load_library().sa_layout(self._ctx, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def capture_count(self) -> int:
         v = ctypes.c_uint64()

@@ -100,9 +100,19 @@ def test_invalid_problems_are_rejected(S):
 
 
 def test_state_too_large_for_lds_is_unsupported(S):
+    # n = 5000 fits only as a shared start state plus per-chain tables
     lo, hi = np.full(5000, -1.0), np.full(5000, 1.0)
+    assert S.workspace_bytes(0, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9)) > 0
+    # two copies of n = 25000 FP32 coordinates exceed the 160 KiB of LDS in either layout
+    lo, hi = np.full(25000, -1.0), np.full(25000, 1.0)
     with pytest.raises(S.SAError) as e:
         S.workspace_bytes(0, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9))
+    assert e.value.status == -5
+    # the learned proposal needs the dense layout
+    lo, hi = np.full(16, -1.0), np.full(16, 1.0)
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(0, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9, learned=True,
+                                                      overlay=True))
     assert e.value.status == -5
 
 

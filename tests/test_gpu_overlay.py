@@ -1,0 +1,149 @@
+"""GPU parity of the base-plus-overlay state layout (a shared level-start
+state per workgroup plus a per-chain table of changed coordinates) against
+the FP64 oracle.
+
+The layout changes where a chain's coordinates live, not the arithmetic, so
+FP64 runs must reproduce the oracle's trajectory exactly (forced at small n,
+and chosen by the library where the dense state does not fit), and FP32 runs
+are replayed move by move at the large-n workloads' shapes (n = 512
+Rastrigin and n = 1024 Ackley, shifted, 64 steps per level), including a
+full-size n = 1024 run of 131072 chains with its last levels logged.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity_util import check_fp32_run, check_record
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2408_00018_amd import sa
+    sa.load_library()
+    return sa
+
+
+def run(S, wl, chunks=None, **kw):
+    d = dict(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+             precision=wl.precision, radius_frac=wl.radius_frac, trace_x=True)
+    d.update(kw)
+    sched = S.Schedule(**d)
+    say(f"[gpu overlay] {wl.name} n={wl.n} chains={sched.chains} levels={sched.levels} steps={sched.steps} "
+        f"prec={sched.precision} overlay={sched.overlay} log={sched.log_chains}@{sched.log_level}+{sched.log_levels}")
+    with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as a:
+        for c in (chunks or [0]):
+            a.run(c)
+        rec, xb = a.trace(with_x=True)
+        x_rec, f_rec, lvl = a.best()
+        out = dict(rec=rec, xb=xb, x_rec=x_rec, f_rec=f_rec, rec_level=lvl, layout=a.layout())
+        if sched.log_chains:
+            out["moves"], out["final_f"] = a.move_log()
+    say(f"[gpu overlay] layout (workgroup, slots, tiles) = {out['layout']}")
+    return out
+
+
+def oracle_run(wl, move_rule=O.MOVE_RADIUS):
+    return O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=wl.chains, steps=wl.steps, T0=wl.T0,
+                    alpha=wl.alpha, levels=wl.levels, radius_frac=wl.radius_frac, move_rule=move_rule)
+
+
+def assert_trajectory_equal(g, o):
+    assert np.array_equal(g["rec"]["win_chain"], o["win_chain"])
+    assert np.array_equal(g["rec"]["accepts"], o["accepts"])
+    np.testing.assert_allclose(g["xb"], o["x_best"], rtol=1e-12, atol=1e-12)
+    for k in ("f_win", "f_best", "f_rec"):
+        np.testing.assert_allclose(g["rec"][k], o[k], rtol=1e-12, atol=1e-12)
+    assert g["rec_level"] == o["rec_level"]
+
+
+FP64_CASES = [
+    # func, n, chains, levels, steps, box
+    (W.SCHWEFEL, 7, 192, 10, 40, "uneven"),
+    (W.RASTRIGIN, 64, 256, 6, 50, "shifted"),
+    (W.ACKLEY, 9, 320, 8, 25, "shifted"),
+    (W.SCHWEFEL, 1, 64, 4, 30, "canonical"),
+]
+
+
+@pytest.mark.parametrize("func,n,chains,levels,steps,box", FP64_CASES)
+def test_fp64_overlay_trajectory_equals_oracle(S, func, n, chains, levels, steps, box):
+    wl = W.random_problem(func, n, seed=2000 + 10 * func + n, shifted=(box == "shifted"))
+    if box == "uneven":
+        lo, hi = W.uneven_box(n, 91 + n)
+        wl = wl.with_(lower=lo, upper=hi, shift=None)
+    wl = wl.with_(chains=chains, levels=levels, steps=steps, precision=W.FP64)
+    g = run(S, wl, overlay=True)
+    assert g["layout"][1] > steps
+    assert_trajectory_equal(g, oracle_run(wl))
+
+
+def test_fp64_overlay_chosen_for_large_n(S):
+    """n = 700 in FP64 (358 KB of dense state per wave) runs on the overlay."""
+    wl = W.random_problem(W.ACKLEY, 700, seed=5).with_(chains=128, levels=4, steps=16, precision=W.FP64)
+    g = run(S, wl)
+    assert g["layout"][1] > 0
+    assert_trajectory_equal(g, oracle_run(wl))
+
+
+def test_fp64_overlay_resample_graph_and_chunks(S):
+    wl = W.random_problem(W.RASTRIGIN, 11, seed=8).with_(chains=256, levels=7, steps=20, precision=W.FP64)
+    whole = run(S, wl, overlay=True, move=S.MOVE_RESAMPLE)
+    graph = run(S, wl, overlay=True, move=S.MOVE_RESAMPLE, graph=True, chunks=[3, 0])
+    assert np.array_equal(whole["xb"], graph["xb"])
+    assert_trajectory_equal(whole, oracle_run(wl, O.MOVE_RESAMPLE))
+
+
+def shifted_large(func, n, chains, levels, steps=64):
+    base = W.rastrigin_n512_fp32() if func == W.RASTRIGIN else W.ackley_n1024_fp32()
+    return base.with_(n=n, lower=base.lower[:n], upper=base.upper[:n], shift=base.shift[:n], x_star=base.shift[:n],
+                      chains=chains, levels=levels, steps=steps, name=f"{base.name[:9]}_n{n}")
+
+
+@pytest.mark.parametrize("func,n", [(W.RASTRIGIN, 512), (W.ACKLEY, 1024)])
+def test_fp32_overlay_moves_large_n(S, func, n):
+    wl = shifted_large(func, n, chains=1024, levels=3)
+    g = run(S, wl, log_chains=64, log_level=0, log_levels=3)
+    assert g["layout"][1] > 64
+    check_fp32_run(wl, g, 0, chain_ids=list(range(0, 64, 9)), say=say)
+    check_record(wl, g)
+
+
+def test_fp32_overlay_equals_dense_at_moderate_n(S):
+    """The same FP32 run on both layouts is bitwise identical."""
+    wl = W.random_problem(W.SCHWEFEL, 100, seed=12, shifted=False).with_(chains=2048, levels=6, steps=100)
+    dense = run(S, wl)
+    ov = run(S, wl, overlay=True)
+    assert dense["layout"][1] == 0 and ov["layout"][1] > 0
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    assert np.array_equal(dense["rec"][keys], ov["rec"][keys])
+    assert np.array_equal(dense["xb"], ov["xb"])
+
+
+def test_fp32_ackley_n1024_full_size(S):
+    """The n = 1024 Ackley workload at full size (131072 chains, 1000 levels x
+    64 steps): every level's record properties, the re-evaluated broadcasts,
+    and per-move parity of sampled chains at the last two levels."""
+    wl = W.ackley_n1024_fp32()
+    g = run(S, wl, log_chains=wl.chains, log_level=wl.levels - 2, log_levels=2, graph=True)
+    assert g["layout"][1] > 64
+    rng = np.random.default_rng(1)
+    sample = sorted(int(c) for c in rng.choice(wl.chains, 12, replace=False))
+    check_fp32_run(wl, g, wl.levels - 2, chain_ids=sample, say=say)
+    check_record(wl, g)
+    sh = np.asarray(wl.shift, dtype=np.float32).astype(np.float64)
+    for lvl in rng.choice(wl.levels, 12, replace=False):
+        fb = O.f(wl.func, g["xb"][lvl], sh)
+        assert abs(g["rec"]["f_best"][lvl] - fb) <= 1e-11 * max(1.0, abs(fb))
+    say(f"[gpu overlay] ackley n=1024 record {g['f_rec']:.6g} at level {g['rec_level']}")

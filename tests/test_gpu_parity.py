@@ -55,7 +55,7 @@ def run_gpu(S, wl, chunks=None, **kw):
             a.run(c)
         rec, xb = a.trace(with_x=True)
         x_rec, f_rec, lvl = a.best()
-        out = dict(rec=rec, xb=xb, x_rec=x_rec, f_rec=f_rec, rec_level=lvl)
+        out = dict(rec=rec, xb=xb, x_rec=x_rec, f_rec=f_rec, rec_level=lvl, layout=a.layout())
         if sched.log_chains:
             out["moves"], out["final_f"] = a.move_log()
     return out
@@ -210,15 +210,18 @@ def test_edges_single_level_single_step(S):
     assert_trajectory_equal(run_gpu(S, wl), run_oracle(wl))
 
 
-def test_largest_dense_state(S):
-    """n=600 FP32 (153.6 KB of LDS per 64-chain workgroup) runs; n=700 does not fit and is refused."""
-    wl = W.random_problem(W.SCHWEFEL, 600, seed=1, shifted=False).with_(chains=128, levels=2, steps=16)
+def test_layout_choice_by_dimension(S):
+    """n=300 FP32 (76.8 KB per 64-chain workgroup, two waves per CU) keeps the
+    dense state; n=700 (which does not fit densely) runs on the shared start
+    state plus per-chain tables; both replay move for move."""
+    wl = W.random_problem(W.SCHWEFEL, 300, seed=1, shifted=False).with_(chains=128, levels=2, steps=16)
     g = run_gpu(S, wl, log_chains=64, log_level=0, log_levels=2)
+    assert g["layout"][1] == 0
     check_fp32_run(S, wl, g, 0, chain_ids=[0, 33])
     big = W.random_problem(W.SCHWEFEL, 700, seed=1, shifted=False).with_(chains=128, levels=2, steps=16)
-    with pytest.raises(S.SAError) as e:
-        run_gpu(S, big)
-    assert e.value.status == -5
+    g = run_gpu(S, big, log_chains=64, log_level=0, log_levels=2)
+    assert g["layout"][1] > 16
+    check_fp32_run(S, big, g, 0, chain_ids=[0, 33])
 
 
 def test_error_paths(S):
