@@ -196,9 +196,10 @@ sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
  * Learned proposal (an extension of the method, not in the paper).  With
  * params (SA_MLP_PARAMS host floats, the network of sa_mlp_*) every later
  * move is, with probability eps, the plain radius move with the Metropolis
- * test, and otherwise a draw from the network's Gaussian over the chosen
- * coordinate's scaled displacement, dl = mu + exp(s) g (g standard normal by
- * Box-Muller on the Philox block (step, level, chain, 3 | problem << 8)),
+ * test, and otherwise a draw from the network's Cauchy distribution over the
+ * chosen coordinate's scaled displacement, dl = mu + exp(s) t (t standard
+ * Cauchy, tan(pi (U - 1/2)) with U from word 0 of the Philox block
+ * (step, level, chain, 3 | problem << 8)),
  * x'_d = x_d + dl (u_d - l_d); a proposal outside [l_d, u_d] is rejected, and
  * otherwise it is taken iff U < exp(-df/T + ln q(x | x') - ln q(x' | x))
  * (Metropolis-Hastings with the network evaluated at x_d and at x'_d, both
@@ -316,11 +317,12 @@ const char *sa_last_error(void);
  * the chain's last four accepted scaled displacements h, most recent first,
  * each as sign(h) ln(1 + 2^24 |h|) / 16; tau = n for Schwefel and Ackley, 1
  * for Rastrigin) -> 128 (relu) -> 128
- * (relu) -> (mu, s): a Gaussian N(mu, exp(s)^2) over the coordinate's scaled
- * displacement (x'_d - x_d)/(u_d - l_d).  Parameters: SA_MLP_PARAMS floats,
- * W1[6][128], b1[128], W2[128][128], b2[128], W3[128][2], b3[2].  Training
- * minimises the mean Gaussian negative log-likelihood s + (d - mu)^2 /
- * (2 exp(2 s)) of captured accepted displacements d with Adam (FP32 master
+ * (relu) -> (mu, s): a Cauchy distribution with location mu and scale
+ * exp(s) over the coordinate's scaled displacement (x'_d - x_d)/(u_d - l_d).
+ * Parameters: SA_MLP_PARAMS floats, W1[6][128], b1[128], W2[128][128],
+ * b2[128], W3[128][2], b3[2].  Training minimises the mean Cauchy negative
+ * log-likelihood s + ln pi + ln(1 + ((d - mu)/exp(s))^2) of captured accepted
+ * displacements d with Adam (FP32 master
  * weights, BF16 weight matrices, BF16 MFMA with FP32 accumulate).
  * Captured records: 7 floats each, (z[0..5], d).
  * ------------------------------------------------------------------------ */

@@ -101,8 +101,8 @@ def lib():
         L.orc_hist_feature.restype = _d
         L.orc_mlp_forward_bound.argtypes = [_p, _p, _p, _p]
         L.orc_mlp_forward_bound.restype = None
-        L.orc_learn_gauss.argtypes = [_u64, _u32, _u32, _u32, _u32]
-        L.orc_learn_gauss.restype = _d
+        L.orc_learn_draw.argtypes = [_u64, _u32, _u32, _u32, _u32]
+        L.orc_learn_draw.restype = _d
         L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
                                          _p, _d, _p, ctypes.c_uint64, _p]
         L.orc_sa_run_capture.restype = _i
@@ -329,9 +329,9 @@ def hist_feature(h: float) -> float:
     return lib().orc_hist_feature(h)
 
 
-def learn_gauss(seed, problem, level, chain, step) -> float:
-    """Standard normal draw of a learned move (Box-Muller, Philox tag 3)."""
-    return lib().orc_learn_gauss(seed, problem, level, chain, step)
+def learn_draw(seed, problem, level, chain, step) -> float:
+    """Standard Cauchy draw of a learned move (inversion, Philox tag 3)."""
+    return lib().orc_learn_draw(seed, problem, level, chain, step)
 
 
 def feature_tau(func, n):

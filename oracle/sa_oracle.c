@@ -483,7 +483,8 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 /* ======================================================================== */
 /* Learned proposal (an extension of the method, not in the paper): a small  */
 /* per-coordinate network maps the features of the chosen coordinate to a   */
-/* Gaussian over its scaled displacement.  FP64 reference of its forward     */
+/* Cauchy distribution over its scaled displacement.  FP64 reference of its */
+/* forward pass,                                                            */
 /* pass, negative log-likelihood loss, gradient and Adam step.               */
 /*                                                                          */
 /* Features z (6): z0 = (x_d - l_d)/(u_d - l_d); z1 = ln(tau T), tau = n    */
@@ -492,11 +493,16 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 /* four accepted scaled displacements h, most recent first, each as          */
 /* sign(h) ln(1 + 2^24 |h|) / 16 (orc_hist_feature).                         */
 /* Network: a1 = z W1 + b1 (6x128), h1 = relu(a1); a2 = h1 W2 + b2 (128x128), */
-/* h2 = relu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma.        */
-/* Loss of a record (z, delta): s + (delta - mu)^2 / (2 exp(2 s)).           */
+/* h2 = relu(a2); o = h2 W3 + b3 (128x2); mu = o0, s = o1 = ln sigma: the    */
+/* location and log scale of a Cauchy distribution over the scaled           */
+/* displacement (heavy tails: a likelihood fit follows the typical accepted  */
+/* step rather than the rare long jumps, and proposals still make some).     */
+/* Loss of a record (z, delta): the Cauchy negative log-likelihood           */
+/* s + ln pi + ln(1 + ((delta - mu) / e^s)^2).                               */
 /* Parameter vector order: W1 (row-major, [in][out]), b1, W2, b2, W3, b3.    */
 /* ======================================================================== */
 #define ORC_H 128
+#define ORC_LN_PI 1.14472988584940017414
 #define ORC_NIN 6
 #define ORC_NPARAM (ORC_NIN * ORC_H + ORC_H + ORC_H * ORC_H + ORC_H + ORC_H * 2 + 2)
 
@@ -569,11 +575,12 @@ double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, 
         }
         const double mu = o[0], s = o[1];
         const double e = delta[r] - mu;
-        const double inv_var = exp(-2.0 * s);
-        loss += (s + 0.5 * e * e * inv_var) * inv_b;
+        const double r = e * exp(-s); /* standardised residual */
+        const double q = 1.0 + r * r;
+        loss += (s + ORC_LN_PI + log(q)) * inv_b;
         if (!grad) continue;
-        const double dmu = -e * inv_var * inv_b;
-        const double ds = (1.0 - e * e * inv_var) * inv_b;
+        const double dmu = -2.0 * r * exp(-s) / q * inv_b;
+        const double ds = (1.0 - 2.0 * r * r / q) * inv_b;
         double dh2[ORC_H], da2[ORC_H], dh1[ORC_H], da1[ORC_H];
         gb3[0] += dmu;
         gb3[1] += ds;
@@ -640,22 +647,22 @@ void orc_mlp_forward_bound(const double *params, const double *z, double *out2, 
     }
 }
 
-/* Standard normal draw of a learned move: Box-Muller on the first two words
- * (U0, U1) of the Philox block (step, level, chain, 3 | problem << 8):
- * g = sqrt(-2 ln(1 - U0)) cos(2 pi U1). */
-double orc_learn_gauss(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
+/* Standard Cauchy draw of a learned move, by inversion of its distribution
+ * function on the first word U0 of the Philox block
+ * (step, level, chain, 3 | problem << 8): t = tan(pi (U0 - 1/2)). */
+double orc_learn_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
 {
     const uint32_t ctr[4] = {step, level, chain, 3u | (problem << 8)};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t r[4];
     orc_philox4x32_10(ctr, key, r);
-    const double u0 = orc_uniform(r[0]), u1 = orc_uniform(r[1]);
-    return sqrt(-2.0 * log(1.0 - u0)) * cos(2.0 * ORC_PI * u1);
+    return tan(ORC_PI * (orc_uniform(r[0]) - 0.5));
 }
 
-/* Log density of the proposal, in scaled units: ln N(delta; mu, sigma^2). */
+/* Log density of the proposal, in scaled units: the Cauchy density with
+ * location mu and scale e^s at delta. */
 double orc_proposal_logpdf(double delta, double mu, double s)
 {
-    const double e = delta - mu;
-    return -s - 0.5 * e * e * exp(-2.0 * s) - 0.91893853320467274178; /* ln sqrt(2 pi) */
+    const double r = (delta - mu) * exp(-s);
+    return -s - ORC_LN_PI - log(1.0 + r * r);
 }

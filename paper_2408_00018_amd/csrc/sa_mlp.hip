@@ -2,8 +2,8 @@
 // include/sa.h).
 //
 // Network (per chosen coordinate): z (6 features) -> 128 (relu) -> 128
-// (relu) -> 2 outputs (mean and log standard deviation of a Gaussian
-// over the coordinate's scaled displacement); loss = Gaussian negative
+// (relu) -> 2 outputs (location and log scale of a Cauchy distribution over
+// the coordinate's scaled displacement); loss = Cauchy negative
 // log-likelihood of accepted displacements.  Master parameters and Adam
 // moments are FP32; the three weight matrices are used in BF16.  The
 // 128x128 layer and its two backward products run on BF16 MFMA
@@ -125,11 +125,12 @@ __global__ void __launch_bounds__(256) layer3_loss(const float *H2, const float 
         o1 += __shfl_xor(o1, off, 64);
     }
     const float mu = o0 + b3[0], s = o1 + b3[1];
-    const float e = delta[r] - mu;
-    const float iv = expf(-2.0f * s);
-    const float dmu = -e * iv * inv_b, ds = (1.0f - e * e * iv) * inv_b;
+    const float is = expf(-s);
+    const float rr = (delta[r] - mu) * is;  // standardised residual
+    const float q = 1.0f + rr * rr;
+    const float dmu = -2.0f * rr * is / q * inv_b, ds = (1.0f - 2.0f * rr * rr / q) * inv_b;
     if (lane == 0) {
-        loss_r[r] = s + 0.5f * e * e * iv;
+        loss_r[r] = s + 1.14472988584940017f + logf(q);  // + ln pi
         dO[2 * r + 0] = dmu;
         dO[2 * r + 1] = ds;
     }

@@ -289,8 +289,8 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
 //   d from r0; a plain move with probability eps (U(r3) < eps): the radius
 //   neighbour from r1 and the Metropolis test on r2, as in run_steps;
 //   otherwise the network gives (mu, s) at the features of x_d, the scaled
-//   displacement is dl = mu + e^s g with g = sqrt(-2 ln(1 - U(q0)))
-//   cos(2 pi U(q1)) (Box-Muller), x'_d = x_d + dl (u_d - l_d); a proposal
+//   displacement is dl = mu + e^s t with t = tan(pi (U(q0) - 1/2)) (a standard
+//   Cauchy draw by inversion), x'_d = x_d + dl (u_d - l_d); a proposal
 //   outside [l_d, u_d] is rejected; otherwise the network is evaluated again
 //   at x'_d (same history) and the move is taken iff
 //       U(r2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
@@ -324,16 +324,19 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
         float z[mlp::kInputs] = {(xd - c.lo) * inv_w, featT, h[0], h[1], h[2], h[3]};
         float mu, s;
         mlp::net_forward(net, z, mu, s);
-        const float gz = hw_sqrt(-2.0f * kLn2 * hw_log2(1.0f - u24f(q.w0))) * hw_cos_rev(u24f(q.w1));
-        const float dl = fmaf(hw_exp2(kLog2e * s), gz, mu);
+        // tan(pi a) = sin(2 pi a/2) / cos(2 pi a/2) on the revolution-based units
+        const float half = 0.5f * (u24f(q.w0) - 0.5f);
+        const float t = hw_sin_rev(half) / hw_cos_rev(half);
+        const float dl = fmaf(hw_exp2(kLog2e * s), t, mu);
         const float xl = fmaf(dl, w, xd);
         const bool inbox = xl >= c.lo && xl <= c.hi;
         z[0] = inbox ? (xl - c.lo) * inv_w : 0.5f;
         float mu2, s2;
         mlp::net_forward(net, z, mu2, s2);
-        // ln q(x | x') - ln q(x' | x); the forward standardised residual is gz
+        // ln q(x | x') - ln q(x' | x) for Cauchy densities; the forward
+        // standardised residual is t
         const float e2 = (dl + mu2) * hw_exp2(-kLog2e * s2);
-        const float lq = (s - s2) + 0.5f * (gz * gz - e2 * e2);
+        const float lq = (s - s2) + kLn2 * (hw_log2(fmaf(t, t, 1.0f)) - hw_log2(fmaf(e2, e2, 1.0f)));
 
         const float xp = neighbour<SA_MOVE_RADIUS>(xd, c, u24f(r.w1));
         const float xn = plain ? xp : xl;

@@ -3,8 +3,10 @@ paper's moves are the plain radius/resample neighbours).
 
 1. ``collect``: plain FP32 runs with capture switched on at every k-th level
    record accepted moves (features at the old state, accepted scaled
-   displacement) across the whole temperature range.
-2. ``train``: Adam on the Gaussian negative log-likelihood of those records,
+   displacement) across the whole temperature range, the same number from
+   every captured level (acceptance falls by orders of magnitude as T drops,
+   so levels with fewer accepted moves are repeated to the quota).
+2. ``train``: Adam on the Cauchy negative log-likelihood of those records,
    on the GPU (``MLPTrainer``).
 3. ``time_to_target``: run a schedule with plain or learned moves and report
    the first level whose record is within ``target`` of f*, with its device
@@ -39,10 +41,11 @@ def init_params(seed: int = 0, sigma0: float = 0.01) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, per_level: int = 20000):
+def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, per_level: int = 2000):
     """Run `schedule` (plain moves) and capture the accepted moves of every
-    `every`-th level, at most `per_level` records each.  Returns a float32
-    CUDA tensor [N, 7]."""
+    `every`-th level: the first `per_level` of each, or all of them repeated
+    up to `per_level` when there are fewer.  Returns a float32 CUDA tensor
+    [N, 7]."""
     import torch
     nlev = (schedule.levels + every - 1) // every
     rec = torch.empty((nlev * per_level, 7), dtype=torch.float32, device="cuda")
@@ -53,8 +56,13 @@ def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, pe
         while level < sched.levels:
             ann.capture(rec[off:off + per_level])
             ann.run(1)
-            off += min(ann.capture_count(), per_level)
+            got = min(ann.capture_count(), per_level)
             ann.capture(None)
+            if got:
+                if got < per_level:
+                    rep = off + torch.arange(per_level - got, device=rec.device) % got
+                    rec[off + got:off + per_level] = rec[rep]
+                off += per_level
             level += 1
             rest = min(every - 1, sched.levels - level)
             if rest:
@@ -63,7 +71,7 @@ def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, pe
     return rec[:off]
 
 
-def train(records, steps: int = 2000, batch: int = 1024, lr: float = 1e-3, seed: int = 0,
+def train(records, steps: int = 6000, batch: int = 1024, lr: float = 1e-3, seed: int = 0,
           params: Optional[np.ndarray] = None):
     """Train the proposal network on `records`; returns (params, loss trace)."""
     tr = sa.MLPTrainer(max_batch=batch)

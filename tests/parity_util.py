@@ -266,15 +266,17 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                 hf = [O.hist_feature(v) for v in h]
                 z = [(x_old - lo) / w, featT] + hf
                 (mu, sl), (bmu, bs) = O.mlp_forward_bound(params64, z)
-                g = O.learn_gauss(seed, problem, level, c, s)
+                t = O.learn_draw(seed, problem, level, c, s)
                 sig = math.exp(sl)
-                dl_ref = mu + sig * g
+                dl_ref = mu + sig * t
                 dl_gpu = (float(m["x_new"]) - x_old) / w
-                # network bound, the FP32 rounding of the sampled displacement
-                # and of x' = x + dl w (relative to the box width), and the
-                # hardware log/sqrt/cos/exp2 error of g and e^s (a few ulp)
-                tol_dl = bmu + sig * abs(g) * (math.expm1(bs) + 2.0 ** -18) + sig * 2.0 ** -18 * (1 + abs(g)) \
-                    + 4 * U32 * (abs(dl_ref) + (abs(x_old) + abs(float(m["x_new"]))) / w)
+                # rounding of x' = x + dl w and of the logged positions, in dl units
+                ddl = 4 * U32 * (abs(x_old) + abs(float(m["x_new"]))) / w
+                # network bound; e^s within e^{+-bs}; the hardware sin/cos quotient
+                # for t (relative error growing like |t| towards the poles); FP32
+                # rounding of the draw and the fused multiply-add
+                tol_dl = (bmu + sig * abs(t) * (math.expm1(bs) + 2.0 ** -18)
+                          + sig * 2.0 ** -18 * (1 + abs(t) + t * t) + 4 * U32 * abs(dl_ref) + ddl)
                 err = abs(dl_gpu - dl_ref)
                 stats["max_dl_excess"] = max(stats["max_dl_excess"], err / tol_dl)
                 assert err <= tol_dl, (level, c, s, dl_gpu, dl_ref, tol_dl)
@@ -290,11 +292,14 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                     assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
                     stats["max_rel_excess"] = max(stats["max_rel_excess"], abs(m["df"] - df_ref) / tol)
                     lq = O.proposal_logpdf(-dl_gpu, mu2, s2) - O.proposal_logpdf(dl_gpu, mu, sl)
-                    # first-order sensitivity of lq to the network outputs
+                    # first-order sensitivity of the two Cauchy log densities to
+                    # their location and log scale (and to dl's rounding)
                     e1 = (dl_gpu - mu) * math.exp(-sl)
                     e2 = (-dl_gpu - mu2) * math.exp(-s2)
-                    tol_lq = (abs(e1) * math.exp(-sl) * bmu + abs(1 - e1 * e1) * bs
-                              + abs(e2) * math.exp(-s2) * bmu2 + abs(1 - e2 * e2) * bs2)
+                    tol_lq = (2 * abs(e1) * math.exp(-sl) / (1 + e1 * e1) * (bmu + ddl)
+                              + abs(1 - 2 * e1 * e1 / (1 + e1 * e1)) * bs
+                              + 2 * abs(e2) * math.exp(-s2) / (1 + e2 * e2) * (bmu2 + ddl)
+                              + abs(1 - 2 * e2 * e2 / (1 + e2 * e2)) * bs2)
                     r = -df_ref / T + lq
                     tol_r = 2 * tol_lq + tol / T + 2.0 ** -16 * (1 + abs(r))
                     lu = math.log(u2) if u2 > 0 else -math.inf

@@ -206,7 +206,7 @@ def test_learned_per_move_parity(S, name):
     wl = learned_case(name)
     kw = dict(chains=512, levels=3, steps=32, T0=5.0 if wl.func != W.SCHWEFEL else 20.0, alpha=0.7, seed=23)
     eps = 0.25
-    p = learned_params(31, scale=0.08, sigma0=0.03)
+    p = learned_params(31, scale=0.05, sigma0=0.03)
     say(f"[gpu learned] per-move {name}")
     g = run_learned(S, wl, p, eps, log_chains=64, **kw)
     lo32, hi32 = box32(wl.lower, wl.upper)
@@ -237,7 +237,7 @@ def test_learned_per_move_parity(S, name):
 
 def test_learned_graph_and_chunks_equal_eager(S):
     wl = learned_case("schwefel_n16")
-    p = learned_params(5, scale=0.08, sigma0=0.02)
+    p = learned_params(5, scale=0.05, sigma0=0.02)
     kw = dict(chains=1024, levels=6, steps=20, T0=10.0, alpha=0.8, seed=2)
     a = run_learned(S, wl, p, 0.1, **kw)
     b = run_learned(S, wl, p, 0.1, graph=True, chunks=[2, 4], **kw)

@@ -1,7 +1,7 @@
 """Pins of the oracle's learned-proposal network (FP64): forward pass, loss,
-gradient, activation, optimiser and proposal density, each against a library
-routine (PyTorch CPU float64 autograd / functional / optimiser, scipy), a
-finite difference, or a closed form."""
+gradient, activation, optimiser, proposal density and draws, each against a
+library routine (PyTorch CPU float64 autograd / functional / optimiser,
+scipy), a finite difference, or a closed form."""
 import math
 
 import numpy as np
@@ -48,8 +48,9 @@ def test_forward_zero_weights_closed_form():
     out, a1, a2 = O.mlp_forward(p, [0.5, 1.0, 0.1, 0.2, 0.3, 0.4])
     assert out[0] == 0.3 and out[1] == -1.2
     assert np.all(a1 == 0) and np.all(a2 == 0)
+    # Cauchy negative log-likelihood of d = 0.7: s + ln pi + ln(1 + ((d - mu)/e^s)^2)
     loss = O.mlp_loss_grad(p, np.zeros((1, 6)), [0.7], with_grad=False)
-    assert abs(loss - (-1.2 + 0.5 * 0.4 ** 2 * math.exp(2.4))) < 1e-12
+    assert abs(loss - (-1.2 + math.log(math.pi) + math.log1p((0.4 * math.exp(1.2)) ** 2))) < 1e-12
 
 
 def _torch_loss_grad(params, Z, d):
@@ -61,7 +62,7 @@ def _torch_loss_grad(params, Z, d):
     o = h2 @ W3 + b3
     mu, s = o[:, 0], o[:, 1]
     dd = torch.tensor(d, dtype=torch.float64)
-    loss = (s + 0.5 * (dd - mu) ** 2 * torch.exp(-2 * s)).mean()
+    loss = -torch.distributions.Cauchy(mu, torch.exp(s)).log_prob(dd).mean()
     loss.backward()
     g = np.concatenate([t.grad.numpy().ravel() for t in (W1, b1, W2, b2, W3, b3)])
     return float(loss.detach()), g
@@ -117,14 +118,14 @@ def test_adam_against_torch_optimizer():
     assert np.max(np.abs(p - tp.detach().numpy())) < 1e-12
 
 
-def test_proposal_logpdf_is_a_normal_density():
-    from scipy.stats import norm
+def test_proposal_logpdf_is_a_cauchy_density():
+    from scipy.stats import cauchy
     for mu, s in ((0.0, 0.0), (0.1, -2.0), (-0.3, 0.5)):
         for x in (-1.0, 0.0, 0.05, 2.0):
-            assert abs(O.proposal_logpdf(x, mu, s) - norm.logpdf(x, loc=mu, scale=math.exp(s))) < 1e-12
-    xs = np.linspace(-1, 1, 200001)
-    dens = np.exp([O.proposal_logpdf(x, 0.02, -3.0) for x in xs])
-    assert abs(np.trapezoid(dens, xs) - 1.0) < 1e-9
+            assert abs(O.proposal_logpdf(x, mu, s) - cauchy.logpdf(x, loc=mu, scale=math.exp(s))) < 1e-12
+    from scipy.integrate import quad
+    total, err = quad(lambda x: math.exp(O.proposal_logpdf(x, 0.02, -3.0)), -np.inf, np.inf, points=None)
+    assert abs(total - 1.0) < 1e-8
 
 
 def test_training_reduces_loss_on_synthetic_data():
@@ -149,21 +150,20 @@ def test_training_reduces_loss_on_synthetic_data():
     assert s_hi - s_lo > 1.0  # ln(0.1 / 0.01) = 2.3
 
 
-def test_learn_gauss_is_standard_normal_and_follows_its_counters():
-    """Box-Muller draws of learned moves: a standard normal sample (KS test),
-    different counters give independent draws, and each draw is the
-    Box-Muller transform of the two uniforms of its Philox block."""
+def test_learn_draw_is_standard_cauchy_and_follows_its_counters():
+    """Draws of learned moves: a standard Cauchy sample (KS test, median and
+    quartiles), each the inverse distribution function at the first uniform
+    of its Philox block, and a different stream per problem id."""
     from scipy import stats
-    g = np.array([O.learn_gauss(5, 0, lv, ch, st) for lv in range(4) for ch in range(50) for st in range(100)])
-    assert stats.kstest(g, "norm").pvalue > 1e-3
-    assert abs(g.mean()) < 0.03 and abs(g.std() - 1.0) < 0.03
+    t = np.array([O.learn_draw(5, 0, lv, ch, st) for lv in range(4) for ch in range(50) for st in range(100)])
+    assert stats.kstest(t, "cauchy").pvalue > 1e-3
+    assert abs(np.median(t)) < 0.05
+    assert abs(np.quantile(t, 0.75) - 1.0) < 0.06 and abs(np.quantile(t, 0.25) + 1.0) < 0.06
     r = O.philox4x32_10([7, 3, 11, 3], [5, 0])
-    u0, u1 = O.uniform(int(r[0])), O.uniform(int(r[1]))
-    # the transform's radius and angle, recovered independently: g^2 is the
-    # chi-square radius times cos^2 of the angle
-    assert abs(O.learn_gauss(5, 0, 3, 11, 7) ** 2 - (-2 * math.log(1 - u0)) * math.cos(2 * math.pi * u1) ** 2) < 1e-12
-    # problem id in the counter's top bits changes the stream
-    assert O.learn_gauss(5, 1, 3, 11, 7) != O.learn_gauss(5, 0, 3, 11, 7)
+    u0 = O.uniform(int(r[0]))
+    # the Cauchy distribution function 1/2 + atan(t)/pi returns the uniform
+    assert abs(0.5 + math.atan(O.learn_draw(5, 0, 3, 11, 7)) / math.pi - u0) < 1e-12
+    assert O.learn_draw(5, 1, 3, 11, 7) != O.learn_draw(5, 0, 3, 11, 7)
 
 
 def _bf16(a):
