@@ -62,7 +62,8 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 TRAFFIC_MEASURED = {"sources_sha256_16": "1fcb9b05e6b46ecd", "fetch_kib": 143.5145, "fetch_scale": 2.0,
                     "write_kib": 120.58125, "write_scale": 1.0}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
-                  "paper_2408_00018_amd/csrc/sa_internal.hpp"]
+                  "paper_2408_00018_amd/csrc/sa_internal.hpp", "paper_2408_00018_amd/csrc/sa_step.hpp",
+                  "paper_2408_00018_amd/csrc/sa_level_common.hpp", "paper_2408_00018_amd/csrc/sa_mlp_net.hpp"]
 
 
 def measured_traffic_bytes():
