@@ -137,8 +137,8 @@ def time_to_target_report(wl, seeds):
     """Learned vs plain proposal: time until the record is within 1e-4 of f*.
 
     Collection: plain runs (4096 chains, 100 steps, T0 10, alpha 0.995, 4000
-    levels, seed 1001) capture accepted moves at every 8th level, 2000 per
-    level (repeated where fewer were accepted).  Training: 6000 Adam steps,
+    levels, seed 1001) capture accepted moves at every 8th level, 20000 per
+    level (repeated where fewer were accepted): 10^7 records.  Training: 6000 Adam steps,
     minibatch 4096, lr 1e-3.  Arms, on 65536 chains x 100 steps,
     T_k = 10 * 0.995^k up to k = 3999: 'full' starts at level 0 from random
     points; 'final_approach' starts at level 3000 (T = 2.9e-6, where the thermal
@@ -153,7 +153,7 @@ def time_to_target_report(wl, seeds):
     t0 = time.perf_counter()
     col = sa.Schedule(chains=4096, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
                       precision=sa.FP32)
-    rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=8, per_level=2000)
+    rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=8, per_level=20000)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     params, trace = Lp.train(rec, steps=6000, batch=4096, lr=1e-3, seed=0)

@@ -246,3 +246,29 @@ def test_error_paths(S):
     with pytest.raises(S.SAError) as e:
         run_gpu(S, bad)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("case", ["schwefel_n100", "rastrigin_n64_shift", "ackley_n37_uneven", "resample_n9"])
+def test_fp32_generator_waves_are_bitwise_identical(S, case):
+    """FP32 plain levels with generator waves (draws computed ahead by separate
+    waves) and without them give the same bits: winners, counts, costs and
+    broadcast states."""
+    if case == "schwefel_n100":
+        wl = W.schwefel_n100_fp32().with_(chains=4096, levels=8)
+        kw = {}
+    elif case == "rastrigin_n64_shift":
+        wl = W.random_problem(W.RASTRIGIN, 64, seed=21).with_(chains=1024, levels=6, steps=37)
+        kw = {}
+    elif case == "ackley_n37_uneven":
+        lo, hi = W.uneven_box(37, 9)
+        wl = W.random_problem(W.ACKLEY, 37, seed=22, shifted=False).with_(lower=lo, upper=hi, chains=768, levels=5,
+                                                                          steps=50)
+        kw = {}
+    else:
+        wl = W.random_problem(W.SCHWEFEL, 9, seed=23).with_(chains=512, levels=6, steps=30)
+        kw = dict(move=S.MOVE_RESAMPLE)
+    split = run_gpu(S, wl, **kw)
+    single = run_gpu(S, wl, generator_waves=False, **kw)
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    assert np.array_equal(split["rec"][keys], single["rec"][keys])
+    assert np.array_equal(split["xb"], single["xb"])
