@@ -87,6 +87,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
     p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
+    p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
     p.add_argument("--ttt-seeds", type=int, default=1, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
@@ -185,6 +186,57 @@ def time_to_target_report(wl, seeds):
     return out
 
 
+def extra_workloads():
+    """Throughput of the other workloads, one timed run each after a warm-up
+    run (graph-replayed levels, HIP events on the library's stream): the
+    n = 512 Rastrigin and n = 1024 Ackley runs (131072 chains, 1000 levels x
+    64 steps, shifted), and 1024 batched problems (n ~ U{2..256}, 500 levels
+    x 64 steps, chains per problem and waves per workgroup from the
+    autotuner)."""
+    import torch
+    from paper_2408_00018_amd import sa
+    out = {}
+    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32()):
+        sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
+                            seed=wl.seed, precision=sa.FP32, graph=True)
+        with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+            ann.run()
+            ann.reset(wl.seed)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ann.stream)
+            ann.run()
+            e1.record(ann.stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            _, f_rec, _ = ann.best()
+            wg, slots, tiles = ann.layout()
+        out[wl.name] = {"moves_per_s": float(f"{wl.moves / (ms * 1e-3):.4g}"), "ms_per_run": round(ms, 3),
+                        "workgroup": wg, "overlay_slots": slots, "gap_to_f_star": f_rec - wl.f_star}
+        print(f"[extra] {wl.name}: {out[wl.name]}", file=sys.stderr, flush=True)
+    probs = W.batch_problems()
+    bs = sa.BatchSchedule(levels=500, steps=64, T0=10.0, alpha=0.99, seed=4, precision=sa.FP32, graph=True)
+    t0 = time.perf_counter()
+    chains, wpg, rate = sa.batch_autotune(probs, bs, trial_levels=4)
+    tune_s = time.perf_counter() - t0
+    bs.waves_per_group = wpg
+    with sa.BatchAnnealer(probs, chains, schedule=bs) as b:
+        b.run()
+        b.reset(4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(b._stream)
+        b.run()
+        e1.record(b._stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+    moves = float(np.sum(chains.astype(np.float64))) * bs.steps * bs.levels
+    out["batched_1024"] = {"moves_per_s": float(f"{moves / (ms * 1e-3):.4g}"), "ms_per_run": round(ms, 3),
+                           "problems": len(probs), "total_chains": int(np.sum(chains)),
+                           "chains_per_problem": sorted({int(c) for c in chains}), "waves_per_group": wpg,
+                           "autotune_s": round(tune_s, 2)}
+    print(f"[extra] batched: {out['batched_1024']}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -264,6 +316,11 @@ def main():
         out["valu_rates_per_s"] = probe_rates()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
+    if not args.no_extra:
+        try:
+            out["other_workloads"] = extra_workloads()
+        except Exception as e:  # the throughput line is printed regardless
+            out["other_workloads"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_ttt:
         try:
             out["time_to_target"] = time_to_target_report(wl, args.ttt_seeds)

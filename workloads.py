@@ -121,6 +121,25 @@ def uneven_box(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return c - w / 2, c + w / 2
 
 
+def batch_problems(nprob: int = 1024, seed: int = 4, nmin: int = 2, nmax: int = 256):
+    """Batched workload: nprob problems, function uniform over the three
+    families, n uniform in {nmin..nmax}, per-problem shift uniform in the inner
+    80% of the canonical box (Schwefel: the box translated by the shift, so its
+    minimiser stays inside).  Returns [(func, lower, upper, shift)]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nprob):
+        func = int(rng.integers(0, 3))
+        n = int(rng.integers(nmin, nmax + 1))
+        half = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768}[func]
+        lo, hi = _box(n, half)
+        s = inner_shift(lo, hi, rng)
+        if func == SCHWEFEL:
+            lo, hi = lo + s, hi + s
+        out.append((func, lo, hi, s))
+    return out
+
+
 ALL = {
     "schwefel_n4_fp64": schwefel_n4_fp64,
     "schwefel_n100_fp32": schwefel_n100_fp32,
