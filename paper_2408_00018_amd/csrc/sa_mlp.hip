@@ -142,34 +142,52 @@ __global__ void __launch_bounds__(256) layer3_loss(const float *H2, const float 
     }
 }
 
-// The small gradients (W1, b1, b2, W3, b3), each a sum over the minibatch in
-// record order; one thread per parameter.  W2's gradient comes from MFMA.
-__global__ void small_grads(const float *Z, const float *dA1, const float *dA2, const float *H2, const float *dO,
-                            uint32_t batch, float *g)
+// The small gradients (W1, b1, b2, W3, b3): 1282 sums over the minibatch.
+// Pass 1: one thread per (parameter, chunk of kGradChunk records) sums its
+// chunk in record order; pass 2 adds the chunks in order.  W2's gradient comes
+// from MFMA.
+constexpr uint32_t kSmallGrads = kInputs * kHidden + kHidden + kHidden + 2 * kHidden + 2;  // W1, b1, b2, W3, b3
+static_assert(kSmallGrads == kNumParams - kHidden * kHidden, "every parameter but W2");
+constexpr uint32_t kGradChunk = 128;
+
+__global__ void small_grads_partial(const float *Z, const float *dA1, const float *dA2, const float *H2,
+                                    const float *dO, uint32_t batch, float *partial)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kSmallGrads) return;
+    const uint32_t r0 = blockIdx.y * kGradChunk, r1 = min(batch, r0 + kGradChunk);
     float s = 0.0f;
     if (t < kOffB1) {  // W1[i][j]
         const uint32_t i = t / kHidden, j = t % kHidden;
-        for (uint32_t r = 0; r < batch; ++r) s = fmaf(Z[(size_t)r * kInputs + i], dA1[(size_t)r * kHidden + j], s);
-        g[kOffW1 + t] = s;
+        for (uint32_t r = r0; r < r1; ++r) s = fmaf(Z[(size_t)r * kInputs + i], dA1[(size_t)r * kHidden + j], s);
     } else if (t < kOffB1 + kHidden) {  // b1
         const uint32_t j = t - kOffB1;
-        for (uint32_t r = 0; r < batch; ++r) s += dA1[(size_t)r * kHidden + j];
-        g[kOffB1 + j] = s;
+        for (uint32_t r = r0; r < r1; ++r) s += dA1[(size_t)r * kHidden + j];
     } else if (t < kOffB1 + 2 * kHidden) {  // b2
         const uint32_t j = t - kOffB1 - kHidden;
-        for (uint32_t r = 0; r < batch; ++r) s += dA2[(size_t)r * kHidden + j];
-        g[kOffB2 + j] = s;
-    } else if (t < kOffB1 + 2 * kHidden + 2 * kHidden) {  // W3[j][k]
+        for (uint32_t r = r0; r < r1; ++r) s += dA2[(size_t)r * kHidden + j];
+    } else if (t < kOffB1 + 4 * kHidden) {  // W3[j][k]
         const uint32_t q = t - kOffB1 - 2 * kHidden, j = q / 2, k = q % 2;
-        for (uint32_t r = 0; r < batch; ++r) s = fmaf(H2[(size_t)r * kHidden + j], dO[2 * r + k], s);
-        g[kOffW3 + q] = s;
-    } else if (t < kOffB1 + 4 * kHidden + 2) {  // b3
+        for (uint32_t r = r0; r < r1; ++r) s = fmaf(H2[(size_t)r * kHidden + j], dO[2 * r + k], s);
+    } else {  // b3
         const uint32_t k = t - kOffB1 - 4 * kHidden;
-        for (uint32_t r = 0; r < batch; ++r) s += dO[2 * r + k];
-        g[kOffB3 + k] = s;
+        for (uint32_t r = r0; r < r1; ++r) s += dO[2 * r + k];
     }
+    partial[(size_t)blockIdx.y * kSmallGrads + t] = s;
+}
+
+__global__ void small_grads_sum(const float *partial, uint32_t chunks, float *g)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= kSmallGrads) return;
+    float s = 0.0f;
+    for (uint32_t c = 0; c < chunks; ++c) s += partial[(size_t)c * kSmallGrads + t];
+    uint32_t at;
+    if (t < kOffB1 + kHidden) at = t;                                   // W1, b1
+    else if (t < kOffB1 + 2 * kHidden) at = kOffB2 + (t - kOffB1 - kHidden);  // b2
+    else if (t < kOffB1 + 4 * kHidden) at = kOffW3 + (t - kOffB1 - 2 * kHidden);  // W3
+    else at = kOffB3 + (t - kOffB1 - 4 * kHidden);                       // b3
+    g[at] = s;
 }
 
 // Mean of the per-record losses (one workgroup, fixed order).
@@ -260,6 +278,7 @@ struct sa_mlp {
     uint16_t *W1b, *W2b, *W3b, *H1b, *dA2b;
     uint32_t *idx;
     unsigned char *net;  // packed copy for inference
+    float *partial;      // chunk partial sums of the small gradients
     uint32_t t = 0;  // Adam steps taken
 };
 
@@ -276,7 +295,8 @@ sa_status mlp_alloc(sa_mlp *p)
         {(void **)&p->dA2, B * H * 4},        {(void **)&p->dA1, B * H * 4},     {(void **)&p->loss_r, B * 4},
         {(void **)&p->dO, B * 2 * 4},         {(void **)&p->loss, 4},            {(void **)&p->W1b, kInputs * H * 2},
         {(void **)&p->W2b, H * H * 2},        {(void **)&p->W3b, H * 2 * 2},     {(void **)&p->H1b, B * H * 2},
-        {(void **)&p->dA2b, B * H * 2},       {(void **)&p->idx, B * 4},         {(void **)&p->net, kNetBytes}};
+        {(void **)&p->dA2b, B * H * 2},       {(void **)&p->idx, B * 4},         {(void **)&p->net, kNetBytes},
+        {(void **)&p->partial, ((B + kGradChunk - 1) / kGradChunk) * kSmallGrads * 4}};
     std::vector<size_t> at;
     for (auto &q : parts) {
         at.push_back(off);
@@ -312,9 +332,11 @@ sa_status mlp_grad_pass(sa_mlp *p, const float *records, uint32_t batch)
     hipLaunchKernelGGL((gemm_bf16<kEpiActBwd>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
                        kHidden, p->dA2b, kHidden, 1, p->W2b, 1, kHidden, p->dA1, kHidden, (const float *)nullptr,
                        p->A1, (float *)nullptr);
-    const uint32_t nsmall = kOffB1 + 4 * kHidden + 2;
-    hipLaunchKernelGGL(small_grads, dim3((nsmall + 255) / 256), blk, 0, p->stream, p->Z, p->dA1, p->dA2, p->H2,
-                       p->dO, batch, p->g);
+    const uint32_t chunks = (batch + kGradChunk - 1) / kGradChunk;
+    hipLaunchKernelGGL(small_grads_partial, dim3((kSmallGrads + 255) / 256, chunks), blk, 0, p->stream, p->Z,
+                       p->dA1, p->dA2, p->H2, p->dO, batch, p->partial);
+    hipLaunchKernelGGL(small_grads_sum, dim3((kSmallGrads + 255) / 256), blk, 0, p->stream, p->partial, chunks,
+                       p->g);
     hipLaunchKernelGGL(loss_mean, dim3(1), blk, 0, p->stream, p->loss_r, batch, p->loss);
     SA_HIP(hipGetLastError());
     return SA_OK;
