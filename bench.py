@@ -88,6 +88,8 @@ def parse():
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
     p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
     p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
+    p.add_argument("--generator-waves", action="store_true",
+                   help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
     p.add_argument("--ttt-seeds", type=int, default=1, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
@@ -260,7 +262,7 @@ def main():
         return
     wl = W.schwefel_n100_fp32()
     sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
-                        precision=sa.FP32, graph=True)
+                        precision=sa.FP32, graph=True, generator_waves=args.generator_waves)
     ann = sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched)
     stream = ann.stream
     for _ in range(args.warmup):

@@ -120,11 +120,11 @@ typedef struct {
  * in FP32).  Plain and logged moves only (not with SA_FLAG_LEARNED or
  * sa_capture); results are identical to the dense layout. */
 #define SA_FLAG_OVERLAY 0x8u
-/* FP32 plain levels normally run 256 chains per workgroup with four extra
- * waves that compute the random draws ahead into LDS (two waves per SIMD
- * issue more than one); this flag keeps one wave per 64 chains.  Results are
- * identical either way. */
-#define SA_FLAG_NO_GENERATOR_WAVES 0x10u
+/* FP32 plain levels with 256 chains per workgroup: run them with four extra
+ * waves that compute the random draws ahead into LDS (two waves per SIMD)
+ * instead of one wave per 64 chains.  Results are identical either way; on
+ * MI355X it is currently slower (see the design notes), so it is opt-in. */
+#define SA_FLAG_GENERATOR_WAVES 0x10u
 
 /* Per-level record returned by sa_trace. */
 typedef struct {

@@ -96,7 +96,7 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_NO_GENERATOR_WAVES))
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_GENERATOR_WAVES))
         return fail(SA_ERR_INVALID, "unknown flag bits");
     if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs on the dense state layout");
@@ -137,7 +137,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     }
     if (pl.wg == 0)
         return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
-    pl.split = !pl.overlay && c->precision == SA_FP32 && pl.wg == 256 && !(c->flags & SA_FLAG_NO_GENERATOR_WAVES) &&
+    pl.split = !pl.overlay && c->precision == SA_FP32 && pl.wg == 256 && (c->flags & SA_FLAG_GENERATOR_WAVES) &&
                sa::split_lds_bytes(p->n, pl.table) <= lds_limit;
     pl.groups = c->chains / pl.wg;
     const size_t n = p->n, L = c->levels, R = pl.real;

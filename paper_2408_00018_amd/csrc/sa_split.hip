@@ -26,10 +26,9 @@ namespace {
 constexpr uint32_t kChains = 256;  // chains per workgroup (state lanes)
 constexpr uint32_t kChunk = 4;     // moves per ring half
 
-// One move's draws: coordinate, the two uniforms (as FP32 bit patterns).
-struct Draw {
-    uint32_t d, u1, u2, pad;
-};
+// One move's draws in a 16-byte ring entry: coordinate, the two uniforms
+// (FP32 bit patterns), unused.
+typedef uint4 Draw;
 
 }  // namespace
 
@@ -113,8 +112,8 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                 const uint32_t step = k * kChunk + j;
                 if (step < steps) {
                     const Ctr r = philox4x32_10(Ctr{step, level, chain, ctr3}, k0, k1);
-                    half[j * kChains + col] = Draw{pick(r.w0, n), __float_as_uint(u24f(r.w1)),
-                                                   __float_as_uint(u24f(r.w2)), 0u};
+                    half[j * kChains + col] = make_uint4(pick(r.w0, n), __float_as_uint(u24f(r.w1)),
+                                                         __float_as_uint(u24f(r.w2)), 0u);
                 }
             }
         };
@@ -124,27 +123,36 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
             if (gen) {
                 if (k + 1 < nchunks) produce(k + 1);
             } else {
+                // The chunk's draws and the states at their coordinates are read
+                // up front (one LDS round trip); a coordinate a later move of the
+                // chunk repeats is forwarded from the earlier move's result.
                 const Draw *half = ring + (k & 1u) * kChunk * kChains;
-                Draw dr = half[col];
-                float xd = xs[__umul24(dr.d, kChains) + col];
+                const uint32_t valid = min(kChunk, steps - k * kChunk);
+                uint32_t d[kChunk];
+                float u1[kChunk], u2[kChunk], xv[kChunk];
 #pragma unroll
                 for (uint32_t j = 0; j < kChunk; ++j) {
-                    if (k * kChunk + j >= steps) break;
-                    // read the next move's draws and coordinate one move ahead
-                    // (only entries this chunk's generator wrote)
-                    const bool more = j + 1 < kChunk && k * kChunk + j + 1 < steps;
-                    const Draw dn = more ? half[(j + 1) * kChains + col] : dr;
-                    const float xn_lds = more ? xs[__umul24(dn.d, kChains) + col] : xd;
-                    const Coord<float> c = coord<float, TABLE>(a, tab, dr.d);
-                    const float xn = neighbour<MOVE>(xd, c, __uint_as_float(dr.u1));
-                    const float df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-                    const bool take = metropolis(df, __uint_as_float(dr.u2), 0.0, nl2T);
-                    const float xwr = take ? xn : xd;
-                    xs[__umul24(dr.d, kChains) + col] = xwr;
-                    cost.commit(take, a.inv_n);
-                    accepted += take ? 1u : 0u;
-                    xd = dn.d == dr.d ? xwr : xn_lds;
-                    dr = dn;
+                    const Draw e = half[(j < valid ? j : 0u) * kChains + col];
+                    d[j] = e.x;
+                    u1[j] = __uint_as_float(e.y);
+                    u2[j] = __uint_as_float(e.z);
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < kChunk; ++j) xv[j] = xs[__umul24(d[j], kChains) + col];
+#pragma unroll
+                for (uint32_t j = 0; j < kChunk; ++j) {
+                    if (j < valid) {
+                        const Coord<float> c = coord<float, TABLE>(a, tab, d[j]);
+                        const float xn = neighbour<MOVE>(xv[j], c, u1[j]);
+                        const float df = cost.delta(xv[j] - c.sh, xn - c.sh, n, a.inv_n);
+                        const bool take = metropolis(df, u2[j], 0.0, nl2T);
+                        const float xwr = take ? xn : xv[j];
+                        xs[__umul24(d[j], kChains) + col] = xwr;
+                        cost.commit(take, a.inv_n);
+                        accepted += take ? 1u : 0u;
+#pragma unroll
+                        for (uint32_t m = j + 1; m < kChunk; ++m) xv[m] = d[m] == d[j] ? xwr : xv[m];
+                    }
                 }
             }
             __syncthreads();

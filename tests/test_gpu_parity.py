@@ -267,8 +267,8 @@ def test_fp32_generator_waves_are_bitwise_identical(S, case):
     else:
         wl = W.random_problem(W.SCHWEFEL, 9, seed=23).with_(chains=512, levels=6, steps=30)
         kw = dict(move=S.MOVE_RESAMPLE)
-    split = run_gpu(S, wl, **kw)
-    single = run_gpu(S, wl, generator_waves=False, **kw)
+    split = run_gpu(S, wl, generator_waves=True, **kw)
+    single = run_gpu(S, wl, **kw)
     keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
     assert np.array_equal(split["rec"][keys], single["rec"][keys])
     assert np.array_equal(split["xb"], single["xb"])
