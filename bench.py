@@ -59,8 +59,8 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "1fcb9b05e6b46ecd", "fetch_kib": 143.5145, "fetch_scale": 2.0,
-                    "write_kib": 120.58125, "write_scale": 1.0}
+TRAFFIC_MEASURED = {"sources_sha256_16": "4f57d0323e05e600", "fetch_kib": 153.013, "fetch_scale": 2.0,
+                    "write_kib": 120.581, "write_scale": 1.0}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
                   "paper_2408_00018_amd/csrc/sa_internal.hpp", "paper_2408_00018_amd/csrc/sa_step.hpp",
                   "paper_2408_00018_amd/csrc/sa_level_common.hpp", "paper_2408_00018_amd/csrc/sa_mlp_net.hpp"]
@@ -90,7 +90,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
     p.add_argument("--generator-waves", action="store_true",
                    help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
-    p.add_argument("--ttt-seeds", type=int, default=1, help="seeds per arm of the time-to-target comparison")
+    p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
     return p.parse_args()
@@ -181,9 +181,15 @@ def time_to_target_report(wl, seeds):
                              "final_gap": r.final_gap})
                 print(f"[ttt] {regime} {arm} seed {seed}: {runs[-1]}", file=sys.stderr, flush=True)
             res[arm] = runs
-        hits = {a: [r["seconds"] for r in res[a] if r["hit"]] for a in res}
-        if hits["plain"] and hits["learned"]:
-            res["speedup_median"] = float(np.median(hits["plain"]) / np.median(hits["learned"]))
+        summary = {}
+        for a in ("plain", "learned"):
+            secs = [r["seconds"] for r in res[a] if r["hit"]]
+            summary[a] = {"hit_fraction": len(secs) / len(res[a]),
+                          "median_seconds": float(np.median(secs)) if secs else None,
+                          "median_final_gap": float(np.median([r["final_gap"] for r in res[a]]))}
+        if summary["plain"]["median_seconds"] and summary["learned"]["median_seconds"]:
+            summary["speedup_median"] = summary["plain"]["median_seconds"] / summary["learned"]["median_seconds"]
+        res["summary"] = summary
         out[regime] = res
     return out
 
