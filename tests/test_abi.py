@@ -122,3 +122,14 @@ def test_null_arguments(S):
     assert L.sa_run(None, 0) == -1
     assert L.sa_best(None, None, None, None) == -1
     L.sa_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
