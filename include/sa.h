@@ -48,6 +48,14 @@
  *     publishes the last level; each level's launch reduces the previous
  *     level's per-workgroup candidates to the winner on the device.  There is
  *     no host work and no grid-wide barrier inside a launch.
+ *
+ * Beyond the paper's single problem with plain moves:
+ *   - sa_batch_*: many independent problems of uneven dimension advanced
+ *     together, one launch per level, with a measuring autotuner;
+ *   - sa_set_proposal / sa_capture / sa_mlp_*: a learned proposal (a small
+ *     network trained on the accepted moves the method generates) mixed with
+ *     the plain move and corrected by Metropolis-Hastings;
+ *   - sa_set_start: a run that starts from a given state at a given level.
  */
 #ifndef SA_H
 #define SA_H
