@@ -261,7 +261,8 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
     uint32_t d = pick(r.w0, n);
     uint32_t d1 = pick(r1.w0, n);
     R xd = xs[__umul24(d, stride) + lane_off];
-    for (uint32_t step = 0; step < steps; ++step) {
+    // One move; the pipeline state (r, r1, d, d1, xd) advances by one.
+    const auto move = [&](uint32_t step) {
         const R x1_lds = xs[__umul24(d1, stride) + lane_off];
         const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
         const Coord<R> c = coordf(d);
@@ -278,7 +279,16 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
         r = r1;
         r1 = r2;
         d1 = pick(r2.w0, n);
+    };
+    // Three moves per iteration: the generator blocks rotate through three
+    // register sets, so a three-fold body needs no register copies.
+    uint32_t step = 0;
+    for (; step + 3 <= steps; step += 3) {
+        move(step);
+        move(step + 1);
+        move(step + 2);
     }
+    for (; step < steps; ++step) move(step);
     return accepted;
 }
 
