@@ -75,6 +75,10 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
     const uint32_t WG = blockDim.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = WG >> 6;
     const uint32_t n = a.n;
     const size_t base = (size_t)(lvl & 1u) * a.tiles;
+    // The record the previous launch left is loaded together with the
+    // candidates, not after the winner is known (one global round trip fewer
+    // on the publishing workgroup's path).
+    const double rec_prev = publish ? a.rec[0] : 0.0;
     R gf = widen_inf<R>();
     uint32_t gc = 0xFFFFFFFFu, gj = 0;
     uint64_t gacc = 0;
@@ -119,22 +123,23 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
     }
     if (gj >= groups) gj = 0;  // only if every candidate cost were NaN; keeps the index in range
     const size_t w = base + gj;
-    for (uint32_t i = tid; i < n; i += WG) xw[i] = a.slot_x[w * n + i];
     const Slot<R> ws = a.slots[w];
+    const bool improved = publish && ws.ff < rec_prev;
+    for (uint32_t i = tid; i < n; i += WG) {
+        const R v = a.slot_x[w * n + i];
+        xw[i] = v;
+        if (publish) {
+            a.x_best[i] = v;
+            if (a.trace_x) a.trace_x[(size_t)lvl * n + i] = v;
+            if (improved) a.x_rec[i] = v;
+        }
+    }
     if (tid == 0) {
         start[0] = ws.ff;
         start[1] = ws.s1;
         start[2] = ws.s2;
     }
     if (publish) {
-        const bool improved = ws.ff < a.rec[0];
-        __syncthreads();
-        for (uint32_t i = tid; i < n; i += WG) {
-            const R v = a.slot_x[w * n + i];
-            a.x_best[i] = v;
-            if (a.trace_x) a.trace_x[(size_t)lvl * n + i] = v;
-            if (improved) a.x_rec[i] = v;
-        }
         if (tid == 0) {
             if (improved) {
                 a.rec[0] = ws.ff;
@@ -145,7 +150,7 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
             t.reserved = 0;
             t.f_win = (double)gf;
             t.f_best = ws.ff;
-            t.f_rec = improved ? ws.ff : a.rec[0];
+            t.f_rec = improved ? ws.ff : rec_prev;
             t.accepts = gacc;
             t.t_ticks = wall_clock64();
             a.trace[lvl] = t;
