@@ -16,9 +16,13 @@
  *
  * Fixed readings (the paper leaves them open):
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = (seed low
- *     word, seed high word), move counter = (step, level, chain, 0 | problem<<8),
- *     start counter = (i/4, 0xFFFFFFFF, chain, 1 | problem<<8) for coordinate i.
- *     Uniform U = (r >> 8) * 2^-24; coordinate d = (r0 * n) >> 32.
+ *     word, seed high word).  A chain's move stream at a level is the word
+ *     sequence of the blocks (b, level, chain, 0 | problem<<8), b = 0, 1, ...
+ *     (word i is word i mod 4 of block i/4); move `step` takes words 3 step,
+ *     3 step + 1, 3 step + 2 (coordinate, change, acceptance), so four moves
+ *     use three blocks.  Start counter = (i/4, 0xFFFFFFFF, chain,
+ *     1 | problem<<8), word i mod 4, for coordinate i.
+ *     Uniform U = (r >> 8) * 2^-24; coordinate d = (r * n) >> 32.
  *   - Move: x'_d = clamp(x_d + rho_d (2 U1 - 1), l_d, u_d) with
  *     rho_d = radius_frac (u_d - l_d) (SA_MOVE_RADIUS), or
  *     x'_d = l_d + (u_d - l_d) U1 (SA_MOVE_RESAMPLE).
@@ -216,8 +220,10 @@ sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
  * x'_d = x_d + dl (u_d - l_d); a proposal outside [l_d, u_d] is rejected, and
  * otherwise it is taken iff U < exp(-df/T + ln q(x | x') - ln q(x' | x))
  * (Metropolis-Hastings with the network evaluated at x_d and at x'_d, both
- * with the chain's current history).  The plain/learned choice is U(r3) < eps
- * of the move block.  The history (last four accepted scaled displacements,
+ * with the chain's current history); the change and acceptance uniforms of
+ * either component are the move's words of the plain move stream.  The
+ * plain/learned choice is U < eps with U from word 1 of the learned block.
+ * The history (last four accepted scaled displacements,
  * most recent first) restarts at zero at every level.  params = NULL returns
  * to plain moves.  Needs SA_FLAG_LEARNED; SA_ERR_STATE while capturing.
  * Synchronises.

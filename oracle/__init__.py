@@ -59,7 +59,7 @@ def lib():
         L.orc_uniform.restype = _d
         L.orc_pick.argtypes = [_u32, _u32]
         L.orc_pick.restype = _u32
-        L.orc_move_draw.argtypes = [_u64, _u32, _u32, _u32, _u32, _u32, _p, _p, _p, _p]
+        L.orc_move_draw.argtypes = [_u64, _u32, _u32, _u32, _u32, _u32, _p, _p, _p]
         L.orc_move_draw.restype = None
         L.orc_init_point.argtypes = [_u64, _u32, _u32, _u32, _p, _p, _p]
         L.orc_init_point.restype = None
@@ -103,6 +103,8 @@ def lib():
         L.orc_mlp_forward_bound.restype = None
         L.orc_learn_draw.argtypes = [_u64, _u32, _u32, _u32, _u32]
         L.orc_learn_draw.restype = _d
+        L.orc_learn_mix.argtypes = [_u64, _u32, _u32, _u32, _u32]
+        L.orc_learn_mix.restype = _d
         L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
                                          _p, _d, _p, ctypes.c_uint64, _p]
         L.orc_sa_run_capture.restype = _i
@@ -135,13 +137,13 @@ def pick(r: int, n: int) -> int:
 
 
 def move_draw(seed, problem, level, chain, step, n):
+    """(coordinate, change uniform, acceptance uniform) of move `step`: words
+    3 step .. 3 step + 2 of the chain's move stream at `level`."""
     d = ctypes.c_uint32()
     u1 = ctypes.c_double()
     u2 = ctypes.c_double()
-    r3 = ctypes.c_uint32()
-    lib().orc_move_draw(seed, problem, level, chain, step, n, ctypes.byref(d), ctypes.byref(u1),
-                        ctypes.byref(u2), ctypes.byref(r3))
-    return d.value, u1.value, u2.value, r3.value
+    lib().orc_move_draw(seed, problem, level, chain, step, n, ctypes.byref(d), ctypes.byref(u1), ctypes.byref(u2))
+    return d.value, u1.value, u2.value
 
 
 def init_point(seed, problem, chain, lower, upper):
@@ -332,6 +334,12 @@ def hist_feature(h: float) -> float:
 def learn_draw(seed, problem, level, chain, step) -> float:
     """Standard Cauchy draw of a learned move (inversion, Philox tag 3)."""
     return lib().orc_learn_draw(seed, problem, level, chain, step)
+
+
+def learn_mix(seed, problem, level, chain, step) -> float:
+    """Uniform that chooses the mixture component of a learned-mode move (the
+    plain move iff it is below eps): second word of the learned block."""
+    return lib().orc_learn_mix(seed, problem, level, chain, step)
 
 
 def feature_tau(func, n):

@@ -28,8 +28,11 @@
  * Readings where the paper is silent (all are stated again, with reasons, in
  * the project design notes):
  *   - random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), key =
- *     (seed_lo, seed_hi); move counter = (step, level, chain, tag | problem<<8);
- *     uniform U = (r >> 8) * 2^-24; coordinate d = (r0 * n) >> 32;
+ *     (seed_lo, seed_hi); the move stream of a chain at a level is the word
+ *     sequence of the blocks (b, level, chain, tag | problem<<8), b = 0, 1, ...
+ *     (word i of the stream is word i mod 4 of block i / 4), and move `step`
+ *     takes its words 3 step, 3 step + 1, 3 step + 2 (coordinate, change,
+ *     acceptance); uniform U = (r >> 8) * 2^-24; coordinate d = (r * n) >> 32;
  *   - neighbour: x'_d = clamp(x_d + rho_d (2U - 1), l_d, u_d),
  *     rho_d = radius_frac (u_d - l_d); or resampling x'_d = l_d + (u_d - l_d) U;
  *   - accept iff dE <= 0 or U2 < exp(-dE/T);
@@ -100,17 +103,25 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
     orc_philox4x32_10(ctr, key, out);
 }
 
-/* The three uniforms of one move (Sec. 2.1, Step 3): coordinate, change,
- * acceptance.  r[3] is returned for callers that need a fourth word. */
-void orc_move_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step,
-                   uint32_t n, uint32_t *d, double *u1, double *u2, uint32_t *r3)
+/* Word i of the move stream of one chain at one level: word i mod 4 of the
+ * block with counter (i / 4, level, chain, MOVE | problem << 8). */
+static uint32_t move_word(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint64_t i)
 {
     uint32_t r[4];
-    draw(seed, step, level, chain, ORC_TAG_MOVE | (problem << 8), r);
-    *d = orc_pick(r[0], n);
-    *u1 = orc_uniform(r[1]);
-    *u2 = orc_uniform(r[2]);
-    if (r3) *r3 = r[3];
+    draw(seed, (uint32_t)(i >> 2), level, chain, ORC_TAG_MOVE | (problem << 8), r);
+    return r[i & 3u];
+}
+
+/* The three random numbers of one move (Sec. 2.1, Step 3): coordinate,
+ * change, acceptance -- words 3 step, 3 step + 1 and 3 step + 2 of the move
+ * stream (so four moves take three blocks). */
+void orc_move_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step,
+                   uint32_t n, uint32_t *d, double *u1, double *u2)
+{
+    const uint64_t i = 3u * (uint64_t)step;
+    *d = orc_pick(move_word(seed, problem, level, chain, i), n);
+    *u1 = orc_uniform(move_word(seed, problem, level, chain, i + 1u));
+    *u2 = orc_uniform(move_word(seed, problem, level, chain, i + 2u));
 }
 
 /* Random start of one chain (Sec. 2.2.2: threads start from a random initial
@@ -306,7 +317,7 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
     for (uint32_t step = 0; step < p->steps; ++step) {
         uint32_t d;
         double u1, u2;
-        orc_move_draw(p->seed, p->problem, level, chain, step, p->n, &d, &u1, &u2, NULL);
+        orc_move_draw(p->seed, p->problem, level, chain, step, p->n, &d, &u1, &u2);
         double xd = x[d];
         double xn = orc_neighbour(p->move_rule, xd, p->lower[d], p->upper[d], p->radius_frac, u1);
         orc_cost cn;
@@ -456,7 +467,7 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
         for (uint32_t step = 0; step < steps; ++step) {
             uint32_t d;
             double u1, u2;
-            orc_move_draw(seed, problem, level, ch, step, n, &d, &u1, &u2, NULL);
+            orc_move_draw(seed, problem, level, ch, step, n, &d, &u1, &u2);
             double xd = x[d];
             double xn = orc_neighbour(move_rule, xd, lower[d], upper[d], radius_frac, u1);
             orc_cost cn;
@@ -647,16 +658,30 @@ void orc_mlp_forward_bound(const double *params, const double *z, double *out2, 
     }
 }
 
-/* Standard Cauchy draw of a learned move, by inversion of its distribution
- * function on the first word U0 of the Philox block
- * (step, level, chain, 3 | problem << 8): t = tan(pi (U0 - 1/2)). */
-double orc_learn_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
+/* The learned block of a move: counter (step, level, chain, 3 | problem << 8).
+ * Its first word U0 gives the standard Cauchy draw, by inversion of the
+ * distribution function: t = tan(pi (U0 - 1/2)); its second word U1 chooses
+ * the component of the mixture (the plain move iff U1 < eps). */
+static void learn_block(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step,
+                        uint32_t r[4])
 {
     const uint32_t ctr[4] = {step, level, chain, 3u | (problem << 8)};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-    uint32_t r[4];
     orc_philox4x32_10(ctr, key, r);
+}
+
+double orc_learn_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
+{
+    uint32_t r[4];
+    learn_block(seed, problem, level, chain, step, r);
     return tan(ORC_PI * (orc_uniform(r[0]) - 0.5));
+}
+
+double orc_learn_mix(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint32_t step)
+{
+    uint32_t r[4];
+    learn_block(seed, problem, level, chain, step, r);
+    return orc_uniform(r[1]);
 }
 
 /* Log density of the proposal, in scaled units: the Cauchy density with

@@ -153,7 +153,7 @@ __device__ void batch_tile(const BatchArgs<R> &a, const BatchProblem &P, uint32_
         }
         cost.set(acc.finish(n), n);
     } else {
-        for (uint32_t i = 0; i < n; ++i) xs[(i << 6) + lane] = xw[i];
+        fill_tile(xs, 64u, lane, xw, n);
         cost.set(Full{start[0], start[1], start[2]}, n);
     }
     const double T = a.T[level];

@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(256)
             }
             cost.set(acc.finish(n), n);
         } else {
-            for (uint32_t i = 0; i < n; ++i) xs[i * WG + tid] = xw[i];
+            fill_tile(xs, WG, tid, xw, n);
             cost.set(start, n);
         }
 

@@ -49,7 +49,7 @@ __device__ __forceinline__ R start_coord(const LevelArgs<R> &a, const R *tab, co
 }
 
 // N Metropolis steps of one chain per lane on the overlay state.  The next
-// move's generator block is computed ahead as independent work.
+// group's generator blocks are computed a group ahead as independent work.
 template <typename R, int F, bool TABLE, int MOVE, typename LogFn>
 __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, const R *tab, const R *xw,
                                                       uint16_t *keys, R *vals, uint32_t K, uint32_t WG, uint32_t tid,
@@ -59,10 +59,13 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
     const uint32_t n = a.n, k0 = a.seed_lo, k1 = a.seed_hi;
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
     uint32_t accepted = 0;
-    Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
+    MoveGroup m = move_group(0u, level, chain, ctr3, k0, k1), next{};
     for (uint32_t step = 0; step < a.steps; ++step) {
-        const Ctr rn = philox4x32_10(Ctr{step + 1u, level, chain, ctr3}, k0, k1);
-        const uint32_t d = pick(r.w0, n);
+        const uint32_t j = step & 3u;
+        if (j == 0) next = move_group((step >> 2) + 1u, level, chain, ctr3, k0, k1);
+        uint32_t wd, w1, w2;
+        move_words(m, j, wd, w1, w2);
+        const uint32_t d = pick(wd, n);
         uint32_t h = slot_of(d, K);
         R xd;
         for (;;) {
@@ -78,9 +81,9 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
             h = h + 1u == K ? 0u : h + 1u;
         }
         const Coord<R> c = coord<R, TABLE>(a, tab, d);
-        const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
+        const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
         const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-        const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
+        const bool take = metropolis(df, u24<R>(w2), T, nl2T);
         logf(step, d, take, xd, xn, df);
         if (take) {
             keys[h * WG + tid] = (uint16_t)d;
@@ -88,7 +91,7 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
         }
         cost.commit(take, a.inv_n);
         accepted += take ? 1u : 0u;
-        r = rn;
+        if (j == 3u) m = next;
     }
     return accepted;
 }

@@ -8,7 +8,8 @@
 // -- coordinate and both uniforms of each move -- into an LDS ring, a chunk of
 // C moves ahead.  Generator wave w + 4 serves state wave w and shares its
 // SIMD.  A workgroup barrier separates chunks (the ring is double-buffered).
-// The moves are the dense kernel's moves, value for value.
+// A chunk is one group of four moves of the plain move stream (three
+// generator blocks).  The moves are the dense kernel's moves, value for value.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,7 +25,8 @@ namespace sa {
 namespace {
 
 constexpr uint32_t kChains = 256;  // chains per workgroup (state lanes)
-constexpr uint32_t kChunk = 4;     // moves per ring half
+constexpr uint32_t kChunk = 4;     // moves per ring half: one group of the move stream
+static_assert(kChunk == 4, "a chunk is one four-move group of the move stream");
 
 // One move's draws in a 16-byte ring entry: coordinate, the two uniforms
 // (FP32 bit patterns), unused.
@@ -99,21 +101,24 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                 }
                 cost.set(acc.finish(n), n);
             } else {
-                for (uint32_t i = 0; i < n; ++i) xs[i * kChains + col] = xw[i];
+                fill_tile(xs, kChains, col, xw, n);
                 cost.set(start, n);
             }
         }
 
-        // Generator: draws of chunk k into ring half k & 1.
+        // Generator: draws of chunk k (group k of the move stream) into ring
+        // half k & 1.
         const auto produce = [&](uint32_t k) {
             Draw *half = ring + (k & 1u) * kChunk * kChains;
+            const MoveGroup m = move_group(k, level, chain, ctr3, k0, k1);
 #pragma unroll
             for (uint32_t j = 0; j < kChunk; ++j) {
                 const uint32_t step = k * kChunk + j;
                 if (step < steps) {
-                    const Ctr r = philox4x32_10(Ctr{step, level, chain, ctr3}, k0, k1);
-                    half[j * kChains + col] = make_uint4(pick(r.w0, n), __float_as_uint(u24f(r.w1)),
-                                                         __float_as_uint(u24f(r.w2)), 0u);
+                    uint32_t wd, w1, w2;
+                    move_words(m, j, wd, w1, w2);
+                    half[j * kChains + col] = make_uint4(pick(wd, n), __float_as_uint(u24f(w1)),
+                                                         __float_as_uint(u24f(w2)), 0u);
                 }
             }
         };

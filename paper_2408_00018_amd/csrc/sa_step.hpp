@@ -239,15 +239,77 @@ template <> __device__ __forceinline__ float widen_inf<float>() { return __built
 template <> __device__ __forceinline__ double widen_inf<double>() { return __builtin_inf(); }
 
 // ---------------------------------------------------------------------------
+// Start every chain of a tile from the level's start state:
+// xs[i * stride + col] = xw[i] for i < n.  The reads are issued sixteen (then
+// four) at a time, so the loop waits for one LDS round trip per batch instead
+// of one per coordinate.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void fill_tile(R *xs, uint32_t stride, uint32_t col, const R *xw, uint32_t n)
+{
+    uint32_t i = 0;
+    for (; i + 16u <= n; i += 16u) {
+        R v[16];
+#pragma unroll
+        for (uint32_t k = 0; k < 16u; ++k) v[k] = xw[i + k];
+#pragma unroll
+        for (uint32_t k = 0; k < 16u; ++k) xs[(i + k) * stride + col] = v[k];
+    }
+    for (; i + 4u <= n; i += 4u) {
+        R v[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) v[k] = xw[i + k];
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) xs[(i + k) * stride + col] = v[k];
+    }
+    for (; i < n; ++i) xs[i * stride + col] = xw[i];
+}
+
+// ---------------------------------------------------------------------------
+// The plain move stream of one chain at one level.  The words of the Philox
+// blocks (b, level, chain, tag), b = 0, 1, ..., are taken in order, three per
+// move: coordinate, change, acceptance.  Four moves use three blocks, so
+// moves 4g .. 4g+3 read blocks 3g, 3g+1, 3g+2:
+//   move 4g    b0.w0  b0.w1  b0.w2
+//   move 4g+1  b0.w3  b1.w0  b1.w1
+//   move 4g+2  b1.w2  b1.w3  b2.w0
+//   move 4g+3  b2.w1  b2.w2  b2.w3
+// ---------------------------------------------------------------------------
+struct MoveGroup {
+    Ctr b0, b1, b2;
+};
+
+__device__ __forceinline__ MoveGroup move_group(uint32_t g, uint32_t level, uint32_t chain, uint32_t ctr3,
+                                                uint32_t k0, uint32_t k1)
+{
+    const uint32_t b = 3u * g;
+    return MoveGroup{philox4x32_10(Ctr{b, level, chain, ctr3}, k0, k1),
+                     philox4x32_10(Ctr{b + 1u, level, chain, ctr3}, k0, k1),
+                     philox4x32_10(Ctr{b + 2u, level, chain, ctr3}, k0, k1)};
+}
+
+// The three words of move j (0-3) of a group.
+__device__ __forceinline__ void move_words(const MoveGroup &m, uint32_t j, uint32_t &wd, uint32_t &w1, uint32_t &w2)
+{
+    switch (j) {
+    case 0: wd = m.b0.w0; w1 = m.b0.w1; w2 = m.b0.w2; break;
+    case 1: wd = m.b0.w3; w1 = m.b1.w0; w2 = m.b1.w1; break;
+    case 2: wd = m.b1.w2; w1 = m.b1.w3; w2 = m.b2.w0; break;
+    default: wd = m.b2.w1; w1 = m.b2.w2; w2 = m.b2.w3; break;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // N Metropolis steps of one chain per lane at temperature T (Sec. 2.1, Steps
-// 2-4), state in LDS at xs[d * stride + lane_off].  Software-pipelined two
-// moves deep: at the top of move s the (old) value of move s+1's coordinate is
-// read from LDS and move s+2's draws are computed, so neither the LDS latency
-// nor the generator's dependent rounds sit on move s's critical path.  If
-// move s+1 picks the coordinate move s writes, the written value is
-// forwarded.  coordf(d) returns coordinate d's {l, u, rho, s}; logf(step, d,
-// take, x_old, x_new, df) is called for every move (a no-op unless logging).
-// Returns the number of accepted moves.
+// 2-4), state in LDS at xs[d * stride + lane_off].  Software-pipelined: at
+// the top of move s the (old) value of move s+1's coordinate is read from
+// LDS, and each generator block of the next group of four moves is computed
+// as soon as the current group has consumed the block it replaces, so
+// neither the LDS latency nor the generator's dependent rounds sit on a
+// move's critical path.  If move s+1 picks the coordinate move s writes, the
+// written value is forwarded.  coordf(d) returns coordinate d's
+// {l, u, rho, s}; logf(step, d, take, x_old, x_new, df) is called for every
+// move (a no-op unless logging).  Returns the number of accepted moves.
 // ---------------------------------------------------------------------------
 template <typename R, int F, int MOVE, typename CoordFn, typename LogFn>
 __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t lane_off, Cost<R, F> &cost,
@@ -256,54 +318,60 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
                                               uint32_t k1, double T, float nl2T, float inv_n)
 {
     uint32_t accepted = 0;
-    Ctr r = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
-    Ctr r1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
-    uint32_t d = pick(r.w0, n);
-    uint32_t d1 = pick(r1.w0, n);
+    Ctr b0 = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
+    Ctr b1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
+    Ctr b2 = philox4x32_10(Ctr{2u, level, chain, ctr3}, k0, k1);
+    uint32_t d = pick(b0.w0, n);
     R xd = xs[__umul24(d, stride) + lane_off];
-    // One move; the pipeline state (r, r1, d, d1, xd) advances by one.
-    const auto move = [&](uint32_t step) {
-        const R x1_lds = xs[__umul24(d1, stride) + lane_off];
-        const Ctr r2 = philox4x32_10(Ctr{step + 2u, level, chain, ctr3}, k0, k1);
+    // One move on the change and acceptance words (w1, w2); dn is the next
+    // move's coordinate, whose value is read ahead.
+    const auto move = [&](uint32_t step, uint32_t w1, uint32_t w2, uint32_t dn) {
+        const R xn_lds = xs[__umul24(dn, stride) + lane_off];
         const Coord<R> c = coordf(d);
-        const R xn = neighbour<MOVE>(xd, c, u24<R>(r.w1));
+        const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
         const R df = cost.delta(xd - c.sh, xn - c.sh, n, inv_n);
-        const bool take = metropolis(df, u24<R>(r.w2), T, nl2T);
+        const bool take = metropolis(df, u24<R>(w2), T, nl2T);
         logf(step, d, take, xd, xn, df);
         const R xwr = take ? xn : xd;
         xs[__umul24(d, stride) + lane_off] = xwr;
         cost.commit(take, inv_n);
         accepted += take ? 1u : 0u;
-        xd = d1 == d ? xwr : x1_lds;
-        d = d1;
-        r = r1;
-        r1 = r2;
-        d1 = pick(r2.w0, n);
+        xd = dn == d ? xwr : xn_lds;
+        d = dn;
     };
-    // Three moves per iteration: the generator blocks rotate through three
-    // register sets, so a three-fold body needs no register copies.
-    uint32_t step = 0;
-    for (; step + 3 <= steps; step += 3) {
-        move(step);
-        move(step + 1);
-        move(step + 2);
+    // One group of four moves per iteration; each block variable is
+    // overwritten by its successor in the next group once its last word is
+    // consumed, so the rotation needs no register copies.
+    uint32_t step = 0, blk = 3;
+    for (; step + 4 <= steps; step += 4, blk += 3) {
+        move(step, b0.w1, b0.w2, pick(b0.w3, n));
+        b0 = philox4x32_10(Ctr{blk, level, chain, ctr3}, k0, k1);
+        move(step + 1, b1.w0, b1.w1, pick(b1.w2, n));
+        move(step + 2, b1.w3, b2.w0, pick(b2.w1, n));
+        b1 = philox4x32_10(Ctr{blk + 1u, level, chain, ctr3}, k0, k1);
+        move(step + 3, b2.w2, b2.w3, pick(b0.w0, n));
+        b2 = philox4x32_10(Ctr{blk + 2u, level, chain, ctr3}, k0, k1);
     }
-    for (; step < steps; ++step) move(step);
+    // The last one to three moves, on the blocks of their group (already drawn).
+    if (step < steps) move(step, b0.w1, b0.w2, pick(b0.w3, n));
+    if (step + 1 < steps) move(step + 1, b1.w0, b1.w1, pick(b1.w2, n));
+    if (step + 2 < steps) move(step + 2, b1.w3, b2.w0, pick(b2.w1, n));
     return accepted;
 }
 
 // ---------------------------------------------------------------------------
 // N steps of the learned-proposal mixture, FP32 (an extension of the method,
-// not in the paper).  Per move, with the move draws r (the plain method's
-// counters) and the learned draws q (tag kTagLearn, same step/level/chain):
-//   d from r0; a plain move with probability eps (U(r3) < eps): the radius
-//   neighbour from r1 and the Metropolis test on r2, as in run_steps;
+// not in the paper).  Per move, with the move's three words (wd, w1, w2) of
+// the plain move stream and the learned block q (counter (step, level,
+// chain, kTagLearn)):
+//   d from wd; a plain move with probability eps (U(q1) < eps): the radius
+//   neighbour from w1 and the Metropolis test on w2, as in run_steps;
 //   otherwise the network gives (mu, s) at the features of x_d, the scaled
 //   displacement is dl = mu + e^s t with t = tan(pi (U(q0) - 1/2)) (a standard
 //   Cauchy draw by inversion), x'_d = x_d + dl (u_d - l_d); a proposal
 //   outside [l_d, u_d] is rejected; otherwise the network is evaluated again
 //   at x'_d (same history) and the move is taken iff
-//       U(r2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
+//       U(w2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
 //   (Metropolis-Hastings: each component is reversible on its own, so the
 //   state-independent mixture is too).
 // h holds the history features of the chain's last four accepted scaled
@@ -320,16 +388,19 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
                                                       const unsigned char *net, float (&h)[4])
 {
     uint32_t accepted = 0;
+    MoveGroup m{};
     for (uint32_t step = 0; step < steps; ++step) {
-        const Ctr r = philox4x32_10(Ctr{step, level, chain, ctr_move}, k0, k1);
+        if ((step & 3u) == 0) m = move_group(step >> 2, level, chain, ctr_move, k0, k1);
+        uint32_t wd, w1, w2;
+        move_words(m, step & 3u, wd, w1, w2);
         const Ctr q = philox4x32_10(Ctr{step, level, chain, ctr_learn}, k0, k1);
-        const uint32_t d = pick(r.w0, n);
+        const uint32_t d = pick(wd, n);
         const Coord<float> c = coordf(d);
         const uint32_t at = __umul24(d, stride) + lane_off;
         const float xd = xs[at];
         const float w = c.hi - c.lo;
         const float inv_w = 1.0f / w;
-        const bool plain = u24f(r.w3) < eps;
+        const bool plain = u24f(q.w1) < eps;
 
         float z[mlp::kInputs] = {(xd - c.lo) * inv_w, featT, h[0], h[1], h[2], h[3]};
         float mu, s;
@@ -348,11 +419,11 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
         const float e2 = (dl + mu2) * hw_exp2(-kLog2e * s2);
         const float lq = (s - s2) + kLn2 * (hw_log2(fmaf(t, t, 1.0f)) - hw_log2(fmaf(e2, e2, 1.0f)));
 
-        const float xp = neighbour<SA_MOVE_RADIUS>(xd, c, u24f(r.w1));
+        const float xp = neighbour<SA_MOVE_RADIUS>(xd, c, u24f(w1));
         const float xn = plain ? xp : xl;
         const bool valid = plain || inbox;
         const float df = cost.delta(xd - c.sh, (valid ? xn : xd) - c.sh, n, inv_n);
-        const float u2 = u24f(r.w2);
+        const float u2 = u24f(w2);
         const bool take = plain ? metropolis(df, u2, 0.0, nl2T) : (inbox && u2 < hw_exp2(fmaf(df, nl2T, kLog2e * lq)));
         logf(step, d, take, xd, xn, df);
         xs[at] = take ? xn : xd;

@@ -86,7 +86,7 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
         f_acc_err = 0.0
         for s in range(moves.shape[-1]):
             m = moves[j, s]
-            d_ref, u1, u2, _ = O.move_draw(seed, problem, level, c, s, n)
+            d_ref, u1, u2 = O.move_draw(seed, problem, level, c, s, n)
             assert int(m["d"]) == d_ref, (level, c, s)
             assert m["x_old"] == x[d_ref], (level, c, s)
             xn_ref = O.neighbour(move_rule, float(m["x_old"]), float(lower32[d_ref]), float(upper32[d_ref]),
@@ -240,12 +240,12 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
         f_acc_err = 0.0
         for s in range(moves.shape[-1]):
             m = moves[j, s]
-            d, u1, u2, r3 = O.move_draw(seed, problem, level, c, s, n)
+            d, u1, u2 = O.move_draw(seed, problem, level, c, s, n)
             assert int(m["d"]) == d, (level, c, s)
             assert m["x_old"] == x[d], (level, c, s)
             lo, hi = float(lower32[d]), float(upper32[d])
             w = hi - lo
-            plain = O.uniform(r3) < eps32
+            plain = O.learn_mix(seed, problem, level, c, s) < eps32
             xn = x.copy()
             xn[d] = m["x_new"]
             if plain:
