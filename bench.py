@@ -38,11 +38,12 @@ import workloads as W  # noqa: E402
 # Algorithmic work of one FP32 normalized-Schwefel move with the radius rule:
 SLOT_WEIGHT = {"mad_u64": 2.17, "mul_hi": 1.7, "trans": 3.15, "valu": 1.0}
 SLOTS_PER_MOVE = {
-    # counter-based generator: of Philox4x32-10's ten rounds, rounds 3-10 depend
-    # on the step counter in every word (two 32x32->64 multiplies and two
-    # three-input XORs each); rounds 1-2 leave two step-dependent XORs, the rest
-    # is fixed per chain and level
-    "philox": 16 * SLOT_WEIGHT["mad_u64"] + 16 * 1 + 2 * 1,
+    # counter-based generator: a move takes three of a block's four words, so
+    # 3/4 of a block per move.  Of Philox4x32-10's ten rounds, rounds 3-10
+    # depend on the block counter in every word (two 32x32->64 multiplies and
+    # two three-input XORs each); rounds 1-2 leave two counter-dependent XORs,
+    # the rest is fixed per chain and level
+    "philox": 0.75 * (16 * SLOT_WEIGHT["mad_u64"] + 16 * 1 + 2 * 1),
     "coordinate_pick": SLOT_WEIGHT["mul_hi"],                 # high word of r0 * n
     "uniforms": 2 * 3,                                        # (r >> 8), convert, scale; twice
     "neighbour": 3,                                           # 2u - 1, fma, clamp (med3)

@@ -69,6 +69,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n = P.n, tiles = P.chains >> 6;
     const size_t sbase = (size_t)(lvl & 1u) * a.ntiles;
+    const double rec_prev = publish ? a.rec[p] : 0.0;  // loaded with the candidates
     R gf = widen_inf<R>();
     uint32_t gc = 0xFFFFFFFFu, gj = P.first_tile;
     uint64_t gacc = 0;
@@ -81,17 +82,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
         }
         gacc += s.accepts;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const R f2 = __shfl_xor(gf, off, 64);
-        const uint32_t c2 = __shfl_xor(gc, off, 64);
-        const uint32_t j2 = __shfl_xor(gj, off, 64);
-        if (f2 < gf || (f2 == gf && c2 < gc)) {
-            gf = f2;
-            gc = c2;
-            gj = j2;
-        }
-    }
+    wave_best(gf, gc, gj);
     gacc = wave_sum(gacc);
     gj = __builtin_amdgcn_readfirstlane(gj);
     if (gj < P.first_tile || gj >= P.first_tile + tiles) gj = P.first_tile;  // all-NaN guard
@@ -102,7 +93,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
     start[1] = ws.s1;
     start[2] = ws.s2;
     if (publish) {
-        const bool improved = ws.ff < a.rec[p];
+        const bool improved = ws.ff < rec_prev;
         for (uint32_t i = lane; i < n; i += 64) {
             const R v = a.slot_x[xoff + i];
             a.x_best[P.x_off + i] = v;
@@ -119,7 +110,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
             t.reserved = 0;
             t.f_win = (double)gf;
             t.f_best = ws.ff;
-            t.f_rec = improved ? ws.ff : a.rec[p];
+            t.f_rec = improved ? ws.ff : rec_prev;
             t.accepts = gacc;
             t.t_ticks = wall_clock64();
             a.trace[(size_t)p * a.levels + lvl] = t;
@@ -131,7 +122,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
 // One level of one tile (64 chains of problem p).
 template <typename R, int F, int MOVE, bool LOG>
 __device__ void batch_tile(const BatchArgs<R> &a, const BatchProblem &P, uint32_t p, uint32_t tile, R *xs, R *xw,
-                           const R *tab, uint32_t level, const double *start)
+                           const R *tab, uint32_t level, const double *start, double T, float nl2T)
 {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n = P.n;
@@ -156,8 +147,6 @@ __device__ void batch_tile(const BatchArgs<R> &a, const BatchProblem &P, uint32_
         fill_tile(xs, 64u, lane, xw, n);
         cost.set(Full{start[0], start[1], start[2]}, n);
     }
-    const double T = a.T[level];
-    const float nl2T = -kLog2e * a.inv_T[level];
     const bool log_level = LOG && p == a.log_problem && level >= a.log_level && level - a.log_level < a.log_levels;
     const bool logging = log_level && chain < a.log_chains;
     const auto coordf = [&](uint32_t d) { return table_coord(tab, d); };
@@ -203,6 +192,9 @@ __global__ void __launch_bounds__(256) batch_level_kernel(const BatchArgs<R> a, 
     if (tile == 0xFFFFFFFFu) return;
     const uint32_t p = __builtin_amdgcn_readfirstlane(a.tile_prob[tile]);
     const BatchProblem P = a.probs[p];
+    // The level's constants are loaded before the hand-off (latency overlap).
+    const double T = a.T[level];
+    const float nl2T = -kLog2e * a.inv_T[level];
     R *xs = reinterpret_cast<R *>(lds_raw + __builtin_amdgcn_readfirstlane(a.wg_lds[slot]));
     R *xw = xs + ((size_t)P.n << 6);
     R *tab = xw + P.n;
@@ -212,9 +204,9 @@ __global__ void __launch_bounds__(256) batch_level_kernel(const BatchArgs<R> a, 
     if (level > 0) batch_adopt<R>(a, P, p, level - 1, xw, start, tile == P.first_tile);
     wave_sync();
     switch (P.func) {
-    case kSchwefel: batch_tile<R, kSchwefel, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start); break;
-    case kRastrigin: batch_tile<R, kRastrigin, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start); break;
-    default: batch_tile<R, kAckley, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start); break;
+    case kSchwefel: batch_tile<R, kSchwefel, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
+    case kRastrigin: batch_tile<R, kRastrigin, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
+    default: batch_tile<R, kAckley, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
     }
 }
 

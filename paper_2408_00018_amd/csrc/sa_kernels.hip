@@ -55,6 +55,11 @@ __global__ void __launch_bounds__(256)
     R *xb = xw + n;
     R *tab = xb + n;
 
+    // The level's constants are loaded first, so their latency overlaps the
+    // hand-off's loads instead of following it.
+    const double T = a.T[level];
+    const float nl2T = -kLog2e * a.inv_T[level];
+    const float featT = (LEARN || CAPTURE) ? a.featT[level] : 0.0f;
     if (LEARN) mlp::stage_net(net_lds, a.net);
     if (TABLE) {
         for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
@@ -75,9 +80,6 @@ __global__ void __launch_bounds__(256)
 
     const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
-    const double T = a.T[level];
-    const float nl2T = -kLog2e * a.inv_T[level];
-    const float featT = (LEARN || CAPTURE) ? a.featT[level] : 0.0f;
     const bool log_level = LOG && level >= a.log_level && level - a.log_level < a.log_levels;
     const Full start{sh_start[0], sh_start[1], sh_start[2]};
     R wf = widen_inf<R>();

@@ -91,17 +91,7 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
         }
         gacc += s.accepts;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const R f2 = __shfl_xor(gf, off, 64);
-        const uint32_t c2 = __shfl_xor(gc, off, 64);
-        const uint32_t j2 = __shfl_xor(gj, off, 64);
-        if (f2 < gf || (f2 == gf && c2 < gc)) {
-            gf = f2;
-            gc = c2;
-            gj = j2;
-        }
-    }
+    wave_best(gf, gc, gj);
     gacc = wave_sum(gacc);
     __syncthreads();
     if (lane == 0) {

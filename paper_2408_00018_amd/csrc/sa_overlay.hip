@@ -59,39 +59,44 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
     const uint32_t n = a.n, k0 = a.seed_lo, k1 = a.seed_hi;
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
     uint32_t accepted = 0;
-    MoveGroup m = move_group(0u, level, chain, ctr3, k0, k1), next{};
-    for (uint32_t step = 0; step < a.steps; ++step) {
-        const uint32_t j = step & 3u;
-        if (j == 0) next = move_group((step >> 2) + 1u, level, chain, ctr3, k0, k1);
-        uint32_t wd, w1, w2;
-        move_words(m, j, wd, w1, w2);
-        const uint32_t d = pick(wd, n);
-        uint32_t h = slot_of(d, K);
-        R xd;
-        for (;;) {
-            const uint32_t key = keys[h * WG + tid];
-            if (key == d) {
-                xd = vals[h * WG + tid];
-                break;
+    MoveGroup m = move_group(0u, level, chain, ctr3, k0, k1);
+    const uint32_t steps = a.steps;
+    for (uint32_t g = 0; 4u * g < steps; ++g) {
+        const MoveGroup next = move_group(g + 1u, level, chain, ctr3, k0, k1);
+#pragma unroll
+        for (uint32_t j = 0; j < 4u; ++j) {
+            const uint32_t step = 4u * g + j;
+            if (step >= steps) break;
+            uint32_t wd, w1, w2;
+            move_words(m, j, wd, w1, w2);
+            const uint32_t d = pick(wd, n);
+            uint32_t h = slot_of(d, K);
+            R xd;
+            for (;;) {
+                const uint32_t key = keys[h * WG + tid];
+                if (key == d) {
+                    xd = vals[h * WG + tid];
+                    break;
+                }
+                if (key == kEmptyKey) {
+                    xd = start_coord<R, TABLE>(a, tab, xw, level, chain, d);
+                    break;
+                }
+                h = h + 1u == K ? 0u : h + 1u;
             }
-            if (key == kEmptyKey) {
-                xd = start_coord<R, TABLE>(a, tab, xw, level, chain, d);
-                break;
+            const Coord<R> c = coord<R, TABLE>(a, tab, d);
+            const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
+            const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
+            const bool take = metropolis(df, u24<R>(w2), T, nl2T);
+            logf(step, d, take, xd, xn, df);
+            if (take) {
+                keys[h * WG + tid] = (uint16_t)d;
+                vals[h * WG + tid] = xn;
             }
-            h = h + 1u == K ? 0u : h + 1u;
+            cost.commit(take, a.inv_n);
+            accepted += take ? 1u : 0u;
         }
-        const Coord<R> c = coord<R, TABLE>(a, tab, d);
-        const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
-        const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-        const bool take = metropolis(df, u24<R>(w2), T, nl2T);
-        logf(step, d, take, xd, xn, df);
-        if (take) {
-            keys[h * WG + tid] = (uint16_t)d;
-            vals[h * WG + tid] = xn;
-        }
-        cost.commit(take, a.inv_n);
-        accepted += take ? 1u : 0u;
-        if (j == 3u) m = next;
+        m = next;
     }
     return accepted;
 }
@@ -119,6 +124,9 @@ __global__ void __launch_bounds__(256)
     R *tab = xb + n;
     R *vals = tab + (TABLE ? 4 * n : 0);
     uint16_t *keys = reinterpret_cast<uint16_t *>(vals + (size_t)K * WG);
+    // The level's constants are loaded before the hand-off (latency overlap).
+    const double T = a.T[level];
+    const float nl2T = -kLog2e * a.inv_T[level];
 
     if (TABLE) {
         for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
@@ -137,8 +145,6 @@ __global__ void __launch_bounds__(256)
     }
     __syncthreads();
 
-    const double T = a.T[level];
-    const float nl2T = -kLog2e * a.inv_T[level];
     const bool log_level = LOG && level >= a.log_level && level - a.log_level < a.log_levels;
     const Full start{sh_start[0], sh_start[1], sh_start[2]};
     R wf = widen_inf<R>();

@@ -54,6 +54,8 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
     float *xw = xs + (size_t)n * kChains;
     float *xb = xw + n;
     float *tab = xb + n;
+    // The level's constant is loaded before the hand-off (latency overlap).
+    const float nl2T = -kLog2e * a.inv_T[level];
 
     if (TABLE) {
         for (uint32_t i = tid; i < 4 * n; i += blockDim.x) tab[i] = a.table[i];
@@ -74,7 +76,6 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
 
     const uint32_t k0 = a.seed_lo, k1 = a.seed_hi;
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
-    const float nl2T = -kLog2e * a.inv_T[level];
     const Full start{sh_start[0], sh_start[1], sh_start[2]};
     const uint32_t steps = a.steps, nchunks = (steps + kChunk - 1) / kChunk;
     float wf = widen_inf<float>();

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "sa_device.hpp"
 #include "sa_internal.hpp"
 #include "sa_mlp_net.hpp"
@@ -201,29 +203,116 @@ template <typename R> __device__ __forceinline__ void best_of(R &f, uint32_t &c,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-wide reductions without the LDS crossbar.  Step k (k = 0..5) hands
+// every lane two operands a, b whose combination covers the lane's group of
+// 2^(k+1) lanes: steps 0-3 pair a lane with a partner in its 16-lane row
+// through DPP (quad permutations, half-row and row mirrors), steps 4 and 5
+// exchange whole rows and half-waves with gfx950's permlane16/permlane32
+// swaps (both operands are then swapped copies; their combination is the
+// same).  For a commutative, associative combination every lane ends with the
+// wave's result.
+// ---------------------------------------------------------------------------
+template <int K> __device__ __forceinline__ void lane_pair(uint32_t v, uint32_t &a, uint32_t &b)
+{
+    if constexpr (K < 4) {
+        constexpr int ctrl = K == 0 ? 0xB1 : K == 1 ? 0x4E : K == 2 ? 0x141 : 0x140;
+        a = v;
+        b = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+    } else if constexpr (K == 4) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = p[0];
+        b = p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = p[0];
+        b = p[1];
+    }
+}
+
+template <int K> __device__ __forceinline__ void lane_pair(float v, float &a, float &b)
+{
+    uint32_t ua, ub;
+    lane_pair<K>(__float_as_uint(v), ua, ub);
+    a = __uint_as_float(ua);
+    b = __uint_as_float(ub);
+}
+
+template <int K> __device__ __forceinline__ void lane_pair(uint64_t v, uint64_t &a, uint64_t &b)
+{
+    uint32_t alo, blo, ahi, bhi;
+    lane_pair<K>((uint32_t)v, alo, blo);
+    lane_pair<K>((uint32_t)(v >> 32), ahi, bhi);
+    a = ((uint64_t)ahi << 32) | alo;
+    b = ((uint64_t)bhi << 32) | blo;
+}
+
+template <int K> __device__ __forceinline__ void lane_pair(double v, double &a, double &b)
+{
+    uint64_t ua, ub;
+    lane_pair<K>((uint64_t)__double_as_longlong(v), ua, ub);
+    a = __longlong_as_double((long long)ua);
+    b = __longlong_as_double((long long)ub);
+}
+
+// Calls f(integral_constant<int, K>) for K = 0..5.
+template <typename Fn> __device__ __forceinline__ void over_lane_steps(Fn &&f)
+{
+    f(std::integral_constant<int, 0>{});
+    f(std::integral_constant<int, 1>{});
+    f(std::integral_constant<int, 2>{});
+    f(std::integral_constant<int, 3>{});
+    f(std::integral_constant<int, 4>{});
+    f(std::integral_constant<int, 5>{});
+}
+
+// Lexicographic (cost, chain) minimum over the wave; every lane gets it.
 template <typename R> __device__ __forceinline__ void wave_best(R &f, uint32_t &c)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const R f2 = __shfl_xor(f, off, 64);
-        const uint32_t c2 = __shfl_xor(c, off, 64);
-        best_of(f, c, f2, c2);
-    }
+    over_lane_steps([&](auto k) {
+        constexpr int K = decltype(k)::value;
+        R fa, fb;
+        uint32_t ca, cb;
+        lane_pair<K>(f, fa, fb);
+        lane_pair<K>(c, ca, cb);
+        best_of(fa, ca, fb, cb);
+        f = fa;
+        c = ca;
+    });
+}
+
+// The same with a payload j that travels with the chosen (cost, chain).
+template <typename R> __device__ __forceinline__ void wave_best(R &f, uint32_t &c, uint32_t &j)
+{
+    over_lane_steps([&](auto k) {
+        constexpr int K = decltype(k)::value;
+        R fa, fb;
+        uint32_t ca, cb, ja, jb;
+        lane_pair<K>(f, fa, fb);
+        lane_pair<K>(c, ca, cb);
+        lane_pair<K>(j, ja, jb);
+        if (fb < fa || (fb == fa && cb < ca)) {
+            fa = fb;
+            ca = cb;
+            ja = jb;
+        }
+        f = fa;
+        c = ca;
+        j = ja;
+    });
 }
 
 template <typename T> __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    over_lane_steps([&](auto k) {
+        T a, b;
+        lane_pair<decltype(k)::value>(v, a, b);
+        v = a + b;
+    });
     return v;
 }
 
-__device__ __forceinline__ double wave_sum_d(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum_d(double v) { return wave_sum<double>(v); }
 
 // History feature of the learned proposal: a scaled displacement h enters the
 // network as sign(h) ln(1 + 2^24 |h|) / 16 (a signed log magnitude, so a step
