@@ -85,6 +85,10 @@ __global__ void __launch_bounds__(256)
     R wf = widen_inf<R>();
     uint32_t wc = 0xFFFFFFFFu;
     uint32_t accepted = 0;
+    // The workgroup's best state: copied to xb while another tile follows,
+    // read in place (column of xs) when it comes from the last tile.
+    const R *best = xb;
+    uint32_t best_stride = 1;
 
     for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += G) {
         const uint32_t chain = tile * WG + tid;
@@ -186,27 +190,35 @@ __global__ void __launch_bounds__(256)
         R nf = wf;
         uint32_t nc = wc;
         best_of(nf, nc, tf, tc);
+        const bool last = tile + G >= a.tiles;
         if (nc != wc) {
             const uint32_t col = tc - tile * WG;
-            for (uint32_t i = tid; i < n; i += WG) xb[i] = xs[i * WG + col];
+            if (last) {
+                best = xs + col;
+                best_stride = WG;
+            } else {
+                for (uint32_t i = tid; i < n; i += WG) xb[i] = xs[i * WG + col];
+                best = xb;
+                best_stride = 1;
+            }
             wf = nf;
             wc = nc;
         }
-        __syncthreads();
+        if (!last) __syncthreads();  // xs, xb and wave_slot are reused by the next tile
     }
 
-    // ---- publish this workgroup's candidate, re-evaluated in full
-    const Full fr = full_eval_wg<R, F, TABLE>(a, tab, xb, sh_part);
+    // ---- publish this workgroup's candidate, re-evaluated in full; the
+    // evaluation's barriers also order the per-wave acceptance counts
     const uint32_t wacc = wave_sum(accepted);
     if (lane == 0) wave_acc[wave] = wacc;
-    __syncthreads();
+    const Full fr = full_eval_wg<R, F, TABLE>(a, tab, best, sh_part, best_stride);
     const size_t slot = (size_t)(level & 1u) * a.tiles + blockIdx.x;
     if (tid == 0) {
         uint32_t acc = 0;
         for (uint32_t w = 0; w < nwaves; ++w) acc += (uint32_t)wave_acc[w];
         a.slots[slot] = Slot<R>{wf, wc, acc, 0u, fr.f, fr.s1, fr.s2};
     }
-    for (uint32_t i = tid; i < n; i += WG) a.slot_x[slot * n + i] = xb[i];
+    for (uint32_t i = tid; i < n; i += WG) a.slot_x[slot * n + i] = best[i * best_stride];
 }
 
 // Close a run of levels: reduce the last level's candidates and publish its

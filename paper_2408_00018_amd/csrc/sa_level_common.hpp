@@ -21,19 +21,22 @@ __device__ __forceinline__ Coord<R> coord(const LevelArgs<R> &a, const R *tab, u
 }
 
 // ---------------------------------------------------------------------------
-// Full evaluation of a state held in LDS, FP64 arithmetic.  FP64 runs sum in
-// coordinate order on one lane (the order of a plain sequential
-// evaluation); FP32 runs use a fixed parallel order.
+// Full evaluation of a state held in LDS (coordinate i at x[i * stride]),
+// FP64 arithmetic.  FP64 runs sum in coordinate order on one lane (the order
+// of a plain sequential evaluation); FP32 runs use a fixed parallel order.
+// Contains workgroup barriers: LDS writes made before the call are visible to
+// every thread of the workgroup after it.
 // ---------------------------------------------------------------------------
 template <typename R, int F, bool TABLE>
-__device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, double (*part)[2])
+__device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, double (*part)[2],
+                             uint32_t stride = 1)
 {
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = blockDim.x >> 6;
     const uint32_t n = a.n;
     if (sizeof(R) == sizeof(double)) {
         if (tid == 0) {
             FullAcc<F> acc;
-            for (uint32_t i = 0; i < n; ++i) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+            for (uint32_t i = 0; i < n; ++i) acc.add((double)x[i * stride] - (double)coord<R, TABLE>(a, tab, i).sh);
             const Full v = acc.finish(n);
             part[0][0] = v.f;
             part[0][1] = v.s1;
@@ -45,7 +48,8 @@ __device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, do
         return v;
     }
     FullAcc<F> acc;
-    for (uint32_t i = tid; i < n; i += blockDim.x) acc.add((double)x[i] - (double)coord<R, TABLE>(a, tab, i).sh);
+    for (uint32_t i = tid; i < n; i += blockDim.x)
+        acc.add((double)x[i * stride] - (double)coord<R, TABLE>(a, tab, i).sh);
     const double pa = wave_sum_d(acc.a), pb = wave_sum_d(acc.b);
     if (lane == 0) {
         part[wave][0] = pa;

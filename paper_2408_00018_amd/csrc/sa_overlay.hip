@@ -207,10 +207,10 @@ __global__ void __launch_bounds__(256)
         __syncthreads();
     }
 
-    const Full fr = full_eval_wg<R, F, TABLE>(a, tab, xb, sh_part);
+    // the evaluation's barriers also order the per-wave acceptance counts
     const uint32_t wacc = wave_sum(accepted);
     if (lane == 0) wave_acc[wave] = wacc;
-    __syncthreads();
+    const Full fr = full_eval_wg<R, F, TABLE>(a, tab, xb, sh_part);
     const size_t slot = (size_t)(level & 1u) * a.tiles + blockIdx.x;
     if (tid == 0) {
         uint32_t acc = 0;

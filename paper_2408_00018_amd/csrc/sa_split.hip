@@ -81,6 +81,10 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
     float wf = widen_inf<float>();
     uint32_t wc = 0xFFFFFFFFu;
     uint32_t accepted = 0;
+    // The workgroup's best state: copied to xb while another tile follows,
+    // read in place (column of xs) when it comes from the last tile.
+    const float *best = xb;
+    uint32_t best_stride = 1;
 
     for (uint32_t tile = blockIdx.x; tile < a.tiles; tile += G) {
         const uint32_t chain = tile * kChains + col;
@@ -176,26 +180,34 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
         float nf = wf;
         uint32_t nc = wc;
         best_of(nf, nc, tf, tc);
+        const bool last = tile + G >= a.tiles;
         if (nc != wc) {
             const uint32_t bcol = tc - tile * kChains;
-            for (uint32_t i = tid; i < n; i += blockDim.x) xb[i] = xs[i * kChains + bcol];
+            if (last) {
+                best = xs + bcol;
+                best_stride = kChains;
+            } else {
+                for (uint32_t i = tid; i < n; i += blockDim.x) xb[i] = xs[i * kChains + bcol];
+                best = xb;
+                best_stride = 1;
+            }
             wf = nf;
             wc = nc;
         }
-        __syncthreads();
+        if (!last) __syncthreads();  // xs, xb, the ring and wave_slot are reused by the next tile
     }
 
-    const Full fr = full_eval_wg<float, F, TABLE>(a, tab, xb, sh_part);
+    // the evaluation's barriers also order the per-wave acceptance counts
     const uint32_t wacc = wave_sum(accepted);
     if (lane == 0) wave_acc[wave] = wacc;
-    __syncthreads();
+    const Full fr = full_eval_wg<float, F, TABLE>(a, tab, best, sh_part, best_stride);
     const size_t slot = (size_t)(level & 1u) * a.tiles + blockIdx.x;
     if (tid == 0) {
         uint32_t acc = 0;
         for (uint32_t w = 0; w < kChains / 64; ++w) acc += (uint32_t)wave_acc[w];
         a.slots[slot] = Slot<float>{wf, wc, acc, 0u, fr.f, fr.s1, fr.s2};
     }
-    for (uint32_t i = tid; i < n; i += blockDim.x) a.slot_x[slot * n + i] = xb[i];
+    for (uint32_t i = tid; i < n; i += blockDim.x) a.slot_x[slot * n + i] = best[i * best_stride];
 }
 
 size_t split_lds_bytes(uint32_t n, bool table)
