@@ -43,7 +43,13 @@ __device__ __forceinline__ Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1)
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c.w2;
         const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
         const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        c = Ctr{xor3_key(hi1, c.w1, k0), lo1, xor3_key(hi0, c.w3, k1), lo0};
+        // Rounds 1-2 use plain XORs: where their inputs are wave-uniform (a
+        // uniform counter word) the compiler keeps them on the scalar unit;
+        // the later rounds use the single-instruction three-input XOR.
+        if (round < 2)
+            c = Ctr{hi1 ^ c.w1 ^ k0, lo1, hi0 ^ c.w3 ^ k1, lo0};
+        else
+            c = Ctr{xor3_key(hi1, c.w1, k0), lo1, xor3_key(hi0, c.w3, k1), lo0};
         k0 += kPhiloxW0;
         k1 += kPhiloxW1;
     }

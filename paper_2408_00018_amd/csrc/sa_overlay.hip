@@ -85,9 +85,9 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
                 h = h + 1u == K ? 0u : h + 1u;
             }
             const Coord<R> c = coord<R, TABLE>(a, tab, d);
-            const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
+            const R xn = neighbour_w<MOVE>(xd, c, w1);
             const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-            const bool take = metropolis(df, u24<R>(w2), T, nl2T);
+            const bool take = metropolis_w(df, w2, T, nl2T);
             logf(step, d, take, xd, xn, df);
             if (take) {
                 keys[h * WG + tid] = (uint16_t)d;

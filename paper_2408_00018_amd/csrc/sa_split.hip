@@ -28,8 +28,8 @@ constexpr uint32_t kChains = 256;  // chains per workgroup (state lanes)
 constexpr uint32_t kChunk = 4;     // moves per ring half: one group of the move stream
 static_assert(kChunk == 4, "a chunk is one four-move group of the move stream");
 
-// One move's draws in a 16-byte ring entry: coordinate, the two uniforms
-// (FP32 bit patterns), unused.
+// One move's draws in a 16-byte ring entry: coordinate, the change uniform,
+// the acceptance word's top 24 bits as a float (FP32 bit patterns), unused.
 typedef uint4 Draw;
 
 }  // namespace
@@ -123,7 +123,7 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                     uint32_t wd, w1, w2;
                     move_words(m, j, wd, w1, w2);
                     half[j * kChains + col] = make_uint4(pick(wd, n), __float_as_uint(u24f(w1)),
-                                                         __float_as_uint(u24f(w2)), 0u);
+                                                         __float_as_uint((float)(w2 >> 8)), 0u);
                 }
             }
         };
@@ -139,13 +139,13 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                 const Draw *half = ring + (k & 1u) * kChunk * kChains;
                 const uint32_t valid = min(kChunk, steps - k * kChunk);
                 uint32_t d[kChunk];
-                float u1[kChunk], u2[kChunk], xv[kChunk];
+                float u1[kChunk], k2[kChunk], xv[kChunk];
 #pragma unroll
                 for (uint32_t j = 0; j < kChunk; ++j) {
                     const Draw e = half[(j < valid ? j : 0u) * kChains + col];
                     d[j] = e.x;
                     u1[j] = __uint_as_float(e.y);
-                    u2[j] = __uint_as_float(e.z);
+                    k2[j] = __uint_as_float(e.z);
                 }
 #pragma unroll
                 for (uint32_t j = 0; j < kChunk; ++j) xv[j] = xs[__umul24(d[j], kChains) + col];
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                         const Coord<float> c = coord<float, TABLE>(a, tab, d[j]);
                         const float xn = neighbour<MOVE>(xv[j], c, u1[j]);
                         const float df = cost.delta(xv[j] - c.sh, xn - c.sh, n, a.inv_n);
-                        const bool take = metropolis(df, u2[j], 0.0, nl2T);
+                        const bool take = metropolis_k(df, k2[j], nl2T);
                         const float xwr = take ? xn : xv[j];
                         xs[__umul24(d[j], kChains) + col] = xwr;
                         cost.commit(take, a.inv_n);

@@ -184,10 +184,43 @@ template <int MOVE> __device__ __forceinline__ double neighbour(double xd, const
     return xn;
 }
 
+// FP32 radius neighbour straight from the generator word w (U = (w >> 8) 2^-24):
+// 2U - 1 = (w >> 8) 2^-23 - 1 in one exact multiply-add, so the result is
+// neighbour<SA_MOVE_RADIUS>(xd, c, U) bit for bit.
+__device__ __forceinline__ float radius_neighbour_w(float xd, const Coord<float> &c, uint32_t w)
+{
+    const float t = fmaf((float)(w >> 8), 0x1p-23f, -1.0f);
+    return __builtin_amdgcn_fmed3f(fmaf(c.rho, t, xd), c.lo, c.hi);
+}
+
 // Metropolis acceptance (eq. (5), k_b = 1): always downhill, else U < exp(-df/T).
 __device__ __forceinline__ bool metropolis(float df, float u2, double, float neg_log2e_inv_T)
 {
     return df <= 0.0f || u2 < hw_exp2(df * neg_log2e_inv_T);
+}
+// The same test on k = (w >> 8) as a float (U = k 2^-24): k < 2^(24 - df log2(e) / T).
+__device__ __forceinline__ bool metropolis_k(float df, float k, float neg_log2e_inv_T)
+{
+    return df <= 0.0f || k < hw_exp2(fmaf(df, neg_log2e_inv_T, 24.0f));
+}
+
+// Neighbour and acceptance straight from the move's generator words.
+template <int MOVE> __device__ __forceinline__ float neighbour_w(float xd, const Coord<float> &c, uint32_t w)
+{
+    if constexpr (MOVE == SA_MOVE_RADIUS) return radius_neighbour_w(xd, c, w);
+    return neighbour<MOVE>(xd, c, u24f(w));
+}
+template <int MOVE> __device__ __forceinline__ double neighbour_w(double xd, const Coord<double> &c, uint32_t w)
+{
+    return neighbour<MOVE>(xd, c, u24<double>(w));
+}
+__device__ __forceinline__ bool metropolis_w(float df, uint32_t w, double, float neg_log2e_inv_T)
+{
+    return metropolis_k(df, (float)(w >> 8), neg_log2e_inv_T);
+}
+__device__ __forceinline__ bool metropolis_w(double df, uint32_t w, double T, float)
+{
+    return metropolis(df, u24<double>(w), T, 0.0f);
 }
 __device__ __forceinline__ bool metropolis(double df, double u2, double T, float)
 {
@@ -411,22 +444,26 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
     Ctr b1 = philox4x32_10(Ctr{1u, level, chain, ctr3}, k0, k1);
     Ctr b2 = philox4x32_10(Ctr{2u, level, chain, ctr3}, k0, k1);
     uint32_t d = pick(b0.w0, n);
-    R xd = xs[__umul24(d, stride) + lane_off];
+    uint32_t at = __umul24(d, stride) + lane_off;  // LDS index of the current move's coordinate
+    R xd = xs[at];
     // One move on the change and acceptance words (w1, w2); dn is the next
     // move's coordinate, whose value is read ahead.
     const auto move = [&](uint32_t step, uint32_t w1, uint32_t w2, uint32_t dn) {
-        const R xn_lds = xs[__umul24(dn, stride) + lane_off];
+        const uint32_t at_n = __umul24(dn, stride) + lane_off;
+        const R xn_lds = xs[at_n];
         const Coord<R> c = coordf(d);
-        const R xn = neighbour<MOVE>(xd, c, u24<R>(w1));
+        const R xn = neighbour_w<MOVE>(xd, c, w1);
         const R df = cost.delta(xd - c.sh, xn - c.sh, n, inv_n);
-        const bool take = metropolis(df, u24<R>(w2), T, nl2T);
+        const bool take = metropolis_w(df, w2, T, nl2T);
         logf(step, d, take, xd, xn, df);
         const R xwr = take ? xn : xd;
-        xs[__umul24(d, stride) + lane_off] = xwr;
+        xs[at] = xwr;
         cost.commit(take, inv_n);
         accepted += take ? 1u : 0u;
-        xd = dn == d ? xwr : xn_lds;
+        // the same coordinate has the same index: compare the 32-bit indices
+        xd = at_n == at ? xwr : xn_lds;
         d = dn;
+        at = at_n;
     };
     // One group of four moves per iteration; each block variable is
     // overwritten by its successor in the next group once its last word is
