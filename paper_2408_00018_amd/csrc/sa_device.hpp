@@ -83,6 +83,7 @@ __device__ __forceinline__ float hw_exp2(float t) { return __builtin_amdgcn_exp2
 __device__ __forceinline__ float hw_log2(float t) { return __builtin_amdgcn_logf(t); }
 
 constexpr float kInv2Pi = 0.159154943091895335768883763372514362f;
+constexpr float kInv4Pi2 = 0.0253302959105844428049187623077562f;  // 1 / (4 pi^2)
 constexpr float kLog2e = 1.44269504088896340735992468100189214f;
 constexpr float kLn2 = 0.693147180559945309417232121458176568f;
 constexpr double kPi = 3.14159265358979323846;

@@ -86,8 +86,15 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
             }
             const Coord<R> c = coord<R, TABLE>(a, tab, d);
             const R xn = neighbour_w<MOVE>(xd, c, w1);
-            const R df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
-            const bool take = metropolis_w(df, w2, T, nl2T);
+            R df;
+            bool take;
+            if constexpr (sizeof(R) == sizeof(float)) {
+                take = cost.step(xd, xn, c.sh, (float)(w2 >> 8), nl2T, a.inv_n);
+                df = cost.df_;
+            } else {
+                df = cost.delta(xd - c.sh, xn - c.sh, n, a.inv_n);
+                take = metropolis_w(df, w2, T, nl2T);
+            }
             logf(step, d, take, xd, xn, df);
             if (take) {
                 keys[h * WG + tid] = (uint16_t)d;

@@ -154,8 +154,7 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                     if (j < valid) {
                         const Coord<float> c = coord<float, TABLE>(a, tab, d[j]);
                         const float xn = neighbour<MOVE>(xv[j], c, u1[j]);
-                        const float df = cost.delta(xv[j] - c.sh, xn - c.sh, n, a.inv_n);
-                        const bool take = metropolis_k(df, k2[j], nl2T);
+                        const bool take = cost.step(xv[j], xn, c.sh, k2[j], nl2T, a.inv_n);
                         const float xwr = take ? xn : xv[j];
                         xs[__umul24(d[j], kChains) + col] = xwr;
                         cost.commit(take, a.inv_n);

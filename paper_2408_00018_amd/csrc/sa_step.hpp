@@ -21,6 +21,14 @@ namespace sa {
 // ---------------------------------------------------------------------------
 template <typename R, int F> struct Cost;
 
+// FP32 Metropolis test (eq. (5), k_b = 1) on k = (w >> 8) as a float, where
+// U = k 2^-24 is the acceptance uniform: accept iff df <= 0 or
+// k < 2^(24 - df log2(e) / T).
+__device__ __forceinline__ bool metropolis_k(float df, float k, float neg_log2e_inv_T)
+{
+    return df <= 0.0f || k < hw_exp2(fmaf(df, neg_log2e_inv_T, 24.0f));
+}
+
 // FP64: the increments are the definitions, evaluated in the same order as a
 // plain FP64 implementation would (the FP64 path is checked move for move).
 template <> struct Cost<double, kSchwefel> {
@@ -85,6 +93,21 @@ template <> struct Cost<float, kSchwefel> {
         df_ = (schwefel_h(y) - schwefel_h(yn)) * inv_n;
         return df_;
     }
+    // Increment and acceptance of x_d: xd -> xn (shift sh, acceptance k), with
+    // as few dependent operations after xn as the arithmetic allows: the sine's
+    // argument in revolutions is sqrt|y / (4 pi^2)| with y / (4 pi^2) one
+    // multiply-add from x, the difference of the terms one more, and 1/n
+    // is folded into the exponent of the acceptance test.
+    __device__ bool step(float xd, float xn, float sh, float k, float nl2T, float inv_n)
+    {
+        const float shs = -sh * kInv4Pi2;
+        const float y = xd - sh, yn = xn - sh;
+        const float so = hw_sin_rev(hw_sqrt(fabsf(fmaf(xd, kInv4Pi2, shs))));
+        const float sn = hw_sin_rev(hw_sqrt(fabsf(fmaf(xn, kInv4Pi2, shs))));
+        const float d = fmaf(-yn, sn, y * so);  // h(y) - h(y'), so df = d / n
+        df_ = d * inv_n;
+        return d <= 0.0f || k < hw_exp2(fmaf(d, nl2T * inv_n, 24.0f));
+    }
     __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
 };
 
@@ -96,6 +119,10 @@ template <> struct Cost<float, kRastrigin> {
         const float dl = yn - y, sg = yn + y;
         df_ = fmaf(dl, sg, 20.0f * hw_sin_rev(0.5f * dl) * hw_sin_rev(0.5f * sg));
         return df_;
+    }
+    __device__ bool step(float xd, float xn, float sh, float k, float nl2T, float inv_n)
+    {
+        return metropolis_k(delta(xd - sh, xn - sh, 0u, inv_n), k, nl2T);
     }
     __device__ void commit(bool take, float) { f = take ? f + df_ : f; }
 };
@@ -125,6 +152,10 @@ template <> struct Cost<float, kAckley> {
         const float da = den > 0.0f ? (-0.2f * (ds1 * inv_n)) / den : 0.0f;
         df_ = -20.0f * ea * expm1f(da) - eb * expm1f(ds2 * inv_n);
         return df_;
+    }
+    __device__ bool step(float xd, float xn, float sh, float k, float nl2T, float inv_n)
+    {
+        return metropolis_k(delta(xd - sh, xn - sh, 0u, inv_n), k, nl2T);
     }
     __device__ void commit(bool take, float inv_n)
     {
@@ -198,13 +229,11 @@ __device__ __forceinline__ bool metropolis(float df, float u2, double, float neg
 {
     return df <= 0.0f || u2 < hw_exp2(df * neg_log2e_inv_T);
 }
-// The same test on k = (w >> 8) as a float (U = k 2^-24): k < 2^(24 - df log2(e) / T).
-__device__ __forceinline__ bool metropolis_k(float df, float k, float neg_log2e_inv_T)
+__device__ __forceinline__ bool metropolis(double df, double u2, double T, float)
 {
-    return df <= 0.0f || k < hw_exp2(fmaf(df, neg_log2e_inv_T, 24.0f));
+    return df <= 0.0 || u2 < exp(-df / T);
 }
-
-// Neighbour and acceptance straight from the move's generator words.
+// Neighbour and FP64 acceptance straight from the move's generator words.
 template <int MOVE> __device__ __forceinline__ float neighbour_w(float xd, const Coord<float> &c, uint32_t w)
 {
     if constexpr (MOVE == SA_MOVE_RADIUS) return radius_neighbour_w(xd, c, w);
@@ -214,17 +243,9 @@ template <int MOVE> __device__ __forceinline__ double neighbour_w(double xd, con
 {
     return neighbour<MOVE>(xd, c, u24<double>(w));
 }
-__device__ __forceinline__ bool metropolis_w(float df, uint32_t w, double, float neg_log2e_inv_T)
-{
-    return metropolis_k(df, (float)(w >> 8), neg_log2e_inv_T);
-}
 __device__ __forceinline__ bool metropolis_w(double df, uint32_t w, double T, float)
 {
     return metropolis(df, u24<double>(w), T, 0.0f);
-}
-__device__ __forceinline__ bool metropolis(double df, double u2, double T, float)
-{
-    return df <= 0.0 || u2 < exp(-df / T);
 }
 
 // Lexicographic (cost, chain) minimum: ties go to the lower chain index.
@@ -453,15 +474,25 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
         const R xn_lds = xs[at_n];
         const Coord<R> c = coordf(d);
         const R xn = neighbour_w<MOVE>(xd, c, w1);
-        const R df = cost.delta(xd - c.sh, xn - c.sh, n, inv_n);
-        const bool take = metropolis_w(df, w2, T, nl2T);
+        R df;
+        bool take;
+        if constexpr (sizeof(R) == sizeof(float)) {
+            take = cost.step(xd, xn, c.sh, (float)(w2 >> 8), nl2T, inv_n);
+            df = cost.df_;
+        } else {
+            df = cost.delta(xd - c.sh, xn - c.sh, n, inv_n);
+            take = metropolis_w(df, w2, T, nl2T);
+        }
         logf(step, d, take, xd, xn, df);
-        const R xwr = take ? xn : xd;
-        xs[at] = xwr;
+        // the next move's value: forwarded from this move when it picks the
+        // same coordinate (same 32-bit LDS index), so a single select waits
+        // for the decision
+        const bool same = at_n == at;
+        const R if_taken = same ? xn : xn_lds, if_kept = same ? xd : xn_lds;
+        xs[at] = take ? xn : xd;
         cost.commit(take, inv_n);
         accepted += take ? 1u : 0u;
-        // the same coordinate has the same index: compare the 32-bit indices
-        xd = at_n == at ? xwr : xn_lds;
+        xd = take ? if_taken : if_kept;
         d = dn;
         at = at_n;
     };
