@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -92,6 +93,8 @@ def parse():
     p.add_argument("--generator-waves", action="store_true",
                    help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
     p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
+    p.add_argument("--level-sweep", action="store_true",
+                   help="also time the bench workload's level at 1-100 steps and fit fixed + per-step cost")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 1 GiB device copy (torch) three times, to scale HBM byte counters")
     return p.parse_args()
@@ -246,6 +249,39 @@ def extra_workloads():
     return out
 
 
+def level_sweep(wl):
+    """Per-level time of the bench workload's shape at several step counts
+    (graph-replayed runs of 100 levels), and the least-squares line through
+    them: its intercept is the fixed cost of a level launch (hand-off, tile
+    start, level end, launch gap), its slope the cost of one step of all
+    chains."""
+    import torch
+    from paper_2408_00018_amd import sa
+    levels, pts = 100, []
+    for steps in (1, 25, 50, 75, 100):
+        sched = sa.Schedule(chains=wl.chains, levels=levels, steps=steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+                            precision=sa.FP32, graph=True)
+        with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+            ann.reset(wl.seed)
+            ann.run()
+            torch.cuda.synchronize()
+            best = math.inf
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(ann.stream)
+                ann.reset(wl.seed)
+                ann.run()
+                e1.record(ann.stream)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1) * 1e3 / levels)
+        pts.append((steps, best))
+    x = np.array([p[0] for p in pts], dtype=np.float64)
+    y = np.array([p[1] for p in pts], dtype=np.float64)
+    slope, icpt = np.polyfit(x, y, 1)
+    return {"us_per_level": {str(int(a)): round(b, 3) for a, b in pts}, "fixed_us_per_level": round(float(icpt), 3),
+            "us_per_step": round(float(slope), 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -323,6 +359,8 @@ def main():
     }
     if args.probe:
         out["valu_rates_per_s"] = probe_rates()
+    if args.level_sweep:
+        out["level_sweep"] = level_sweep(wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
     if not args.no_extra:
