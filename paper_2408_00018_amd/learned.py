@@ -94,18 +94,20 @@ class TargetResult:
 
 
 def time_to_target(func, lower, upper, shift, schedule: sa.Schedule, f_star: float, target: float = 1e-4, *,
-                   params=None, eps: float = 0.1, start_level: int = 0, x_start=None, chunk: int = 100):
+                   params=None, eps: float = 0.1, start_level: int = 0, x_start=None, chunk: int = 100,
+                   learn_from: int = 0):
     """Run levels in chunks until the record is within `target` of f_star or
-    the schedule ends.  The time to the hit is the chunks' device time (HIP
-    events on the annealer's stream), pro rata within the last chunk."""
+    the schedule ends.  With `params`, levels from `learn_from` on use the
+    learned mixture and earlier ones the plain moves.  The time to the hit is
+    the chunks' device time (HIP events on the annealer's stream), pro rata
+    within the last chunk."""
     import torch
     sched = sa.Schedule(**{**schedule.__dict__, "trace_x": False, "graph": False, "learned": params is not None,
                            "log_chains": 0})
     with sa.Annealer(func, lower, upper, shift, schedule=sched) as ann:
-        if params is not None:
-            ann.set_proposal(params, eps)
         if start_level:
             ann.set_start(start_level, x_start)
+        learning = False
         first = ann.levels_done()
         elapsed = 0.0
         hit_level, hit_time = None, None
@@ -113,7 +115,12 @@ def time_to_target(func, lower, upper, shift, schedule: sa.Schedule, f_star: flo
         with torch.cuda.stream(ann.stream):
             while ann.levels_done() < sched.levels:
                 k0 = ann.levels_done()
+                if params is not None and not learning and k0 >= learn_from:
+                    ann.set_proposal(params, eps)
+                    learning = True
                 count = min(chunk, sched.levels - k0)
+                if params is not None and not learning:
+                    count = min(count, learn_from - k0)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(ann.stream)
                 ann.run(count)
