@@ -150,7 +150,10 @@ def time_to_target_report(wl, seeds):
     T_k = 10 * 0.995^k up to k = 3999: 'full' starts at level 0 from random
     points; 'final_approach' starts at level 3000 (T = 2.9e-6, where the thermal
     gap n T / 2 = 1.5e-4 is at the target's scale) with every chain at
-    x* + U(-2, 2) per coordinate.
+    x* + U(-2, 2) per coordinate.  Arms: plain moves, the learned mixture from
+    the first level, and (full regime) 'learned_late': plain moves until the
+    first level whose thermal gap n T / 2 is at most the target, the learned
+    mixture from there on.
     """
     import torch
     from paper_2408_00018_amd import learned as Lp
@@ -171,28 +174,40 @@ def time_to_target_report(wl, seeds):
     del rec
     rng = np.random.default_rng(7)
     x0 = W.SCHWEFEL_X_STAR + rng.uniform(-2, 2, wl.n)
+    # 'learned_late': plain moves until the thermal gap n T / 2 has fallen to the
+    # target, the learned mixture from there on
+    k_late = int(math.ceil(math.log(2.0 * 1e-4 / (wl.n * wl.T0)) / math.log(wl.alpha)))
+    out["learned_late_from_level"] = k_late
     for regime, start in (("full", 0), ("final_approach", 3000)):
         res = {}
-        for arm, p in (("plain", None), ("learned", params)):
+        arms = [("plain", None, 0), ("learned", params, 0)]
+        if start == 0:
+            arms.append(("learned_late", params, k_late))
+        for arm, p, learn_from in arms:
             runs = []
             for seed in range(1, seeds + 1):
                 sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
                                     seed=seed, precision=sa.FP32)
                 r = Lp.time_to_target(wl.func, wl.lower, wl.upper, wl.shift, sched, W.SCHWEFEL_F_STAR, 1e-4,
-                                      params=p, eps=0.1, start_level=start, x_start=x0 if start else None)
+                                      params=p, eps=0.1, start_level=start, x_start=x0 if start else None,
+                                      learn_from=learn_from)
                 runs.append({"seed": seed, "hit": r.hit, "level": r.level, "seconds": r.seconds,
                              "levels_run": r.levels_run, "ms_per_level": round(r.ms_per_level, 4),
                              "final_gap": r.final_gap})
                 print(f"[ttt] {regime} {arm} seed {seed}: {runs[-1]}", file=sys.stderr, flush=True)
             res[arm] = runs
         summary = {}
-        for a in ("plain", "learned"):
+        for a in [arm[0] for arm in arms]:
             secs = [r["seconds"] for r in res[a] if r["hit"]]
             summary[a] = {"hit_fraction": len(secs) / len(res[a]),
                           "median_seconds": float(np.median(secs)) if secs else None,
                           "median_final_gap": float(np.median([r["final_gap"] for r in res[a]]))}
         if summary["plain"]["median_seconds"] and summary["learned"]["median_seconds"]:
             summary["speedup_median"] = summary["plain"]["median_seconds"] / summary["learned"]["median_seconds"]
+        if "learned_late" in summary and summary["learned"]["median_seconds"] and \
+                summary["learned_late"]["median_seconds"]:
+            summary["late_vs_learned_median"] = (summary["learned"]["median_seconds"] /
+                                                 summary["learned_late"]["median_seconds"])
         res["summary"] = summary
         out[regime] = res
     return out
