@@ -110,7 +110,8 @@ __global__ void __launch_bounds__(256)
             }
             cost.set(acc.finish(n), n);
         } else {
-            fill_tile(xs, WG, tid, xw, n);
+            fill_tile_rows(xs, WG, tid, xw, n);
+            __syncthreads();  // columns are written by other threads
             cost.set(start, n);
         }
 
