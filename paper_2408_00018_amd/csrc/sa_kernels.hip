@@ -110,8 +110,10 @@ __global__ void __launch_bounds__(256)
             }
             cost.set(acc.finish(n), n);
         } else {
-            fill_tile_rows(xs, WG, tid, xw, n);
-            __syncthreads();  // columns are written by other threads
+            if (WG == 256)
+                fill_tile_c<256>(xs, tid, xw, n);
+            else
+                fill_tile(xs, WG, tid, xw, n);
             cost.set(start, n);
         }
 

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(512) split_level_kernel(const LevelArgs<float>
                 }
                 cost.set(acc.finish(n), n);
             } else {
-                fill_tile_rows(xs, kChains, col, xw, n);  // the barrier before the chunk loop follows
+                fill_tile_c<kChains>(xs, col, xw, n);
                 cost.set(start, n);
             }
         }
