@@ -493,12 +493,13 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
     uint32_t d = pick(b0.w0, n);
     uint32_t at = __umul24(d, stride) + lane_off;  // LDS index of the current move's coordinate
     R xd = xs[at];
+    Coord<R> c = coordf(d);
     // One move on the change and acceptance words (w1, w2); dn is the next
-    // move's coordinate, whose value is read ahead.
+    // move's coordinate, whose value and box/shift entry are read ahead.
     const auto move = [&](uint32_t step, uint32_t w1, uint32_t w2, uint32_t dn) {
         const uint32_t at_n = __umul24(dn, stride) + lane_off;
         const R xn_lds = xs[at_n];
-        const Coord<R> c = coordf(d);
+        const Coord<R> c_n = coordf(dn);
         const R xn = neighbour_w<MOVE>(xd, c, w1);
         R df;
         bool take;
@@ -522,6 +523,7 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
         xd = at_n == at ? xwr : xn_lds;
         d = dn;
         at = at_n;
+        c = c_n;
     };
     // One group of four moves per iteration; each block variable is
     // overwritten by its successor in the next group once its last word is
