@@ -70,6 +70,9 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
             uint32_t wd, w1, w2;
             move_words(m, j, wd, w1, w2);
             const uint32_t d = pick(wd, n);
+            // the coordinate's box/shift entry is read before the probe, so the
+            // two LDS round trips overlap
+            const Coord<R> c = coord<R, TABLE>(a, tab, d);
             uint32_t h = slot_of(d, K);
             R xd;
             for (;;) {
@@ -84,7 +87,6 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
                 }
                 h = h + 1u == K ? 0u : h + 1u;
             }
-            const Coord<R> c = coord<R, TABLE>(a, tab, d);
             const R xn = neighbour_w<MOVE>(xd, c, w1);
             R df;
             bool take;
