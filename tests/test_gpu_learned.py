@@ -249,6 +249,41 @@ def test_learned_graph_and_chunks_equal_eager(S):
     assert np.array_equal(a["xb"], b["xb"])
 
 
+def test_learned_from_a_later_level(S):
+    """The learned mixture switched on after k plain levels (the late arm of
+    the time-to-target comparison): levels before k equal a plain run's bit
+    for bit, later levels use the network (they differ from the plain run's)
+    and equal a run that switches at the same level through learned.time_to_target's
+    sequence of calls (plain run(k), set_proposal, run)."""
+    from paper_2408_00018_amd import learned as Lp
+    wl = learned_case("schwefel_n16")
+    p = learned_params(5, scale=0.05, sigma0=0.02)
+    kw = dict(chains=1024, levels=8, steps=20, T0=10.0, alpha=0.8, seed=2)
+    k = 5
+    cols = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+
+    def run(learned, switch):
+        sched = S.Schedule(precision=S.FP32, trace_x=True, learned=learned, **kw)
+        with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+            if switch is not None:
+                ann.run(switch)
+                ann.set_proposal(p, 0.1)
+            ann.run(0)
+            return ann.trace(with_x=True)
+
+    plain, plain_x = run(False, None)
+    late, late_x = run(True, k)
+    assert np.array_equal(late[cols][:k], plain[cols][:k])
+    assert np.array_equal(late_x[:k], plain_x[:k])
+    assert not np.array_equal(late_x[k:], plain_x[k:])
+    again, again_x = run(True, k)
+    assert np.array_equal(again[cols], late[cols]) and np.array_equal(again_x, late_x)
+    sched = S.Schedule(precision=S.FP32, **kw)
+    r = Lp.time_to_target(wl.func, wl.lower, wl.upper, wl.shift, sched, W.SCHWEFEL_F_STAR, 1e9, params=p, eps=0.1,
+                          learn_from=k, chunk=3)
+    assert r.hit and r.level == 0 and r.levels_run == 3  # a target every level meets: the first chunk ends it
+
+
 def test_learned_rejects_unsupported(S):
     wl = W.schwefel_n4_fp64()
     sched = S.Schedule(chains=64, levels=2, steps=4, T0=1.0, alpha=0.9, precision=S.FP64, learned=True)
