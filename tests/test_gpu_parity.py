@@ -102,6 +102,7 @@ FP64_CASES = [
     (W.RASTRIGIN, 16, 384, 6, 50, "uneven"),
     (W.ACKLEY, 9, 320, 8, 25, "shifted"),
     (W.ACKLEY, 3, 128, 1, 64, "canonical"),
+    (W.SCHWEFEL, 6, 128, 7, 35, "shifted"),  # a three-move tail after the four-move groups
 ]
 
 
@@ -162,6 +163,19 @@ def test_fp32_shifted_moves(S, func, n):
                     levels=4, name=f"{base.name[:9]}_n{n}")
     g = run_gpu(S, wl, log_chains=64, log_level=0, log_levels=4)
     check_fp32_run(S, wl, g, 0, chain_ids=list(range(0, 64, 7)))
+    check_record(wl, g)
+
+
+@pytest.mark.parametrize("steps", [1, 2, 3, 7])
+def test_fp32_step_tails(S, steps):
+    """Per-move parity when a level's step count leaves one to three moves
+    after the last four-move group (per-coordinate table path)."""
+    n = 21
+    lo, hi = W.uneven_box(n, 6)
+    wl = W.random_problem(W.RASTRIGIN, n, seed=5, shifted=False).with_(lower=lo, upper=hi, chains=256, levels=3,
+                                                                        steps=steps)
+    g = run_gpu(S, wl, log_chains=64, log_level=0, log_levels=3)
+    check_fp32_run(S, wl, g, 0, chain_ids=list(range(0, 64, 5)))
     check_record(wl, g)
 
 
@@ -248,7 +262,8 @@ def test_error_paths(S):
     assert e.value.status == -1
 
 
-@pytest.mark.parametrize("case", ["schwefel_n100", "rastrigin_n64_shift", "ackley_n37_uneven", "resample_n9"])
+@pytest.mark.parametrize("case", ["schwefel_n100", "rastrigin_n64_shift", "ackley_n37_uneven", "resample_n9",
+                                  "schwefel_n20_tail3"])
 def test_fp32_generator_waves_are_bitwise_identical(S, case):
     """FP32 plain levels with generator waves (draws computed ahead by separate
     waves) and without them give the same bits: winners, counts, costs and
@@ -264,9 +279,12 @@ def test_fp32_generator_waves_are_bitwise_identical(S, case):
         wl = W.random_problem(W.ACKLEY, 37, seed=22, shifted=False).with_(lower=lo, upper=hi, chains=768, levels=5,
                                                                           steps=50)
         kw = {}
-    else:
+    elif case == "resample_n9":
         wl = W.random_problem(W.SCHWEFEL, 9, seed=23).with_(chains=512, levels=6, steps=30)
         kw = dict(move=S.MOVE_RESAMPLE)
+    else:
+        wl = W.random_problem(W.SCHWEFEL, 20, seed=24, shifted=False).with_(chains=512, levels=4, steps=31)
+        kw = {}
     split = run_gpu(S, wl, generator_waves=True, **kw)
     single = run_gpu(S, wl, **kw)
     keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
