@@ -74,15 +74,18 @@ def run_batch(S, probs, chains, sched, chunks=None):
     return out, lay
 
 
-@pytest.mark.parametrize("wpg", [1, 2, 4])
-def test_fp64_batch_matches_oracle_per_problem(S, wpg):
+@pytest.mark.parametrize("wpg,steps", [(1, 24), (2, 24), (4, 24), (2, 23)])
+def test_fp64_batch_matches_oracle_per_problem(S, wpg, steps):
+    """Every problem's trajectory equals the oracle's (23 steps: a three-move
+    tail after the four-move groups)."""
     probs, chains, _ = make_batch(11, seed=5)
-    sched = S.BatchSchedule(levels=7, steps=24, T0=10.0, alpha=0.9, seed=42, precision=S.FP64, trace_x=True,
+    sched = S.BatchSchedule(levels=7, steps=steps, T0=10.0, alpha=0.9, seed=42, precision=S.FP64, trace_x=True,
                             waves_per_group=wpg)
     g, lay = run_batch(S, probs, chains, sched)
     assert lay["tiles"] == sum(chains) // 64
     for p, (func, lo, hi, s) in enumerate(probs):
-        o = O.sa_run(func, lo, hi, s, seed=42, problem=p, chains=chains[p], steps=24, T0=10.0, alpha=0.9, levels=7)
+        o = O.sa_run(func, lo, hi, s, seed=42, problem=p, chains=chains[p], steps=steps, T0=10.0, alpha=0.9,
+                     levels=7)
         gp = g[p]
         assert np.array_equal(gp["rec"]["win_chain"], o["win_chain"]), p
         assert np.array_equal(gp["rec"]["accepts"], o["accepts"]), p

@@ -74,6 +74,7 @@ FP64_CASES = [
     (W.RASTRIGIN, 64, 256, 6, 50, "shifted"),
     (W.ACKLEY, 9, 320, 8, 25, "shifted"),
     (W.SCHWEFEL, 1, 64, 4, 30, "canonical"),
+    (W.RASTRIGIN, 13, 192, 5, 27, "shifted"),  # a three-move tail after the four-move groups
 ]
 
 
