@@ -37,6 +37,7 @@ import workloads as W  # noqa: E402
 #   v_mad_u64_u32 2.17, v_mul_hi_u32 1.7, v_sin/v_cos/v_sqrt/v_exp_f32 3.15,
 #   FP32 add/mul/fma/med3/cvt, integer shift/xor/bitop3/compare/select 1.
 # Algorithmic work of one FP32 normalized-Schwefel move with the radius rule:
+CLOCK_HZ = 2.4e9  # MI355X peak engine clock
 SLOT_WEIGHT = {"mad_u64": 2.17, "mul_hi": 1.7, "trans": 3.15, "valu": 1.0}
 SLOTS_PER_MOVE = {
     # counter-based generator: a move takes three of a block's four words, so
@@ -61,11 +62,12 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "9dc576aefca6ae7e", "fetch_kib": 168.972, "fetch_scale": 2.0,
+TRAFFIC_MEASURED = {"sources_sha256_16": "8374a4c874f32a53", "fetch_kib": 170.458, "fetch_scale": 2.0,
                     "write_kib": 120.592, "write_scale": 1.0}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
                   "paper_2408_00018_amd/csrc/sa_internal.hpp", "paper_2408_00018_amd/csrc/sa_step.hpp",
-                  "paper_2408_00018_amd/csrc/sa_level_common.hpp", "paper_2408_00018_amd/csrc/sa_mlp_net.hpp"]
+                  "paper_2408_00018_amd/csrc/sa_level_common.hpp", "paper_2408_00018_amd/csrc/sa_mlp_net.hpp",
+                  "paper_2408_00018_amd/build.py"]
 
 
 def measured_traffic_bytes():
@@ -93,6 +95,8 @@ def parse():
     p.add_argument("--generator-waves", action="store_true",
                    help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
     p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
+    p.add_argument("--wave-sweep", action="store_true",
+                   help="cost of a wave's move at 1, 2 and 3 waves per SIMD (Schwefel n=40)")
     p.add_argument("--level-sweep", action="store_true",
                    help="also time the bench workload's level at 1-100 steps and fit fixed + per-step cost")
     p.add_argument("--copy-calibration", action="store_true",
@@ -264,37 +268,60 @@ def extra_workloads():
     return out
 
 
+def us_per_level(wl, chains, steps, levels=100):
+    """Best of three graph-replayed runs of `levels` plain FP32 levels of
+    workload `wl` with the given chain and step counts: microseconds per level."""
+    import torch
+    from paper_2408_00018_amd import sa
+    sched = sa.Schedule(chains=chains, levels=levels, steps=steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+                        precision=sa.FP32, graph=True)
+    with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+        ann.reset(wl.seed)
+        ann.run()
+        torch.cuda.synchronize()
+        best = math.inf
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(ann.stream)
+            ann.reset(wl.seed)
+            ann.run()
+            e1.record(ann.stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / levels)
+    return best
+
+
 def level_sweep(wl):
     """Per-level time of the bench workload's shape at several step counts
     (graph-replayed runs of 100 levels), and the least-squares line through
     them: its intercept is the fixed cost of a level launch (hand-off, tile
     start, level end, launch gap), its slope the cost of one step of all
     chains."""
-    import torch
-    from paper_2408_00018_amd import sa
-    levels, pts = 100, []
-    for steps in (1, 25, 50, 75, 100):
-        sched = sa.Schedule(chains=wl.chains, levels=levels, steps=steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
-                            precision=sa.FP32, graph=True)
-        with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
-            ann.reset(wl.seed)
-            ann.run()
-            torch.cuda.synchronize()
-            best = math.inf
-            for _ in range(3):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(ann.stream)
-                ann.reset(wl.seed)
-                ann.run()
-                e1.record(ann.stream)
-                e1.synchronize()
-                best = min(best, e0.elapsed_time(e1) * 1e3 / levels)
-        pts.append((steps, best))
+    pts = [(steps, us_per_level(wl, wl.chains, steps)) for steps in (1, 25, 50, 75, 100)]
     x = np.array([p[0] for p in pts], dtype=np.float64)
     y = np.array([p[1] for p in pts], dtype=np.float64)
     slope, icpt = np.polyfit(x, y, 1)
     return {"us_per_level": {str(int(a)): round(b, 3) for a, b in pts}, "fixed_us_per_level": round(float(icpt), 3),
             "us_per_step": round(float(slope), 4)}
+
+
+def wave_sweep():
+    """Cost of a move of one wave with 1, 2 and 3 waves per SIMD: Schwefel at
+    n = 40 (three 256-chain workgroups fit one CU's LDS) with 65536, 131072 and
+    196608 chains; the per-step time is the difference between 100-step and
+    1-step levels.  Shows how much of the SIMD one wave leaves unused."""
+    lo, hi = np.full(40, -500.0), np.full(40, 500.0)
+    wl = W.Workload("schwefel_n40_fp32", W.SCHWEFEL, 40, lo, hi, None, chains=65536, levels=100, steps=100,
+                    T0=10.0, alpha=0.995, seed=1, precision=W.FP32)
+    out = {}
+    for waves in (1, 2, 3):
+        chains = 65536 * waves
+        t1, t100 = us_per_level(wl, chains, 1), us_per_level(wl, chains, 100)
+        per_step = (t100 - t1) / 99.0
+        out[str(waves)] = {"chains": chains, "us_per_level_1_step": round(t1, 3),
+                           "us_per_level_100_steps": round(t100, 3), "us_per_step": round(per_step, 4),
+                           "cycles_per_wave_move": round(per_step * 1e-6 * CLOCK_HZ / waves, 1)}
+    return out
 
 
 def main():
@@ -376,6 +403,8 @@ def main():
         out["valu_rates_per_s"] = probe_rates()
     if args.level_sweep:
         out["level_sweep"] = level_sweep(wl)
+    if args.wave_sweep:
+        out["wave_sweep"] = wave_sweep()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
     if not args.no_extra:

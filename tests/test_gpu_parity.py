@@ -262,6 +262,22 @@ def test_error_paths(S):
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("func,n,steps,move", [(W.SCHWEFEL, 100, 100, "radius"), (W.RASTRIGIN, 33, 37, "radius"),
+                                                 (W.ACKLEY, 20, 31, "radius"), (W.SCHWEFEL, 9, 30, "resample")])
+def test_fp32_unshifted_kernel_is_bitwise_identical(S, func, n, steps, move):
+    """Plain FP32 levels on a uniform box with a +0 shift run a kernel with the
+    shift folded away at compile time; a -0 shift (the same problem) takes the
+    general kernel.  Both give the same bits: winners, counts, costs, states."""
+    wl = W.random_problem(func, n, seed=31, shifted=False).with_(chains=2048, levels=6, steps=steps)
+    kw = dict(move=S.MOVE_RESAMPLE) if move == "resample" else {}
+    folded = run_gpu(S, wl, **kw)
+    general = run_gpu(S, wl.with_(shift=np.full(n, -0.0)), **kw)
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    assert np.array_equal(folded["rec"][keys], general["rec"][keys])
+    assert np.array_equal(folded["xb"], general["xb"])
+    assert np.array_equal(folded["x_rec"], general["x_rec"])
+
+
 @pytest.mark.parametrize("case", ["schwefel_n100", "rastrigin_n64_shift", "ackley_n37_uneven", "resample_n9",
                                   "schwefel_n20_tail3"])
 def test_fp32_generator_waves_are_bitwise_identical(S, case):
