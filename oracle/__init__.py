@@ -50,7 +50,7 @@ _p = ctypes.c_void_p
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
             build(force=True)
         L = ctypes.CDLL(_LIB)
         L.orc_philox4x32_10.argtypes = [_p, _p, _p]
@@ -77,8 +77,8 @@ def lib():
         L.orc_neighbour.restype = _d
         L.orc_temperature.argtypes = [_d, _d, _u32]
         L.orc_temperature.restype = _d
-        L.orc_sa_run.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _i, _u32, _u32,
-                                 _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_sa_run.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32, _u32,
+                                 _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
         L.orc_sa_run.restype = _i
         L.orc_replay_level.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _d, _d, _i, _u32, _p, _u32, _u32,
                                        _p, _p, _p, _p, _p, _p, _p]
@@ -185,17 +185,24 @@ def temperature(T0, alpha, level):
 
 def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
            move_rule=MOVE_RADIUS, exchange=True, problem=0, level_begin=0, x_start=None, chain_x=None,
-           record=None, keep_x_best=True, final_f=False):
+           chain_cost=None, record=None, keep_x_best=True, final_f=False):
     """Run levels [level_begin, level_begin+levels) of the multi-chain SA.
 
+    ``exchange``: levels between broadcasts of the winner -- 1 or True: every
+    level (synchronous); k > 1: every k-th level (periodic); 0 or False:
+    never (asynchronous).  Without a broadcast a chain continues from its own
+    state and carried cost (``chain_x`` [chains, n] and ``chain_cost``
+    [chains, 3] = f, s1, s2, carried in from an earlier call and returned).
     ``record`` = (x_rec, f_rec, rec_level) carried in from an earlier call.
     Returns a dict of per-level outputs and the record."""
     lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
     n = lo.size
+    period = 1 if exchange is True else 0 if exchange is False else int(exchange)
     xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
-    cx = None
-    if not exchange:
+    cx = cc = None
+    if period != 1:
         cx = np.zeros(chains * n) if chain_x is None else _f64(chain_x).copy().reshape(-1)
+        cc = np.zeros(chains * 3) if chain_cost is None else _f64(chain_cost).copy().reshape(-1)
     if record is None:
         x_rec = np.zeros(n)
         f_rec_io = ctypes.c_double(np.inf)
@@ -212,7 +219,7 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
     acc = np.zeros(levels, dtype=np.uint64)
     ff = np.zeros(chains) if final_f else None
     rc = lib().orc_sa_run(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
-                          radius_frac, move_rule, 1 if exchange else 0, level_begin, levels, _ptr(xs), _ptr(cx),
+                          radius_frac, move_rule, period, level_begin, levels, _ptr(xs), _ptr(cx), _ptr(cc),
                           _ptr(x_rec), ctypes.byref(f_rec_io), ctypes.byref(rec_level), _ptr(win), _ptr(f_win),
                           _ptr(f_best), _ptr(f_rec), _ptr(xb), _ptr(acc), _ptr(ff))
     if rc != 0:
@@ -223,8 +230,9 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
         out["x_best"] = xb.reshape(levels, n)
     if final_f:
         out["final_f"] = ff
-    if not exchange:
+    if period != 1:
         out["chain_x"] = cx.reshape(chains, n)
+        out["chain_cost"] = cc.reshape(chains, 3)
     return out
 
 

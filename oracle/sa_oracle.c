@@ -334,13 +334,19 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
 }
 
 /*
- * Synchronous (exchange = 1) or asynchronous (exchange = 0) multi-chain SA
- * over levels [level_begin, level_begin + count).
+ * Multi-chain SA over levels [level_begin, level_begin + count), with the
+ * level winner broadcast to every chain every `exchange` levels (Sec. 2.2):
+ * exchange = 1 is the synchronous scheme with an exchange at each level
+ * (Sec. 2.2.2), k > 1 the periodic exchange every k levels, 0 the
+ * asynchronous scheme (Sec. 2.2.1: no exchange, only the final reduction).
  *
- * Level start: at level 0 every chain starts from its own random point; later,
- * with exchange, every chain starts from x_start (the previous level's
- * winner); without exchange, chain p continues from its own state in
- * `chain_x` (chains * n, in/out; required when exchange = 0).
+ * Level start: at level 0 every chain starts from its own random point.  At a
+ * later level L with exchange > 0 and L % exchange == 0 every chain starts
+ * from x_start (the previous level's winner) with its cost evaluated in full.
+ * At any other level chain p continues from its own state and carried cost,
+ * as the asynchronous kernel carries f(x0) through every temperature level:
+ * `chain_x` (chains * n) and `chain_cost` (chains * 3: f, s1, s2), in/out,
+ * required when exchange != 1.
  *
  * Per level k (index k - level_begin into the per-level outputs):
  *   win_chain[k]  chain with the lowest final cost (ties: lowest index)
@@ -354,13 +360,13 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
  */
 int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
                uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
-               double radius_frac, int move_rule, int exchange, uint32_t level_begin, uint32_t count,
-               double *x_start, double *chain_x, double *x_rec, double *f_rec_io, uint32_t *rec_level_io,
-               uint32_t *win_chain, double *f_win, double *f_best, double *f_rec, double *x_best,
-               uint64_t *accepts, double *final_f)
+               double radius_frac, int move_rule, uint32_t exchange, uint32_t level_begin, uint32_t count,
+               double *x_start, double *chain_x, double *chain_cost, double *x_rec, double *f_rec_io,
+               uint32_t *rec_level_io, uint32_t *win_chain, double *f_win, double *f_best, double *f_rec,
+               double *x_best, uint64_t *accepts, double *final_f)
 {
     if (n == 0 || chains == 0) return -1;
-    if (!exchange && !chain_x) return -1;
+    if (exchange != 1 && (!chain_x || !chain_cost)) return -1;
     if (exchange && level_begin > 0 && !x_start) return -1;
     orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
     double *x = (double *)malloc(sizeof(double) * n);
@@ -373,22 +379,30 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
         double best_f = INFINITY;
         uint32_t best_chain = 0;
         uint64_t acc_total = 0;
+        const int broadcast = level > 0 && exchange > 0 && level % exchange == 0;
         orc_cost start_cost;
-        if (exchange && level > 0) cost_full(func, n, x_start, shift, &start_cost);
+        if (broadcast) cost_full(func, n, x_start, shift, &start_cost);
         for (uint32_t ch = 0; ch < chains; ++ch) {
             orc_cost c;
             if (level == 0) {
                 orc_init_point(seed, problem, ch, n, lower, upper, x);
                 cost_full(func, n, x, shift, &c);
-            } else if (exchange) {
+            } else if (broadcast) {
                 memcpy(x, x_start, sizeof(double) * n);
                 c = start_cost;
             } else {
                 memcpy(x, chain_x + (size_t)ch * n, sizeof(double) * n);
-                cost_full(func, n, x, shift, &c);
+                c.f = chain_cost[3 * (size_t)ch];
+                c.s1 = chain_cost[3 * (size_t)ch + 1];
+                c.s2 = chain_cost[3 * (size_t)ch + 2];
             }
             acc_total += run_chain(&p, level, ch, T, x, &c);
-            if (!exchange) memcpy(chain_x + (size_t)ch * n, x, sizeof(double) * n);
+            if (exchange != 1) {
+                memcpy(chain_x + (size_t)ch * n, x, sizeof(double) * n);
+                chain_cost[3 * (size_t)ch] = c.f;
+                chain_cost[3 * (size_t)ch + 1] = c.s1;
+                chain_cost[3 * (size_t)ch + 2] = c.s2;
+            }
             if (final_f && k + 1 == count) final_f[ch] = c.f;
             if (c.f < best_f || ch == 0) {
                 best_f = c.f;
@@ -436,8 +450,8 @@ int orc_sa_run_capture(int func, uint32_t n, const double *lower, const double *
     capture_sink.count = 0;
     capture_sink.tau = tau;
     int rc = orc_sa_run(func, n, lower, upper, shift, seed, problem, chains, steps, T0, alpha, radius_frac, move_rule,
-                        1, level_begin, count, x_start, NULL, x_rec, &f_rec, &rec_level, NULL, NULL, NULL, NULL, NULL,
-                        NULL, NULL);
+                        1, level_begin, count, x_start, NULL, NULL, x_rec, &f_rec, &rec_level, NULL, NULL, NULL, NULL,
+                        NULL, NULL, NULL);
     *n_captured = capture_sink.count;
     capture_sink.rec = NULL;
     free(x_rec);

@@ -440,6 +440,67 @@ def test_async_variant_keeps_chains_apart():
     assert np.array_equal(r["chain_x"][5], x)
 
 
+KEYS = ("win_chain", "f_win", "f_best", "accepts")
+
+
+def _levels(r, a, b):
+    return {k: r[k][a:b] for k in KEYS} | {"x_best": r["x_best"][a:b]}
+
+
+def _same(x, y):
+    for k in x:
+        assert np.array_equal(x[k], y[k]), k
+
+
+def test_exchange_period_one_is_the_synchronous_run():
+    lo, hi = np.full(3, -5.12), np.full(3, 5.12)
+    kw = dict(seed=8, chains=64, steps=10, T0=10.0, alpha=0.9, levels=5)
+    a = O.sa_run(W.RASTRIGIN, lo, hi, exchange=True, **kw)
+    b = O.sa_run(W.RASTRIGIN, lo, hi, exchange=1, **kw)
+    _same(_levels(a, 0, 5), _levels(b, 0, 5))
+
+
+@pytest.mark.parametrize("func", [W.SCHWEFEL, W.ACKLEY])
+def test_periodic_exchange_every_third_level(func):
+    """Periodic exchange (Sec. 2.2) every 3 levels, pinned level by level
+    against the two schemes it interleaves: before the first exchange it is
+    the asynchronous run; at level 3 every chain restarts from level 2's
+    winner with its cost evaluated in full, exactly as one synchronous level
+    started from that state; at levels 4-5 the chains carry their own states
+    and costs again (an asynchronous continuation of the level-3 chains)."""
+    half = 500.0 if func == W.SCHWEFEL else 32.768
+    lo, hi = np.full(4, -half), np.full(4, half)
+    kw = dict(seed=9, chains=64, steps=11, T0=10.0, alpha=0.9)
+    per = O.sa_run(func, lo, hi, levels=6, exchange=3, **kw)
+    asy = O.sa_run(func, lo, hi, levels=3, exchange=False, **kw)
+    _same(_levels(per, 0, 3), _levels(asy, 0, 3))
+    rec = (asy["x_rec"], asy["f_rec_final"], asy["rec_level"])
+    sync3 = O.sa_run(func, lo, hi, levels=1, level_begin=3, x_start=per["x_best"][2], record=rec,
+                     exchange=True, final_f=True, **kw)
+    _same(_levels(per, 3, 4), _levels(sync3, 0, 1))
+    # the chains after level 3, then levels 4-5 without exchange
+    upto3 = O.sa_run(func, lo, hi, levels=4, exchange=3, **kw)
+    _same(_levels(upto3, 0, 4), _levels(per, 0, 4))
+    rec3 = (upto3["x_rec"], upto3["f_rec_final"], upto3["rec_level"])
+    cont = O.sa_run(func, lo, hi, levels=2, level_begin=4, exchange=False, chain_x=upto3["chain_x"],
+                    chain_cost=upto3["chain_cost"], record=rec3, **kw)
+    _same(_levels(per, 4, 6), _levels(cont, 0, 2))
+    assert np.array_equal(per["f_rec"][4:], cont["f_rec"])
+
+
+def test_asynchronous_chains_carry_their_cost():
+    """Without exchange a chain's cost is carried through every level, never
+    re-evaluated: after 6 levels each chain's carried Ackley cost (through its
+    two sums) still equals the definition evaluated at its state, to the
+    rounding of ~6 x 20 increments."""
+    lo, hi = np.full(5, -32.768), np.full(5, 32.768)
+    r = O.sa_run(W.ACKLEY, lo, hi, seed=10, chains=64, steps=20, T0=5.0, alpha=0.9, levels=6, exchange=0)
+    for ch in range(64):
+        fx = O.f(W.ACKLEY, r["chain_x"][ch])
+        assert abs(r["chain_cost"][ch][0] - fx) <= 1e-11 * max(1.0, abs(fx))
+        assert abs(r["chain_cost"][ch][1] - float(np.sum(r["chain_x"][ch] ** 2))) <= 1e-9
+
+
 def test_reaches_schwefel_minimum():
     """The method reaches the closed-form minimum (Sec. 4.1) within 1e-4: at
     n=2 with either move rule, and at n=4 under the 256-chain, 200x50 FP64
