@@ -95,6 +95,8 @@ def parse():
     p.add_argument("--generator-waves", action="store_true",
                    help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
     p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
+    p.add_argument("--exchange-sweep", action="store_true",
+                   help="bench workload with the winner broadcast every level, every 10 levels and never")
     p.add_argument("--wave-sweep", action="store_true",
                    help="cost of a wave's move at 1, 2 and 3 waves per SIMD (Schwefel n=40)")
     p.add_argument("--level-sweep", action="store_true",
@@ -305,6 +307,37 @@ def level_sweep(wl):
             "us_per_step": round(float(slope), 4)}
 
 
+def exchange_sweep(wl, reps=3):
+    """The bench workload with the winner broadcast every level (the
+    synchronous scheme), every 10 levels (periodic exchange) and never (the
+    asynchronous scheme, Sec. 2.2.1): device time per 500-level run (best of
+    `reps` graph replays), moves/s and the final gap to f*."""
+    import torch
+    from paper_2408_00018_amd import sa
+    out = {}
+    for name, k in (("every_level", 1), ("every_10_levels", 10), ("never", 0)):
+        sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
+                            seed=wl.seed, precision=sa.FP32, graph=True, exchange=k)
+        with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+            ann.reset(wl.seed)
+            ann.run()
+            torch.cuda.synchronize()
+            best = math.inf
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(ann.stream)
+                ann.reset(wl.seed)
+                ann.run()
+                e1.record(ann.stream)
+                e1.synchronize()
+                best = min(best, e0.elapsed_time(e1))
+            _, f_rec, lvl = ann.best()
+        out[name] = {"exchange": k, "ms_per_run": round(best, 3),
+                     "moves_per_s": float(f"{wl.moves / (best * 1e-3):.4g}"), "f_rec": f_rec,
+                     "gap_to_f_star": f_rec - W.SCHWEFEL_F_STAR, "rec_level": lvl}
+    return out
+
+
 def wave_sweep():
     """Cost of a move of one wave with 1, 2 and 3 waves per SIMD: Schwefel at
     n = 40 (three 256-chain workgroups fit one CU's LDS) with 65536, 131072 and
@@ -405,6 +438,8 @@ def main():
         out["level_sweep"] = level_sweep(wl)
     if args.wave_sweep:
         out["wave_sweep"] = wave_sweep()
+    if args.exchange_sweep:
+        out["exchange_sweep"] = exchange_sweep(wl)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
     if not args.no_extra:

@@ -114,8 +114,20 @@ typedef struct {
     uint32_t log_chains;
     uint32_t log_level;
     uint32_t log_levels;
-    uint32_t reserved;
+    /* Levels between broadcasts of the level winner (Sec. 2.2).  0 or 1: at
+     * every level (the synchronous scheme of Sec. 2.2.2); k >= 2: at levels
+     * k, 2k, ... (periodic exchange); SA_EXCHANGE_NEVER: never, only the
+     * reduction of each level's best for the trace and record (the
+     * asynchronous scheme of Sec. 2.2.1).  A level that starts without a
+     * broadcast continues every chain from its own state and carried cost,
+     * kept in the workspace (chains x (n + 6) reals).  Values other than 0/1
+     * need the dense state layout (not SA_FLAG_OVERLAY, not an n that only
+     * fits the overlay) and plain or logged moves (not SA_FLAG_LEARNED);
+     * SA_FLAG_GENERATOR_WAVES is ignored. */
+    uint32_t exchange;
 } sa_config;
+
+#define SA_EXCHANGE_NEVER 0xFFFFFFFFu
 
 /* Keep the winner state of every level (sa_trace x_best output). */
 #define SA_FLAG_TRACE_X 0x1u

@@ -74,7 +74,7 @@ constexpr uint32_t kNoStart = 0xFFFFFFFFu;
 
 struct Layout {
     size_t table, T, inv_T, featT, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final;
-    size_t x_start, theta, net, cap_count, total;
+    size_t x_start, theta, net, cap_count, chain_x, chain_cost, total;
 };
 
 struct Plan {
@@ -100,6 +100,10 @@ sa_status validate(const sa_problem *p, const sa_config *c)
         return fail(SA_ERR_INVALID, "unknown flag bits");
     if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs on the dense state layout");
+    if (c->exchange > 1 && (c->flags & SA_FLAG_LEARNED))
+        return fail(SA_ERR_UNSUPPORTED, "an exchange period other than 1 runs plain or logged moves only");
+    if (c->exchange > 1 && (c->flags & SA_FLAG_OVERLAY))
+        return fail(SA_ERR_UNSUPPORTED, "an exchange period other than 1 needs the dense state layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->precision != SA_FP32 || c->move != SA_MOVE_RADIUS))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs in FP32 with the radius move as its plain part");
     if (c->log_chains) {
@@ -130,14 +134,17 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     // is asked for): then a shared level-start state plus per-chain tables.
     const size_t dense_waves =
         pl.wg ? (lds_limit / sa::level_lds_bytes(p->n, pl.wg, pl.real, pl.table, learn)) * (pl.wg / 64) : 0;
-    if (!learn && ((c->flags & SA_FLAG_OVERLAY) || dense_waves < 2)) {
+    // Chains that keep their own state between levels need the dense layout.
+    const bool periodic = c->exchange > 1;
+    if (!learn && !periodic && ((c->flags & SA_FLAG_OVERLAY) || dense_waves < 2)) {
         if (!pick_overlay(p->n, c->chains, c->steps, pl.real, pl.table, lds_limit, &pl.wg, &pl.ov_slots))
             return fail(SA_ERR_UNSUPPORTED, "n=%u with %u steps fits neither state layout in LDS", p->n, c->steps);
         pl.overlay = true;
     }
     if (pl.wg == 0)
         return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
-    pl.split = !pl.overlay && c->precision == SA_FP32 && pl.wg == 256 && (c->flags & SA_FLAG_GENERATOR_WAVES) &&
+    pl.split = !pl.overlay && !periodic && c->precision == SA_FP32 && pl.wg == 256 &&
+               (c->flags & SA_FLAG_GENERATOR_WAVES) &&
                sa::split_lds_bytes(p->n, pl.table) <= lds_limit;
     pl.groups = c->chains / pl.wg;
     const size_t n = p->n, L = c->levels, R = pl.real;
@@ -168,6 +175,8 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.theta = take(learn ? sa::mlp::kNumParams * sizeof(float) : 0);
     l.net = take(learn ? sa::mlp::kNetBytes : 0);
     l.cap_count = take(sizeof(unsigned long long));
+    l.chain_x = take(periodic ? (size_t)c->chains * n * R : 0);
+    l.chain_cost = take(periodic ? (size_t)sa::kCostWords * c->chains * R : 0);
     l.total = off;
     *out = pl;
     return SA_OK;
@@ -228,6 +237,9 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.x_rec = reinterpret_cast<R *>(w + l.x_rec);
     a.rec = reinterpret_cast<double *>(w + l.rec);
     a.rec_level = reinterpret_cast<uint32_t *>(w + l.rec_level);
+    a.exchange = c->cfg.exchange <= 1 ? 1u : c->cfg.exchange == SA_EXCHANGE_NEVER ? 0u : c->cfg.exchange;
+    a.chain_x = a.exchange != 1 ? reinterpret_cast<R *>(w + l.chain_x) : nullptr;
+    a.chain_cost = a.exchange != 1 ? reinterpret_cast<R *>(w + l.chain_cost) : nullptr;
     a.trace = reinterpret_cast<sa_level *>(w + l.trace);
     a.trace_x = (c->cfg.flags & SA_FLAG_TRACE_X) ? reinterpret_cast<R *>(w + l.trace_x) : nullptr;
     a.log = c->cfg.log_chains ? reinterpret_cast<sa_move_rec *>(w + l.log) : nullptr;

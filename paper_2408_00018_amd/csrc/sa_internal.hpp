@@ -32,6 +32,9 @@ template <typename R> struct Slot {
 
 // Arguments of one level launch.  Device pointers point into the context's
 // workspace.  R is the state precision (float or double).
+// Words of a chain's carried cost state between levels (the most any Cost keeps).
+constexpr uint32_t kCostWords = 6;
+
 template <typename R> struct LevelArgs {
     uint32_t n, chains, steps, move;
     uint32_t problem, seed_lo, seed_hi, wg;
@@ -51,6 +54,12 @@ template <typename R> struct LevelArgs {
     R *x_rec;            // n
     double *rec;         // {f_rec}
     uint32_t *rec_level;
+    // Exchange period (Sec. 2.2): level L > 0 starts from the broadcast winner
+    // when exchange > 0 and L % exchange == 0 (exchange = 1: every level);
+    // otherwise every chain continues from its own state and carried cost.
+    uint32_t exchange;
+    R *chain_x;     // n x chains, coordinate-major: chain c's x_i at [i * chains + c]
+    R *chain_cost;  // kCostWords x chains: the carried cost state (Cost::save)
     sa_level *trace;     // one per level
     R *trace_x;          // n per level, or nullptr
     sa_move_rec *log;    // move log, or nullptr

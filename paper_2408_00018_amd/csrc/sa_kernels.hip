@@ -86,6 +86,12 @@ __global__ void __launch_bounds__(256)
     const uint32_t ctr3 = kTagMove | (a.problem << 8);
     const bool log_level = LOG && level >= a.log_level && level - a.log_level < a.log_levels;
     const Full start{sh_start[0], sh_start[1], sh_start[2]};
+    // Without a broadcast at this level's start every chain continues from its
+    // own state and carried cost; they are kept at the end unless the next
+    // level starts from a broadcast.
+    const uint32_t ex = a.exchange;
+    const bool own = level > 0 && level != a.start_level && !(ex != 0 && level % ex == 0);
+    const bool keep = ex != 1 && !(ex != 0 && (level + 1) % ex == 0);
     R wf = widen_inf<R>();
     uint32_t wc = 0xFFFFFFFFu;
     uint32_t accepted = 0;
@@ -113,6 +119,9 @@ __global__ void __launch_bounds__(256)
                 acc.add((double)xi - (double)c.sh);
             }
             cost.set(acc.finish(n), n);
+        } else if (own) {
+            load_column(xs, WG, tid, a.chain_x + chain, a.chains, n);
+            cost.load(a.chain_cost + chain, a.chains);
         } else {
             if (WG == 256)
                 fill_tile_c<256>(xs, tid, xw, n);
@@ -188,6 +197,10 @@ __global__ void __launch_bounds__(256)
                                               k1, T, nl2T, a.inv_n);
         }
         if (LOG && log_level) a.log_final[(size_t)(level - a.log_level) * a.chains + chain] = (double)cost.f;
+        if (keep) {
+            store_column(xs, WG, tid, a.chain_x + chain, a.chains, n);
+            cost.save(a.chain_cost + chain, a.chains);
+        }
 
         // ---- tile argmin of (final cost, chain); keep the workgroup's best
         R bf = cost.f;

@@ -33,6 +33,10 @@ __device__ __forceinline__ bool metropolis_k(float df, float k, float neg_log2e_
 // plain FP64 implementation would (the FP64 path is checked move for move).
 template <> struct Cost<double, kSchwefel> {
     double f, fn;
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(double *p, uint32_t) const { p[0] = f; }
+    __device__ void load(const double *p, uint32_t) { f = p[0]; }
     __device__ void set(const Full &v, uint32_t) { f = v.f; }
     __device__ double delta(double y, double yn, uint32_t n, float)
     {
@@ -45,6 +49,10 @@ template <> struct Cost<double, kSchwefel> {
 
 template <> struct Cost<double, kRastrigin> {
     double f, fn;
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(double *p, uint32_t) const { p[0] = f; }
+    __device__ void load(const double *p, uint32_t) { f = p[0]; }
     __device__ void set(const Full &v, uint32_t) { f = v.f; }
     __device__ double delta(double y, double yn, uint32_t, float)
     {
@@ -57,6 +65,20 @@ template <> struct Cost<double, kRastrigin> {
 
 template <> struct Cost<double, kAckley> {
     double f, s1, s2, fn, s1n, s2n;
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(double *p, uint32_t stride) const
+    {
+        p[0] = f;
+        p[stride] = s1;
+        p[2 * stride] = s2;
+    }
+    __device__ void load(const double *p, uint32_t stride)
+    {
+        f = p[0];
+        s1 = p[stride];
+        s2 = p[2 * stride];
+    }
     __device__ void set(const Full &v, uint32_t)
     {
         f = v.f;
@@ -87,6 +109,10 @@ template <> struct Cost<double, kAckley> {
 //              a = -0.2 sqrt(S1/n), b = S2/n, a'-a = -0.2 (dS1/n) / (sqrt(S1'/n) + sqrt(S1/n))
 template <> struct Cost<float, kSchwefel> {
     float f, df_;
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(float *p, uint32_t) const { p[0] = f; }
+    __device__ void load(const float *p, uint32_t) { f = p[0]; }
     __device__ void set(const Full &v, uint32_t) { f = (float)v.f; }
     __device__ float delta(float y, float yn, uint32_t, float inv_n)
     {
@@ -113,6 +139,10 @@ template <> struct Cost<float, kSchwefel> {
 
 template <> struct Cost<float, kRastrigin> {
     float f, df_;
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(float *p, uint32_t) const { p[0] = f; }
+    __device__ void load(const float *p, uint32_t) { f = p[0]; }
     __device__ void set(const Full &v, uint32_t) { f = (float)v.f; }
     __device__ float delta(float y, float yn, uint32_t, float)
     {
@@ -129,6 +159,26 @@ template <> struct Cost<float, kRastrigin> {
 
 template <> struct Cost<float, kAckley> {
     float f, s1, s2, q, ea, eb;  // q = sqrt(S1/n), ea = exp(-0.2 q), eb = exp(S2/n)
+    // Carried state between levels that start without a broadcast: word k of
+    // a chain's record at p[k * stride].
+    __device__ void save(float *p, uint32_t stride) const
+    {
+        p[0] = f;
+        p[stride] = s1;
+        p[2 * stride] = s2;
+        p[3 * stride] = q;
+        p[4 * stride] = ea;
+        p[5 * stride] = eb;
+    }
+    __device__ void load(const float *p, uint32_t stride)
+    {
+        f = p[0];
+        s1 = p[stride];
+        s2 = p[2 * stride];
+        q = p[3 * stride];
+        ea = p[4 * stride];
+        eb = p[5 * stride];
+    }
     float df_, s1n_, s2n_, qn_;
     __device__ void set(const Full &v, uint32_t n)
     {
@@ -432,6 +482,30 @@ __device__ __forceinline__ void fill_tile_c(R *xs, uint32_t col, const R *xw, ui
         for (uint32_t k = 0; k < 4u; ++k) c[(i + k) * STRIDE] = v[k];
     }
     for (; i < n; ++i) c[i * STRIDE] = xw[i];
+}
+
+// A chain's own state between levels without a broadcast: its column of a
+// coordinate-major global array (row stride `gstride`) to and from its LDS
+// column.  Loads are issued 16 at a time.
+template <typename R>
+__device__ __forceinline__ void load_column(R *xs, uint32_t stride, uint32_t col, const R *src, uint32_t gstride,
+                                            uint32_t n)
+{
+    uint32_t i = 0;
+    for (; i + 16u <= n; i += 16u) {
+        R v[16];
+#pragma unroll
+        for (uint32_t k = 0; k < 16u; ++k) v[k] = src[(size_t)(i + k) * gstride];
+#pragma unroll
+        for (uint32_t k = 0; k < 16u; ++k) xs[(i + k) * stride + col] = v[k];
+    }
+    for (; i < n; ++i) xs[i * stride + col] = src[(size_t)i * gstride];
+}
+template <typename R>
+__device__ __forceinline__ void store_column(const R *xs, uint32_t stride, uint32_t col, R *dst, uint32_t gstride,
+                                             uint32_t n)
+{
+    for (uint32_t i = 0; i < n; ++i) dst[(size_t)i * gstride] = xs[i * stride + col];
 }
 
 // ---------------------------------------------------------------------------

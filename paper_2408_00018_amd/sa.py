@@ -21,6 +21,7 @@ SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY, FLAG_GENERATOR_WAVES = 0x1, 0x2, 0x4, 0x8, 0x10
+EXCHANGE_NEVER = 0xFFFFFFFF
 
 SA_OK = 0
 STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ERR_DEVICE", -4: "SA_ERR_STATE",
@@ -47,7 +48,7 @@ class Config(ctypes.Structure):
                 ("steps", ctypes.c_uint32), ("precision", ctypes.c_uint32), ("move", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("T0", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("radius_frac", ctypes.c_double), ("log_chains", ctypes.c_uint32), ("log_level", ctypes.c_uint32),
-                ("log_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("log_levels", ctypes.c_uint32), ("exchange", ctypes.c_uint32)]
 
 
 LEVEL_DTYPE = np.dtype([("win_chain", np.uint32), ("reserved", np.uint32), ("f_win", np.float64),
@@ -131,13 +132,17 @@ class Schedule:
     log_chains: int = 0
     log_level: int = 0
     log_levels: int = 0
+    # levels between broadcasts of the winner: 1 every level (synchronous),
+    # k every k-th level (periodic exchange), 0 never (asynchronous)
+    exchange: int = 1
 
     def to_c(self) -> Config:
         flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
                  (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0) |
                  (FLAG_GENERATOR_WAVES if self.generator_waves else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
-                      self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels, 0)
+                      self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels,
+                      EXCHANGE_NEVER if self.exchange == 0 else self.exchange)
 
 
 def _problem_struct(func, lower, upper, shift):

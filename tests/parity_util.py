@@ -75,12 +75,17 @@ def df_floor(func, n, x, xn, d, shift):
 
 
 def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
-                     final_f, chain_ids, rel=1e-5, problem=0):
+                     final_f, chain_ids, rel=1e-5, problem=0, start_err=None):
     """Replay the logged moves of `chain_ids` at one level against the oracle.
 
     x_start: the level's start state (the previous level's broadcast winner,
-    FP32 values).  Returns statistics; raises AssertionError on a mismatch."""
-    stats = dict(moves=0, max_rel_excess=0.0, decision_mismatch=0, ambiguous=0, max_df_err=0.0)
+    or the chain's own state, FP32 values).  start_err: bound on the error of
+    the start cost the chain carries in (default: one FP32 rounding of a full
+    evaluation, as after a broadcast).  Returns statistics, with each chain's
+    error bound on its final cost in stats["f_err"]; raises AssertionError on
+    a mismatch."""
+    stats = dict(moves=0, max_rel_excess=0.0, decision_mismatch=0, ambiguous=0, max_df_err=0.0, f_err={},
+                 x_final={})
     for j, c in enumerate(chain_ids):
         x = np.array(x_start, dtype=np.float64)
         f_acc_err = 0.0
@@ -122,8 +127,11 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
                 f_acc_err += tol + 2 * U32 * abs(O.f(func, x, shift32))
             stats["moves"] += 1
         f_ref = O.f(func, x, shift32)
-        start_err = 2 * U32 * abs(O.f(func, x_start, shift32)) + 1e-12
-        assert abs(final_f[c] - f_ref) <= f_acc_err + start_err + 2 * U32 * abs(f_ref), (level, c)
+        s_err = 2 * U32 * abs(O.f(func, x_start, shift32)) + 1e-12 if start_err is None else start_err
+        bound = f_acc_err + s_err + 2 * U32 * abs(f_ref)
+        assert abs(final_f[c] - f_ref) <= bound, (level, c)
+        stats["f_err"][c] = bound
+        stats["x_final"][c] = x
     return stats
 
 

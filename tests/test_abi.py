@@ -116,6 +116,29 @@ def test_state_too_large_for_lds_is_unsupported(S):
     assert e.value.status == -5
 
 
+def test_exchange_period_options(S):
+    """Chains that keep their own state between broadcasts get a per-chain
+    state buffer (n + 6 reals per chain) in the workspace; the period needs
+    the dense layout and plain or logged moves."""
+    wl = W.schwefel_n100_fp32()
+    b1 = _ws(S, wl)
+    for k in (0, 3):
+        bk = _ws(S, wl, exchange=k)
+        assert bk >= b1 + wl.chains * (wl.n + 6) * 4 - 512  # the empty buffers' alignment slots
+    assert _ws(S, wl, exchange=1) == b1
+    lo, hi = np.full(16, -1.0), np.full(16, 1.0)
+    for kw in (dict(learned=True), dict(overlay=True)):
+        with pytest.raises(S.SAError) as e:
+            S.workspace_bytes(0, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9,
+                                                          exchange=0, **kw))
+        assert e.value.status == -5
+    # n = 5000 fits only the overlay layout: no own-state runs
+    lo, hi = np.full(5000, -1.0), np.full(5000, 1.0)
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(0, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9, exchange=4))
+    assert e.value.status == -5
+
+
 def test_null_arguments(S):
     L = S.load_library()
     assert L.sa_workspace_bytes(None, None, None) == -1

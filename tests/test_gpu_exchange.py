@@ -1,0 +1,153 @@
+"""GPU parity of the exchange period (Sec. 2.2): the level winner broadcast to
+every chain every k levels (periodic exchange) or never (the asynchronous
+scheme of Sec. 2.2.1), each chain carrying its own state and cost between
+broadcasts.
+
+FP64 runs reproduce the oracle's trajectory exactly, also when the run is
+split over several sa_run calls (the chains' states live in the workspace
+between them).  FP32 runs are replayed move by move, each chain from its own
+carried state, at small sizes and at the bench workload's shape (65536
+chains, n = 100); chunked, graph-captured and whole FP32 runs agree bit for
+bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity_util import box32, check_fp32_level, check_record, f32, fp32_init_state, lexi_argmin
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2408_00018_amd import sa
+    sa.load_library()
+    return sa
+
+
+def run(S, wl, chunks=None, **kw):
+    d = dict(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+             precision=wl.precision, radius_frac=wl.radius_frac, trace_x=True)
+    d.update(kw)
+    sched = S.Schedule(**d)
+    say(f"[gpu] {wl.name} n={wl.n} chains={sched.chains} levels={sched.levels} steps={sched.steps} "
+        f"prec={sched.precision} exchange={sched.exchange} chunks={chunks} graph={sched.graph} "
+        f"log={sched.log_chains}")
+    with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as a:
+        for c in (chunks or [0]):
+            a.run(c)
+        rec, xb = a.trace(with_x=True)
+        x_rec, f_rec, lvl = a.best()
+        out = dict(rec=rec, xb=xb, x_rec=x_rec, f_rec=f_rec, rec_level=lvl)
+        if sched.log_chains:
+            out["moves"], out["final_f"] = a.move_log()
+    return out
+
+
+def problem(func, n, box, seed):
+    wl = W.random_problem(func, n, seed=seed, shifted=(box == "shifted"))
+    if box == "uneven":
+        lo, hi = W.uneven_box(n, seed + 1)
+        wl = wl.with_(lower=lo, upper=hi, shift=None)
+    return wl
+
+
+FP64_CASES = [
+    # func, n, chains, levels, steps, box, exchange (0: never), chunks
+    (W.SCHWEFEL, 4, 256, 9, 20, "canonical", 3, None),
+    (W.ACKLEY, 5, 192, 7, 17, "uneven", 0, None),
+    (W.RASTRIGIN, 6, 128, 8, 13, "shifted", 2, [3, 2, 0]),
+    (W.ACKLEY, 9, 320, 6, 31, "shifted", 4, [1, 0]),
+    (W.SCHWEFEL, 7, 64, 5, 7, "uneven", 0, [2, 0]),
+]
+
+
+@pytest.mark.parametrize("func,n,chains,levels,steps,box,exchange,chunks", FP64_CASES)
+def test_fp64_exchange_period_trajectory_equals_oracle(S, func, n, chains, levels, steps, box, exchange, chunks):
+    wl = problem(func, n, box, 2000 + 10 * func + n).with_(chains=chains, levels=levels, steps=steps,
+                                                            precision=W.FP64)
+    g = run(S, wl, chunks=chunks, exchange=exchange)
+    o = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=chains, steps=steps, T0=wl.T0,
+                 alpha=wl.alpha, levels=levels, radius_frac=wl.radius_frac, exchange=exchange)
+    assert np.array_equal(g["rec"]["win_chain"], o["win_chain"])
+    assert np.array_equal(g["rec"]["accepts"], o["accepts"])
+    np.testing.assert_allclose(g["xb"], o["x_best"], rtol=1e-12, atol=1e-12)
+    for k in ("f_win", "f_best", "f_rec"):
+        np.testing.assert_allclose(g["rec"][k], o[k], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(g["x_rec"], o["x_rec"], rtol=1e-12, atol=1e-12)
+    assert g["rec_level"] == o["rec_level"]
+
+
+def test_fp32_exchange_runs_agree_bitwise(S):
+    """Whole, chunked and graph-captured runs with periodic exchange keep the
+    same chain states between calls: identical bits."""
+    wl = W.random_problem(W.RASTRIGIN, 24, seed=41).with_(chains=1024, levels=9, steps=37)
+    whole = run(S, wl, exchange=3)
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    for other in (run(S, wl, exchange=3, chunks=[1, 4, 2, 0]), run(S, wl, exchange=3, graph=True, chunks=[4, 0])):
+        assert np.array_equal(other["rec"][keys], whole["rec"][keys])
+        assert np.array_equal(other["xb"], whole["xb"])
+    check_record(wl, whole)
+    # a period of 1 is the synchronous run, bit for bit
+    sync = run(S, wl)
+    assert np.array_equal(run(S, wl, exchange=1)["rec"][keys], sync["rec"][keys])
+
+
+def replay(wl, g, exchange, chains):
+    """Per-move replay of an FP32 run logged from level 0, each chain from the
+    state its own previous level left (or the broadcast winner), with the
+    level argmin and the winners' full re-evaluations."""
+    lo32, hi32 = box32(wl.lower, wl.upper)
+    sh32 = None if wl.shift is None else f32(wl.shift)
+    moves, final_f, rec, xb = g["moves"], g["final_f"], g["rec"], g["xb"]
+    state, err, total = {}, {}, 0
+    for level in range(moves.shape[0]):
+        T = O.temperature(wl.T0, wl.alpha, level)
+        win = lexi_argmin(final_f[level])
+        assert rec["win_chain"][level] == win
+        assert rec["f_win"][level] == final_f[level][win]
+        fb = O.f(wl.func, xb[level], sh32)
+        assert abs(rec["f_best"][level] - fb) <= 1e-11 * max(1.0, abs(fb))
+        broadcast = level > 0 and exchange > 0 and level % exchange == 0
+        for c in chains:
+            if level == 0:
+                x0, se = fp32_init_state(wl, c), None
+            elif broadcast:
+                x0, se = xb[level - 1], None
+            else:
+                x0, se = state[c], err[c]
+            st = check_fp32_level(wl.func, wl.n, lo32, hi32, sh32, wl.seed, level, T, O.MOVE_RADIUS,
+                                  wl.radius_frac, x0, moves[level, c:c + 1], final_f[level], [c], start_err=se)
+            state[c], err[c] = st["x_final"][c], st["f_err"][c]
+            total += st["moves"]
+    return total
+
+
+@pytest.mark.parametrize("func,n,exchange", [(W.SCHWEFEL, 12, 0), (W.ACKLEY, 10, 2), (W.RASTRIGIN, 8, 3)])
+def test_fp32_own_state_levels_replay_against_oracle(S, func, n, exchange):
+    wl = W.random_problem(func, n, seed=50 + n).with_(chains=256, levels=5, steps=24)
+    g = run(S, wl, exchange=exchange, log_chains=256, log_level=0, log_levels=5)
+    moves = replay(wl, g, exchange, range(0, 256, 17))
+    say(f"[fp32 exchange parity] {wl.name} exchange={exchange}: {moves} moves")
+
+
+def test_fp32_asynchronous_bench_shape(S):
+    """The bench workload's shape (Schwefel n = 100, 65536 chains, 100 steps)
+    without exchange: three levels logged, sampled chains replayed from their
+    own states, record invariants."""
+    wl = W.schwefel_n100_fp32().with_(levels=3)
+    g = run(S, wl, exchange=0, log_chains=512, log_level=0, log_levels=3)
+    moves = replay(wl, g, 0, range(0, 512, 97))
+    check_record(wl, g)
+    say(f"[fp32 exchange parity] bench shape: {moves} moves")
