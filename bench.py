@@ -97,6 +97,8 @@ def parse():
     p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--exchange-sweep", action="store_true",
                    help="bench workload with the winner broadcast every level, every 10 levels and never")
+    p.add_argument("--paper-tables", action="store_true",
+                   help="the paper's V2/V1 setting: Schwefel n=8..512, 16384 chains, T0=1000, rho=0.99, 1146 levels")
     p.add_argument("--wave-sweep", action="store_true",
                    help="cost of a wave's move at 1, 2 and 3 waves per SIMD (Schwefel n=40)")
     p.add_argument("--level-sweep", action="store_true",
@@ -338,6 +340,50 @@ def exchange_sweep(wl, reps=3):
     return out
 
 
+def paper_tables(seed=1):
+    """The paper's own comparison setting (Sec. 4: T0 = 1000, T_min = 0.01,
+    rho = 0.99, i.e. 1146 levels, N = 100 steps, 16384 chains, normalized
+    Schwefel n = 8 ... 512, FP32): the synchronous scheme (V2, a broadcast at
+    every level) and the asynchronous one (V1, no exchange), each with the
+    radius move and with the whole-interval resample move (the two readings
+    of the paper's neighbour), each one run after a warm-up; device time,
+    moves/s, |f_a - f*| and the relative error ||x_a - x*|| / ||x*|| of the
+    record."""
+    import torch
+    from paper_2408_00018_amd import sa
+    levels = math.ceil(math.log(0.01 / 1000.0) / math.log(0.99))  # T_k > T_min for k < levels
+    out = {"levels": levels, "steps": 100, "chains": 16384, "T0": 1000.0, "alpha": 0.99, "rows": []}
+    for n in (8, 16, 32, 64, 128, 256, 512):
+        lo, hi = np.full(n, -500.0), np.full(n, 500.0)
+        x_star = np.full(n, W.SCHWEFEL_X_STAR)
+        for name, k, move in (("V2", 1, sa.MOVE_RADIUS), ("V1", 0, sa.MOVE_RADIUS), ("V2", 1, sa.MOVE_RESAMPLE),
+                              ("V1", 0, sa.MOVE_RESAMPLE)):
+            sched = sa.Schedule(chains=16384, levels=levels, steps=100, T0=1000.0, alpha=0.99, seed=seed,
+                                precision=sa.FP32, graph=True, exchange=k, move=move)
+            with sa.Annealer(W.SCHWEFEL, lo, hi, None, schedule=sched) as ann:
+                ann.reset(seed)
+                ann.run()
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(ann.stream)
+                ann.reset(seed)
+                ann.run()
+                e1.record(ann.stream)
+                e1.synchronize()
+                ms = e0.elapsed_time(e1)
+                x, f, _ = ann.best()
+                wg, ov, _ = ann.layout()
+            moves = 16384 * levels * 100
+            out["rows"].append({"n": n, "scheme": name, "move": "radius" if move == sa.MOVE_RADIUS else "resample",
+                                "seconds": round(ms * 1e-3, 5),
+                                "moves_per_s": float(f"{moves / (ms * 1e-3):.4g}"),
+                                "abs_err_f": float(f"{abs(f - W.SCHWEFEL_F_STAR):.4g}"),
+                                "rel_err_x": float(f"{np.linalg.norm(x - x_star) / np.linalg.norm(x_star):.4g}"),
+                                "layout": "overlay" if ov else f"dense, {wg} chains per workgroup"})
+            print(f"[paper tables] n={n} {name}: {out['rows'][-1]}", flush=True)
+    return out
+
+
 def wave_sweep():
     """Cost of a move of one wave with 1, 2 and 3 waves per SIMD: Schwefel at
     n = 40 (three 256-chain workgroups fit one CU's LDS) with 65536, 131072 and
@@ -440,6 +486,8 @@ def main():
         out["wave_sweep"] = wave_sweep()
     if args.exchange_sweep:
         out["exchange_sweep"] = exchange_sweep(wl)
+    if args.paper_tables:
+        out["paper_tables"] = paper_tables()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
     if not args.no_extra:

@@ -28,9 +28,10 @@ namespace sa {
 // ---------------------------------------------------------------------------
 // The level kernel.  prev_groups: candidates the previous level's launch
 // published (unused at level 0 and at the start level).  UNSHIFTED: the box
-// is uniform and the shift is zero, known at compile time, so the steps skip
-// the x - s subtractions (x - 0 is x exactly: the same bits as the general
-// kernel, two fewer operations per move).
+// is uniform, the shift is zero and every level starts from a broadcast, all
+// known at compile time, so the steps skip the x - s subtractions (x - 0 is x
+// exactly: the same bits as the general kernel, two fewer operations per move)
+// and the kernel carries no own-state paths.
 // LDS: [net (learned modes)] | xs[n][WG] tile states | xw[n] level start |
 //      xb[n] workgroup best | tab[n][4] per-coordinate box/shift (TABLE only)
 // ---------------------------------------------------------------------------
@@ -90,8 +91,8 @@ __global__ void __launch_bounds__(256)
     // own state and carried cost; they are kept at the end unless the next
     // level starts from a broadcast.
     const uint32_t ex = a.exchange;
-    const bool own = level > 0 && level != a.start_level && !(ex != 0 && level % ex == 0);
-    const bool keep = ex != 1 && !(ex != 0 && (level + 1) % ex == 0);
+    const bool own = !UNSHIFTED && level > 0 && level != a.start_level && !(ex != 0 && level % ex == 0);
+    const bool keep = !UNSHIFTED && ex != 1 && !(ex != 0 && (level + 1) % ex == 0);
     R wf = widen_inf<R>();
     uint32_t wc = 0xFFFFFFFFu;
     uint32_t accepted = 0;
@@ -296,7 +297,7 @@ static hipError_t launch_mode(int mode, const LevelArgs<R> &a, uint32_t level, u
     switch (mode) {
     case kModePlain:
         if constexpr (!TABLE && sizeof(R) == sizeof(float)) {
-            if (a.sh == R(0) && !std::signbit(a.sh))  // +0 exactly
+            if (a.sh == R(0) && !std::signbit(a.sh) && a.exchange == 1)  // +0 exactly, synchronous
                 return launch_one<R, F, TABLE, kModePlain, MOVE, true>(a, level, prev, groups, s);
         }
         return launch_one<R, F, TABLE, kModePlain, MOVE>(a, level, prev, groups, s);
