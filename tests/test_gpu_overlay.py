@@ -115,7 +115,7 @@ def shifted_large(func, n, chains, levels, steps=64):
 @pytest.mark.parametrize("func,n", [(W.RASTRIGIN, 512), (W.ACKLEY, 1024)])
 def test_fp32_overlay_moves_large_n(S, func, n):
     wl = shifted_large(func, n, chains=1024, levels=3)
-    g = run(S, wl, log_chains=64, log_level=0, log_levels=3)
+    g = run(S, wl, log_chains=64, log_level=0, log_levels=3, overlay=True)
     assert g["layout"][1] > 64
     check_fp32_run(wl, g, 0, chain_ids=list(range(0, 64, 9)), say=say)
     check_record(wl, g)
