@@ -62,7 +62,7 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "8374a4c874f32a53", "fetch_kib": 170.458, "fetch_scale": 2.0,
+TRAFFIC_MEASURED = {"sources_sha256_16": "a3a0f7f3df843ce4", "fetch_kib": 167.470, "fetch_scale": 2.0,
                     "write_kib": 120.592, "write_scale": 1.0}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
                   "paper_2408_00018_amd/csrc/sa_internal.hpp", "paper_2408_00018_amd/csrc/sa_step.hpp",

@@ -140,9 +140,11 @@ typedef struct {
 #define SA_FLAG_LEARNED 0x4u
 /* Keep chain states as one shared level-start state per workgroup plus a
  * per-chain table of the coordinates changed this level (chosen anyway when
- * the dense per-chain state leaves fewer than two waves per CU, e.g. n >= 512
- * in FP32).  Plain and logged moves only (not with SA_FLAG_LEARNED or
- * sa_capture); results are identical to the dense layout. */
+ * the dense per-chain state does not fit in LDS, e.g. n = 1024 in FP32, or
+ * when the tables keep at least twice as many waves in flight on the device,
+ * e.g. n = 512 with 131072 chains).  Plain and logged moves only (not with
+ * SA_FLAG_LEARNED or sa_capture); results are identical to the dense
+ * layout. */
 #define SA_FLAG_OVERLAY 0x8u
 /* FP32 plain levels with 256 chains per workgroup: run them with four extra
  * waves that compute the random draws ahead into LDS (two waves per SIMD)
