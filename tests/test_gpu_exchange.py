@@ -151,3 +151,19 @@ def test_fp32_asynchronous_bench_shape(S):
     moves = replay(wl, g, 0, range(0, 512, 97))
     check_record(wl, g)
     say(f"[fp32 exchange parity] bench shape: {moves} moves")
+
+
+def test_fp32_own_state_with_several_tiles_per_workgroup(S):
+    """131072 chains at n = 100: 512 tiles of 256 chains on at most 256
+    resident workgroups, so a workgroup runs several tiles in turn, each
+    loading and keeping its own chains.  Chains of the first and of a later
+    tile are replayed from their own states; chunked and whole runs agree."""
+    wl = W.schwefel_n100_fp32().with_(chains=131072, levels=3, steps=12)
+    g = run(S, wl, exchange=0, log_chains=131072, log_level=0, log_levels=3)
+    assert g["rec"]["win_chain"].size == 3
+    moves = replay(wl, g, 0, [0, 255, 65536 + 7, 131071])
+    chunked = run(S, wl, exchange=0, chunks=[1, 0])
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    assert np.array_equal(chunked["rec"][keys], g["rec"][keys])
+    assert np.array_equal(chunked["xb"], g["xb"])
+    say(f"[fp32 exchange parity] several tiles per workgroup: {moves} moves")
