@@ -134,6 +134,27 @@ def test_fp32_batch_is_layout_invariant(S):
             assert np.array_equal(a["xb"], b["xb"])
 
 
+def test_fp32_batch_full_size(S):
+    """The 1024-problem batched workload at full size (n ~ U{2..256}, three
+    families, 512 chains per problem as the autotuner picks on MI355X, four
+    waves per workgroup, 500 levels x 64 steps, graph-captured): record
+    invariants of every problem and per-move parity of sampled chains of the
+    largest problem at the last two levels."""
+    probs = W.batch_problems()
+    chains = np.full(len(probs), 512, dtype=np.uint32)
+    q = int(np.argmax([lo.size for _, lo, _, _ in probs]))
+    sched = S.BatchSchedule(levels=500, steps=64, T0=10.0, alpha=0.99, seed=4, precision=S.FP32, trace_x=True,
+                            graph=True, waves_per_group=4, log_problem=q, log_chains=512, log_level=498,
+                            log_levels=2)
+    g, lay = run_batch(S, probs, chains, sched)
+    say(f"[gpu batch] full size: layout {lay}")
+    wls = [W.Workload(f"batch1024_p{p}", func, lo.size, lo, hi, sh, chains=512, levels=500, steps=64, T0=10.0,
+                      alpha=0.99, seed=4, precision=W.FP32) for p, (func, lo, hi, sh) in enumerate(probs)]
+    check_fp32_run(wls[q], g[q], 498, chain_ids=[0, 1, 130, 257, 511], problem=q, say=say)
+    for p, w in enumerate(wls):
+        check_record(w, g[p])
+
+
 def test_autotune_picks_a_valid_layout(S):
     probs, _, _ = make_batch(64, seed=17, nmax=256, precision=W.FP32)
     sched = S.BatchSchedule(levels=3, steps=16, T0=10.0, alpha=0.9, seed=0, precision=S.FP32)

@@ -132,11 +132,13 @@ def test_fp32_overlay_equals_dense_at_moderate_n(S):
     assert np.array_equal(dense["xb"], ov["xb"])
 
 
-def test_fp32_ackley_n1024_full_size(S):
-    """The n = 1024 Ackley workload at full size (131072 chains, 1000 levels x
-    64 steps): every level's record properties, the re-evaluated broadcasts,
-    and per-move parity of sampled chains at the last two levels."""
-    wl = W.ackley_n1024_fp32()
+@pytest.mark.parametrize("name", ["ackley_n1024_fp32", "rastrigin_n512_fp32"])
+def test_fp32_large_n_full_size(S, name):
+    """The n = 1024 Ackley and n = 512 Rastrigin workloads at full size (131072
+    chains, 1000 levels x 64 steps, the layout the library picks for them):
+    every level's record properties, the re-evaluated broadcasts, and per-move
+    parity of sampled chains at the last two levels."""
+    wl = getattr(W, name)()
     g = run(S, wl, log_chains=wl.chains, log_level=wl.levels - 2, log_levels=2, graph=True)
     assert g["layout"][1] > 64
     rng = np.random.default_rng(1)
