@@ -219,8 +219,11 @@ sa_status sa_move_log(sa_ctx *ctx, sa_move_rec *moves, double *final_f);
 /* Start the run at `level` (1 <= level < cfg->levels) with every chain at x
  * (n doubles inside the box; FP32 runs round them to FP32, kept inside the
  * inward-rounded box), instead of the random starts of level 0: the levels
- * before `level` are skipped and the record starts empty.  Only before the
- * first sa_run (or after sa_reset, which clears it).  Synchronises. */
+ * before `level` are skipped and the record starts empty.  With an exchange
+ * period other than 1, `level` starts every chain from x and the later
+ * levels follow the period (chains keep their own states until its next
+ * multiple).  Only before the first sa_run (or after sa_reset, which clears
+ * it).  Synchronises. */
 sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
 
 /*

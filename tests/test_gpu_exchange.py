@@ -167,3 +167,27 @@ def test_fp32_own_state_with_several_tiles_per_workgroup(S):
     assert np.array_equal(chunked["rec"][keys], g["rec"][keys])
     assert np.array_equal(chunked["xb"], g["xb"])
     say(f"[fp32 exchange parity] several tiles per workgroup: {moves} moves")
+
+
+def test_fp64_start_state_with_exchange_period(S):
+    """A run started at level 6 from a given state (sa_set_start) with a
+    period of 3: level 6 starts every chain from that state, levels 7-8 carry
+    the chains' own states, level 9 broadcasts; equal to the oracle's run
+    from level 6 with that start."""
+    wl = problem(W.ACKLEY, 5, "shifted", 77).with_(chains=192, levels=12, steps=19, precision=W.FP64)
+    rng = np.random.default_rng(3)
+    x0 = wl.shift + rng.uniform(-1.0, 1.0, wl.n)
+    sched = S.Schedule(chains=192, levels=12, steps=19, T0=wl.T0, alpha=wl.alpha, seed=wl.seed, precision=S.FP64,
+                       trace_x=True, exchange=3)
+    with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+        ann.set_start(6, x0)
+        ann.run()
+        rec, xb = ann.trace(6, 6, with_x=True)
+        x_rec, f_rec, lvl = ann.best()
+    o = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=192, steps=19, T0=wl.T0,
+                 alpha=wl.alpha, levels=6, level_begin=6, x_start=x0, exchange=3)
+    assert np.array_equal(rec["win_chain"], o["win_chain"])
+    assert np.array_equal(rec["accepts"], o["accepts"])
+    np.testing.assert_allclose(rec["f_best"], o["f_best"], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(xb, o["x_best"], rtol=1e-12, atol=1e-12)
+    assert lvl == o["rec_level"] and abs(f_rec - o["f_rec_final"]) <= 1e-12
