@@ -225,9 +225,10 @@ def test_edges_single_level_single_step(S):
 
 
 def test_layout_choice_by_dimension(S):
-    """n=300 FP32 (76.8 KB per 64-chain workgroup, two waves per CU) keeps the
-    dense state; n=700 (which does not fit densely) runs on the shared start
-    state plus per-chain tables; both replay move for move."""
+    """n=300 FP32 (76.8 KB per 64-chain workgroup) keeps the dense state (the
+    overlay would not keep twice as many waves in flight); n=700 (which does
+    not fit densely) runs on the shared start state plus per-chain tables;
+    both replay move for move."""
     wl = W.random_problem(W.SCHWEFEL, 300, seed=1, shifted=False).with_(chains=128, levels=2, steps=16)
     g = run_gpu(S, wl, log_chains=64, log_level=0, log_levels=2)
     assert g["layout"][1] == 0
