@@ -92,15 +92,11 @@ def parse():
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
     p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
     p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
-    p.add_argument("--generator-waves", action="store_true",
-                   help="run the levels with separate generator waves (SA_FLAG_GENERATOR_WAVES)")
     p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--exchange-sweep", action="store_true",
                    help="bench workload with the winner broadcast every level, every 10 levels and never")
     p.add_argument("--paper-tables", action="store_true",
                    help="the paper's V2/V1 setting: Schwefel n=8..512, 16384 chains, T0=1000, rho=0.99, 1146 levels")
-    p.add_argument("--paper-scaling", action="store_true",
-                   help="the paper's V2 setting swept over chains (8192..131072) and steps per level (50..3200)")
     p.add_argument("--wave-sweep", action="store_true",
                    help="cost of a wave's move at 1, 2 and 3 waves per SIMD (Schwefel n=40)")
     p.add_argument("--level-sweep", action="store_true",
@@ -386,41 +382,6 @@ def paper_tables(seed=1):
     return out
 
 
-def paper_scaling(seed=1):
-    """The synchronous scheme (V2, resample move, FP32) at the paper's setting
-    (T0 = 1000, T_min = 0.01, rho = 0.99) swept over the number of chains
-    (8192 ... 131072, N = 100) and the steps per level (N = 50, 100, 3200;
-    16384 chains) at n = 16 and 32: device time, moves/s, |f_a - f*|."""
-    import torch
-    from paper_2408_00018_amd import sa
-    levels = math.ceil(math.log(0.01 / 1000.0) / math.log(0.99))
-    cases = [(c, 100) for c in (8192, 16384, 32768, 65536, 131072)] + [(16384, 50), (16384, 3200)]
-    rows = []
-    for n in (16, 32):
-        lo, hi = np.full(n, -500.0), np.full(n, 500.0)
-        for chains, steps in cases:
-            sched = sa.Schedule(chains=chains, levels=levels, steps=steps, T0=1000.0, alpha=0.99, seed=seed,
-                                precision=sa.FP32, graph=True, move=sa.MOVE_RESAMPLE)
-            with sa.Annealer(W.SCHWEFEL, lo, hi, None, schedule=sched) as ann:
-                ann.reset(seed)
-                ann.run()
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(ann.stream)
-                ann.reset(seed)
-                ann.run()
-                e1.record(ann.stream)
-                e1.synchronize()
-                ms = e0.elapsed_time(e1)
-                _, f, _ = ann.best()
-            moves = chains * levels * steps
-            rows.append({"n": n, "chains": chains, "steps": steps, "seconds": round(ms * 1e-3, 5),
-                         "moves_per_s": float(f"{moves / (ms * 1e-3):.4g}"),
-                         "abs_err_f": float(f"{abs(f - W.SCHWEFEL_F_STAR):.4g}")})
-            print(f"[paper scaling] {rows[-1]}", flush=True)
-    return {"levels": levels, "move": "resample", "rows": rows}
-
-
 def wave_sweep():
     """Cost of a move of one wave with 1, 2 and 3 waves per SIMD: Schwefel at
     n = 40 (three 256-chain workgroups fit one CU's LDS) with 65536, 131072 and
@@ -463,7 +424,7 @@ def main():
         return
     wl = W.schwefel_n100_fp32()
     sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
-                        precision=sa.FP32, graph=True, generator_waves=args.generator_waves)
+                        precision=sa.FP32, graph=True)
     ann = sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched)
     stream = ann.stream
     for _ in range(args.warmup):
@@ -525,8 +486,6 @@ def main():
         out["exchange_sweep"] = exchange_sweep(wl)
     if args.paper_tables:
         out["paper_tables"] = paper_tables()
-    if args.paper_scaling:
-        out["paper_scaling"] = paper_scaling()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
     if not args.no_extra:

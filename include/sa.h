@@ -122,8 +122,7 @@ typedef struct {
      * broadcast continues every chain from its own state and carried cost,
      * kept in the workspace (chains x (n + 6) reals).  Values other than 0/1
      * need the dense state layout (not SA_FLAG_OVERLAY, not an n that only
-     * fits the overlay) and plain or logged moves (not SA_FLAG_LEARNED);
-     * SA_FLAG_GENERATOR_WAVES is ignored. */
+     * fits the overlay) and plain or logged moves (not SA_FLAG_LEARNED). */
     uint32_t exchange;
 } sa_config;
 
@@ -146,11 +145,6 @@ typedef struct {
  * SA_FLAG_LEARNED or sa_capture); results are identical to the dense
  * layout. */
 #define SA_FLAG_OVERLAY 0x8u
-/* FP32 plain levels with 256 chains per workgroup: run them with four extra
- * waves that compute the random draws ahead into LDS (two waves per SIMD)
- * instead of one wave per 64 chains.  Results are identical either way; on
- * MI355X it is currently slower (see the design notes), so it is opt-in. */
-#define SA_FLAG_GENERATOR_WAVES 0x10u
 
 /* Per-level record returned by sa_trace. */
 typedef struct {

@@ -8,6 +8,7 @@ from __future__ import annotations
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -15,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa_hip.so")
 PEAK_LIB = os.path.join(PKG, "libsa_peak.so")
 
-SOURCES = ["sa_kernels.hip", "sa_overlay.hip", "sa_split.hip", "sa_api.hip", "sa_batch.hip", "sa_batch_api.hip", "sa_mlp.hip"]
+SOURCES = ["sa_kernels.hip", "sa_overlay.hip", "sa_api.hip", "sa_batch.hip", "sa_batch_api.hip", "sa_mlp.hip"]
 PEAK_SOURCES = ["peak_probe.hip"]
 
 HIPCC_FLAGS = [
@@ -50,10 +51,30 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the gfx950 library cannot be built")
 
 
+OBJ_DIR = os.path.join(PKG, "_build")
+
+
 def _compile(sources, out, verbose):
-    srcs = [os.path.join(CSRC, s) for s in sources]
+    """Compile each source to its own object in parallel (each translation
+    unit holds its kernels and their launchers, so no device-code linking is
+    needed), then link the shared library."""
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+
+    def one(src):
+        obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *compile_flags, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, src),
+               "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    jobs = max(1, min(len(sources), int(os.environ.get("MAX_JOBS", "0") or 0) or (os.cpu_count() or 1)))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, sources))
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *srcs, "-o", tmp]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

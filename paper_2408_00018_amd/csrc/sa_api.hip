@@ -80,7 +80,6 @@ struct Layout {
 struct Plan {
     bool table = false;
     bool overlay = false;
-    bool split = false;  // FP32 plain levels use the generator-wave kernel
     uint32_t ov_slots = 0;
     uint32_t wg = 0, groups = 0;
     size_t real = 0;
@@ -96,7 +95,7 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_GENERATOR_WAVES))
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY))
         return fail(SA_ERR_INVALID, "unknown flag bits");
     if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs on the dense state layout");
@@ -165,9 +164,6 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     }
     if (pl.wg == 0)
         return fail(SA_ERR_UNSUPPORTED, "state of n=%u does not fit in LDS for a 64-lane workgroup", p->n);
-    pl.split = !pl.overlay && !periodic && c->precision == SA_FP32 && pl.wg == 256 &&
-               (c->flags & SA_FLAG_GENERATOR_WAVES) &&
-               sa::split_lds_bytes(p->n, pl.table) <= lds_limit;
     pl.groups = c->chains / pl.wg;
     const size_t n = p->n, L = c->levels, R = pl.real;
     Layout &l = pl.lay;
@@ -361,8 +357,6 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
         if (c->pl.overlay)
             e = c->fp64 ? sa::launch_overlay_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
                         : sa::launch_overlay_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
-        else if (c->pl.split && mode == sa::kModePlain)
-            e = sa::launch_split_level_f32(c->prob.func, c->pl.table, c->a32, k, *groups, &g, s);
         else
             e = c->fp64 ? sa::launch_level_f64(c->prob.func, c->pl.table, mode, c->a64, k, *groups, &g, s)
                         : sa::launch_level_f32(c->prob.func, c->pl.table, mode, c->a32, k, *groups, &g, s);

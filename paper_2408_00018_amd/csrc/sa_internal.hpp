@@ -110,12 +110,6 @@ hipError_t launch_overlay_level_f64(int func, bool table, bool log, const LevelA
                                     uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 size_t overlay_lds_bytes(uint32_t n, uint32_t wg, uint32_t slots, size_t real_size, bool table);
 
-// FP32 plain levels with generator waves (256 chains and 512 threads per
-// workgroup); a.wg must be 256.
-hipError_t launch_split_level_f32(int func, bool table, const LevelArgs<float> &a, uint32_t level,
-                                  uint32_t prev_groups, uint32_t *groups, hipStream_t s);
-size_t split_lds_bytes(uint32_t n, bool table);
-
 }  // namespace sa
 
 namespace sa {

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
-FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY, FLAG_GENERATOR_WAVES = 0x1, 0x2, 0x4, 0x8, 0x10
+FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8
 EXCHANGE_NEVER = 0xFFFFFFFF
 
 SA_OK = 0
@@ -128,7 +128,6 @@ class Schedule:
     graph: bool = False
     learned: bool = False  # reserve room for a learned proposal (sa_set_proposal)
     overlay: bool = False  # force the base-plus-overlay state layout
-    generator_waves: bool = False  # FP32 plain levels: draws computed ahead by separate waves
     log_chains: int = 0
     log_level: int = 0
     log_levels: int = 0
@@ -138,8 +137,7 @@ class Schedule:
 
     def to_c(self) -> Config:
         flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
-                 (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0) |
-                 (FLAG_GENERATOR_WAVES if self.generator_waves else 0))
+                 (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
                       self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels,
                       EXCHANGE_NEVER if self.exchange == 0 else self.exchange)

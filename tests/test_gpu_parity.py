@@ -277,33 +277,3 @@ def test_fp32_unshifted_kernel_is_bitwise_identical(S, func, n, steps, move):
     assert np.array_equal(folded["rec"][keys], general["rec"][keys])
     assert np.array_equal(folded["xb"], general["xb"])
     assert np.array_equal(folded["x_rec"], general["x_rec"])
-
-
-@pytest.mark.parametrize("case", ["schwefel_n100", "rastrigin_n64_shift", "ackley_n37_uneven", "resample_n9",
-                                  "schwefel_n20_tail3"])
-def test_fp32_generator_waves_are_bitwise_identical(S, case):
-    """FP32 plain levels with generator waves (draws computed ahead by separate
-    waves) and without them give the same bits: winners, counts, costs and
-    broadcast states."""
-    if case == "schwefel_n100":
-        wl = W.schwefel_n100_fp32().with_(chains=4096, levels=8)
-        kw = {}
-    elif case == "rastrigin_n64_shift":
-        wl = W.random_problem(W.RASTRIGIN, 64, seed=21).with_(chains=1024, levels=6, steps=37)
-        kw = {}
-    elif case == "ackley_n37_uneven":
-        lo, hi = W.uneven_box(37, 9)
-        wl = W.random_problem(W.ACKLEY, 37, seed=22, shifted=False).with_(lower=lo, upper=hi, chains=768, levels=5,
-                                                                          steps=50)
-        kw = {}
-    elif case == "resample_n9":
-        wl = W.random_problem(W.SCHWEFEL, 9, seed=23).with_(chains=512, levels=6, steps=30)
-        kw = dict(move=S.MOVE_RESAMPLE)
-    else:
-        wl = W.random_problem(W.SCHWEFEL, 20, seed=24, shifted=False).with_(chains=512, levels=4, steps=31)
-        kw = {}
-    split = run_gpu(S, wl, generator_waves=True, **kw)
-    single = run_gpu(S, wl, **kw)
-    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
-    assert np.array_equal(split["rec"][keys], single["rec"][keys])
-    assert np.array_equal(split["xb"], single["xb"])

@@ -28,8 +28,9 @@ SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 FP32, FP64 = 0, 1
 
 # Closed-form minimum of the normalized Schwefel function (Sec. 4.1): the
-# paper prints x_i* = 420.968746 and f* = -418.982887; the digits below solve
-# d/dx [x sin(sqrt x)] = 0 in FP64 (see tests/golden/schwefel_minimum.txt).
+# paper prints x_i* = 420.968746 and f* = -418.982887 (tests/golden/paper_values.txt);
+# the digits below solve d/dx [x sin(sqrt x)] = 0 in FP64 (a root finder on the
+# derivative; the oracle tests pin both against the printed values).
 SCHWEFEL_X_STAR = 420.968746359982
 SCHWEFEL_F_STAR = -418.9828872724337
 
