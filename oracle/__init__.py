@@ -108,6 +108,17 @@ def lib():
         L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
                                          _p, _d, _p, ctypes.c_uint64, _p]
         L.orc_sa_run_capture.restype = _i
+        L.orc_mlp_forward_device.argtypes = [_p, _p, _p, _p, _p]
+        L.orc_mlp_forward_device.restype = None
+        L.orc_learned_propose.argtypes = [_p, _i, _u64, _u32, _u32, _u32, _u32, _u32, _p, _p, _p, _d, _d, _d, _p,
+                                          _p, _p]
+        L.orc_learned_propose.restype = None
+        L.orc_learned_accept.argtypes = [_p, _i, _i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _u32, _d, _d, _i, _p,
+                                         _u32, _d, _d, _d, _p, _p]
+        L.orc_learned_accept.restype = _i
+        L.orc_learned_run.argtypes = [_p, _i, _i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _u32, _u32, _d, _d, _d,
+                                      _d, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_learned_run.restype = _i
         _lib = L
     return _lib
 
@@ -371,3 +382,75 @@ def sa_run_capture(func, lower, upper, shift=None, *, seed, chains, steps, T0, a
     if rc != 0:
         raise RuntimeError(f"orc_sa_run_capture failed: {rc}")
     return rec[:min(cnt.value, capacity)], cnt.value
+
+
+# ---------------------------------------------------------------------------
+# Learned-proposal mixture move (oracle side; an extension of the method)
+# ---------------------------------------------------------------------------
+NET_FP64, NET_DEVICE = 0, 1
+
+
+def mlp_forward_device(params, z, ez=None):
+    """(mu, s) of the network under the device's stated precision (BF16 weight
+    matrices -- already rounded in params --, BF16 hidden activations, features
+    as BF16 high part plus remainder, FP32 accumulation) carried out in FP64,
+    and a bound on the deviation of any FP32 accumulation order (plus feature
+    errors ez)."""
+    p = _f64(params)
+    zz = _f64(z)
+    e = None if ez is None else _f64(ez)
+    out = np.zeros(2)
+    bound = np.zeros(2)
+    lib().orc_mlp_forward_device(_ptr(p), _ptr(zz), _ptr(e), _ptr(out), _ptr(bound))
+    return out, bound
+
+
+def learned_propose(params, mode, *, seed, problem=0, level, chain, step, x, lower, upper, radius_frac=0.1, featT,
+                    eps, hist):
+    """Proposal of one learned-mixture move from state x with history hist (the
+    chain's last four accepted scaled displacements, most recent first)."""
+    p, xx, lo, hi = _f64(params), _f64(x), _f64(lower), _f64(upper)
+    h = _f64(hist)
+    ou = np.zeros(2, dtype=np.uint32)
+    od = np.zeros(7)
+    lib().orc_learned_propose(_ptr(p), mode, seed, problem, level, chain, step, xx.size, _ptr(xx), _ptr(lo), _ptr(hi),
+                              radius_frac, featT, eps, _ptr(h), _ptr(ou), _ptr(od))
+    return dict(d=int(ou[0]), plain=bool(ou[1]), x_old=od[0], x_new=od[1], mu=od[2], s=od[3], t=od[4], b_mu=od[5],
+                b_s=od[6])
+
+
+def learned_accept(params, mode, func, *, lower, upper, shift=None, seed, problem=0, level, chain, step, T, featT,
+                   plain, x, d, x_new, mu, s, hist):
+    """Metropolis-Hastings decision on the proposal x_new for coordinate d of
+    the state x (network at x: mu, s).  Returns (taken, details)."""
+    p, xx, lo, hi, sh = _f64(params), _f64(x), _f64(lower), _f64(upper), _f64(shift)
+    h = _f64(hist)
+    out = np.zeros(8)
+    take = lib().orc_learned_accept(_ptr(p), mode, func, xx.size, _ptr(lo), _ptr(hi), _ptr(sh), seed, problem, level,
+                                    chain, step, T, featT, int(plain), _ptr(xx), d, x_new, mu, s, _ptr(h), _ptr(out))
+    return bool(take), dict(df=out[0], lq=out[1], log_ratio=out[2], u2=out[3], mu2=out[4], s2=out[5], b_mu2=out[6],
+                            b_s2=out[7])
+
+
+def learned_run(params, mode, func, lower, upper, shift=None, *, seed, problem=0, level, chain0=0, nchains, steps,
+                T, featT, eps, radius_frac=0.1, x_start, log=False, trace0=False):
+    """One learned-mixture level for chains [chain0, chain0 + nchains) from
+    x_start (empty history), in the oracle.  Returns a dict with final states,
+    costs, accepted counts, and optionally the per-move log and x[0] path."""
+    p, lo, hi, sh, xs = _f64(params), _f64(lower), _f64(upper), _f64(shift), _f64(x_start)
+    n = lo.size
+    m = nchains * steps
+    out = dict(x_final=np.zeros((nchains, n)), f_final=np.zeros(nchains), accepts=np.zeros(nchains, dtype=np.uint64))
+    if log:
+        out.update(d=np.zeros(m, dtype=np.uint32), plain=np.zeros(m, dtype=np.uint8), x_old=np.zeros(m),
+                   x_new=np.zeros(m), df=np.zeros(m), accept=np.zeros(m, dtype=np.uint8))
+    if trace0:
+        out["trace0"] = np.zeros(m)
+    g = out.get
+    rc = lib().orc_learned_run(_ptr(p), mode, func, n, _ptr(lo), _ptr(hi), _ptr(sh), seed, problem, level, chain0,
+                               nchains, steps, T, featT, eps, radius_frac, _ptr(xs), _ptr(g("d")), _ptr(g("plain")),
+                               _ptr(g("x_old")), _ptr(g("x_new")), _ptr(g("df")), _ptr(g("accept")),
+                               _ptr(out["x_final"]), _ptr(out["f_final"]), _ptr(out["accepts"]), _ptr(g("trace0")))
+    if rc != 0:
+        raise RuntimeError(f"orc_learned_run failed: {rc}")
+    return out

@@ -705,3 +705,317 @@ double orc_proposal_logpdf(double delta, double mu, double s)
     const double r = (delta - mu) * exp(-s);
     return -s - ORC_LN_PI - log(1.0 + r * r);
 }
+
+/* ------------------------------------------------------------------------ */
+/* The network under the device's stated precision: weight matrices in BF16  */
+/* (the caller passes them already rounded), features represented as a BF16 */
+/* high part plus a BF16 remainder, hidden activations rounded to BF16       */
+/* (round to nearest even, after the FP32 accumulator) before each product,  */
+/* biases and accumulation in FP32.  The values below are that arithmetic    */
+/* carried out in FP64, with a bound on how far an FP32 accumulation in any  */
+/* order (and feature errors up to ez[i]) can move the outputs: an           */
+/* activation whose pre-activation interval rounds to one BF16 value is      */
+/* exact; one whose interval straddles a rounding boundary may land on       */
+/* either neighbour.  Rounding to BF16 decides values the way a quantised     */
+/* code does, so both sides take that decision in the same precision.       */
+/* ------------------------------------------------------------------------ */
+static float bf16_round(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7F800000u) == 0x7F800000u) return f;
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
+/* BF16 value of relu(a) for the FP32 accumulator holding a. */
+static double bf16_relu(double a) { return a > 0.0 ? (double)bf16_round((float)a) : 0.0; }
+
+/* Largest |v - value| over FP32 accumulators v within [a - e, a + e], for
+ * the BF16 activation value = bf16_relu(a). */
+static double bf16_relu_err(double a, double e)
+{
+    const double v = bf16_relu(a), lo = bf16_relu(a - e), hi = bf16_relu(a + e);
+    if (lo == v && hi == v) return 0.0;
+    return fmax(fabs(hi - v), fabs(v - lo));
+}
+
+/* FP32 accumulation of k terms in any order: |error| <= gamma_k * sum |terms|,
+ * gamma_k = k u / (1 - k u), u = 2^-24; doubled for the MFMA's internal
+ * summation order. */
+static double acc_bound(int k, double sum_abs)
+{
+    const double ku = (double)k * ldexp(1.0, -24);
+    return 2.0 * ku / (1.0 - ku) * sum_abs;
+}
+
+void orc_mlp_forward_device(const double *params, const double *z, const double *ez, double *out2, double *bound2)
+{
+    orc_mlp m = mlp_view(params);
+    double zin[ORC_NIN], ezin[ORC_NIN];
+    for (int i = 0; i < ORC_NIN; ++i) {
+        const float zf = (float)z[i];
+        const float hi = bf16_round(zf);
+        const float lo = bf16_round(zf - hi);
+        zin[i] = (double)hi + (double)lo;
+        /* split of the FP32 feature, plus the feature's own error and the
+         * FP32 rounding of z */
+        ezin[i] = fabs((double)zf - zin[i]) + ldexp(fabs(z[i]), -18) + (ez ? ez[i] : 0.0) +
+                  ldexp(fabs(z[i]), -24);
+    }
+    double h1[ORC_H], e1[ORC_H], h2[ORC_H], e2[ORC_H];
+    for (int j = 0; j < ORC_H; ++j) {
+        const double b = (double)(float)m.b1[j];
+        double a = b, sa = fabs(b), prop = 0.0;
+        int k = 1; /* terms the accumulator adds (a zero product adds exactly nothing) */
+        for (int i = 0; i < ORC_NIN; ++i) {
+            const double t = zin[i] * m.W1[i * ORC_H + j];
+            a += t;
+            sa += 2.0 * fabs(t);
+            prop += fabs(m.W1[i * ORC_H + j]) * ezin[i];
+            k += t != 0.0 ? 2 : 0;
+        }
+        const double e = prop + acc_bound(k, sa);
+        h1[j] = bf16_relu(a);
+        e1[j] = bf16_relu_err(a, e);
+    }
+    for (int j = 0; j < ORC_H; ++j) {
+        const double b = (double)(float)m.b2[j];
+        double a = b, sa = fabs(b), prop = 0.0;
+        int k = 1;
+        for (int i = 0; i < ORC_H; ++i) {
+            const double t = h1[i] * m.W2[i * ORC_H + j];
+            a += t;
+            sa += fabs(t);
+            prop += fabs(m.W2[i * ORC_H + j]) * e1[i];
+            k += (t != 0.0 || (e1[i] != 0.0 && m.W2[i * ORC_H + j] != 0.0)) ? 1 : 0;
+        }
+        /* activations that may differ enlarge the accumulated magnitudes too */
+        const double e = prop + acc_bound(k, sa + prop);
+        h2[j] = bf16_relu(a);
+        e2[j] = bf16_relu_err(a, e);
+    }
+    for (int k = 0; k < 2; ++k) {
+        const double b = (double)(float)m.b3[k];
+        double a = b, sa = fabs(b), prop = 0.0;
+        int terms = 1;
+        for (int i = 0; i < ORC_H; ++i) {
+            const double t = h2[i] * m.W3[i * 2 + k];
+            a += t;
+            sa += fabs(t);
+            prop += fabs(m.W3[i * 2 + k]) * e2[i];
+            terms += (t != 0.0 || (e2[i] != 0.0 && m.W3[i * 2 + k] != 0.0)) ? 1 : 0;
+        }
+        out2[k] = a;
+        if (bound2) bound2[k] = prop + acc_bound(terms, sa + prop);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The learned-proposal mixture move (an extension of the method, not in the */
+/* paper; Metropolis-Hastings form of the acceptance of Sec. 2.1, eq. (5)).  */
+/* Per move, with the move's plain words (coordinate, change, acceptance)    */
+/* and the learned block of the move:                                        */
+/*   - the coordinate d from the plain stream;                               */
+/*   - with probability eps (U1 of the learned block < eps): the plain radius */
+/*     move and the plain Metropolis test;                                   */
+/*   - otherwise the network at the features of x_d gives (mu, s); the      */
+/*     scaled displacement is dl = mu + e^s t with t the standard Cauchy draw */
+/*     by inversion of U0; x'_d = x_d + dl (u_d - l_d); a proposal outside   */
+/*     [l_d, u_d] is rejected (no clamp, which would change the proposal     */
+/*     density); otherwise the network is evaluated again at x'_d with the   */
+/*     same history and the move is taken iff                               */
+/*        U2 < exp(-df/T + ln q(x | x') - ln q(x' | x)),                    */
+/*     q the Cauchy densities, U2 the plain acceptance uniform;              */
+/*   - an accepted move (either component) pushes its scaled displacement    */
+/*     onto the chain's history of the last four (most recent first).        */
+/* With the history features the proposal depends on the chain's past, so    */
+/* the chain is adaptive: exp(-f/T) is left exactly invariant for a fixed    */
+/* history (a network that ignores the history features), and approximately */
+/* otherwise.                                                                */
+/* mode 0 evaluates the network in FP64 (its definition); mode 1 under the   */
+/* device's stated precision (orc_mlp_forward_device), with bounds.          */
+/* ------------------------------------------------------------------------ */
+static void learned_features(double xd, double lo, double hi, double featT, const double hist[4], double z[ORC_NIN])
+{
+    z[0] = (xd - lo) / (hi - lo);
+    z[1] = featT;
+    for (int k = 0; k < 4; ++k) z[2 + k] = orc_hist_feature(hist[k]);
+}
+
+/* Feature error the device's FP32 evaluation of the features may add. */
+static void feature_errors(const double z[ORC_NIN], double ez[ORC_NIN])
+{
+    for (int i = 0; i < ORC_NIN; ++i) ez[i] = i == 1 ? 0.0 : ldexp(fabs(z[i]), -21) + ldexp(1.0, -22);
+}
+
+static void net_eval(const double *params, int mode, const double z[ORC_NIN], double out[2], double bound[2])
+{
+    if (mode == 1) {
+        double ez[ORC_NIN];
+        feature_errors(z, ez);
+        orc_mlp_forward_device(params, z, ez, out, bound);
+    } else {
+        orc_mlp_forward(params, z, out, NULL, NULL);
+        bound[0] = bound[1] = 0.0;
+    }
+}
+
+/*
+ * Proposal of move `step` of one chain from state x with history hist.
+ * out_u[0] = d, out_u[1] = 1 if the plain component was chosen;
+ * out_d[0] = x_d, out_d[1] = proposed x'_d (plain: clamped; learned: as
+ * drawn, possibly outside the box), out_d[2..3] = mu, s of the network at
+ * x_d (learned), out_d[4] = t, out_d[5..6] = bounds on mu, s (mode 1).
+ */
+void orc_learned_propose(const double *params, int mode, uint64_t seed, uint32_t problem, uint32_t level,
+                         uint32_t chain, uint32_t step, uint32_t n, const double *x, const double *lower,
+                         const double *upper, double radius_frac, double featT, double eps, const double hist[4],
+                         uint32_t *out_u, double *out_d)
+{
+    uint32_t d;
+    double u1, u2;
+    orc_move_draw(seed, problem, level, chain, step, n, &d, &u1, &u2);
+    const int plain = orc_learn_mix(seed, problem, level, chain, step) < eps;
+    const double xd = x[d], lo = lower[d], hi = upper[d];
+    out_u[0] = d;
+    out_u[1] = (uint32_t)plain;
+    out_d[0] = xd;
+    for (int k = 2; k < 7; ++k) out_d[k] = 0.0;
+    if (plain) {
+        out_d[1] = orc_neighbour(ORC_MOVE_RADIUS, xd, lo, hi, radius_frac, u1);
+        return;
+    }
+    double z[ORC_NIN], o[2], b[2];
+    learned_features(xd, lo, hi, featT, hist, z);
+    net_eval(params, mode, z, o, b);
+    const double t = orc_learn_draw(seed, problem, level, chain, step);
+    const double dl = o[0] + exp(o[1]) * t;
+    out_d[1] = xd + dl * (hi - lo);
+    out_d[2] = o[0];
+    out_d[3] = o[1];
+    out_d[4] = t;
+    out_d[5] = b[0];
+    out_d[6] = b[1];
+}
+
+/* Decision on the proposal x_new for coordinate d, given the chain's cost
+ * state c at x.  out[0] = df (0 for an outside learned proposal),
+ * out[1] = ln q(x | x') - ln q(x' | x) (learned, inside), out[2] = the log
+ * acceptance ratio -df/T + out[1], out[3] = U2, out[4..5] = mu', s' of the
+ * network at x'_d, out[6..7] = their bounds (mode 1).  *cn gets the cost
+ * state after the move.  Returns 1 if the move is taken. */
+static int learned_decide(const double *params, int mode, int func, uint32_t n, const double *lower,
+                          const double *upper, const double *shift, uint64_t seed, uint32_t problem, uint32_t level,
+                          uint32_t chain, uint32_t step, double T, double featT, int plain, const double *x,
+                          const orc_cost *c, uint32_t d, double x_new, double mu, double s, const double hist[4],
+                          double *out, orc_cost *cn)
+{
+    uint32_t dd;
+    double u1, u2;
+    orc_move_draw(seed, problem, level, chain, step, n, &dd, &u1, &u2);
+    const double xd = x[d], lo = lower[d], hi = upper[d], sd = shift ? shift[d] : 0.0;
+    for (int k = 0; k < 8; ++k) out[k] = 0.0;
+    out[3] = u2;
+    if (plain) {
+        const double df = cost_delta(func, n, c, xd, x_new, sd, cn);
+        out[0] = df;
+        out[2] = -df / T;
+        return orc_accept(df, T, u2);
+    }
+    if (!(x_new >= lo && x_new <= hi)) {
+        *cn = *c;
+        return 0;
+    }
+    const double df = cost_delta(func, n, c, xd, x_new, sd, cn);
+    double z[ORC_NIN], o[2], b[2];
+    learned_features(x_new, lo, hi, featT, hist, z);
+    net_eval(params, mode, z, o, b);
+    const double dl = (x_new - xd) / (hi - lo);
+    const double lq = orc_proposal_logpdf(-dl, o[0], o[1]) - orc_proposal_logpdf(dl, mu, s);
+    out[0] = df;
+    out[1] = lq;
+    out[2] = -df / T + lq;
+    out[4] = o[0];
+    out[5] = o[1];
+    out[6] = b[0];
+    out[7] = b[1];
+    return u2 < exp(out[2]);
+}
+
+/* The decision of learned_decide for a chain at state x (its cost evaluated
+ * in full), for checking a given proposal; returns 1 if taken. */
+int orc_learned_accept(const double *params, int mode, int func, uint32_t n, const double *lower, const double *upper,
+                       const double *shift, uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain,
+                       uint32_t step, double T, double featT, int plain, const double *x, uint32_t d, double x_new,
+                       double mu, double s, const double hist[4], double *out)
+{
+    orc_cost c, cn;
+    cost_full(func, n, x, shift, &c);
+    return learned_decide(params, mode, func, n, lower, upper, shift, seed, problem, level, chain, step, T, featT,
+                          plain, x, &c, d, x_new, mu, s, hist, out, &cn);
+}
+
+/*
+ * One level of the learned mixture for chains [chain0, chain0 + nchains),
+ * each starting from x_start with its cost evaluated in full and an empty
+ * history, `steps` moves at temperature T (ln(tau T) = featT).  Per move m =
+ * (chain - chain0) * steps + step, optional logs: coordinate, plain flag,
+ * x_d, proposal, df, accept.  x_final (nchains x n), f_final (nchains) and
+ * accepts (nchains) optional; trace0 (nchains x steps) gets x[0] after every
+ * move (a one-coordinate chain's path).  With eps = 1 every move is the
+ * plain move, in the same arithmetic as orc_replay_level.
+ */
+int orc_learned_run(const double *params, int mode, int func, uint32_t n, const double *lower, const double *upper,
+                    const double *shift, uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain0,
+                    uint32_t nchains, uint32_t steps, double T, double featT, double eps, double radius_frac,
+                    const double *x_start, uint32_t *log_d, uint8_t *log_plain, double *log_xold, double *log_xnew,
+                    double *log_df, uint8_t *log_acc, double *x_final, double *f_final, uint64_t *accepts,
+                    double *trace0)
+{
+    double *x = (double *)malloc(sizeof(double) * n);
+    if (!x) return -2;
+    for (uint32_t j = 0; j < nchains; ++j) {
+        const uint32_t ch = chain0 + j;
+        memcpy(x, x_start, sizeof(double) * n);
+        orc_cost c;
+        cost_full(func, n, x, shift, &c);
+        double hist[4] = {0.0, 0.0, 0.0, 0.0};
+        uint64_t acc = 0;
+        for (uint32_t step = 0; step < steps; ++step) {
+            uint32_t pu[2];
+            double pd[7], dd[8];
+            orc_learned_propose(params, mode, seed, problem, level, ch, step, n, x, lower, upper, radius_frac, featT,
+                                eps, hist, pu, pd);
+            const uint32_t d = pu[0];
+            orc_cost cn;
+            const int take = learned_decide(params, mode, func, n, lower, upper, shift, seed, problem, level, ch, step,
+                                            T, featT, (int)pu[1], x, &c, d, pd[1], pd[2], pd[3], hist, dd, &cn);
+            const size_t m = (size_t)j * steps + step;
+            if (log_d) log_d[m] = d;
+            if (log_plain) log_plain[m] = (uint8_t)pu[1];
+            if (log_xold) log_xold[m] = x[d];
+            if (log_xnew) log_xnew[m] = pd[1];
+            if (log_df) log_df[m] = dd[0];
+            if (log_acc) log_acc[m] = (uint8_t)take;
+            if (take) {
+                const double dl = (pd[1] - x[d]) / (upper[d] - lower[d]);
+                hist[3] = hist[2];
+                hist[2] = hist[1];
+                hist[1] = hist[0];
+                hist[0] = dl;
+                x[d] = pd[1];
+                c = cn;
+                ++acc;
+            }
+            if (trace0) trace0[m] = x[0];
+        }
+        if (x_final) memcpy(x_final + (size_t)j * n, x, sizeof(double) * n);
+        if (f_final) f_final[j] = c.f;
+        if (accepts) accepts[j] = acc;
+    }
+    free(x);
+    return 0;
+}
