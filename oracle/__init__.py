@@ -24,6 +24,7 @@ _SRC = os.path.join(_HERE, "sa_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 
 CFLAGS = ["-O2", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off", "-std=c11"]

@@ -55,6 +55,9 @@
 #define ORC_SCHWEFEL 0
 #define ORC_RASTRIGIN 1
 #define ORC_ACKLEY 2
+#define ORC_GRIEWANK 3
+#define ORC_LEVY_MONTALVO 4
+#define ORC_ROSENBROCK 5
 
 #define ORC_TAG_MOVE 0u
 #define ORC_TAG_INIT 1u
@@ -163,9 +166,68 @@ double orc_ackley_from_sums(double s1, double s2, uint32_t n)
 
 static double shifted(const double *x, const double *s, uint32_t i) { return s ? x[i] - s[i] : x[i]; }
 
+/* Coordinate i of y = x - s, with coordinate d replaced by xdn when d < n. */
+static double y_at(const double *x, const double *s, uint32_t i, uint32_t d, double xdn)
+{
+    const double v = i == d ? xdn : x[i];
+    return s ? v - s[i] : v;
+}
+
+/*
+ * The non-separable families, evaluated in full (the paper's move evaluates
+ * f(x1) in full, Sec. 3.3).  Coordinate d may be replaced by xdn (d >= n:
+ * none).  Sums and products run over the coordinates in order 1..n.
+ *   Griewank (Appendix, Test 8): 1 + sum y_i^2 / 4000 - prod cos(y_i / sqrt(i)).
+ *     The printed form puts the product inside the sum; with it f(0) = 1 - n,
+ *     not the stated minimum 0, so the sum and the product are read as
+ *     separate terms (Griewank's own definition).
+ *   Levy and Montalvo (Appendix, Test 10), w_i = 1 + (y_i + 1) / 4:
+ *     (pi / n) [10 sin^2(pi w_1) + sum_{i<n} (w_i - 1)^2 (1 + 10 sin^2(pi w_{i+1}))
+ *     + (w_n - 1)^2].
+ *   Generalized Rosenbrock (Appendix, Test 14):
+ *     sum_{i<n} [100 (y_{i+1} - y_i^2)^2 + (1 - y_i)^2].  The printed form has
+ *     (y_{i+1} - y_i)^2; the named function (De Jong's second) squares y_i,
+ *     and both have the stated minimum 0 at (1, ..., 1).
+ */
+static double f_coupled(int func, uint32_t n, const double *x, const double *s, uint32_t d, double xdn)
+{
+    if (func == ORC_GRIEWANK) {
+        double sum = 0.0, prod = 1.0;
+        for (uint32_t i = 0; i < n; ++i) {
+            const double y = y_at(x, s, i, d, xdn);
+            sum += y * y / 4000.0;
+            prod *= cos(y / sqrt((double)(i + 1)));
+        }
+        return 1.0 + sum - prod;
+    }
+    if (func == ORC_LEVY_MONTALVO) {
+        double w0 = 1.0 + (y_at(x, s, 0, d, xdn) + 1.0) / 4.0;
+        const double sp = sin(ORC_PI * w0);
+        double acc = 10.0 * sp * sp;
+        for (uint32_t i = 0; i + 1 < n; ++i) {
+            const double w1 = 1.0 + (y_at(x, s, i + 1, d, xdn) + 1.0) / 4.0;
+            const double sn = sin(ORC_PI * w1);
+            acc += (w0 - 1.0) * (w0 - 1.0) * (1.0 + 10.0 * sn * sn);
+            w0 = w1;
+        }
+        acc += (w0 - 1.0) * (w0 - 1.0);
+        return ORC_PI / (double)n * acc;
+    }
+    if (func == ORC_ROSENBROCK) {
+        double acc = 0.0;
+        for (uint32_t i = 0; i + 1 < n; ++i) {
+            const double a = y_at(x, s, i, d, xdn), b = y_at(x, s, i + 1, d, xdn);
+            acc += 100.0 * (b - a * a) * (b - a * a) + (1.0 - a) * (1.0 - a);
+        }
+        return acc;
+    }
+    return NAN;
+}
+
 /* Full evaluation, summing the coordinates in order 0..n-1. */
 double orc_f(int func, uint32_t n, const double *x, const double *s)
 {
+    if (func >= ORC_GRIEWANK) return f_coupled(func, n, x, s, n, 0.0);
     if (func == ORC_SCHWEFEL) {
         double acc = 0.0;
         for (uint32_t i = 0; i < n; ++i) acc += orc_schwefel_term(shifted(x, s, i));
@@ -209,13 +271,19 @@ static void cost_full(int func, uint32_t n, const double *x, const double *s, or
     }
 }
 
-/* Cost increment of changing coordinate d from xd to xn, and the new cost
- * state.  Separable costs: only coordinate d's term is re-evaluated. */
-static double cost_delta(int func, uint32_t n, const orc_cost *c, double xd, double xn, double sd,
-                         orc_cost *out)
+/* Cost increment of changing coordinate d of x (shift s) to xn, and the new
+ * cost state.  Separable costs: only coordinate d's term is re-evaluated;
+ * the other families: f(x') evaluated in full. */
+static double cost_delta(int func, uint32_t n, const orc_cost *c, const double *x, const double *s, uint32_t d,
+                         double xn, orc_cost *out)
 {
-    double y = xd - sd, yn = xn - sd;
+    const double sd = s ? s[d] : 0.0;
+    double y = x[d] - sd, yn = xn - sd;
     *out = *c;
+    if (func >= ORC_GRIEWANK) {
+        out->f = f_coupled(func, n, x, s, d, xn);
+        return out->f - c->f;
+    }
     if (func == ORC_SCHWEFEL) {
         double df = -(orc_schwefel_term(yn) - orc_schwefel_term(y)) / (double)n;
         out->f = c->f + df;
@@ -321,8 +389,7 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
         double xd = x[d];
         double xn = orc_neighbour(p->move_rule, xd, p->lower[d], p->upper[d], p->radius_frac, u1);
         orc_cost cn;
-        double sd = p->shift ? p->shift[d] : 0.0;
-        double df = cost_delta(p->func, p->n, c, xd, xn, sd, &cn);
+        double df = cost_delta(p->func, p->n, c, x, p->shift, d, xn, &cn);
         if (orc_accept(df, T, u2)) {
             if (capture_sink.rec) capture_move(p, T, d, xd, xn, hist);
             x[d] = xn;
@@ -485,7 +552,7 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
             double xd = x[d];
             double xn = orc_neighbour(move_rule, xd, lower[d], upper[d], radius_frac, u1);
             orc_cost cn;
-            double df = cost_delta(func, n, &c, xd, xn, shift ? shift[d] : 0.0, &cn);
+            double df = cost_delta(func, n, &c, x, shift, d, xn, &cn);
             int a = orc_accept(df, T, u2);
             size_t m = (size_t)j * steps + step;
             if (log_d) log_d[m] = d;
@@ -916,11 +983,11 @@ static int learned_decide(const double *params, int mode, int func, uint32_t n, 
     uint32_t dd;
     double u1, u2;
     orc_move_draw(seed, problem, level, chain, step, n, &dd, &u1, &u2);
-    const double xd = x[d], lo = lower[d], hi = upper[d], sd = shift ? shift[d] : 0.0;
+    const double xd = x[d], lo = lower[d], hi = upper[d];
     for (int k = 0; k < 8; ++k) out[k] = 0.0;
     out[3] = u2;
     if (plain) {
-        const double df = cost_delta(func, n, c, xd, x_new, sd, cn);
+        const double df = cost_delta(func, n, c, x, shift, d, x_new, cn);
         out[0] = df;
         out[2] = -df / T;
         return orc_accept(df, T, u2);
@@ -929,7 +996,7 @@ static int learned_decide(const double *params, int mode, int func, uint32_t n, 
         *cn = *c;
         return 0;
     }
-    const double df = cost_delta(func, n, c, xd, x_new, sd, cn);
+    const double df = cost_delta(func, n, c, x, shift, d, x_new, cn);
     double z[ORC_NIN], o[2], b[2];
     learned_features(x_new, lo, hi, featT, hist, z);
     net_eval(params, mode, z, o, b);
