@@ -34,7 +34,7 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no GPU code involved)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm", "-lpthread"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -109,6 +109,10 @@ def lib():
         L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
                                          _p, _d, _p, ctypes.c_uint64, _p]
         L.orc_sa_run_capture.restype = _i
+        L.orc_nelder_mead.argtypes = [_i, _u32, _p, _p, _p, _p, _u32, _d, _d, _p, _p, _p, _p, _p]
+        L.orc_nelder_mead.restype = _i
+        L.orc_set_threads.argtypes = [_i]
+        L.orc_set_threads.restype = None
         L.orc_mlp_forward_device.argtypes = [_p, _p, _p, _p, _p]
         L.orc_mlp_forward_device.restype = None
         L.orc_learned_propose.argtypes = [_p, _i, _u64, _u32, _u32, _u32, _u32, _u32, _p, _p, _p, _d, _d, _d, _p,
@@ -193,6 +197,12 @@ def neighbour(move_rule, xd, lo, hi, radius_frac, u1):
 
 def temperature(T0, alpha, level):
     return lib().orc_temperature(T0, alpha, level)
+
+
+def set_threads(threads: int):
+    """Threads the oracle's multi-chain runs use for the chains of a level
+    (results are identical for every count)."""
+    lib().orc_set_threads(int(threads))
 
 
 def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
@@ -455,3 +465,25 @@ def learned_run(params, mode, func, lower, upper, shift=None, *, seed, problem=0
     if rc != 0:
         raise RuntimeError(f"orc_learned_run failed: {rc}")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Nelder-Mead polish (the paper's hybrid strategy)
+# ---------------------------------------------------------------------------
+NM_REFLECT, NM_EXPAND, NM_OUTSIDE, NM_INSIDE, NM_SHRINK = 0, 1, 2, 3, 4
+
+
+def nelder_mead(func, lower, upper, shift=None, *, x0, maxiter=10000, ftol=1e-12, xtol=1e-10):
+    """Box-projected Nelder-Mead from x0; returns dict(x, f, iters, evals, steps)."""
+    lo, hi, s, x = _f64(lower), _f64(upper), _f64(shift), _f64(x0)
+    n = lo.size
+    xo = np.zeros(n)
+    f = ctypes.c_double()
+    it = ctypes.c_uint32()
+    ev = ctypes.c_uint32()
+    log = np.zeros(maxiter, dtype=np.uint8)
+    rc = lib().orc_nelder_mead(func, n, _ptr(lo), _ptr(hi), _ptr(s), _ptr(x), maxiter, ftol, xtol, _ptr(xo),
+                               ctypes.byref(f), ctypes.byref(it), ctypes.byref(ev), _ptr(log))
+    if rc != 0:
+        raise RuntimeError(f"orc_nelder_mead failed: {rc}")
+    return dict(x=xo, f=f.value, iters=it.value, evals=ev.value, steps=log[:it.value].copy())

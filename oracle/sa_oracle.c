@@ -45,9 +45,10 @@
  * re-evaluated (the increment is mathematically f(x') - f(x)); for Ackley the
  * two sums under the exponentials are updated and f is re-formed from them.
  *
- * Build: gcc -O2 -shared -fPIC -fno-fast-math -ffp-contract=off -lm
+ * Build: gcc -O2 -shared -fPIC -fno-fast-math -ffp-contract=off -lm -lpthread
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -425,6 +426,74 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
  * x_rec/f_rec_io/rec_level_io carry the record in and out (f_rec_io = +inf
  * for a fresh run).  x_start is in/out: the last winner on return.
  */
+/* Threads orc_sa_run spreads a level's chains over (1 = the plain sequential
+ * loop).  Chains are independent within a level; the winner is reduced in
+ * chain order afterwards, so every thread count gives the same bits. */
+static int orc_threads = 1;
+
+void orc_set_threads(int threads) { orc_threads = threads < 1 ? 1 : threads; }
+
+/* One level's work on chains [ch0, ch1): each chain from its start, its
+ * final cost into final_f, and the chunk's candidate for the level winner
+ * (the first chain of lowest non-NaN final cost; none if every cost is NaN)
+ * with its state. */
+typedef struct {
+    const orc_problem *p;
+    uint32_t level, ch0, ch1, exchange;
+    int broadcast;
+    double T;
+    const double *x_start;
+    orc_cost start_cost;
+    double *chain_x, *chain_cost, *fin;
+    /* outputs */
+    uint64_t acc;
+    int has_best;
+    double best_f;
+    uint32_t best_chain;
+    double *bx, *x; /* n each, owned by the caller */
+    double *x0;     /* chain 0's final state (the chunk holding chain 0) */
+} level_chunk;
+
+static void *run_level_chunk(void *arg)
+{
+    level_chunk *w = (level_chunk *)arg;
+    const orc_problem *p = w->p;
+    const uint32_t n = p->n;
+    w->acc = 0;
+    w->has_best = 0;
+    for (uint32_t ch = w->ch0; ch < w->ch1; ++ch) {
+        orc_cost c;
+        if (w->level == 0) {
+            orc_init_point(p->seed, p->problem, ch, n, p->lower, p->upper, w->x);
+            cost_full(p->func, n, w->x, p->shift, &c);
+        } else if (w->broadcast) {
+            memcpy(w->x, w->x_start, sizeof(double) * n);
+            c = w->start_cost;
+        } else {
+            memcpy(w->x, w->chain_x + (size_t)ch * n, sizeof(double) * n);
+            c.f = w->chain_cost[3 * (size_t)ch];
+            c.s1 = w->chain_cost[3 * (size_t)ch + 1];
+            c.s2 = w->chain_cost[3 * (size_t)ch + 2];
+        }
+        w->acc += run_chain(p, w->level, ch, w->T, w->x, &c);
+        if (w->exchange != 1) {
+            memcpy(w->chain_x + (size_t)ch * n, w->x, sizeof(double) * n);
+            w->chain_cost[3 * (size_t)ch] = c.f;
+            w->chain_cost[3 * (size_t)ch + 1] = c.s1;
+            w->chain_cost[3 * (size_t)ch + 2] = c.s2;
+        }
+        w->fin[ch] = c.f;
+        if (ch == 0) memcpy(w->x0, w->x, sizeof(double) * n);
+        if (!isnan(c.f) && (!w->has_best || c.f < w->best_f)) {
+            w->has_best = 1;
+            w->best_f = c.f;
+            w->best_chain = ch;
+            memcpy(w->bx, w->x, sizeof(double) * n);
+        }
+    }
+    return NULL;
+}
+
 int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
                uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
                double radius_frac, int move_rule, uint32_t exchange, uint32_t level_begin, uint32_t count,
@@ -436,54 +505,76 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
     if (exchange != 1 && (!chain_x || !chain_cost)) return -1;
     if (exchange && level_begin > 0 && !x_start) return -1;
     orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
-    double *x = (double *)malloc(sizeof(double) * n);
-    double *bx = (double *)malloc(sizeof(double) * n);
-    if (!x || !bx) { free(x); free(bx); return -2; }
+    /* the capture sink appends in chain order: one thread while it is set */
+    uint32_t nt = capture_sink.rec ? 1u : (uint32_t)orc_threads;
+    if (nt > chains) nt = chains;
+    level_chunk *w = (level_chunk *)calloc(nt, sizeof(level_chunk));
+    pthread_t *tid = (pthread_t *)calloc(nt, sizeof(pthread_t));
+    double *bufs = (double *)malloc(sizeof(double) * n * (2 * (size_t)nt + 1));
+    double *fin = (double *)malloc(sizeof(double) * chains);
+    if (!w || !tid || !bufs || !fin) {
+        free(w); free(tid); free(bufs); free(fin);
+        return -2;
+    }
 
     for (uint32_t k = 0; k < count; ++k) {
         uint32_t level = level_begin + k;
         double T = orc_temperature(T0, alpha, level);
-        double best_f = INFINITY;
-        uint32_t best_chain = 0;
-        uint64_t acc_total = 0;
         const int broadcast = level > 0 && exchange > 0 && level % exchange == 0;
-        orc_cost start_cost;
+        orc_cost start_cost = {0.0, 0.0, 0.0};
         if (broadcast) cost_full(func, n, x_start, shift, &start_cost);
-        for (uint32_t ch = 0; ch < chains; ++ch) {
-            orc_cost c;
-            if (level == 0) {
-                orc_init_point(seed, problem, ch, n, lower, upper, x);
-                cost_full(func, n, x, shift, &c);
-            } else if (broadcast) {
-                memcpy(x, x_start, sizeof(double) * n);
-                c = start_cost;
-            } else {
-                memcpy(x, chain_x + (size_t)ch * n, sizeof(double) * n);
-                c.f = chain_cost[3 * (size_t)ch];
-                c.s1 = chain_cost[3 * (size_t)ch + 1];
-                c.s2 = chain_cost[3 * (size_t)ch + 2];
-            }
-            acc_total += run_chain(&p, level, ch, T, x, &c);
-            if (exchange != 1) {
-                memcpy(chain_x + (size_t)ch * n, x, sizeof(double) * n);
-                chain_cost[3 * (size_t)ch] = c.f;
-                chain_cost[3 * (size_t)ch + 1] = c.s1;
-                chain_cost[3 * (size_t)ch + 2] = c.s2;
-            }
-            if (final_f && k + 1 == count) final_f[ch] = c.f;
-            if (c.f < best_f || ch == 0) {
-                best_f = c.f;
-                best_chain = ch;
-                memcpy(bx, x, sizeof(double) * n);
+        for (uint32_t t = 0; t < nt; ++t) {
+            level_chunk *c = &w[t];
+            c->p = &p;
+            c->level = level;
+            c->ch0 = (uint32_t)((uint64_t)chains * t / nt);
+            c->ch1 = (uint32_t)((uint64_t)chains * (t + 1) / nt);
+            c->exchange = exchange;
+            c->broadcast = broadcast;
+            c->T = T;
+            c->x_start = x_start;
+            c->start_cost = start_cost;
+            c->chain_x = chain_x;
+            c->chain_cost = chain_cost;
+            c->fin = fin;
+            c->bx = bufs + (size_t)2 * n * t;
+            c->x = c->bx + n;
+            c->x0 = bufs + (size_t)2 * n * nt;
+        }
+        if (nt == 1) {
+            run_level_chunk(&w[0]);
+        } else {
+            uint32_t started = 0;
+            for (; started < nt; ++started)
+                if (pthread_create(&tid[started], NULL, run_level_chunk, &w[started]) != 0) break;
+            for (uint32_t t = started; t < nt; ++t) run_level_chunk(&w[t]); /* could not start: run here */
+            for (uint32_t t = 0; t < started; ++t) pthread_join(tid[t], NULL);
+        }
+        /* Winner in chain order: chain 0 if its cost is NaN (nothing compares
+         * below it), else the first chain of lowest cost; accepted moves summed. */
+        uint64_t acc_total = 0;
+        double best_f = fin[0];
+        uint32_t best_chain = 0;
+        const double *bx = NULL;
+        for (uint32_t t = 0; t < nt; ++t) acc_total += w[t].acc;
+        if (!isnan(fin[0])) {
+            for (uint32_t t = 0; t < nt; ++t) {
+                if (w[t].has_best && (bx == NULL || w[t].best_f < best_f)) {
+                    best_f = w[t].best_f;
+                    best_chain = w[t].best_chain;
+                    bx = w[t].bx;
+                }
             }
         }
+        if (!bx) bx = w[0].x0;
+        if (final_f && k + 1 == count) memcpy(final_f, fin, sizeof(double) * chains);
         double fresh = orc_f(func, n, bx, shift);
         if (fresh < *f_rec_io) {
             *f_rec_io = fresh;
             *rec_level_io = level;
             memcpy(x_rec, bx, sizeof(double) * n);
         }
-        if (x_start) memcpy(x_start, bx, sizeof(double) * n);
+        if (x_start) memmove(x_start, bx, sizeof(double) * n);
         if (win_chain) win_chain[k] = best_chain;
         if (f_win) f_win[k] = best_f;
         if (f_best) f_best[k] = fresh;
@@ -491,8 +582,10 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
         if (x_best) memcpy(x_best + (size_t)k * n, bx, sizeof(double) * n);
         if (accepts) accepts[k] = acc_total;
     }
-    free(x);
-    free(bx);
+    free(w);
+    free(tid);
+    free(bufs);
+    free(fin);
     return 0;
 }
 
@@ -1084,5 +1177,156 @@ int orc_learned_run(const double *params, int mode, int func, uint32_t n, const 
         if (accepts) accepts[j] = acc;
     }
     free(x);
+    return 0;
+}
+
+/* ======================================================================== */
+/* Nelder-Mead polish of an annealing result (the paper's hybrid strategy:   */
+/* a local minimizer started where the annealing stopped, Sec. 4.2 and its   */
+/* hybrid results table).  The paper names the method, not its details; the */
+/* steps below are the standard simplex method with the coefficients of     */
+/* Lagarias, Reeds, Wright and Wright (SIAM J. Optim. 9, 1998): reflection   */
+/* 1, expansion 2, contraction 1/2, shrink 1/2.                              */
+/*   Vertices live in slots 0..n.  Per iteration: b = lowest f (ties: lowest */
+/*   slot), w = highest f among the other slots (ties: lowest slot), s =     */
+/*   highest f among slots other than w (ties: lowest slot); stop when       */
+/*   f[w] - f[b] <= ftol and every vertex is within xtol of x_b in every     */
+/*   coordinate, or after maxiter iterations.  xm = mean of the slots other  */
+/*   than w; xr = xm + (xm - x_w).                                          */
+/*   - f[b] <= fr < f[s]: take xr (reflect);                                */
+/*   - fr < f[b]: xe = xm + 2 (xm - x_w); take xe if fe < fr, else xr        */
+/*     (expand);                                                            */
+/*   - f[s] <= fr < f[w]: xc = xm + (xr - xm)/2; take xc if fc <= fr         */
+/*     (outside contraction), else shrink;                                  */
+/*   - fr >= f[w]: xc = xm - (xm - x_w)/2; take xc if fc < f[w] (inside     */
+/*     contraction), else shrink;                                           */
+/*   - shrink: every slot v other than b becomes x_b + (v - x_b)/2.         */
+/*   A taken point replaces slot w.  The problem is box-constrained and the  */
+/*   method is not: every trial point is projected onto the box (clamped)    */
+/*   before it is evaluated, and the projected point is the one taken.       */
+/*   Start: slot 0 = x0, slot i = x0 + h_i e_i, h_i = x0_i / 20 (0.00025 if   */
+/*   x0_i = 0), reflected to x0 - h_i e_i when x0 + h_i e_i leaves the box.  */
+/* Step codes logged per iteration: 0 reflect, 1 expand, 2 outside          */
+/* contraction, 3 inside contraction, 4 shrink.                              */
+/* ======================================================================== */
+static void nm_point(uint32_t n, const double *lower, const double *upper, const double *xm, const double *xw,
+                     double t, double *out)
+{
+    /* out = xm + t (xm - xw), projected onto the box */
+    for (uint32_t j = 0; j < n; ++j) {
+        double v = xm[j] + t * (xm[j] - xw[j]);
+        if (v > upper[j]) v = upper[j];
+        if (v < lower[j]) v = lower[j];
+        out[j] = v;
+    }
+}
+
+int orc_nelder_mead(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+                    const double *x0, uint32_t maxiter, double ftol, double xtol, double *x_out, double *f_out,
+                    uint32_t *iters_out, uint32_t *evals_out, uint8_t *step_log)
+{
+    const uint32_t m = n + 1;
+    double *V = (double *)malloc(sizeof(double) * (size_t)m * n);
+    double *F = (double *)malloc(sizeof(double) * m);
+    double *xm = (double *)malloc(sizeof(double) * n);
+    double *xr = (double *)malloc(sizeof(double) * n);
+    double *xt = (double *)malloc(sizeof(double) * n);
+    if (!V || !F || !xm || !xr || !xt) {
+        free(V); free(F); free(xm); free(xr); free(xt);
+        return -2;
+    }
+    uint32_t evals = 0;
+    for (uint32_t i = 0; i < m; ++i) {
+        double *v = V + (size_t)i * n;
+        memcpy(v, x0, sizeof(double) * n);
+        if (i > 0) {
+            const uint32_t j = i - 1;
+            const double h = x0[j] != 0.0 ? x0[j] / 20.0 : 0.00025;
+            v[j] = x0[j] + h;
+            if (v[j] > upper[j] || v[j] < lower[j]) v[j] = x0[j] - h;
+            if (v[j] > upper[j]) v[j] = upper[j];
+            if (v[j] < lower[j]) v[j] = lower[j];
+        }
+        F[i] = orc_f(func, n, v, shift);
+        ++evals;
+    }
+    uint32_t it = 0;
+    for (; it < maxiter; ++it) {
+        uint32_t b = 0;
+        for (uint32_t i = 1; i < m; ++i)
+            if (F[i] < F[b]) b = i;
+        uint32_t w = b == 0 ? 1 : 0;
+        for (uint32_t i = 0; i < m; ++i)
+            if (i != b && F[i] > F[w]) w = i;
+        uint32_t s = w == 0 ? 1 : 0;
+        for (uint32_t i = 0; i < m; ++i)
+            if (i != w && F[i] > F[s]) s = i;
+        /* convergence */
+        double spread = 0.0;
+        const double *xb = V + (size_t)b * n;
+        for (uint32_t i = 0; i < m; ++i)
+            for (uint32_t j = 0; j < n; ++j) spread = fmax(spread, fabs(V[(size_t)i * n + j] - xb[j]));
+        if (F[w] - F[b] <= ftol && spread <= xtol) break;
+        /* centroid of every slot but w */
+        for (uint32_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (uint32_t i = 0; i < m; ++i)
+                if (i != w) acc += V[(size_t)i * n + j];
+            xm[j] = acc / (double)n;
+        }
+        const double *xw = V + (size_t)w * n;
+        nm_point(n, lower, upper, xm, xw, 1.0, xr);
+        const double fr = orc_f(func, n, xr, shift);
+        ++evals;
+        int code;
+        const double *take = NULL;
+        double ftake = 0.0;
+        if (fr < F[b]) {
+            nm_point(n, lower, upper, xm, xw, 2.0, xt);
+            const double fe = orc_f(func, n, xt, shift);
+            ++evals;
+            code = 1;
+            if (fe < fr) { take = xt; ftake = fe; }
+            else { take = xr; ftake = fr; }
+        } else if (fr < F[s]) {
+            code = 0;
+            take = xr;
+            ftake = fr;
+        } else if (fr < F[w]) {
+            nm_point(n, lower, upper, xm, xw, 0.5, xt);
+            const double fc = orc_f(func, n, xt, shift);
+            ++evals;
+            code = 2;
+            if (fc <= fr) { take = xt; ftake = fc; }
+        } else {
+            nm_point(n, lower, upper, xm, xw, -0.5, xt);
+            const double fc = orc_f(func, n, xt, shift);
+            ++evals;
+            code = 3;
+            if (fc < F[w]) { take = xt; ftake = fc; }
+        }
+        if (take) {
+            memcpy(V + (size_t)w * n, take, sizeof(double) * n);
+            F[w] = ftake;
+        } else {
+            code = 4;
+            for (uint32_t i = 0; i < m; ++i) {
+                if (i == b) continue;
+                double *v = V + (size_t)i * n;
+                for (uint32_t j = 0; j < n; ++j) v[j] = xb[j] + 0.5 * (v[j] - xb[j]);
+                F[i] = orc_f(func, n, v, shift);
+                ++evals;
+            }
+        }
+        if (step_log) step_log[it] = (uint8_t)code;
+    }
+    uint32_t b = 0;
+    for (uint32_t i = 1; i < m; ++i)
+        if (F[i] < F[b]) b = i;
+    memcpy(x_out, V + (size_t)b * n, sizeof(double) * n);
+    *f_out = F[b];
+    if (iters_out) *iters_out = it;
+    if (evals_out) *evals_out = evals;
+    free(V); free(F); free(xm); free(xr); free(xt);
     return 0;
 }

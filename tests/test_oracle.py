@@ -519,3 +519,23 @@ def test_reaches_schwefel_minimum():
     # the minimiser: |x - x*| within the quadratic bound sqrt(2 n gap / h''), h'' = 0.2524
     gap = r["f_rec_final"] - W.SCHWEFEL_F_STAR
     assert np.max(np.abs(r["x_rec"] - W.SCHWEFEL_X_STAR)) <= math.sqrt(2 * 4 * max(gap, 1e-12) / 0.25) + 1e-6
+
+
+@pytest.mark.parametrize("func,exchange", [(O.SCHWEFEL, 1), (O.ACKLEY, 1), (O.RASTRIGIN, 3), (O.SCHWEFEL, 0),
+                                           (O.GRIEWANK, 1), (O.ROSENBROCK, 2)])
+def test_chain_threads_are_bit_identical(func, exchange):
+    """The oracle's chain-threaded mode (threads over a level's chains, winner
+    reduced in chain order afterwards) gives the single-thread bits for every
+    thread count, including counts that do not divide the chains."""
+    wl = W.random_problem(func, 6, seed=71 + func)
+    outs = []
+    for t in (1, 3, 8):
+        O.set_threads(t)
+        try:
+            outs.append(O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=7, chains=200, steps=40, T0=3.0,
+                                 alpha=0.8, levels=7, exchange=exchange, final_f=True))
+        finally:
+            O.set_threads(1)
+    for o in outs[1:]:
+        for k in ("win_chain", "accepts", "f_win", "f_best", "f_rec", "x_best", "x_rec", "final_f"):
+            assert np.array_equal(np.asarray(o[k]), np.asarray(outs[0][k])), k
