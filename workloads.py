@@ -25,7 +25,17 @@ from typing import Optional
 import numpy as np
 
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+# Non-separable families (Appendix: Test 8 Griewank, Test 10 Levy-Montalvo,
+# Test 14 generalized Rosenbrock): every move re-evaluates the whole cost.
+GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5
 FP32, FP64 = 0, 1
+
+# Half-width of each family's canonical box [-h, h]^n: the paper's boxes for
+# Rastrigin (Test 13), Griewank (Test 8), Levy-Montalvo (Test 10) and
+# Rosenbrock (Test 14); Schwefel and Ackley at the widths used by the
+# annealing workloads here (500 and 32.768).
+HALF_BOX = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768, GRIEWANK: 600.0, LEVY_MONTALVO: 10.0,
+            ROSENBROCK: 2.048}
 
 # Closed-form minimum of the normalized Schwefel function (Sec. 4.1): the
 # paper prints x_i* = 420.968746 and f* = -418.982887 (tests/golden/paper_values.txt);
@@ -104,9 +114,9 @@ def ackley_n1024_fp32(shift_seed: int = 1024) -> Workload:
 
 
 def random_problem(func: int, n: int, seed: int, shifted: bool = True) -> Workload:
-    """A small random problem of one of the three families, for parity tests:
+    """A small random problem of one of the families, for parity tests:
     canonical box, optional inner shift, random FP32 schedule."""
-    half = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768}[func]
+    half = HALF_BOX[func]
     lo, hi = _box(n, half)
     rng = np.random.default_rng(seed)
     s = inner_shift(lo, hi, rng) if shifted else None
@@ -132,8 +142,7 @@ def batch_problems(nprob: int = 1024, seed: int = 4, nmin: int = 2, nmax: int = 
     for _ in range(nprob):
         func = int(rng.integers(0, 3))
         n = int(rng.integers(nmin, nmax + 1))
-        half = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768}[func]
-        lo, hi = _box(n, half)
+        lo, hi = _box(n, HALF_BOX[func])
         s = inner_shift(lo, hi, rng)
         if func == SCHWEFEL:
             lo, hi = lo + s, hi + s
