@@ -39,6 +39,22 @@
  *   SA_RASTRIGIN  f = 10 n + sum (y_i^2 - 10 cos(2 pi y_i))  (Appendix, Test 13)
  *   SA_ACKLEY     f = -20 exp(-0.2 sqrt(sum y^2 / n)) - exp(sum cos(2 pi y)/n)
  *                     + 20 + e                                (Appendix, Test 1)
+ *   SA_GRIEWANK   f = 1 + sum y_i^2 / 4000 - prod_i cos(y_i / sqrt(i))
+ *                                                             (Appendix, Test 8)
+ *   SA_LEVY_MONTALVO  f = (pi/n) [10 sin^2(pi w_1) + sum_{i<n} (w_i - 1)^2
+ *                     (1 + 10 sin^2(pi w_{i+1})) + (w_n - 1)^2],
+ *                     w_i = 1 + (y_i + 1)/4                   (Appendix, Test 10)
+ *   SA_ROSENBROCK f = sum_{i<n} [100 (y_{i+1} - y_i^2)^2 + (1 - y_i)^2]
+ *                                                             (Appendix, Test 14)
+ * The first three are sums of per-coordinate terms (Ackley through its two
+ * sums), so a move updates the cost by the changed coordinate's terms; the
+ * other three are not, and every move evaluates f(x') in full, as the paper's
+ * kernel does for every function (Sec. 3.3).  The printed Griewank form puts
+ * the product inside the sum and the printed Rosenbrock form squares
+ * (y_{i+1} - y_i); the forms above are the named functions, with the stated
+ * minima 0 at y = 0 and 0 at y = (1, ..., 1).  The non-separable families
+ * run on the dense state layout with plain or logged moves (not with
+ * SA_FLAG_OVERLAY, SA_FLAG_LEARNED, sa_capture or in batches).
  *
  * Conventions for every call:
  *   - Host pointers are read during the call only; the library copies what it
@@ -82,7 +98,14 @@ typedef enum {
     SA_ERR_UNSUPPORTED = -5  /* valid request this build does not support */
 } sa_status;
 
-typedef enum { SA_SCHWEFEL = 0, SA_RASTRIGIN = 1, SA_ACKLEY = 2 } sa_func;
+typedef enum {
+    SA_SCHWEFEL = 0,
+    SA_RASTRIGIN = 1,
+    SA_ACKLEY = 2,
+    SA_GRIEWANK = 3,      /* non-separable: every move re-evaluates f in full */
+    SA_LEVY_MONTALVO = 4, /* non-separable */
+    SA_ROSENBROCK = 5     /* non-separable */
+} sa_func;
 typedef enum { SA_FP32 = 0, SA_FP64 = 1 } sa_precision;
 typedef enum { SA_MOVE_RADIUS = 0, SA_MOVE_RESAMPLE = 1 } sa_move;
 

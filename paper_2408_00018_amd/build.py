@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsa_hip.so")
 PEAK_LIB = os.path.join(PKG, "libsa_peak.so")
 
-SOURCES = ["sa_kernels.hip", "sa_overlay.hip", "sa_api.hip", "sa_batch.hip", "sa_batch_api.hip", "sa_mlp.hip"]
+SOURCES = ["sa_kernels.hip", "sa_coupled.hip", "sa_overlay.hip", "sa_api.hip", "sa_batch.hip", "sa_batch_api.hip",
+           "sa_mlp.hip"]
 PEAK_SOURCES = ["peak_probe.hip"]
 
 HIPCC_FLAGS = [

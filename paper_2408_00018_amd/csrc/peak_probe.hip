@@ -92,9 +92,38 @@ __global__ void __launch_bounds__(256) probe_kernel(int kind, int iters, uint32_
     sink[tid] = acc;
 }
 
+// One hardware transcendental per element: 0 sin(2 pi t), 1 cos(2 pi t) (the
+// instructions take revolutions), 2 sqrt(t), 3 2^t.
+__global__ void __launch_bounds__(256) accuracy_kernel(int op, const float *in, float *out, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float t = in[i];
+    float r;
+    switch (op) {
+    case 0: r = __builtin_amdgcn_sinf(t); break;
+    case 1: r = __builtin_amdgcn_cosf(t); break;
+    case 2: r = __builtin_amdgcn_sqrtf(t); break;
+    default: r = __builtin_amdgcn_exp2f(t); break;
+    }
+    out[i] = r;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Apply hardware transcendental `op` (see accuracy_kernel) to n FP32 values:
+// in and out are device pointers to n floats.  Synchronises.  Used to measure
+// the instructions' error against an FP64 evaluation of the same inputs.
+int sa_peak_accuracy(int op, const float *in, float *out, uint32_t n)
+{
+    if (op < 0 || op > 3 || !in || !out) return -1;
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(accuracy_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, op, in, out, n);
+    if (hipGetLastError() != hipSuccess) return -3;
+    return hipDeviceSynchronize() == hipSuccess ? 0 : -3;
+}
 
 // Run `kind` on `blocks` x 256 lanes for `iters` rounds of 16 chains; return
 // the elapsed milliseconds (HIP events on the null stream) in *ms.  The

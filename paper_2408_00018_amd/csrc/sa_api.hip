@@ -74,7 +74,7 @@ constexpr uint32_t kNoStart = 0xFFFFFFFFu;
 
 struct Layout {
     size_t table, T, inv_T, featT, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final;
-    size_t x_start, theta, net, cap_count, chain_x, chain_cost, total;
+    size_t x_start, theta, net, cap_count, chain_x, chain_cost, gcoef, total;
 };
 
 struct Plan {
@@ -105,6 +105,8 @@ sa_status validate(const sa_problem *p, const sa_config *c)
         return fail(SA_ERR_UNSUPPORTED, "an exchange period other than 1 needs the dense state layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->precision != SA_FP32 || c->move != SA_MOVE_RADIUS))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs in FP32 with the radius move as its plain part");
+    if (!sa::separable(p->func) && (c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)))
+        return fail(SA_ERR_UNSUPPORTED, "the non-separable families run plain or logged moves on the dense layout");
     if (c->log_chains) {
         if (c->log_chains > c->chains) return fail(SA_ERR_INVALID, "log_chains exceeds chains");
         if (c->log_levels == 0 || c->log_level >= c->levels || c->log_levels > c->levels - c->log_level)
@@ -149,7 +151,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     // operations per move; measured at n = 512: 1.7x faster than the dense
     // layout with 131072 chains, 2.8x slower with 16384, where both put 256
     // waves in flight).
-    if (!learn && !periodic) {
+    if (!learn && !periodic && sa::separable(p->func)) {
         uint32_t ov_wg = 0, ov_slots = 0;
         const bool ov_fits = pick_overlay(p->n, c->chains, c->steps, pl.real, pl.table, lds_limit, &ov_wg, &ov_slots);
         const uint64_t ov_flight =
@@ -195,6 +197,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.cap_count = take(sizeof(unsigned long long));
     l.chain_x = take(periodic ? (size_t)c->chains * n * R : 0);
     l.chain_cost = take(periodic ? (size_t)sa::kCostWords * c->chains * R : 0);
+    l.gcoef = take(p->func == SA_GRIEWANK ? n * sizeof(float) : 0);
     l.total = off;
     *out = pl;
     return SA_OK;
@@ -273,6 +276,8 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.cap_rec = nullptr;
     a.cap_count = reinterpret_cast<unsigned long long *>(w + l.cap_count);
     a.cap_capacity = 0;
+    a.gcoef = reinterpret_cast<const float *>(w + l.gcoef);
+    a.cscale = (float)(3.14159265358979323846 / (double)c->prob.n);
 }
 
 // Temperature feature of the proposal network: ln(tau T), tau = n for the
@@ -323,6 +328,13 @@ sa_status upload_tables(sa_ctx *c)
                                   c->stream));
         }
     }
+    if (c->prob.func == SA_GRIEWANK) {
+        // Griewank's cos(y_i / sqrt(i)) in revolutions: y_i c_i, c_i = 1/(2 pi sqrt(i)), i = 1..n
+        std::vector<float> g(n);
+        for (uint32_t i = 0; i < n; ++i) g[i] = (float)(1.0 / (2.0 * 3.14159265358979323846 * std::sqrt(i + 1.0)));
+        SA_HIP(hipMemcpyAsync(c->ws + l.gcoef, g.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        SA_HIP(hipStreamSynchronize(c->stream));
+    }
     coord_values(c, 0, v);
     if (c->fp64) {
         c->a64.lo = v[0];
@@ -354,7 +366,10 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
                                     : (log ? sa::kModeLog : (c->capturing ? sa::kModeCapture : sa::kModePlain));
         uint32_t g = 0;
         hipError_t e;
-        if (c->pl.overlay)
+        if (!sa::separable(c->prob.func))
+            e = c->fp64 ? sa::launch_coupled_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
+                        : sa::launch_coupled_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
+        else if (c->pl.overlay)
             e = c->fp64 ? sa::launch_overlay_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
                         : sa::launch_overlay_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
         else
@@ -711,6 +726,8 @@ sa_status sa_capture(sa_ctx *c, float *records, uint64_t capacity)
         return fail(SA_ERR_INVALID, "records must be float-aligned");
     if (records && c->learned) return fail(SA_ERR_STATE, "capture records plain runs; clear the proposal first");
     if (records && c->pl.overlay) return fail(SA_ERR_UNSUPPORTED, "capture runs on the dense state layout");
+    if (records && !sa::separable(c->prob.func))
+        return fail(SA_ERR_UNSUPPORTED, "capture records moves of the separable families");
     drop_graphs(c);
     c->a32.cap_rec = records;
     c->a64.cap_rec = records;

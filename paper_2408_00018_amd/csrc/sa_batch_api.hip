@@ -48,6 +48,9 @@ sa_status validate_batch(const sa_problem *probs, uint32_t nprob, const uint32_t
     if (nprob >= (1u << 24)) return fail(SA_ERR_INVALID, "nprob must be < 2^24 (problem ids share a counter word)");
     for (uint32_t p = 0; p < nprob; ++p) {
         if (sa_status st = sa::validate_problem(&probs[p], p); st != SA_OK) return st;
+        if (!sa::separable(probs[p].func))
+            return fail(SA_ERR_UNSUPPORTED, "problem %u: batches hold the separable families (Schwefel, Rastrigin, "
+                        "Ackley)", p);
         if (chains[p] == 0 || chains[p] % 64 || chains[p] > kMaxChainsPerProblem)
             return fail(SA_ERR_INVALID, "problem %u: chains must be a multiple of 64 in [64, 2^20]", p);
     }

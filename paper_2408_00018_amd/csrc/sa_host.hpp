@@ -38,11 +38,15 @@ inline sa_status fail(sa_status st, const char *fmt, ...)
         if (e_ != hipSuccess) return sa::fail(SA_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Families whose cost is a sum of per-coordinate terms (a move updates it
+// incrementally); the others are re-evaluated in full at every move.
+inline bool separable(uint32_t func) { return func <= SA_ACKLEY; }
+
 // One problem: known function, n >= 1, finite box with lower < upper, finite shift.
 inline sa_status validate_problem(const sa_problem *p, uint32_t index)
 {
     if (!p) return fail(SA_ERR_INVALID, "problem %u is NULL", index);
-    if (p->func > SA_ACKLEY) return fail(SA_ERR_INVALID, "problem %u: unknown function id %u", index, p->func);
+    if (p->func > SA_ROSENBROCK) return fail(SA_ERR_INVALID, "problem %u: unknown function id %u", index, p->func);
     if (p->n == 0) return fail(SA_ERR_INVALID, "problem %u: dimension n must be >= 1", index);
     if (!p->lower || !p->upper) return fail(SA_ERR_INVALID, "problem %u: lower/upper must not be NULL", index);
     for (uint32_t i = 0; i < p->n; ++i) {

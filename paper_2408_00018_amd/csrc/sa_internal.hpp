@@ -12,6 +12,9 @@ namespace sa {
 constexpr int kSchwefel = SA_SCHWEFEL;
 constexpr int kRastrigin = SA_RASTRIGIN;
 constexpr int kAckley = SA_ACKLEY;
+constexpr int kGriewank = SA_GRIEWANK;
+constexpr int kLevyMontalvo = SA_LEVY_MONTALVO;
+constexpr int kRosenbrock = SA_ROSENBROCK;
 
 // Full evaluation of a state in FP64 arithmetic: the cost and, for Ackley,
 // the two sums under its exponentials.
@@ -76,6 +79,10 @@ template <typename R> struct LevelArgs {
     float *cap_rec;             // captured records, 7 floats each
     unsigned long long *cap_count;  // accepted moves seen by the capture
     uint64_t cap_capacity;      // records cap_rec holds
+    // Non-separable families: Griewank's c_i = 1/(2 pi sqrt(i+1)) (n FP32
+    // values, FP32 runs) and Levy-Montalvo's pi/n in FP32.
+    const float *gcoef;
+    float cscale;
 };
 
 // What a level launch does besides the plain steps.
@@ -109,6 +116,13 @@ hipError_t launch_overlay_level_f32(int func, bool table, bool log, const LevelA
 hipError_t launch_overlay_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
                                     uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 size_t overlay_lds_bytes(uint32_t n, uint32_t wg, uint32_t slots, size_t real_size, bool table);
+
+// Level launches for the non-separable families (full re-evaluation per
+// move; dense state layout; plain and logged moves).
+hipError_t launch_coupled_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
+                                    uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+hipError_t launch_coupled_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,
+                                    uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 
 }  // namespace sa
 

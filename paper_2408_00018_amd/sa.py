@@ -18,6 +18,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
 
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
+GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5  # non-separable: full re-evaluation per move
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8

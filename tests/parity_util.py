@@ -12,9 +12,14 @@ import numpy as np
 import oracle as O
 
 U32 = 2.0 ** -24  # FP32 unit roundoff
-# Absolute error bound of the FP32 hardware sine/cosine on the arguments used
-# here (|t| <= 64 revolutions), with margin; see the design notes.
+# Error bounds of the FP32 hardware transcendentals, checked against FP64 on
+# the GPU by tests/test_gpu_trig.py: absolute for sine/cosine on arguments up
+# to 64 revolutions (E_TRIG) and up to 256 (E_TRIG_WIDE, Griewank's
+# cos(y/sqrt(i)) at |y| up to 1200), relative for sqrt and 2^t.
 E_TRIG = 2.0 ** -19
+E_TRIG_WIDE = 2.0 ** -17
+E_SQRT = 2.0 ** -22
+E_EXP2 = 2.0 ** -21
 
 
 def f32(v):
@@ -32,10 +37,82 @@ def box32(lower, upper):
     return l32.astype(np.float64), h32.astype(np.float64)
 
 
+COUPLED = (O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK)
+
+
+def eval_err32(func, x, shift):
+    """First-order bound on the absolute error of the FP32 full evaluation of
+    a non-separable family at state x (FP64 copy of the FP32 state), following
+    the kernel's operation order: y = x - s rounded, then per coordinate
+      Griewank     s += y^2 (fma); p *= cos_rev(y c_i), c_i = fl(1/(2 pi sqrt(i)));
+                   f = fma(s, fl(1/4000), 1) - p
+      Levy         h = fma(y, 1/8, 1/8) = v/2; S = sin_rev(h);
+                   acc = fma(v_prev^2, fma(10 S, S, 1), acc); f = acc fl(pi/n)
+      Rosenbrock   t = fma(-a, a, b); acc = fma(100 t, t, acc); acc = fma(u, u, acc)
+    Every rounding contributes U32 times the magnitude of its result, the
+    hardware sine/cosine E_TRIG (E_TRIG_WIDE past 64 revolutions) absolutely,
+    and errors propagate through first derivatives.  Sums of n roundings are
+    bounded by n U32 times the sum of the magnitudes."""
+    x = np.asarray(x, dtype=np.float64)
+    n = x.size
+    y = x - (0.0 if shift is None else np.asarray(shift, dtype=np.float64))
+    dy = U32 * np.abs(y) if shift is not None else np.zeros(n)
+    if func == O.GRIEWANK:
+        idx = np.arange(1, n + 1, dtype=np.float64)
+        th = y / np.sqrt(idx)
+        S = float(np.sum(y * y))
+        c = np.cos(th)
+        # leave-one-out products of |cos| through prefix/suffix products
+        a = np.abs(c)
+        pre = np.concatenate([[1.0], np.cumprod(a)[:-1]])
+        suf = np.concatenate([np.cumprod(a[::-1])[::-1][1:], [1.0]])
+        loo = pre * suf
+        rev = np.abs(th) / (2 * np.pi)
+        e_trig = np.where(rev <= 64.0, E_TRIG, E_TRIG_WIDE)
+        dth = np.abs(th) * 3 * U32 + dy / np.sqrt(idx)
+        e_p = float(np.sum(loo * (np.abs(np.sin(th)) * dth + e_trig))) + n * U32 * float(np.prod(a))
+        e_s = (n + 2) * U32 * S + float(np.sum(2 * np.abs(y) * dy))
+        f = 1.0 + S / 4000.0 - float(np.prod(c))
+        return e_p + e_s / 4000.0 + U32 * S / 4000.0 + U32 * (1.0 + S / 4000.0) + U32 * abs(f)
+    if func == O.LEVY_MONTALVO:
+        v = (y + 1.0) / 4.0
+        dh = U32 * (np.abs(y) / 8.0 + np.abs(v) / 2.0) + dy / 8.0
+        dv = 2 * dh
+        S = np.sin(np.pi * v)
+        dS = 2 * np.pi * np.abs(np.cos(np.pi * v)) * dh + E_TRIG
+        q = 1.0 + 10.0 * S * S
+        dq = 20 * np.abs(S) * dS + U32 * (10 * S * S + q)
+        terms = np.concatenate([[10 * S[0] ** 2], v[:-1] ** 2 * q[1:], [v[-1] ** 2]])
+        dterms = np.concatenate([[20 * abs(S[0]) * dS[0] + U32 * 10 * S[0] ** 2],
+                                 2 * np.abs(v[:-1]) * dv[:-1] * q[1:] + v[:-1] ** 2 * dq[1:]
+                                 + 2 * U32 * v[:-1] ** 2 * q[1:],
+                                 [2 * abs(v[-1]) * dv[-1]]])
+        tot = float(np.sum(terms))
+        return (np.pi / n) * (float(np.sum(dterms)) + (n + 3) * U32 * tot)
+    # Rosenbrock
+    if n < 2:
+        return 0.0
+    aa, bb = y[:-1], y[1:]
+    da, db = dy[:-1], dy[1:]
+    t = bb - aa * aa
+    u = 1.0 - aa
+    dt = 2 * np.abs(aa) * da + db + U32 * (np.abs(t) + aa * aa)
+    du = da + U32 * np.abs(u)
+    terms = 100 * t * t + u * u
+    dterms = 100 * (2 * np.abs(t) * dt + 2 * U32 * t * t) + 2 * np.abs(u) * du
+    return float(np.sum(dterms)) + 2 * (n + 1) * U32 * float(np.sum(terms))
+
+
 def df_floor(func, n, x, xn, d, shift):
     """Absolute error floor of an FP32 cost increment, from the rounding of its
     inputs and the hardware transcendental error (the relative 1e-5 is added
-    on top).  x, xn: FP64 copies of the FP32 states before/after the move."""
+    on top).  x, xn: FP64 copies of the FP32 states before/after the move.
+    Non-separable families: the increment is the difference of two full FP32
+    evaluations (the carried cost is the last one, or the FP64 start value
+    rounded to FP32), so the floor is the sum of their error bounds, doubled
+    for the first-order analysis."""
+    if func in COUPLED:
+        return 2.0 * (eval_err32(func, x, shift) + eval_err32(func, xn, shift))
     s = 0.0 if shift is None else shift[d]
     y, yn = x[d] - s, xn[d] - s
     if func == O.SCHWEFEL:

@@ -156,3 +156,31 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_non_separable_families(S):
+    """Griewank, Levy-Montalvo and Rosenbrock are valid problems (Griewank's
+    FP32 runs keep n cosine-argument factors in the workspace); they run on the
+    dense layout with plain or logged moves only, and not in batches."""
+    sched = S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9)
+    lo, hi = np.full(300, -2.0), np.full(300, 2.0)
+    ros = S.workspace_bytes(W.ROSENBROCK, lo, hi, None, sched)
+    assert S.workspace_bytes(W.LEVY_MONTALVO, lo, hi, None, sched) == ros
+    assert S.workspace_bytes(W.GRIEWANK, lo, hi, None, sched) >= ros + 300 * 4 - 256  # the empty entry's slot
+    for kw in (dict(overlay=True), dict(learned=True)):
+        with pytest.raises(S.SAError) as e:
+            S.workspace_bytes(W.GRIEWANK, lo, hi, None, S.Schedule(chains=64, levels=2, steps=2, T0=1.0,
+                                                                   alpha=0.9, **kw))
+        assert e.value.status == -5
+    # n = 5000 would only fit the overlay layout, which these families do not use
+    lo, hi = np.full(5000, -1.0), np.full(5000, 1.0)
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(W.ROSENBROCK, lo, hi, None, sched)
+    assert e.value.status == -5
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(6, lo[:4], hi[:4], None, sched)
+    assert e.value.status == -1
+    bs = S.BatchSchedule(levels=2, steps=2, T0=1.0, alpha=0.9)
+    with pytest.raises(S.SAError) as e:
+        S.batch_workspace_bytes([(W.GRIEWANK, lo[:4], hi[:4], None)], [64], bs)
+    assert e.value.status == -5

@@ -1,0 +1,95 @@
+"""Error of the gfx950 FP32 transcendental instructions the kernels use
+(v_sin_f32 and v_cos_f32 on revolutions, v_sqrt_f32, v_exp_f32), measured
+against FP64 evaluations of the same FP32 inputs.
+
+The per-move tolerances of the FP32 parity tests take the sine/cosine error
+as an absolute bound (parity_util.E_TRIG, for arguments up to 64
+revolutions, and E_TRIG_WIDE up to 256 revolutions, which Griewank's
+cos(y_i / sqrt(i)) reaches) and the square root and 2^t errors as relative
+bounds (E_SQRT, E_EXP2).  These tests check that the hardware stays within
+them over the argument ranges the kernels use, and print the measured
+maxima.
+"""
+import ctypes
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import parity_util as P
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def probe():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2408_00018_amd", "libsa_peak.so"))
+    lib.sa_peak_accuracy.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]
+    lib.sa_peak_accuracy.restype = ctypes.c_int
+
+    def run(op, x):
+        xin = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+        out = torch.empty_like(xin)
+        torch.cuda.synchronize()
+        rc = lib.sa_peak_accuracy(op, xin.data_ptr(), out.data_ptr(), xin.numel())
+        assert rc == 0, rc
+        return out.cpu().numpy().astype(np.float64)
+    return run
+
+
+def rev_samples(bound, count, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-bound, bound, count).astype(np.float32)
+    # quarter and eighth revolutions, where the result is 0, +-1 or +-sqrt(1/2)
+    k = np.arange(-8 * int(bound), 8 * int(bound) + 1, dtype=np.float64) / 8.0
+    return np.concatenate([x, k.astype(np.float32)])
+
+
+def sin_cos_ref(t):
+    frac = t - np.round(t)  # exact in FP64 for FP32 inputs
+    return np.sin(2 * np.pi * frac), np.cos(2 * np.pi * frac)
+
+
+@pytest.mark.parametrize("bound,limit_name", [(1.0, "E_TRIG"), (8.0, "E_TRIG"), (64.0, "E_TRIG"),
+                                              (256.0, "E_TRIG_WIDE")])
+def test_sin_cos_absolute_error(probe, bound, limit_name):
+    t = rev_samples(bound, 1 << 21, int(bound))
+    ref_s, ref_c = sin_cos_ref(t.astype(np.float64))
+    es = np.max(np.abs(probe(0, t) - ref_s))
+    ec = np.max(np.abs(probe(1, t) - ref_c))
+    limit = getattr(P, limit_name)
+    say(f"[trig] |t| <= {bound} rev: max |sin err| = {es:.3e}, max |cos err| = {ec:.3e} "
+        f"({es / 2 ** -24:.2f}, {ec / 2 ** -24:.2f} x 2^-24); {limit_name} = {limit:.3e}")
+    assert es <= limit and ec <= limit
+
+
+def test_sqrt_relative_error(probe):
+    rng = np.random.default_rng(5)
+    x = np.concatenate([rng.uniform(0, 1, 1 << 20), rng.uniform(0, 30, 1 << 20),
+                        np.exp(rng.uniform(-40, 10, 1 << 20))]).astype(np.float32)
+    x = x[x > 0]
+    ref = np.sqrt(x.astype(np.float64))
+    err = np.max(np.abs(probe(2, x) - ref) / ref)
+    say(f"[trig] sqrt: max relative error {err:.3e} ({err / 2 ** -24:.2f} x 2^-24); E_SQRT = {P.E_SQRT:.3e}")
+    assert err <= P.E_SQRT
+
+
+def test_exp2_relative_error(probe):
+    rng = np.random.default_rng(6)
+    x = np.concatenate([rng.uniform(-30, 24, 1 << 21), rng.uniform(-1, 1, 1 << 20)]).astype(np.float32)
+    ref = np.exp2(x.astype(np.float64))
+    err = np.max(np.abs(probe(3, x) - ref) / ref)
+    say(f"[trig] exp2: max relative error {err:.3e} ({err / 2 ** -24:.2f} x 2^-24); E_EXP2 = {P.E_EXP2:.3e}")
+    assert err <= P.E_EXP2
+    assert math.isfinite(err)

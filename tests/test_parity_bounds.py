@@ -1,0 +1,86 @@
+"""CPU checks of the FP32 error bounds the GPU parity tests use for the
+non-separable families (parity_util.eval_err32).
+
+The FP32 evaluation is emulated in numpy float32 in the kernels' operation
+order, with the hardware sine/cosine replaced by the FP64 value of the same
+FP32 revolution argument rounded to FP32 (an error below E_TRIG).  The bound
+must cover the emulation's error against the FP64 definition on random
+states, and must not be vacuous (a small fraction of the cost's scale).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity_util import eval_err32
+
+F32 = np.float32
+
+
+def emulate32(func, x, shift):
+    x = np.asarray(x, dtype=np.float32)
+    n = x.size
+    sh = np.zeros(n, dtype=np.float32) if shift is None else np.asarray(shift, dtype=np.float32)
+    y = (x - sh).astype(np.float32)
+
+    def fma(a, b, c):  # one rounding
+        return F32(np.float64(a) * np.float64(b) + np.float64(c))
+
+    def hw_cos_rev(t):
+        return F32(np.cos(2 * np.pi * (np.float64(t) - np.round(np.float64(t)))))
+
+    def hw_sin_rev(t):
+        return F32(np.sin(2 * np.pi * (np.float64(t) - np.round(np.float64(t)))))
+
+    if func == O.GRIEWANK:
+        c = (1.0 / (2 * np.pi * np.sqrt(np.arange(1, n + 1, dtype=np.float64)))).astype(np.float32)
+        s, p = F32(0), F32(1)
+        for i in range(n):
+            s = fma(y[i], y[i], s)
+            p = F32(p * hw_cos_rev(F32(y[i] * c[i])))
+        return float(F32(fma(s, F32(2.5e-4), F32(1)) - p))
+    if func == O.LEVY_MONTALVO:
+        h0 = fma(y[0], F32(0.125), F32(0.125))
+        s0 = hw_sin_rev(h0)
+        acc = F32(F32(F32(10) * s0) * s0)
+        vp = F32(2 * h0)
+        for i in range(1, n):
+            h = fma(y[i], F32(0.125), F32(0.125))
+            si = hw_sin_rev(h)
+            acc = fma(F32(vp * vp), fma(F32(F32(10) * si), si, F32(1)), acc)
+            vp = F32(2 * h)
+        acc = fma(vp, vp, acc)
+        return float(F32(acc * F32(np.pi / n)))
+    acc = F32(0)
+    a = y[0]
+    for i in range(1, n):
+        b = y[i]
+        t = fma(-a, a, b)
+        u = F32(F32(1) - a)
+        acc = fma(F32(F32(100) * t), t, acc)
+        acc = fma(u, u, acc)
+        a = b
+    return float(acc)
+
+
+@pytest.mark.parametrize("func", [O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK])
+@pytest.mark.parametrize("n,shifted", [(1, False), (2, True), (17, False), (100, True), (100, False)])
+def test_fp32_evaluation_within_bound(func, n, shifted):
+    half = W.HALF_BOX[func]
+    rng = np.random.default_rng(1000 * func + n)
+    worst = 0.0
+    for trial in range(12):
+        shift = rng.uniform(-0.8 * half, 0.8 * half, n).astype(np.float32).astype(np.float64) if shifted else None
+        # states across the box, and near the minimiser (where the increments are small)
+        scale = half if trial % 2 == 0 else half * 1e-3
+        centre = (0.0 if shift is None else shift) + (1.0 if func == O.ROSENBROCK else
+                                                      -1.0 if func == O.LEVY_MONTALVO else 0.0)
+        x = np.clip(centre + rng.uniform(-scale, scale, n), -half, half).astype(np.float32).astype(np.float64)
+        exact = O.f(func, x, shift)
+        err = abs(emulate32(func, x, shift) - exact)
+        bound = eval_err32(func, x, shift)
+        assert err <= bound, (trial, err, bound)
+        worst = max(worst, err / bound if bound > 0 else 0.0)
+        # not vacuous: far below the cost's own scale
+        assert bound <= 1e-4 * max(1.0, abs(exact)) + (2e-3 if func == O.GRIEWANK else 0.0)
+    print(f"func {func} n {n}: max err/bound {worst:.3f}")

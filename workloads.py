@@ -15,6 +15,9 @@ Workloads (the paper's test functions at the sizes used here):
                          1000 levels x 64 steps
   ackley_n1024_fp32      Ackley (Appendix, Test 1), n=1024, box [-32.768,32.768]^1024, shift as
                          above, 131072 chains, FP32, 1000 levels x 64 steps
+  griewank_n100_fp32     Griewank (Appendix, Test 8), n=100, box [-600,600]^100, 65536 chains,
+                         FP32, T0=10, alpha=0.97, 200 levels x 100 steps, seed 5 (full
+                         re-evaluation of f at every move)
 Every move uses the radius rule with radius 0.1 (u - l) unless stated.
 """
 from __future__ import annotations
@@ -113,6 +116,15 @@ def ackley_n1024_fp32(shift_seed: int = 1024) -> Workload:
                     T0=10.0, alpha=0.99, seed=3, precision=FP32, f_star=0.0, x_star=s.copy())
 
 
+def griewank_n100_fp32() -> Workload:
+    """Griewank (Appendix, Test 8) at the paper's smallest size n = 100 (F8_a),
+    box [-600, 600]^100, unshifted (minimum 0 at the origin); non-separable,
+    so every move re-evaluates f in full."""
+    lo, hi = _box(100, 600.0)
+    return Workload("griewank_n100_fp32", GRIEWANK, 100, lo, hi, None, chains=65536, levels=200, steps=100,
+                    T0=10.0, alpha=0.97, seed=5, precision=FP32, f_star=0.0, x_star=np.zeros(100))
+
+
 def random_problem(func: int, n: int, seed: int, shifted: bool = True) -> Workload:
     """A small random problem of one of the families, for parity tests:
     canonical box, optional inner shift, random FP32 schedule."""
@@ -155,4 +167,5 @@ ALL = {
     "schwefel_n100_fp32": schwefel_n100_fp32,
     "rastrigin_n512_fp32": rastrigin_n512_fp32,
     "ackley_n1024_fp32": ackley_n1024_fp32,
+    "griewank_n100_fp32": griewank_n100_fp32,
 }
