@@ -309,74 +309,83 @@ def bf16_matrices(params):
 
 def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, featT, eps32, params64, radius_frac,
                         x_start, moves, final_f, chain_ids, problem=0):
-    """Replay the logged moves of a learned-mixture level against the oracle.
+    """Replay the logged moves of a learned-mixture level against the oracle's
+    learned move (oracle.learned_propose / oracle.learned_accept with the
+    network under the device's stated precision, NET_DEVICE, and its bounds).
 
     Each move: the coordinate and the plain/learned choice are bit-exact; a
     plain move is checked as in check_fp32_level; a learned move's proposal
-    must equal the oracle's mu + e^s g within the network's BF16 error bound,
-    a proposal outside the box must be rejected with df = 0, and an in-box
-    decision must equal the oracle's Metropolis-Hastings decision wherever the
-    bounds cannot flip it.  The chain state follows the GPU's own accepted
-    moves.  Returns statistics."""
+    must equal the oracle's mu + e^s t within the bounds the oracle gives for
+    mu and s, a proposal outside the box must be rejected with df = 0, and an
+    in-box decision must equal the oracle's Metropolis-Hastings decision
+    wherever those bounds (and the FP32 increment's) cannot flip it.  The
+    chain state and history follow the GPU's own accepted moves.  Returns
+    statistics."""
     stats = dict(moves=0, learned=0, outside=0, ambiguous=0, max_dl_excess=0.0, max_rel_excess=0.0)
+    nd = O.NET_DEVICE
     for j, c in enumerate(chain_ids):
         x = np.array(x_start, dtype=np.float64)
         h = [0.0, 0.0, 0.0, 0.0]
         f_acc_err = 0.0
         for s in range(moves.shape[-1]):
             m = moves[j, s]
-            d, u1, u2 = O.move_draw(seed, problem, level, c, s, n)
+            pr = O.learned_propose(params64, nd, seed=seed, problem=problem, level=level, chain=c, step=s, x=x,
+                                   lower=lower32, upper=upper32, radius_frac=radius_frac, featT=featT, eps=eps32,
+                                   hist=h)
+            d = pr["d"]
             assert int(m["d"]) == d, (level, c, s)
             assert m["x_old"] == x[d], (level, c, s)
             lo, hi = float(lower32[d]), float(upper32[d])
             w = hi - lo
-            plain = O.learn_mix(seed, problem, level, c, s) < eps32
             xn = x.copy()
             xn[d] = m["x_new"]
-            if plain:
-                xn_ref = O.neighbour(O.MOVE_RADIUS, float(m["x_old"]), lo, hi, radius_frac, u1)
-                assert abs(m["x_new"] - xn_ref) <= 2.0 ** -23 * (abs(xn_ref) + radius_frac * w), (level, c, s)
-                df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
+            x_old, x_new = float(m["x_old"]), float(m["x_new"])
+            if pr["plain"]:
+                assert abs(x_new - pr["x_new"]) <= 2.0 ** -23 * (abs(pr["x_new"]) + radius_frac * w), (level, c, s)
+                take, det = O.learned_accept(params64, nd, func, lower=lower32, upper=upper32, shift=shift32, seed=seed,
+                                             problem=problem, level=level, chain=c, step=s, T=T, featT=featT,
+                                             plain=True, x=x, d=d, x_new=x_new, mu=0.0, s=0.0, hist=h)
+                df_ref = det["df"]
                 tol = 1e-5 * abs(df_ref) + df_floor(func, n, x, xn, d, shift32)
                 assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
+                stats["max_rel_excess"] = max(stats["max_rel_excess"], abs(m["df"] - df_ref) / tol)
                 margin = tol + 2.0 ** -18 * T
+                u2 = det["u2"]
                 firm = O.accept(df_ref - margin, T, u2) == O.accept(df_ref + margin, T, u2)
                 if firm:
-                    assert bool(m["accept"]) == O.accept(df_ref, T, u2), (level, c, s)
+                    assert bool(m["accept"]) == take, (level, c, s)
                 else:
                     stats["ambiguous"] += 1
             else:
                 stats["learned"] += 1
-                x_old = float(m["x_old"])
-                hf = [O.hist_feature(v) for v in h]
-                z = [(x_old - lo) / w, featT] + hf
-                (mu, sl), (bmu, bs) = O.mlp_forward_bound(params64, z)
-                t = O.learn_draw(seed, problem, level, c, s)
+                mu, sl, t, bmu, bs = pr["mu"], pr["s"], pr["t"], pr["b_mu"], pr["b_s"]
                 sig = math.exp(sl)
-                dl_ref = mu + sig * t
-                dl_gpu = (float(m["x_new"]) - x_old) / w
+                dl_ref = (pr["x_new"] - x_old) / w
+                dl_gpu = (x_new - x_old) / w
                 # rounding of x' = x + dl w and of the logged positions, in dl units
-                ddl = 4 * U32 * (abs(x_old) + abs(float(m["x_new"]))) / w
-                # network bound; e^s within e^{+-bs}; the hardware sin/cos quotient
-                # for t (relative error growing like |t| towards the poles); FP32
-                # rounding of the draw and the fused multiply-add
+                ddl = 4 * U32 * (abs(x_old) + abs(x_new)) / w
+                # network bounds on mu and s (e^s within e^{+-bs}); the hardware
+                # sin/cos quotient for t (relative error growing like |t| towards
+                # the poles); FP32 rounding of the draw and the fused multiply-add
                 tol_dl = (bmu + sig * abs(t) * (math.expm1(bs) + 2.0 ** -18)
                           + sig * 2.0 ** -18 * (1 + abs(t) + t * t) + 4 * U32 * abs(dl_ref) + ddl)
                 err = abs(dl_gpu - dl_ref)
                 stats["max_dl_excess"] = max(stats["max_dl_excess"], err / tol_dl)
                 assert err <= tol_dl, (level, c, s, dl_gpu, dl_ref, tol_dl)
-                inside = lo <= m["x_new"] <= hi
+                inside = lo <= x_new <= hi
                 if not inside:
                     stats["outside"] += 1
                     assert m["accept"] == 0 and m["df"] == 0.0, (level, c, s)
+                    tol = 0.0
                 else:
-                    z2 = [(float(m["x_new"]) - lo) / w, featT] + hf
-                    (mu2, s2), (bmu2, bs2) = O.mlp_forward_bound(params64, z2)
-                    df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
+                    take, det = O.learned_accept(params64, nd, func, lower=lower32, upper=upper32, shift=shift32,
+                                                 seed=seed, problem=problem, level=level, chain=c, step=s, T=T,
+                                                 featT=featT, plain=False, x=x, d=d, x_new=x_new, mu=mu, s=sl, hist=h)
+                    df_ref = det["df"]
                     tol = 1e-5 * abs(df_ref) + df_floor(func, n, x, xn, d, shift32)
                     assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
                     stats["max_rel_excess"] = max(stats["max_rel_excess"], abs(m["df"] - df_ref) / tol)
-                    lq = O.proposal_logpdf(-dl_gpu, mu2, s2) - O.proposal_logpdf(dl_gpu, mu, sl)
+                    mu2, s2, bmu2, bs2 = det["mu2"], det["s2"], det["b_mu2"], det["b_s2"]
                     # first-order sensitivity of the two Cauchy log densities to
                     # their location and log scale (and to dl's rounding)
                     e1 = (dl_gpu - mu) * math.exp(-sl)
@@ -385,15 +394,16 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                               + abs(1 - 2 * e1 * e1 / (1 + e1 * e1)) * bs
                               + 2 * abs(e2) * math.exp(-s2) / (1 + e2 * e2) * (bmu2 + ddl)
                               + abs(1 - 2 * e2 * e2 / (1 + e2 * e2)) * bs2)
-                    r = -df_ref / T + lq
+                    r = det["log_ratio"]
                     tol_r = 2 * tol_lq + tol / T + 2.0 ** -16 * (1 + abs(r))
+                    u2 = det["u2"]
                     lu = math.log(u2) if u2 > 0 else -math.inf
                     if abs(lu - r) > tol_r:
-                        assert bool(m["accept"]) == (lu < r), (level, c, s, lu, r, tol_r)
+                        assert bool(m["accept"]) == take, (level, c, s, lu, r, tol_r)
                     else:
                         stats["ambiguous"] += 1
             if m["accept"]:
-                h = [(float(m["x_new"]) - float(m["x_old"])) / w] + h[:3]
+                h = [(x_new - x_old) / w] + h[:3]
                 x = xn
                 f_acc_err += tol + 2 * U32 * abs(O.f(func, x, shift32))
             stats["moves"] += 1

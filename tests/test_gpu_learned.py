@@ -13,7 +13,10 @@
   (coordinate and plain/learned choice bit-exact, proposal within the network
   bound, Metropolis-Hastings decision equal where the bounds cannot flip it),
   level winners and records as in the plain path, and graph replay equal to
-  eager launches.
+  eager launches.  The decisions come from the oracle's learned move
+  (oracle.learned_propose / learned_accept), not from the checker.
+- The network the time-to-target comparison trains (learned.collect and
+  learned.train on the device), replayed the same way at the benchmark shape.
 """
 import math
 import sys
@@ -207,17 +210,17 @@ def test_learned_per_move_parity(S, name, steps):
     wl = learned_case(name)
     kw = dict(chains=512, levels=3, steps=steps, T0=5.0 if wl.func != W.SCHWEFEL else 20.0, alpha=0.7, seed=23)
     eps = 0.25
-    # weights small enough that the network's BF16 error bound leaves most
-    # Metropolis-Hastings decisions checkable (the bound is first-order
-    # worst case), large enough that the proposal visibly depends on the features
-    p = learned_params(31, scale=0.03, sigma0=0.1)
+    # random weights at the scale of a trained network's hidden layers; the
+    # oracle's device-precision network bound decides which
+    # Metropolis-Hastings decisions are checkable
+    p = learned_params(31, scale=0.05, sigma0=0.1)
     say(f"[gpu learned] per-move {name}")
     g = run_learned(S, wl, p, eps, log_chains=64, **kw)
     lo32, hi32 = box32(wl.lower, wl.upper)
     sh32 = None if wl.shift is None else f32(wl.shift)
     q = bf16_matrices(p)
     tau = O.feature_tau(wl.func, wl.n)
-    totals = dict(moves=0, learned=0, outside=0, ambiguous=0)
+    totals = dict(moves=0, learned=0, outside=0, ambiguous=0, max_dl_excess=0.0, max_rel_excess=0.0)
     wl_run = wl.with_(chains=kw["chains"], seed=kw["seed"])
     for level in range(kw["levels"]):
         T = O.temperature(kw["T0"], kw["alpha"], level)
@@ -232,10 +235,10 @@ def test_learned_per_move_parity(S, name, steps):
             st = check_learned_level(wl.func, wl.n, lo32, hi32, sh32, kw["seed"], level, T, featT,
                                      float(np.float32(eps)), q, 0.1, x0, g["moves"][level, c:c + 1], fin, [c])
             for k in totals:
-                totals[k] += st[k]
+                totals[k] = max(totals[k], st[k]) if k.startswith("max") else totals[k] + st[k]
     say(f"[gpu learned] {name}: {totals}")
     assert totals["learned"] > 0.5 * totals["moves"]
-    assert totals["ambiguous"] <= 0.10 * totals["moves"]
+    assert totals["ambiguous"] <= 0.05 * totals["moves"]
     check_record(wl_run.with_(levels=kw["levels"]), g)
 
 
@@ -296,3 +299,52 @@ def test_learned_rejects_unsupported(S):
         with pytest.raises(S.SAError) as e:
             ann.set_proposal(learned_params(1), 0.1)
         assert e.value.status == -4
+
+
+def test_trained_network_replay_at_the_bench_shape(S):
+    """The network as the time-to-target comparison uses it -- trained by
+    learned.collect / learned.train on the device -- replayed move by move
+    against the oracle's learned move at the benchmark shape (n = 100
+    Schwefel, 65536 chains, 100 steps, eps = 0.1), at a late level started
+    near the minimizer (where the learned proposal matters): 16 of the
+    logged chains, every move."""
+    from paper_2408_00018_amd import learned as Lp
+    wl = W.schwefel_n100_fp32()
+    col = S.Schedule(chains=4096, levels=1600, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
+                     precision=S.FP32)
+    say("[gpu learned] trained network: collect + train")
+    rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=16, per_level=2000)
+    params, trace = Lp.train(rec, steps=1500, batch=4096, lr=1e-3, seed=0)
+    say(f"[gpu learned] trained: {rec.shape[0]} records, loss {float(trace[:20].mean()):.3f} -> "
+        f"{float(trace[-50:].mean()):.3f}")
+    assert float(trace[-50:].mean()) < float(trace[:20].mean())
+    q = bf16_matrices(params)
+    rng = np.random.default_rng(7)
+    x0 = W.SCHWEFEL_X_STAR + rng.uniform(-2, 2, wl.n)
+    eps = 0.1
+    for level in (900, 1500):
+        sched = S.Schedule(chains=wl.chains, levels=level + 1, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
+                           seed=wl.seed, precision=S.FP32, trace_x=True, learned=True, log_chains=64,
+                           log_level=level, log_levels=1)
+        say(f"[gpu learned] bench shape level {level}")
+        with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+            ann.set_start(level, x0)
+            ann.set_proposal(params, eps)
+            ann.run(0)
+            moves, final_f = ann.move_log()
+            rec_l, xb = ann.trace(level, 1, with_x=True)
+        T = O.temperature(wl.T0, wl.alpha, level)
+        featT = float(np.float32(math.log(O.feature_tau(wl.func, wl.n) * T)))
+        lo32, hi32 = box32(wl.lower, wl.upper)
+        fin = final_f[0]
+        win = lexi_argmin(fin)
+        assert rec_l["win_chain"][0] == win and rec_l["f_win"][0] == fin[win]
+        totals = dict(moves=0, learned=0, outside=0, ambiguous=0)
+        for c in range(0, 64, 4):
+            st = check_learned_level(wl.func, wl.n, lo32, hi32, None, wl.seed, level, T, featT,
+                                     float(np.float32(eps)), q, wl.radius_frac, f32(x0), moves[0, c:c + 1], fin, [c])
+            for k in totals:
+                totals[k] += st[k]
+        say(f"[gpu learned] trained network, level {level}: {totals}")
+        assert totals["learned"] > 0.8 * totals["moves"]
+        assert totals["ambiguous"] <= 0.05 * totals["moves"]

@@ -84,3 +84,39 @@ def test_fp32_evaluation_within_bound(func, n, shifted):
         # not vacuous: far below the cost's own scale
         assert bound <= 1e-4 * max(1.0, abs(exact)) + (2e-3 if func == O.GRIEWANK else 0.0)
     print(f"func {func} n {n}: max err/bound {worst:.3f}")
+
+
+def _oracle_learned_log(func, n, lo, hi, shift, params, eps, T, featT, steps, chains, seed=3, level=1):
+    """The oracle's own learned level, logged in the device's move-record layout."""
+    from paper_2408_00018_amd.sa import MOVE_DTYPE
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(lo, hi)
+    out = O.learned_run(params, O.NET_DEVICE, func, lo, hi, shift, seed=seed, level=level, nchains=chains,
+                        steps=steps, T=T, featT=featT, eps=eps, x_start=x0, log=True)
+    mv = np.zeros((chains, steps), dtype=MOVE_DTYPE)
+    for key in ("d", "accept", "x_old", "x_new", "df"):
+        mv[key] = out[key].reshape(chains, steps)
+    return x0, mv, out["f_final"]
+
+
+@pytest.mark.parametrize("func,n,lo,hi", [(O.SCHWEFEL, 8, -500.0, 500.0), (O.ACKLEY, 6, -32.768, 32.768)])
+def test_learned_checker_accepts_the_oracle_and_rejects_a_flipped_decision(func, n, lo, hi):
+    """check_learned_level, fed the oracle's own learned level (the device's
+    record layout), passes; the same log with one firm decision flipped
+    fails.  The checker itself holds no Metropolis-Hastings arithmetic: it
+    asks the oracle's learned move for every decision."""
+    import parity_util as P
+    lo_v, hi_v = np.full(n, lo), np.full(n, hi)
+    p = P.bf16_matrices(P.learned_params(11, scale=0.05, sigma0=0.02))
+    T, eps, steps = 2.0, 0.25, 24
+    featT = float(np.float32(np.log(O.feature_tau(func, n) * T)))
+    x0, mv, ff = _oracle_learned_log(func, n, lo_v, hi_v, None, p, eps, T, featT, steps, chains=3)
+    st = P.check_learned_level(func, n, lo_v, hi_v, None, 3, 1, T, featT, eps, p, 0.1, x0, mv, ff, [0, 1, 2])
+    assert st["learned"] > 0 and st["moves"] == 3 * steps
+    # flip the decision of chain 0's first move: the checker must object (at
+    # that decision, at a later move whose logged old value no longer follows,
+    # or at the final cost)
+    bad = mv.copy()
+    bad[0, 0]["accept"] ^= 1
+    with pytest.raises(AssertionError):
+        P.check_learned_level(func, n, lo_v, hi_v, None, 3, 1, T, featT, eps, p, 0.1, x0, bad, ff, [0])
