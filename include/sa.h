@@ -287,6 +287,32 @@ sa_status sa_layout(const sa_ctx *ctx, uint32_t *workgroup, uint32_t *overlay_sl
 /* Release the context and any memory the library allocated. */
 void sa_destroy(sa_ctx *ctx);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * run -- sa_create, sa_run of every level, sa_best and sa_destroy in one call
+ * -- with the workspace in a file-scope device array of
+ * SA_STATIC_SCRATCH_BYTES per GPU (held by each GPU the library runs on
+ * until the process ends) instead of allocated memory.  The call makes no
+ * hipMalloc/hipFree and no host heap allocation; it enqueues on `stream`
+ * (NULL = the null stream), synchronises it, and writes the record as
+ * sa_best does: x_out (n doubles), f_out, level_found (any may be NULL).
+ * Results equal those of sa_create + sa_run(ctx, 0) + sa_best on the same
+ * problem and config (the same kernels and launches).
+ * Limits: n <= SA_STATIC_MAX_N, levels <= SA_STATIC_MAX_LEVELS, a workspace
+ * (sa_workspace_bytes) of at most SA_STATIC_SCRATCH_BYTES, flags 0 or
+ * SA_FLAG_OVERLAY, log_chains = 0; otherwise SA_ERR_UNSUPPORTED with the
+ * reason in sa_last_error().  Every call on a GPU shares that GPU's array,
+ * which keeps the last call's contents (each call clears what it reads
+ * before writing it).  Calls are serialised within a process; calls from
+ * different processes on one GPU use different arrays.
+ */
+#define SA_STATIC_SCRATCH_BYTES ((size_t)8 << 20)
+#define SA_STATIC_MAX_N 4096u
+#define SA_STATIC_MAX_LEVELS 16384u
+sa_status sa_run_static(const sa_problem *prob, const sa_config *cfg, void *stream, double *x_out, double *f_out,
+                        uint32_t *level_found);
+
 /* ------------------------------------------------------------------------
  * Batched runs: nprob independent problems (each with its own function,
  * dimension, box, shift and chain count) advance together, one launch per

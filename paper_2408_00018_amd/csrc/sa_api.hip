@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <new>
 #include <string>
@@ -287,53 +288,61 @@ double feature_tau(const sa_problem &p) { return p.func == SA_RASTRIGIN ? 1.0 : 
 // Box/shift values of coordinate i in the run's precision: (l, u, rho, s).
 void coord_values(const sa_ctx *c, uint32_t i, double out[4])
 {
-    sa::coord_values(c->lower[i], c->upper[i], c->shift.empty() ? 0.0 : c->shift[i], c->fp64, c->cfg.move,
+    sa::coord_values(c->prob.lower[i], c->prob.upper[i], c->prob.shift ? c->prob.shift[i] : 0.0, c->fp64, c->cfg.move,
                      c->cfg.radius_frac, out);
 }
 
-sa_status upload_tables(sa_ctx *c)
+// Host memory the tables are built in before their copies to the device:
+// T (levels doubles), inv_T and featT (levels floats each), tab (4 n reals of
+// the run's precision, used with a per-coordinate table), gco (n floats,
+// Griewank).  It must stay untouched until upload_tables returns.
+struct Staging {
+    double *T;
+    float *inv_T, *featT;
+    void *tab;
+    float *gco;
+};
+
+sa_status upload_tables(sa_ctx *c, const Staging &hs)
 {
     const Layout &l = c->pl.lay;
     const uint32_t n = c->prob.n, L = c->cfg.levels;
-    std::vector<double> T(L);
-    std::vector<float> inv_T(L), featT(L);
     const double tau = feature_tau(c->prob);
     double t = c->cfg.T0;
     for (uint32_t k = 0; k < L; ++k) {
-        T[k] = t;
-        inv_T[k] = (float)(1.0 / t);
-        featT[k] = (float)std::log(tau * t);
+        hs.T[k] = t;
+        hs.inv_T[k] = (float)(1.0 / t);
+        hs.featT[k] = (float)std::log(tau * t);
         t = t * c->cfg.alpha;
     }
-    SA_HIP(hipMemcpyAsync(c->ws + l.T, T.data(), L * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    SA_HIP(hipMemcpyAsync(c->ws + l.inv_T, inv_T.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
-    SA_HIP(hipMemcpyAsync(c->ws + l.featT, featT.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipMemcpyAsync(c->ws + l.T, hs.T, L * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipMemcpyAsync(c->ws + l.inv_T, hs.inv_T, L * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipMemcpyAsync(c->ws + l.featT, hs.featT, L * sizeof(float), hipMemcpyHostToDevice, c->stream));
     double v[4];
     if (c->pl.table) {
         if (c->fp64) {
-            std::vector<double> tab(4 * (size_t)n);
+            double *tab = static_cast<double *>(hs.tab);
             for (uint32_t i = 0; i < n; ++i) {
                 coord_values(c, i, v);
                 for (int k = 0; k < 4; ++k) tab[4 * i + k] = v[k];
             }
-            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice,
+            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab, 4 * (size_t)n * sizeof(double), hipMemcpyHostToDevice,
                                   c->stream));
         } else {
-            std::vector<float> tab(4 * (size_t)n);
+            float *tab = static_cast<float *>(hs.tab);
             for (uint32_t i = 0; i < n; ++i) {
                 coord_values(c, i, v);
                 for (int k = 0; k < 4; ++k) tab[4 * i + k] = (float)v[k];
             }
-            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice,
+            SA_HIP(hipMemcpyAsync(c->ws + l.table, tab, 4 * (size_t)n * sizeof(float), hipMemcpyHostToDevice,
                                   c->stream));
         }
     }
     if (c->prob.func == SA_GRIEWANK) {
         // Griewank's cos(y_i / sqrt(i)) in revolutions: y_i c_i, c_i = 1/(2 pi sqrt(i)), i = 1..n
-        std::vector<float> g(n);
-        for (uint32_t i = 0; i < n; ++i) g[i] = (float)(1.0 / (2.0 * 3.14159265358979323846 * std::sqrt(i + 1.0)));
-        SA_HIP(hipMemcpyAsync(c->ws + l.gcoef, g.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
-        SA_HIP(hipStreamSynchronize(c->stream));
+        for (uint32_t i = 0; i < n; ++i)
+            hs.gco[i] = (float)(1.0 / (2.0 * 3.14159265358979323846 * std::sqrt(i + 1.0)));
+        SA_HIP(hipMemcpyAsync(c->ws + l.gcoef, hs.gco, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
     }
     coord_values(c, 0, v);
     if (c->fp64) {
@@ -347,10 +356,19 @@ sa_status upload_tables(sa_ctx *c)
         c->a32.rho = (float)v[2];
         c->a32.sh = (float)v[3];
     }
-    // The host copies above read pageable memory; finish them before the
-    // vectors go out of scope.
+    // The copies above read pageable host memory; finish them before the
+    // staging memory is reused or released.
     SA_HIP(hipStreamSynchronize(c->stream));
     return SA_OK;
+}
+
+// upload_tables with staging in host vectors of the right sizes.
+sa_status upload_tables(sa_ctx *c)
+{
+    const size_t n = c->prob.n, L = c->cfg.levels;
+    std::vector<double> T(L), tab(4 * n);
+    std::vector<float> inv_T(L), featT(L), gco(n);
+    return upload_tables(c, Staging{T.data(), inv_T.data(), featT.data(), tab.data(), gco.data()});
 }
 
 // Enqueue levels [first, first + count), one launch each (the logged levels
@@ -759,3 +777,125 @@ void sa_destroy(sa_ctx *c)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free run (sa_run_static): the workspace of sa_create lives in a
+// file-scope device array, one copy per GPU, instead of hipMalloc'd memory.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kStaticScratchBytes = SA_STATIC_SCRATCH_BYTES;
+constexpr uint32_t kStaticMaxLevels = SA_STATIC_MAX_LEVELS;
+constexpr uint32_t kStaticMaxN = SA_STATIC_MAX_N;
+constexpr int kStaticMaxDevices = 64;
+
+// Device scratch: one copy per GPU the library's code object is loaded on.
+// Host code never passes this name to a kernel or a copy: it reaches the
+// memory through the per-device address hipGetSymbolAddress returns.
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Host staging of the tables and of the record's read-back (sized for the
+// largest level count and dimension sa_run_static accepts).
+alignas(64) double g_static_T[kStaticMaxLevels];
+alignas(64) float g_static_inv_T[kStaticMaxLevels];
+alignas(64) float g_static_featT[kStaticMaxLevels];
+alignas(64) double g_static_tab[4 * (size_t)kStaticMaxN];
+alignas(64) float g_static_gco[kStaticMaxN];
+alignas(64) float g_static_x[kStaticMaxN];
+
+// Serialises sa_run_static within the process (the host staging above and the
+// device scratch are shared by every call).
+std::mutex g_static_mu;
+unsigned char *g_static_ptr[kStaticMaxDevices];  // device address of `scratch`, per device
+
+}  // namespace
+
+extern "C" sa_status sa_run_static(const sa_problem *prob, const sa_config *cfg, void *stream, double *x_out,
+                                   double *f_out, uint32_t *level_found)
+{
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    sa::g_last_error.clear();
+    sa_status st = validate(prob, cfg);
+    if (st != SA_OK) return st;
+    if (cfg->flags & ~SA_FLAG_OVERLAY)
+        return fail(SA_ERR_UNSUPPORTED, "sa_run_static takes SA_FLAG_OVERLAY only (no trace, graph or learned runs)");
+    if (cfg->log_chains) return fail(SA_ERR_UNSUPPORTED, "sa_run_static keeps no move log");
+    if (prob->n > kStaticMaxN) return fail(SA_ERR_UNSUPPORTED, "sa_run_static: n = %u exceeds %u", prob->n, kStaticMaxN);
+    if (cfg->levels > kStaticMaxLevels)
+        return fail(SA_ERR_UNSUPPORTED, "sa_run_static: %u levels exceed %u", cfg->levels, kStaticMaxLevels);
+
+    int dev = 0;
+    SA_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(SA_ERR_UNSUPPORTED, "device index %d out of range", dev);
+    if (!g_static_ptr[dev]) {
+        hipDeviceProp_t prop;
+        SA_HIP(hipGetDeviceProperties(&prop, dev));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(SA_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950 only", dev,
+                        prop.gcnArchName);
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(SA_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_static_ptr[dev] = static_cast<unsigned char *>(ptr);
+    }
+    int lds = 0, cus = 0;
+    SA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    SA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+
+    // The context lives on the stack and reads the caller's arrays in place
+    // (they are valid for the duration of the call): no host or device
+    // allocation.
+    sa_ctx c;
+    c.device = dev;
+    c.stream = reinterpret_cast<hipStream_t>(stream);
+    c.cfg = *cfg;
+    c.seed = cfg->seed;
+    c.fp64 = cfg->precision == SA_FP64;
+    c.prob = *prob;
+    if (!c.fp64) {
+        for (uint32_t i = 0; i < prob->n; ++i)
+            if (!(sa::round_up_f(prob->lower[i]) < sa::round_down_f(prob->upper[i])))
+                return fail(SA_ERR_INVALID, "box %u is empty after rounding inward to FP32", i);
+    }
+    st = plan(&c.prob, &c.cfg, std::min<size_t>(kLdsPerWorkgroup, (size_t)lds), &c.pl);
+    if (st != SA_OK) return st;
+    if (c.pl.lay.total > kStaticScratchBytes)
+        return fail(SA_ERR_UNSUPPORTED, "the run needs %zu bytes of workspace; the static scratch holds %zu",
+                    c.pl.lay.total, kStaticScratchBytes);
+    c.ws = g_static_ptr[dev];
+    if (c.fp64)
+        fill_args<double>(&c, c.a64);
+    else
+        fill_args<float>(&c, c.a32);
+    c.a32.num_cus = c.a64.num_cus = (uint32_t)cus;
+    st = upload_tables(&c, Staging{g_static_T, g_static_inv_T, g_static_featT, g_static_tab, g_static_gco});
+    // The record starts empty (a kernel clears it: the scratch keeps the
+    // previous call's contents); every other word a run reads is written by
+    // the level that precedes the read.
+    if (st == SA_OK) st = enqueue_reset(&c);
+    if (st == SA_OK) st = enqueue_levels(&c, 0, cfg->levels, c.stream, &c.groups);
+    if (st != SA_OK) {
+        (void)hipStreamSynchronize(c.stream);
+        return st;
+    }
+    SA_HIP(hipStreamSynchronize(c.stream));
+    const Layout &l = c.pl.lay;
+    double rec[2];
+    uint32_t lvl = 0;
+    SA_HIP(hipMemcpy(rec, c.ws + l.rec, sizeof rec, hipMemcpyDeviceToHost));
+    SA_HIP(hipMemcpy(&lvl, c.ws + l.rec_level, sizeof lvl, hipMemcpyDeviceToHost));
+    if (lvl == 0xFFFFFFFFu) return fail(SA_ERR_STATE, "no record after %u levels", cfg->levels);
+    if (x_out) {
+        const uint32_t n = prob->n;
+        if (c.fp64) {
+            SA_HIP(hipMemcpy(x_out, c.ws + l.x_rec, n * sizeof(double), hipMemcpyDeviceToHost));
+        } else {
+            SA_HIP(hipMemcpy(g_static_x, c.ws + l.x_rec, n * sizeof(float), hipMemcpyDeviceToHost));
+            for (uint32_t i = 0; i < n; ++i) x_out[i] = g_static_x[i];
+        }
+    }
+    if (f_out) *f_out = rec[0];
+    if (level_found) *level_found = lvl;
+    return SA_OK;
+}

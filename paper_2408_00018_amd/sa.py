@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ER
 
 EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
             "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_layout",
-            "sa_destroy", "sa_last_error"]
+            "sa_destroy", "sa_last_error", "sa_run_static"]
 
 
 class SAError(RuntimeError):
@@ -102,6 +102,8 @@ def load_library():
     L.sa_layout.restype = st
     L.sa_destroy.argtypes = [vp]
     L.sa_destroy.restype = None
+    L.sa_run_static.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config), vp, vp, vp, vp]
+    L.sa_run_static.restype = st
     L.sa_last_error.argtypes = []
     L.sa_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -160,6 +162,24 @@ def workspace_bytes(func, lower, upper, shift, sched: Schedule) -> int:
     _check(L.sa_workspace_bytes(ctypes.byref(p), ctypes.byref(cfg), ctypes.byref(nbytes)))
     del keep
     return nbytes.value
+
+
+def run_static(func, lower, upper, shift=None, *, schedule: Schedule, stream=None):
+    """One whole run through ``sa_run_static`` (no device allocation: the
+    workspace is the library's static per-GPU scratch).  Returns the record
+    (x_rec, f_rec, level) as ``Annealer.best`` does."""
+    import torch
+    L = load_library()
+    p, keep = _problem_struct(func, lower, upper, shift)
+    cfg = schedule.to_c()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    x = np.zeros(p.n)
+    f = ctypes.c_double()
+    lvl = ctypes.c_uint32()
+    _check(L.sa_run_static(ctypes.byref(p), ctypes.byref(cfg), ctypes.c_void_p(s.cuda_stream), x.ctypes.data,
+                           ctypes.byref(f), ctypes.byref(lvl)))
+    del keep
+    return x, f.value, lvl.value
 
 
 class Annealer:
