@@ -388,6 +388,57 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
                             double *moves_per_s_out);
 
 /* Description of the calling thread's last error ("" if none). */
+/* ------------------------------------------------------------------------
+ * Nelder-Mead polish (the paper's hybrid strategy: a local minimizer started
+ * where the annealing stopped, Sec. 4.2, hybrid results table).  The paper
+ * names the method only; the steps are the standard simplex method with
+ * reflection 1, expansion 2, contraction 1/2 and shrink 1/2 (Lagarias, Reeds,
+ * Wright, Wright, SIAM J. Optim. 9, 1998), each trial point projected onto
+ * the box.  Start simplex: x0 and x0 + h_i e_i, h_i = x0_i / 20 (0.00025 if
+ * x0_i = 0), reflected to x0 - h_i e_i where that leaves the box.  Per
+ * iteration b = lowest cost, w = highest among the others, s = highest among
+ * all but w (ties to the lowest vertex); stop when f_w - f_b <= ftol and every
+ * vertex is within xtol of x_b in every coordinate, or after maxiter
+ * iterations.  FP64 arithmetic, costs summed in coordinate order.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t maxiter;   /* iteration cap */
+    uint32_t log_steps; /* nonzero: record each iteration's step code */
+    double ftol, xtol;  /* termination tolerances, >= 0 */
+} sa_nm_config;
+
+/* Nelder-Mead step codes in the step log. */
+#define SA_NM_REFLECT 0
+#define SA_NM_EXPAND 1
+#define SA_NM_OUTSIDE 2
+#define SA_NM_INSIDE 3
+#define SA_NM_SHRINK 4
+
+/* Bytes of device workspace sa_nm_polish needs. */
+sa_status sa_nm_workspace_bytes(const sa_problem *prob, uint32_t starts, const sa_nm_config *cfg, size_t *bytes);
+
+/* Polish `starts` start points at once (one wave each) on the current HIP
+ * device.  x0: starts x n host doubles inside the box.  workspace: device
+ * memory of sa_nm_workspace_bytes bytes, 256-byte aligned (NULL = the
+ * library allocates and frees it).  Outputs (host, any may be NULL): x_out
+ * starts x n (each start's lowest vertex at the end), f_out (its cost),
+ * iters_out, evals_out (iterations and cost evaluations), step_log (starts x
+ * maxiter codes, needs cfg->log_steps; entries past iters_out are unset).
+ * n <= 2048.  Synchronises `stream`. */
+sa_status sa_nm_polish(const sa_problem *prob, const double *x0, uint32_t starts, const sa_nm_config *cfg,
+                       void *stream, void *workspace, size_t ws_bytes, double *x_out, double *f_out,
+                       uint32_t *iters_out, uint32_t *evals_out, uint8_t *step_log);
+
+/* The k lowest-cost candidates of the last level enqueued, lowest first
+ * (each the best chain of one workgroup's tiles, by the cost its chain
+ * carried; ties to the lower chain): the start points of a polish from the
+ * top k chains (synchronises).  x_out: k x n doubles; f_out: k full FP64
+ * re-evaluations; chains_out: k chain indices.  k must not exceed the number
+ * of candidates the level published (*available, which may be NULL, returns
+ * it; k = 0 only queries).  Any output may be NULL. */
+sa_status sa_candidates(sa_ctx *ctx, uint32_t k, double *x_out, double *f_out, uint32_t *chains_out,
+                        uint32_t *available);
+
 const char *sa_last_error(void);
 
 /* ------------------------------------------------------------------------

@@ -109,7 +109,7 @@ def lib():
         L.orc_sa_run_capture.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32,
                                          _p, _d, _p, ctypes.c_uint64, _p]
         L.orc_sa_run_capture.restype = _i
-        L.orc_nelder_mead.argtypes = [_i, _u32, _p, _p, _p, _p, _u32, _d, _d, _p, _p, _p, _p, _p]
+        L.orc_nelder_mead.argtypes = [_i, _u32, _p, _p, _p, _p, _u32, _d, _d, _p, _p, _p, _p, _p, _p]
         L.orc_nelder_mead.restype = _i
         L.orc_set_threads.argtypes = [_i]
         L.orc_set_threads.restype = None
@@ -474,7 +474,8 @@ NM_REFLECT, NM_EXPAND, NM_OUTSIDE, NM_INSIDE, NM_SHRINK = 0, 1, 2, 3, 4
 
 
 def nelder_mead(func, lower, upper, shift=None, *, x0, maxiter=10000, ftol=1e-12, xtol=1e-10):
-    """Box-projected Nelder-Mead from x0; returns dict(x, f, iters, evals, steps)."""
+    """Box-projected Nelder-Mead from x0; returns dict(x, f, iters, evals, steps,
+    gaps): steps[i] is iteration i's step code, gaps[i] = f_w - f_b at its start."""
     lo, hi, s, x = _f64(lower), _f64(upper), _f64(shift), _f64(x0)
     n = lo.size
     xo = np.zeros(n)
@@ -482,8 +483,10 @@ def nelder_mead(func, lower, upper, shift=None, *, x0, maxiter=10000, ftol=1e-12
     it = ctypes.c_uint32()
     ev = ctypes.c_uint32()
     log = np.zeros(maxiter, dtype=np.uint8)
+    gaps = np.zeros(maxiter)
     rc = lib().orc_nelder_mead(func, n, _ptr(lo), _ptr(hi), _ptr(s), _ptr(x), maxiter, ftol, xtol, _ptr(xo),
-                               ctypes.byref(f), ctypes.byref(it), ctypes.byref(ev), _ptr(log))
+                               ctypes.byref(f), ctypes.byref(it), ctypes.byref(ev), _ptr(log), _ptr(gaps))
     if rc != 0:
         raise RuntimeError(f"orc_nelder_mead failed: {rc}")
-    return dict(x=xo, f=f.value, iters=it.value, evals=ev.value, steps=log[:it.value].copy())
+    return dict(x=xo, f=f.value, iters=it.value, evals=ev.value, steps=log[:it.value].copy(),
+                gaps=gaps[:it.value].copy())

@@ -1207,7 +1207,8 @@ int orc_learned_run(const double *params, int mode, int func, uint32_t n, const 
 /*   Start: slot 0 = x0, slot i = x0 + h_i e_i, h_i = x0_i / 20 (0.00025 if   */
 /*   x0_i = 0), reflected to x0 - h_i e_i when x0 + h_i e_i leaves the box.  */
 /* Step codes logged per iteration: 0 reflect, 1 expand, 2 outside          */
-/* contraction, 3 inside contraction, 4 shrink.                              */
+/* contraction, 3 inside contraction, 4 shrink.  gap_log (optional) gets     */
+/* f[w] - f[b] at the start of each iteration.                               */
 /* ======================================================================== */
 static void nm_point(uint32_t n, const double *lower, const double *upper, const double *xm, const double *xw,
                      double t, double *out)
@@ -1223,7 +1224,7 @@ static void nm_point(uint32_t n, const double *lower, const double *upper, const
 
 int orc_nelder_mead(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
                     const double *x0, uint32_t maxiter, double ftol, double xtol, double *x_out, double *f_out,
-                    uint32_t *iters_out, uint32_t *evals_out, uint8_t *step_log)
+                    uint32_t *iters_out, uint32_t *evals_out, uint8_t *step_log, double *gap_log)
 {
     const uint32_t m = n + 1;
     double *V = (double *)malloc(sizeof(double) * (size_t)m * n);
@@ -1261,6 +1262,7 @@ int orc_nelder_mead(int func, uint32_t n, const double *lower, const double *upp
         uint32_t s = w == 0 ? 1 : 0;
         for (uint32_t i = 0; i < m; ++i)
             if (i != w && F[i] > F[s]) s = i;
+        if (gap_log) gap_log[it] = F[w] - F[b];
         /* convergence */
         double spread = 0.0;
         const double *xb = V + (size_t)b * n;

@@ -427,6 +427,34 @@ sa_status enqueue_reset(sa_ctx *c)
     return SA_OK;
 }
 
+template <typename R>
+sa_status read_candidates(sa_ctx *c, uint32_t k, double *x_out, double *f_out, uint32_t *chains_out)
+{
+    const Layout &l = c->pl.lay;
+    const uint32_t n = c->prob.n, G = c->groups, last = c->next_level - 1;
+    const size_t base = (size_t)(last & 1u) * c->pl.groups;
+    std::vector<sa::Slot<R>> slots(G);
+    SA_HIP(hipMemcpy(slots.data(), c->ws + l.slots + base * sizeof(sa::Slot<R>), G * sizeof(sa::Slot<R>),
+                     hipMemcpyDeviceToHost));
+    std::vector<uint32_t> order(G);
+    for (uint32_t j = 0; j < G; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t p, uint32_t q) {
+        return slots[p].f < slots[q].f || (slots[p].f == slots[q].f && slots[p].chain < slots[q].chain);
+    });
+    std::vector<R> x(n);
+    for (uint32_t r = 0; r < k; ++r) {
+        const sa::Slot<R> &sl = slots[order[r]];
+        if (f_out) f_out[r] = sl.ff;
+        if (chains_out) chains_out[r] = sl.chain;
+        if (x_out) {
+            SA_HIP(hipMemcpy(x.data(), c->ws + l.slot_x + ((base + order[r]) * n) * sizeof(R), n * sizeof(R),
+                             hipMemcpyDeviceToHost));
+            for (uint32_t i = 0; i < n; ++i) x_out[(size_t)r * n + i] = (double)x[i];
+        }
+    }
+    return SA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -764,6 +792,20 @@ sa_status sa_capture_count(sa_ctx *c, uint64_t *count)
     SA_HIP(hipMemcpy(&v, c->ws + c->pl.lay.cap_count, sizeof v, hipMemcpyDeviceToHost));
     *count = v;
     return SA_OK;
+}
+
+sa_status sa_candidates(sa_ctx *c, uint32_t k, double *x_out, double *f_out, uint32_t *chains_out,
+                        uint32_t *available)
+{
+    sa::g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (c->next_level == 0 || c->next_level == c->first_level) return fail(SA_ERR_STATE, "no level has run");
+    if (available) *available = c->groups;
+    if (k > c->groups) return fail(SA_ERR_INVALID, "k = %u exceeds the %u candidates of the last level", k, c->groups);
+    if (k == 0) return SA_OK;
+    SA_HIP(hipStreamSynchronize(c->stream));
+    return c->fp64 ? read_candidates<double>(c, k, x_out, f_out, chains_out)
+                   : read_candidates<float>(c, k, x_out, f_out, chains_out);
 }
 
 void sa_destroy(sa_ctx *c)

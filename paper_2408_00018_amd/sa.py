@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ER
 
 EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
             "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_layout",
-            "sa_destroy", "sa_last_error", "sa_run_static"]
+            "sa_destroy", "sa_last_error", "sa_run_static", "sa_nm_workspace_bytes", "sa_nm_polish",
+            "sa_candidates"]
 
 
 class SAError(RuntimeError):
@@ -59,6 +60,11 @@ MOVE_DTYPE = np.dtype([("d", np.uint32), ("accept", np.uint32), ("x_old", np.flo
                        ("df", np.float64)])
 
 _lib = None
+
+
+class NMConfig(ctypes.Structure):
+    _fields_ = [("maxiter", ctypes.c_uint32), ("log_steps", ctypes.c_uint32), ("ftol", ctypes.c_double),
+                ("xtol", ctypes.c_double)]
 
 
 def load_library():
@@ -104,6 +110,14 @@ def load_library():
     L.sa_destroy.restype = None
     L.sa_run_static.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Config), vp, vp, vp, vp]
     L.sa_run_static.restype = st
+    L.sa_nm_workspace_bytes.argtypes = [ctypes.POINTER(Problem), u32, ctypes.POINTER(NMConfig),
+                                        ctypes.POINTER(ctypes.c_size_t)]
+    L.sa_nm_workspace_bytes.restype = st
+    L.sa_nm_polish.argtypes = [ctypes.POINTER(Problem), vp, u32, ctypes.POINTER(NMConfig), vp, vp, ctypes.c_size_t,
+                               vp, vp, vp, vp, vp]
+    L.sa_nm_polish.restype = st
+    L.sa_candidates.argtypes = [vp, u32, vp, vp, vp, ctypes.POINTER(u32)]
+    L.sa_candidates.restype = st
     L.sa_last_error.argtypes = []
     L.sa_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -164,6 +178,31 @@ def workspace_bytes(func, lower, upper, shift, sched: Schedule) -> int:
     return nbytes.value
 
 
+def nm_polish(func, lower, upper, shift=None, *, x0, maxiter: int = 10000, ftol: float = 1e-12,
+              xtol: float = 1e-10, log_steps: bool = False, stream=None):
+    """Nelder-Mead polish of the start points x0 ([k, n] or [n]) on the
+    device, one wave per start (``sa_nm_polish``).  Returns dict(x [k, n],
+    f [k], iters [k], evals [k], steps [k, maxiter] or None)."""
+    import torch
+    L = load_library()
+    p, keep = _problem_struct(func, lower, upper, shift)
+    starts = np.ascontiguousarray(np.atleast_2d(np.asarray(x0, dtype=np.float64)))
+    k, n = starts.shape
+    assert n == p.n
+    cfg = NMConfig(maxiter, 1 if log_steps else 0, ftol, xtol)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    x = np.zeros((k, n))
+    f = np.zeros(k)
+    it = np.zeros(k, dtype=np.uint32)
+    ev = np.zeros(k, dtype=np.uint32)
+    steps = np.zeros((k, maxiter), dtype=np.uint8) if log_steps else None
+    _check(L.sa_nm_polish(ctypes.byref(p), starts.ctypes.data, k, ctypes.byref(cfg), ctypes.c_void_p(s.cuda_stream),
+                          None, 0, x.ctypes.data, f.ctypes.data, it.ctypes.data, ev.ctypes.data,
+                          None if steps is None else steps.ctypes.data))
+    del keep
+    return dict(x=x, f=f, iters=it, evals=ev, steps=steps)
+
+
 def run_static(func, lower, upper, shift=None, *, schedule: Schedule, stream=None):
     """One whole run through ``sa_run_static`` (no device allocation: the
     workspace is the library's static per-GPU scratch).  Returns the record
@@ -191,6 +230,10 @@ class Annealer:
         L = load_library()
         self.schedule = schedule
         self.n = int(np.asarray(lower).size)
+        self.func = func
+        self.lower = np.array(lower, dtype=np.float64)
+        self.upper = np.array(upper, dtype=np.float64)
+        self.shift = None if shift is None else np.array(shift, dtype=np.float64)
         p, keep = _problem_struct(func, lower, upper, shift)
         cfg = schedule.to_c()
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -264,6 +307,34 @@ class Annealer:
         assert records.dim() == 2 and records.shape[1] == 7 and records.is_contiguous()
         self._cap = records
         _check(load_library().sa_capture(self._ctx, ctypes.c_void_p(records.data_ptr()), records.shape[0]))
+
+    def candidates(self, k: int = 0):
+        """The k lowest-cost candidates of the last level run (one per
+        workgroup; k = 0: all of them), lowest first: (x [k, n], f [k]
+        re-evaluated in FP64, chains [k])."""
+        L = load_library()
+        avail = ctypes.c_uint32()
+        _check(L.sa_candidates(self._ctx, 0, None, None, None, ctypes.byref(avail)))
+        k = avail.value if k == 0 else k
+        x = np.zeros((k, self.n))
+        f = np.zeros(k)
+        ch = np.zeros(k, dtype=np.uint32)
+        _check(L.sa_candidates(self._ctx, k, x.ctypes.data, f.ctypes.data, ch.ctypes.data, None))
+        return x, f, ch
+
+    def polish(self, k: int = 8, *, maxiter: int = 10000, ftol: float = 1e-12, xtol: float = 1e-10):
+        """The hybrid strategy: Nelder-Mead from the record and the k - 1
+        lowest-cost candidates of the last level, on the device; returns
+        (x, f, start index) of the best polished point."""
+        x_rec, _, _ = self.best()
+        starts = [x_rec]
+        if k > 1:
+            cx, _, _ = self.candidates(0)
+            starts.extend(cx[:k - 1])
+        r = nm_polish(self.func, self.lower, self.upper, self.shift, x0=np.array(starts), maxiter=maxiter, ftol=ftol,
+                      xtol=xtol, stream=self._stream)
+        j = int(np.argmin(r["f"]))
+        return r["x"][j], float(r["f"][j]), j
 
     def layout(self):
         """(lanes per workgroup, overlay slots per chain or 0, tiles)."""
