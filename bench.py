@@ -7,7 +7,7 @@ definition, already on the device.  Prints one JSON line.
 
 Also reported (unless --no-ttt): time to |f - f*| < 1e-4 on the same
 problem, plain radius moves against the learned proposal (network trained on
-the GPU from accepted moves of plain runs), on the schedule extended to 4000
+the GPU from accepted moves of plain runs), on the schedule extended to 8000
 levels, from random starts and from a final-approach start.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--cpu-levels L] [--no-cpu] [--probe] [--no-ttt]
@@ -92,7 +92,7 @@ def parse():
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
     p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
     p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
-    p.add_argument("--ttt-seeds", type=int, default=5, help="seeds per arm of the time-to-target comparison")
+    p.add_argument("--ttt-seeds", type=int, default=10, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--exchange-sweep", action="store_true",
                    help="bench workload with the winner broadcast every level, every 10 levels and never")
     p.add_argument("--paper-tables", action="store_true",
@@ -106,17 +106,47 @@ def parse():
     return p.parse_args()
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, levels):
+    """The FP64 oracle on the host's cores: the first `levels` levels of the
+    workload single-threaded, then the first 4 x `levels` levels with one
+    thread per usable core (chains of a level split over threads; the results
+    are identical for every thread count).  `value` is the all-core rate."""
     import oracle
     oracle.build(force=False)
-    t0 = time.perf_counter()
-    oracle.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=wl.chains, steps=wl.steps, T0=wl.T0,
-                  alpha=wl.alpha, levels=levels, radius_frac=wl.radius_frac, keep_x_best=False)
-    dt = time.perf_counter() - t0
-    moves = wl.chains * wl.steps * levels
-    return {"value": moves / dt, "unit": "moves/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {levels} of {wl.levels} levels, all {wl.chains} chains x {wl.steps} steps, "
-                      f"FP64, single thread, {dt:.1f} s"}
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    # at most the 16 cores a one-GPU share of the host has
+    threads = max(1, min(usable, 16))
+
+    def timed(nthreads, nlev):
+        oracle.set_threads(nthreads)
+        t0 = time.perf_counter()
+        oracle.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=wl.chains, steps=wl.steps,
+                      T0=wl.T0, alpha=wl.alpha, levels=nlev, radius_frac=wl.radius_frac, keep_x_best=False)
+        return time.perf_counter() - t0
+
+    dt1 = timed(1, levels)
+    all_levels = 4 * levels
+    dtn = timed(threads, all_levels)
+    oracle.set_threads(1)
+    per_level = wl.chains * wl.steps
+    single = {"value": per_level * levels / dt1, "unit": "moves/s", "cores": 1,
+              "sample": f"first {levels} of {wl.levels} levels, all {wl.chains} chains x {wl.steps} steps, "
+                        f"FP64, one thread, {dt1:.1f} s"}
+    return {"value": per_level * all_levels / dtn, "unit": "moves/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {all_levels} of {wl.levels} levels, all {wl.chains} chains x {wl.steps} steps, FP64, "
+                      f"{threads} threads over the chains of each level, {dtn:.1f} s",
+            "single_thread": single, "usable_cpus": usable, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def probe_rates():
@@ -153,21 +183,23 @@ def time_to_target_report(wl, seeds):
     levels, seed 1001) capture accepted moves at every 8th level, 20000 per
     level (repeated where fewer were accepted): 10^7 records.  Training: 6000 Adam steps,
     minibatch 4096, lr 1e-3.  Arms, on 65536 chains x 100 steps,
-    T_k = 10 * 0.995^k up to k = 3999: 'full' starts at level 0 from random
+    T_k = 10 * 0.995^k up to k = 7999: 'full' starts at level 0 from random
     points; 'final_approach' starts at level 3000 (T = 2.9e-6, where the thermal
     gap n T / 2 = 1.5e-4 is at the target's scale) with every chain at
-    x* + U(-2, 2) per coordinate.  Arms: plain moves, the learned mixture from
-    the first level, and (full regime) 'learned_late': plain moves until the
-    first level whose thermal gap n T / 2 is at most the target, the learned
-    mixture from there on.
+    x* + U(-2, 2) per coordinate.  Arms: plain radius moves, plain
+    whole-interval resampling moves, the learned mixture from the first
+    level, and (full regime) 'learned_late': plain moves until the first level
+    whose thermal gap n T / 2 is at most the target, the learned mixture from
+    there on.  Each arm runs `seeds` seeds; the summary gives hit fractions,
+    median times and the learned / plain ratios of median times.
     """
     import torch
     from paper_2408_00018_amd import learned as Lp
     from paper_2408_00018_amd import sa
-    levels = 4000
+    levels = 8000
     out = {"target": 1e-4, "f_star": W.SCHWEFEL_F_STAR, "levels_cap": levels}
     t0 = time.perf_counter()
-    col = sa.Schedule(chains=4096, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
+    col = sa.Schedule(chains=4096, levels=4000, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
                       precision=sa.FP32)
     rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=8, per_level=20000)
     torch.cuda.synchronize()
@@ -186,14 +218,15 @@ def time_to_target_report(wl, seeds):
     out["learned_late_from_level"] = k_late
     for regime, start in (("full", 0), ("final_approach", 3000)):
         res = {}
-        arms = [("plain", None, 0), ("learned", params, 0)]
+        arms = [("plain", None, 0, sa.MOVE_RADIUS), ("plain_resample", None, 0, sa.MOVE_RESAMPLE),
+                ("learned", params, 0, sa.MOVE_RADIUS)]
         if start == 0:
-            arms.append(("learned_late", params, k_late))
-        for arm, p, learn_from in arms:
+            arms.append(("learned_late", params, k_late, sa.MOVE_RADIUS))
+        for arm, p, learn_from, move in arms:
             runs = []
             for seed in range(1, seeds + 1):
                 sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
-                                    seed=seed, precision=sa.FP32)
+                                    seed=seed, precision=sa.FP32, move=move)
                 r = Lp.time_to_target(wl.func, wl.lower, wl.upper, wl.shift, sched, W.SCHWEFEL_F_STAR, 1e-4,
                                       params=p, eps=0.1, start_level=start, x_start=x0 if start else None,
                                       learn_from=learn_from)
@@ -208,8 +241,12 @@ def time_to_target_report(wl, seeds):
             summary[a] = {"hit_fraction": len(secs) / len(res[a]),
                           "median_seconds": float(np.median(secs)) if secs else None,
                           "median_final_gap": float(np.median([r["final_gap"] for r in res[a]]))}
-        if summary["plain"]["median_seconds"] and summary["learned"]["median_seconds"]:
-            summary["speedup_median"] = summary["plain"]["median_seconds"] / summary["learned"]["median_seconds"]
+        # learned / plain speedups: median seconds to the target of each plain
+        # arm that hits it, over that of each learned arm
+        for pa in ("plain", "plain_resample"):
+            for la in ("learned", "learned_late"):
+                if la in summary and summary[pa]["median_seconds"] and summary[la]["median_seconds"]:
+                    summary[f"speedup_{la}_vs_{pa}"] = summary[pa]["median_seconds"] / summary[la]["median_seconds"]
         if "learned_late" in summary and summary["learned"]["median_seconds"] and \
                 summary["learned_late"]["median_seconds"]:
             summary["late_vs_learned_median"] = (summary["learned"]["median_seconds"] /
