@@ -81,6 +81,11 @@ def lib():
         L.orc_sa_run.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32, _u32,
                                  _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
         L.orc_sa_run.restype = _i
+        L.orc_sa_run_v.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _u32, _d, _d, _d, _i, _u32, _u32, _u32,
+                                    _u32, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p, _p]
+        L.orc_sa_run_v.restype = _i
+        L.orc_sos_uniform.argtypes = [_u64, _u32, _u32, _u32]
+        L.orc_sos_uniform.restype = _d
         L.orc_replay_level.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _d, _d, _i, _u32, _p, _u32, _u32,
                                        _p, _p, _p, _p, _p, _p, _p]
         L.orc_replay_level.restype = _i
@@ -205,9 +210,18 @@ def set_threads(threads: int):
     lib().orc_set_threads(int(threads))
 
 
+VARIANT_SOS, VARIANT_BEST_SEEN = 1, 2
+
+
+def sos_uniform(seed, problem, level, chain) -> float:
+    """Uniform of the stochastic exchange decision of `chain` at `level`."""
+    return lib().orc_sos_uniform(seed, problem, level, chain)
+
+
 def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
            move_rule=MOVE_RADIUS, exchange=True, problem=0, level_begin=0, x_start=None, chain_x=None,
-           chain_cost=None, record=None, keep_x_best=True, final_f=False):
+           chain_cost=None, record=None, keep_x_best=True, final_f=False, sos=False, best_seen=False,
+           f_win_prev=None, kept=False):
     """Run levels [level_begin, level_begin+levels) of the multi-chain SA.
 
     ``exchange``: levels between broadcasts of the winner -- 1 or True: every
@@ -216,13 +230,20 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
     state and carried cost (``chain_x`` [chains, n] and ``chain_cost``
     [chains, 3] = f, s1, s2, carried in from an earlier call and returned).
     ``record`` = (x_rec, f_rec, rec_level) carried in from an earlier call.
+    ``sos``: stochastic exchange at the levels that start with one (each
+    chain keeps its own state with probability exp(-(f_own - f_win)/T_prev));
+    ``best_seen``: each chain's best-seen state of a level stands in for its
+    final state in the argmin, broadcast and record.  ``f_win_prev``: the
+    winner cost of level level_begin - 1 (sos runs that start past level 0).
+    ``kept``: also return, for the last level, which chains kept their state.
     Returns a dict of per-level outputs and the record."""
     lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
     n = lo.size
     period = 1 if exchange is True else 0 if exchange is False else int(exchange)
+    variant = (VARIANT_SOS if sos else 0) | (VARIANT_BEST_SEEN if best_seen else 0)
     xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
     cx = cc = None
-    if period != 1:
+    if period != 1 or sos:
         cx = np.zeros(chains * n) if chain_x is None else _f64(chain_x).copy().reshape(-1)
         cc = np.zeros(chains * 3) if chain_cost is None else _f64(chain_cost).copy().reshape(-1)
     if record is None:
@@ -240,10 +261,13 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
     xb = np.zeros(levels * n) if keep_x_best else None
     acc = np.zeros(levels, dtype=np.uint64)
     ff = np.zeros(chains) if final_f else None
-    rc = lib().orc_sa_run(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
-                          radius_frac, move_rule, period, level_begin, levels, _ptr(xs), _ptr(cx), _ptr(cc),
-                          _ptr(x_rec), ctypes.byref(f_rec_io), ctypes.byref(rec_level), _ptr(win), _ptr(f_win),
-                          _ptr(f_best), _ptr(f_rec), _ptr(xb), _ptr(acc), _ptr(ff))
+    fw = ctypes.c_double(0.0 if f_win_prev is None else f_win_prev)
+    kp = np.zeros(chains, dtype=np.uint8) if kept else None
+    rc = lib().orc_sa_run_v(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
+                            radius_frac, move_rule, period, variant, level_begin, levels, _ptr(xs), _ptr(cx),
+                            _ptr(cc), ctypes.byref(fw), _ptr(x_rec), ctypes.byref(f_rec_io), ctypes.byref(rec_level),
+                            _ptr(win), _ptr(f_win), _ptr(f_best), _ptr(f_rec), _ptr(xb), _ptr(acc), _ptr(ff),
+                            _ptr(kp))
     if rc != 0:
         raise RuntimeError(f"orc_sa_run failed: {rc}")
     out = dict(win_chain=win, f_win=f_win, f_best=f_best, f_rec=f_rec, accepts=acc, x_last=xs,
@@ -252,9 +276,12 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
         out["x_best"] = xb.reshape(levels, n)
     if final_f:
         out["final_f"] = ff
-    if period != 1:
+    if period != 1 or sos:
         out["chain_x"] = cx.reshape(chains, n)
         out["chain_cost"] = cc.reshape(chains, 3)
+    out["f_win_last"] = fw.value
+    if kept:
+        out["kept"] = kp.astype(bool)
     return out
 
 

@@ -62,6 +62,28 @@
 
 #define ORC_TAG_MOVE 0u
 #define ORC_TAG_INIT 1u
+#define ORC_TAG_SOS 5u
+
+/* Variants of the multi-chain run (orc_sa_run_v).
+ *   ORC_VARIANT_SOS: stochastic exchange.  The paper's synchronous scheme
+ *     reads its minimum operator as a deterministic crossover and names a
+ *     stochastic crossover (the SOS scheme of its reference) without defining
+ *     it (Sec. 2.2).  Reading taken: at a level that starts with an exchange,
+ *     chain p keeps its own state and carried cost with the Metropolis
+ *     probability exp(-(f_p - f_w) / T_prev) -- f_p its final cost, f_w the
+ *     winner's reduced cost, T_prev the temperature of the level that ended --
+ *     and otherwise starts from the winner's state with its full
+ *     re-evaluation; the uniform is word 0 of the Philox block (0, level,
+ *     chain, 5 | problem << 8) and the test is orc_accept's.  T_prev -> 0
+ *     gives the minimum operator for every chain worse than the winner,
+ *     T_prev -> infinity the asynchronous scheme.
+ *   ORC_VARIANT_BEST_SEEN: each chain's best-seen state of the level (the
+ *     first state of lowest carried cost among its start state and its states
+ *     after each accepted move) stands in for its final state in the level's
+ *     argmin, broadcast and record; a chain that continues on its own state
+ *     continues from its final state. */
+#define ORC_VARIANT_SOS 1u
+#define ORC_VARIANT_BEST_SEEN 2u
 
 #define ORC_MOVE_RADIUS 0
 #define ORC_MOVE_RESAMPLE 1
@@ -109,6 +131,14 @@ static void draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t 
 
 /* Word i of the move stream of one chain at one level: word i mod 4 of the
  * block with counter (i / 4, level, chain, MOVE | problem << 8). */
+/* Uniform of the stochastic exchange decision of `chain` at the start of `level`. */
+double orc_sos_uniform(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain)
+{
+    uint32_t r[4];
+    draw(seed, 0u, level, chain, ORC_TAG_SOS | (problem << 8), r);
+    return orc_uniform(r[0]);
+}
+
 static uint32_t move_word(uint64_t seed, uint32_t problem, uint32_t level, uint32_t chain, uint64_t i)
 {
     uint32_t r[4];
@@ -378,8 +408,11 @@ static void capture_move(const orc_problem *p, double T, uint32_t d, double xd, 
     hist[0] = dl;
 }
 
+/* bs_x/bs_f (optional): the chain's best-seen state of the level -- the
+ * first state of lowest carried cost among its start state (set by the
+ * caller) and its states after each accepted move. */
 static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, double T, double *x,
-                          orc_cost *c)
+                          orc_cost *c, double *bs_x, double *bs_f)
 {
     uint64_t accepted = 0;
     double hist[4] = {0.0, 0.0, 0.0, 0.0};
@@ -396,6 +429,10 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
             x[d] = xn;
             *c = cn;
             ++accepted;
+            if (bs_x && c->f < *bs_f) {
+                *bs_f = c->f;
+                memcpy(bs_x, x, sizeof(double) * p->n);
+            }
         }
     }
     return accepted;
@@ -439,9 +476,12 @@ void orc_set_threads(int threads) { orc_threads = threads < 1 ? 1 : threads; }
  * with its state. */
 typedef struct {
     const orc_problem *p;
-    uint32_t level, ch0, ch1, exchange;
+    uint32_t level, ch0, ch1, exchange, variant;
     int broadcast;
     double T;
+    double T_prev, f_win_prev; /* SOS: the previous level's T and winner cost */
+    uint8_t *kept;             /* SOS: per chain, 1 if it kept its own state (optional) */
+    double *bsx;               /* best-seen: n doubles, owned by the caller */
     const double *x_start;
     orc_cost start_cost;
     double *chain_x, *chain_cost, *fin;
@@ -463,10 +503,18 @@ static void *run_level_chunk(void *arg)
     w->has_best = 0;
     for (uint32_t ch = w->ch0; ch < w->ch1; ++ch) {
         orc_cost c;
+        int own = !w->broadcast;
+        if (w->level > 0 && w->broadcast && (w->variant & ORC_VARIANT_SOS)) {
+            /* stochastic exchange: keep the own state with probability
+             * exp(-(f_own - f_win) / T_prev) */
+            const double f_own = w->chain_cost[3 * (size_t)ch];
+            own = orc_accept(f_own - w->f_win_prev, w->T_prev, orc_sos_uniform(p->seed, p->problem, w->level, ch));
+        }
+        if (w->kept) w->kept[ch] = (uint8_t)(w->level > 0 && own);
         if (w->level == 0) {
             orc_init_point(p->seed, p->problem, ch, n, p->lower, p->upper, w->x);
             cost_full(p->func, n, w->x, p->shift, &c);
-        } else if (w->broadcast) {
+        } else if (!own) {
             memcpy(w->x, w->x_start, sizeof(double) * n);
             c = w->start_cost;
         } else {
@@ -475,34 +523,45 @@ static void *run_level_chunk(void *arg)
             c.s1 = w->chain_cost[3 * (size_t)ch + 1];
             c.s2 = w->chain_cost[3 * (size_t)ch + 2];
         }
-        w->acc += run_chain(p, w->level, ch, w->T, w->x, &c);
-        if (w->exchange != 1) {
+        const int bs = (w->variant & ORC_VARIANT_BEST_SEEN) != 0;
+        double bsf = c.f;
+        if (bs) memcpy(w->bsx, w->x, sizeof(double) * n);
+        w->acc += run_chain(p, w->level, ch, w->T, w->x, &c, bs ? w->bsx : NULL, &bsf);
+        if (w->exchange != 1 || (w->variant & ORC_VARIANT_SOS)) {
             memcpy(w->chain_x + (size_t)ch * n, w->x, sizeof(double) * n);
             w->chain_cost[3 * (size_t)ch] = c.f;
             w->chain_cost[3 * (size_t)ch + 1] = c.s1;
             w->chain_cost[3 * (size_t)ch + 2] = c.s2;
         }
-        w->fin[ch] = c.f;
-        if (ch == 0) memcpy(w->x0, w->x, sizeof(double) * n);
-        if (!isnan(c.f) && (!w->has_best || c.f < w->best_f)) {
+        /* the value the level's argmin runs over, and the state it stands for */
+        const double rf = bs ? bsf : c.f;
+        const double *rx = bs ? w->bsx : w->x;
+        w->fin[ch] = rf;
+        if (ch == 0) memcpy(w->x0, rx, sizeof(double) * n);
+        if (!isnan(rf) && (!w->has_best || rf < w->best_f)) {
             w->has_best = 1;
-            w->best_f = c.f;
+            w->best_f = rf;
             w->best_chain = ch;
-            memcpy(w->bx, w->x, sizeof(double) * n);
+            memcpy(w->bx, rx, sizeof(double) * n);
         }
     }
     return NULL;
 }
 
-int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
-               uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
-               double radius_frac, int move_rule, uint32_t exchange, uint32_t level_begin, uint32_t count,
-               double *x_start, double *chain_x, double *chain_cost, double *x_rec, double *f_rec_io,
-               uint32_t *rec_level_io, uint32_t *win_chain, double *f_win, double *f_best, double *f_rec,
-               double *x_best, uint64_t *accepts, double *final_f)
+/* orc_sa_run with a variant (ORC_VARIANT_*).  f_win_io carries the last
+ * level's winner cost in and out (needed in by the stochastic exchange when
+ * level_begin > 0).  kept (optional, chains bytes): at the last level, 1 for
+ * each chain that continued from its own state. */
+int orc_sa_run_v(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+                 uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
+                 double radius_frac, int move_rule, uint32_t exchange, uint32_t variant, uint32_t level_begin,
+                 uint32_t count, double *x_start, double *chain_x, double *chain_cost, double *f_win_io,
+                 double *x_rec, double *f_rec_io, uint32_t *rec_level_io, uint32_t *win_chain, double *f_win,
+                 double *f_best, double *f_rec, double *x_best, uint64_t *accepts, double *final_f, uint8_t *kept)
 {
     if (n == 0 || chains == 0) return -1;
-    if (exchange != 1 && (!chain_x || !chain_cost)) return -1;
+    if ((exchange != 1 || (variant & ORC_VARIANT_SOS)) && (!chain_x || !chain_cost)) return -1;
+    if ((variant & ORC_VARIANT_SOS) && level_begin > 0 && !f_win_io) return -1;
     if (exchange && level_begin > 0 && !x_start) return -1;
     orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
     /* the capture sink appends in chain order: one thread while it is set */
@@ -510,16 +569,18 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
     if (nt > chains) nt = chains;
     level_chunk *w = (level_chunk *)calloc(nt, sizeof(level_chunk));
     pthread_t *tid = (pthread_t *)calloc(nt, sizeof(pthread_t));
-    double *bufs = (double *)malloc(sizeof(double) * n * (2 * (size_t)nt + 1));
+    double *bufs = (double *)malloc(sizeof(double) * n * (3 * (size_t)nt + 1));
     double *fin = (double *)malloc(sizeof(double) * chains);
     if (!w || !tid || !bufs || !fin) {
         free(w); free(tid); free(bufs); free(fin);
         return -2;
     }
 
+    double f_win_prev = f_win_io ? *f_win_io : 0.0;
     for (uint32_t k = 0; k < count; ++k) {
         uint32_t level = level_begin + k;
         double T = orc_temperature(T0, alpha, level);
+        const double T_prev = level > 0 ? orc_temperature(T0, alpha, level - 1) : T;
         const int broadcast = level > 0 && exchange > 0 && level % exchange == 0;
         orc_cost start_cost = {0.0, 0.0, 0.0};
         if (broadcast) cost_full(func, n, x_start, shift, &start_cost);
@@ -530,8 +591,13 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
             c->ch0 = (uint32_t)((uint64_t)chains * t / nt);
             c->ch1 = (uint32_t)((uint64_t)chains * (t + 1) / nt);
             c->exchange = exchange;
+            c->variant = variant;
             c->broadcast = broadcast;
             c->T = T;
+            c->T_prev = T_prev;
+            c->f_win_prev = f_win_prev;
+            c->kept = k + 1 == count ? kept : NULL;
+            c->bsx = bufs + (size_t)n * (2 * (size_t)nt + 1) + (size_t)n * t;
             c->x_start = x_start;
             c->start_cost = start_cost;
             c->chain_x = chain_x;
@@ -577,16 +643,30 @@ int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, c
         if (x_start) memmove(x_start, bx, sizeof(double) * n);
         if (win_chain) win_chain[k] = best_chain;
         if (f_win) f_win[k] = best_f;
+        f_win_prev = best_f;
         if (f_best) f_best[k] = fresh;
         if (f_rec) f_rec[k] = *f_rec_io;
         if (x_best) memcpy(x_best + (size_t)k * n, bx, sizeof(double) * n);
         if (accepts) accepts[k] = acc_total;
     }
+    if (f_win_io) *f_win_io = f_win_prev;
     free(w);
     free(tid);
     free(bufs);
     free(fin);
     return 0;
+}
+
+int orc_sa_run(int func, uint32_t n, const double *lower, const double *upper, const double *shift,
+               uint64_t seed, uint32_t problem, uint32_t chains, uint32_t steps, double T0, double alpha,
+               double radius_frac, int move_rule, uint32_t exchange, uint32_t level_begin, uint32_t count,
+               double *x_start, double *chain_x, double *chain_cost, double *x_rec, double *f_rec_io,
+               uint32_t *rec_level_io, uint32_t *win_chain, double *f_win, double *f_best, double *f_rec,
+               double *x_best, uint64_t *accepts, double *final_f)
+{
+    return orc_sa_run_v(func, n, lower, upper, shift, seed, problem, chains, steps, T0, alpha, radius_frac, move_rule,
+                        exchange, 0u, level_begin, count, x_start, chain_x, chain_cost, NULL, x_rec, f_rec_io,
+                        rec_level_io, win_chain, f_win, f_best, f_rec, x_best, accepts, final_f, NULL);
 }
 
 /*
