@@ -168,6 +168,27 @@ typedef struct {
  * SA_FLAG_LEARNED or sa_capture); results are identical to the dense
  * layout. */
 #define SA_FLAG_OVERLAY 0x8u
+/* Exchange variants (Sec. 2.2 reads the minimum operator of the synchronous
+ * scheme as a deterministic crossover and names a stochastic one without
+ * defining it).  Dense state layout, separable families, plain or logged
+ * moves (not with SA_FLAG_OVERLAY, SA_FLAG_LEARNED or sa_capture).
+ * SA_FLAG_SOS: stochastic exchange.  At a level L > 0 that starts with an
+ *   exchange (every level for exchange 0/1, every k-th for k >= 2), chain p
+ *   keeps its own final state and carried cost of level L-1 iff
+ *   f_p - f_w <= 0 or U < exp(-(f_p - f_w) / T_{L-1}) -- f_w the winner's
+ *   carried (reduced) cost, U from word 0 of the Philox block
+ *   (0, L, p, 5 | problem<<8) -- and otherwise starts from the winner's state
+ *   with its full re-evaluation.  Every chain's state is kept in the
+ *   workspace (chains x (n + 6) reals).  The start level of sa_set_start
+ *   starts every chain from its state.
+ * SA_FLAG_BEST_SEEN: each chain's best-seen state of a level -- the first
+ *   state of lowest carried cost among its start state and its states after
+ *   each accepted move -- stands in for its final state in the level's
+ *   argmin, broadcast and record (sa_trace f_win is its cost; sa_move_log's
+ *   final_f holds it).  A chain that continues on its own state continues
+ *   from its final state. */
+#define SA_FLAG_SOS 0x10u
+#define SA_FLAG_BEST_SEEN 0x20u
 
 /* Per-level record returned by sa_trace. */
 typedef struct {

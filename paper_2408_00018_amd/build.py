@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libsa_hip.so")
 PEAK_LIB = os.path.join(PKG, "libsa_peak.so")
 
 SOURCES = ["sa_kernels.hip", "sa_coupled.hip", "sa_overlay.hip", "sa_api.hip", "sa_batch.hip", "sa_batch_api.hip",
-           "sa_mlp.hip", "sa_nm.hip"]
+           "sa_mlp.hip", "sa_nm.hip", "sa_variant.hip"]
 PEAK_SOURCES = ["peak_probe.hip"]
 
 HIPCC_FLAGS = [

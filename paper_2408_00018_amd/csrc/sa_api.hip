@@ -36,13 +36,28 @@ using sa::fail;
 using sa::kAlign;
 using sa::kLdsPerWorkgroup;
 
+// Exchange variant of a config (sa::kVarSos / sa::kVarBest bits).
+int variant_of(const sa_config *c)
+{
+    return ((c->flags & SA_FLAG_SOS) ? sa::kVarSos : 0) | ((c->flags & SA_FLAG_BEST_SEEN) ? sa::kVarBest : 0);
+}
+
+// Dynamic LDS of a dense level launch (learned: the packed network too;
+// best-seen: its accept bits and replay lists).
+size_t dense_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn, int var, uint32_t steps)
+{
+    return var ? sa::variant_lds_bytes(n, wg, real_size, table, (var & sa::kVarBest) != 0, steps)
+               : sa::level_lds_bytes(n, wg, real_size, table, learn);
+}
+
 // Largest workgroup (4, 2 or 1 waves) that divides `chains` and whose state
 // (and, for learned runs, the packed network) fits in LDS.  0 if none fits.
-uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, bool learn, size_t lds_limit)
+uint32_t pick_wg(uint32_t n, uint32_t chains, size_t real_size, bool table, bool learn, int var, uint32_t steps,
+                 size_t lds_limit)
 {
     for (uint32_t wg = 256; wg >= 64; wg >>= 1) {
         if (chains % wg) continue;
-        if (sa::level_lds_bytes(n, wg, real_size, table, learn) <= lds_limit) return wg;
+        if (dense_lds_bytes(n, wg, real_size, table, learn, var, steps) <= lds_limit) return wg;
     }
     return 0;
 }
@@ -96,8 +111,13 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY))
+    if (c->flags &
+        ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_SOS | SA_FLAG_BEST_SEEN))
         return fail(SA_ERR_INVALID, "unknown flag bits");
+    if ((c->flags & (SA_FLAG_SOS | SA_FLAG_BEST_SEEN)) &&
+        ((c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)) || !sa::separable(p->func)))
+        return fail(SA_ERR_UNSUPPORTED,
+                    "the exchange variants run plain or logged moves of the separable families on the dense layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs on the dense state layout");
     if (c->exchange > 1 && (c->flags & SA_FLAG_LEARNED))
@@ -131,7 +151,8 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     pl.table = !uniform_box(p);
     pl.real = c->precision == SA_FP64 ? sizeof(double) : sizeof(float);
     const bool learn = (c->flags & SA_FLAG_LEARNED) != 0;
-    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, lds_limit);
+    const int var = variant_of(c);
+    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, var, c->steps, lds_limit);
     // Waves a layout keeps in flight on the device: its workgroups per CU (LDS
     // and the 32-wave limit) times the CUs, capped by its tiles.  The plan
     // counts the 256 CUs of the target device rather than querying it, so the
@@ -143,16 +164,16 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
         return std::min<uint64_t>(c->chains / wg, per_cu * kPlanCus) * (wg / 64);
     };
     const uint64_t dense_flight =
-        pl.wg ? in_flight(pl.wg, sa::level_lds_bytes(p->n, pl.wg, pl.real, pl.table, learn)) : 0;
+        pl.wg ? in_flight(pl.wg, dense_lds_bytes(p->n, pl.wg, pl.real, pl.table, learn, var, c->steps)) : 0;
     // Chains that keep their own state between levels need the dense layout.
-    const bool periodic = c->exchange > 1;
+    const bool periodic = c->exchange > 1 || (var & sa::kVarSos);
     // A shared level-start state plus per-chain tables of the changed
     // coordinates where the dense state does not fit or where the tables keep
     // at least twice as many waves in flight (their lookups cost a few
     // operations per move; measured at n = 512: 1.7x faster than the dense
     // layout with 131072 chains, 2.8x slower with 16384, where both put 256
     // waves in flight).
-    if (!learn && !periodic && sa::separable(p->func)) {
+    if (!learn && !periodic && !var && sa::separable(p->func)) {
         uint32_t ov_wg = 0, ov_slots = 0;
         const bool ov_fits = pick_overlay(p->n, c->chains, c->steps, pl.real, pl.table, lds_limit, &ov_wg, &ov_slots);
         const uint64_t ov_flight =
@@ -260,8 +281,9 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.rec = reinterpret_cast<double *>(w + l.rec);
     a.rec_level = reinterpret_cast<uint32_t *>(w + l.rec_level);
     a.exchange = c->cfg.exchange <= 1 ? 1u : c->cfg.exchange == SA_EXCHANGE_NEVER ? 0u : c->cfg.exchange;
-    a.chain_x = a.exchange != 1 ? reinterpret_cast<R *>(w + l.chain_x) : nullptr;
-    a.chain_cost = a.exchange != 1 ? reinterpret_cast<R *>(w + l.chain_cost) : nullptr;
+    const bool own_state = a.exchange != 1 || (c->cfg.flags & SA_FLAG_SOS);
+    a.chain_x = own_state ? reinterpret_cast<R *>(w + l.chain_x) : nullptr;
+    a.chain_cost = own_state ? reinterpret_cast<R *>(w + l.chain_cost) : nullptr;
     a.trace = reinterpret_cast<sa_level *>(w + l.trace);
     a.trace_x = (c->cfg.flags & SA_FLAG_TRACE_X) ? reinterpret_cast<R *>(w + l.trace_x) : nullptr;
     a.log = c->cfg.log_chains ? reinterpret_cast<sa_move_rec *>(w + l.log) : nullptr;
@@ -384,7 +406,10 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
                                     : (log ? sa::kModeLog : (c->capturing ? sa::kModeCapture : sa::kModePlain));
         uint32_t g = 0;
         hipError_t e;
-        if (!sa::separable(c->prob.func))
+        if (const int var = variant_of(&c->cfg))
+            e = c->fp64 ? sa::launch_variant_level_f64(c->prob.func, c->pl.table, var, log, c->a64, k, *groups, &g, s)
+                        : sa::launch_variant_level_f32(c->prob.func, c->pl.table, var, log, c->a32, k, *groups, &g, s);
+        else if (!sa::separable(c->prob.func))
             e = c->fp64 ? sa::launch_coupled_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
                         : sa::launch_coupled_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
         else if (c->pl.overlay)
@@ -774,6 +799,7 @@ sa_status sa_capture(sa_ctx *c, float *records, uint64_t capacity)
     if (records && c->pl.overlay) return fail(SA_ERR_UNSUPPORTED, "capture runs on the dense state layout");
     if (records && !sa::separable(c->prob.func))
         return fail(SA_ERR_UNSUPPORTED, "capture records moves of the separable families");
+    if (records && variant_of(&c->cfg)) return fail(SA_ERR_UNSUPPORTED, "capture records plain-exchange runs");
     drop_graphs(c);
     c->a32.cap_rec = records;
     c->a64.cap_rec = records;

@@ -58,6 +58,7 @@ __device__ __forceinline__ Ctr philox4x32_10(Ctr c, uint32_t k0, uint32_t k1)
 
 constexpr uint32_t kTagMove = 0u;
 constexpr uint32_t kTagInit = 1u;
+constexpr uint32_t kTagSos = 5u;  // stochastic exchange decision
 constexpr uint32_t kTagLearn = 3u;  // draws of the learned proposal
 constexpr uint32_t kInitLevel = 0xFFFFFFFFu;
 

@@ -117,6 +117,19 @@ hipError_t launch_overlay_level_f64(int func, bool table, bool log, const LevelA
                                     uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 size_t overlay_lds_bytes(uint32_t n, uint32_t wg, uint32_t slots, size_t real_size, bool table);
 
+// Exchange variants of the level kernel (bit set): the stochastic exchange
+// and the best-seen reduction.  Plain or logged moves, dense layout,
+// separable families.
+constexpr int kVarSos = 1;
+constexpr int kVarBest = 2;
+hipError_t launch_variant_level_f32(int func, bool table, int var, bool log, const LevelArgs<float> &a,
+                                    uint32_t level, uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+hipError_t launch_variant_level_f64(int func, bool table, int var, bool log, const LevelArgs<double> &a,
+                                    uint32_t level, uint32_t prev_groups, uint32_t *groups, hipStream_t s);
+// Dynamic LDS bytes of a variant launch (best_seen: the accept bits and the
+// replay lists as well).
+size_t variant_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool best_seen, uint32_t steps);
+
 // Level launches for the non-separable families (full re-evaluation per
 // move; dense state layout; plain and logged moves).
 hipError_t launch_coupled_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,

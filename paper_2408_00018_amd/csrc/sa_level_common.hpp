@@ -70,11 +70,12 @@ __device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, do
 // level's winner: lowest carried cost, ties to the lowest chain.  Every
 // workgroup that calls this gets the same winner; its state goes to xw and
 // its full re-evaluation to start.  With `publish` the workgroup also writes
-// the level's trace entry, the record and the broadcast state.
+// the level's trace entry, the record and the broadcast state.  win_f
+// (optional, LDS) gets the winner's carried cost.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t groups, R *xw, double *start,
-                             bool publish, Slot<R> *wave_slot, uint64_t *wave_acc)
+                             bool publish, Slot<R> *wave_slot, uint64_t *wave_acc, double *win_f = nullptr)
 {
     const uint32_t WG = blockDim.x, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6, nwaves = WG >> 6;
     const uint32_t n = a.n;
@@ -132,6 +133,7 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
         start[0] = ws.ff;
         start[1] = ws.s1;
         start[2] = ws.s2;
+        if (win_f) *win_f = (double)gf;
     }
     if (publish) {
         if (tid == 0) {

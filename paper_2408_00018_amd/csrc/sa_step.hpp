@@ -554,11 +554,16 @@ __device__ __forceinline__ void move_words(const MoveGroup &m, uint32_t j, uint3
 // {l, u, rho, s}; logf(step, d, take, x_old, x_new, df) is called for every
 // move (a no-op unless logging).  Returns the number of accepted moves.
 // ---------------------------------------------------------------------------
-template <typename R, int F, int MOVE, typename CoordFn, typename LogFn>
+struct NoPost {
+    template <typename R> __device__ __forceinline__ void operator()(uint32_t, bool, R) const {}
+};
+
+template <typename R, int F, int MOVE, typename CoordFn, typename LogFn, typename PostFn = NoPost>
 __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t lane_off, Cost<R, F> &cost,
                                               const CoordFn &coordf, const LogFn &logf, uint32_t n, uint32_t steps,
                                               uint32_t level, uint32_t chain, uint32_t ctr3, uint32_t k0,
-                                              uint32_t k1, double T, float nl2T, float inv_n)
+                                              uint32_t k1, double T, float nl2T, float inv_n,
+                                              const PostFn &post = PostFn{})
 {
     uint32_t accepted = 0;
     Ctr b0 = philox4x32_10(Ctr{0u, level, chain, ctr3}, k0, k1);
@@ -588,6 +593,7 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
         const R xwr = take ? xn : xd;
         xs[at] = xwr;
         cost.commit(take, inv_n);
+        post(step, take, cost.f);
         accepted += take ? 1u : 0u;
         // the next move's value, forwarded from this move when it picks the
         // same coordinate (same 32-bit LDS index); selecting after the

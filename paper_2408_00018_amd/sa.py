@@ -22,6 +22,7 @@ GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5  # non-separable: full re-evaluati
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8
+FLAG_SOS, FLAG_BEST_SEEN = 0x10, 0x20  # exchange variants
 EXCHANGE_NEVER = 0xFFFFFFFF
 
 SA_OK = 0
@@ -151,10 +152,13 @@ class Schedule:
     # levels between broadcasts of the winner: 1 every level (synchronous),
     # k every k-th level (periodic exchange), 0 never (asynchronous)
     exchange: int = 1
+    sos: bool = False        # stochastic exchange (SA_FLAG_SOS)
+    best_seen: bool = False  # best-seen reduction (SA_FLAG_BEST_SEEN)
 
     def to_c(self) -> Config:
         flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
-                 (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0))
+                 (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0) |
+                 (FLAG_SOS if self.sos else 0) | (FLAG_BEST_SEEN if self.best_seen else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
                       self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels,
                       EXCHANGE_NEVER if self.exchange == 0 else self.exchange)

@@ -152,7 +152,7 @@ def df_floor(func, n, x, xn, d, shift):
 
 
 def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
-                     final_f, chain_ids, rel=1e-5, problem=0, start_err=None):
+                     final_f, chain_ids, rel=1e-5, problem=0, start_err=None, best_seen=False):
     """Replay the logged moves of `chain_ids` at one level against the oracle.
 
     x_start: the level's start state (the previous level's broadcast winner,
@@ -160,12 +160,18 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
     the start cost the chain carries in (default: one FP32 rounding of a full
     evaluation, as after a broadcast).  Returns statistics, with each chain's
     error bound on its final cost in stats["f_err"]; raises AssertionError on
-    a mismatch."""
+    a mismatch.  best_seen: final_f holds each chain's best-seen cost (the
+    lowest cost it carried during the level, start included), which must match
+    the lowest FP64 cost of the states it visited within the same bound;
+    stats["visited"][c] lists those states and stats["f_last"][c] bounds
+    the final state's FP64 cost."""
     stats = dict(moves=0, max_rel_excess=0.0, decision_mismatch=0, ambiguous=0, max_df_err=0.0, f_err={},
-                 x_final={})
+                 x_final={}, visited={}, f_last={})
     for j, c in enumerate(chain_ids):
         x = np.array(x_start, dtype=np.float64)
         f_acc_err = 0.0
+        visited = [x.copy()]
+        vis_f = [O.f(func, x, shift32)] if best_seen else []
         for s in range(moves.shape[-1]):
             m = moves[j, s]
             d_ref, u1, u2 = O.move_draw(seed, problem, level, c, s, n)
@@ -202,12 +208,22 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
             if m["accept"]:
                 x = xn
                 f_acc_err += tol + 2 * U32 * abs(O.f(func, x, shift32))
+                if best_seen:
+                    visited.append(x.copy())
+                    vis_f.append(O.f(func, x, shift32))
             stats["moves"] += 1
         f_ref = O.f(func, x, shift32)
         s_err = 2 * U32 * abs(O.f(func, x_start, shift32)) + 1e-12 if start_err is None else start_err
         bound = f_acc_err + s_err + 2 * U32 * abs(f_ref)
-        assert abs(final_f[c] - f_ref) <= bound, (level, c)
+        if best_seen:
+            # the carried costs of the visited states are each within this bound
+            bound = f_acc_err + s_err + 2 * U32 * max(abs(v) for v in vis_f)
+            assert abs(final_f[c] - min(vis_f)) <= bound, (level, c, final_f[c], min(vis_f), bound)
+            stats["visited"][c] = visited
+        else:
+            assert abs(final_f[c] - f_ref) <= bound, (level, c)
         stats["f_err"][c] = bound
+        stats["f_last"][c] = f_ref
         stats["x_final"][c] = x
     return stats
 

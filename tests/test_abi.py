@@ -184,3 +184,25 @@ def test_non_separable_families(S):
     with pytest.raises(S.SAError) as e:
         S.batch_workspace_bytes([(W.GRIEWANK, lo[:4], hi[:4], None)], [64], bs)
     assert e.value.status == -5
+
+
+def test_exchange_variant_flags(S):
+    """Stochastic exchange and best-seen reduction: accepted on the dense
+    layout of the separable families (the stochastic exchange keeps every
+    chain's state in the workspace), refused with the overlay layout, the
+    learned proposal and the non-separable families."""
+    lo, hi = np.full(100, -500.0), np.full(100, 500.0)
+    base = S.Schedule(chains=65536, levels=10, steps=100, T0=10.0, alpha=0.99)
+    plain = S.workspace_bytes(S.SCHWEFEL, lo, hi, None, base)
+    sos = S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "sos": True}))
+    assert sos - plain >= 65536 * 101 * 4
+    best = S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "best_seen": True}))
+    assert best == plain
+    for kw in (dict(sos=True, overlay=True), dict(best_seen=True, learned=True)):
+        with pytest.raises(S.SAError) as e:
+            S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, **kw}))
+        assert e.value.status == -5
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(S.GRIEWANK, np.full(8, -600.0), np.full(8, 600.0), None,
+                          S.Schedule(**{**base.__dict__, "best_seen": True}))
+    assert e.value.status == -5
