@@ -275,7 +275,10 @@ sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
  * x'_d = x_d + dl (u_d - l_d); a proposal outside [l_d, u_d] is rejected, and
  * otherwise it is taken iff U < exp(-df/T + ln q(x | x') - ln q(x' | x))
  * (Metropolis-Hastings with the network evaluated at x_d and at x'_d, both
- * with the chain's current history); the change and acceptance uniforms of
+ * with the chain's current history: exact for a network that ignores the
+ * history features; with them the chain is adaptive, since an accepted move
+ * changes the history the next proposal sees, and exp(-f/T) is invariant only
+ * approximately); the change and acceptance uniforms of
  * either component are the move's words of the plain move stream.  The
  * plain/learned choice is U < eps with U from word 1 of the learned block.
  * The history (last four accepted scaled displacements,

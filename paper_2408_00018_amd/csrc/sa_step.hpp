@@ -638,8 +638,10 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
 //   outside [l_d, u_d] is rejected; otherwise the network is evaluated again
 //   at x'_d (same history) and the move is taken iff
 //       U(w2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
-//   (Metropolis-Hastings: each component is reversible on its own, so the
-//   state-independent mixture is too).
+//   (Metropolis-Hastings.  For a fixed history each component, and so their
+//   state-independent mixture, is reversible with respect to exp(-f/T); an
+//   accepted move changes the history the next proposal sees, so the chain
+//   is adaptive and the invariance holds only approximately.)
 // h holds the history features of the chain's last four accepted scaled
 // displacements (most recent first); every accepted move, plain or learned,
 // pushes hist_feature((x'_d - x_d)/(u_d - l_d)).
