@@ -30,15 +30,19 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 # ALU roofline.  Unit: one "slot" = one lane-operation at the FP32 FMA issue
-# rate.  Peak: MI355X FP32 vector 157.3 TFLOP/s = 78.6e12 lane-FMA/s
-# (256 CUs x 4 SIMDs x 32 FP32 lane-ops per clock x 2.4 GHz).  An instruction
-# class that issues r times slower than FMA costs r slots; r comes from the
-# issue-rate probe (libsa_peak.so) at 8 waves per SIMD on MI355X:
-#   v_mad_u64_u32 2.17, v_mul_hi_u32 1.7, v_sin/v_cos/v_sqrt/v_exp_f32 3.15,
+# rate.  Peak: MI355X FP32 vector 157.3 TFLOP/s = 78.6e12 lane-FMA/s.  An
+# instruction class that issues r times slower than FMA costs r slots; r comes
+# from the issue-rate probe (libsa_peak.so, bench.py --probe; output kept in
+# profiles/valu_issue_rates.md) on MI355X: the ratio of the class's rate to
+# the FMA rate at 8 waves per SIMD where the probe sweeps occupancy (FMA
+# 5.43e13, v_mad_u64_u32 1.78e13, v_sin_f32 1.77e13 lane-ops/s), else with
+# the grid full (FMA 5.63e13, v_mul_hi_u32 1.99e13, v_sqrt_f32 1.91e13,
+# v_exp_f32 1.89e13):
+#   v_mad_u64_u32 3.05, v_mul_hi_u32 2.83, v_sin/v_cos/v_sqrt/v_exp_f32 3.0,
 #   FP32 add/mul/fma/med3/cvt, integer shift/xor/bitop3/compare/select 1.
 # Algorithmic work of one FP32 normalized-Schwefel move with the radius rule:
 CLOCK_HZ = 2.4e9  # MI355X peak engine clock
-SLOT_WEIGHT = {"mad_u64": 2.17, "mul_hi": 1.7, "trans": 3.15, "valu": 1.0}
+SLOT_WEIGHT = {"mad_u64": 3.05, "mul_hi": 2.83, "trans": 3.0, "valu": 1.0}
 SLOTS_PER_MOVE = {
     # counter-based generator: a move takes three of a block's four words, so
     # 3/4 of a block per move.  Of Philox4x32-10's ten rounds, rounds 3-10
@@ -62,24 +66,46 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "a3a0f7f3df843ce4", "fetch_kib": 167.470, "fetch_scale": 2.0,
+TRAFFIC_MEASURED = {"sources_sha256_16": "847196abcce54231", "fetch_kib": 168.955, "fetch_scale": 2.0,
                     "write_kib": 120.592, "write_scale": 1.0}
-KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_device.hpp",
-                  "paper_2408_00018_amd/csrc/sa_internal.hpp", "paper_2408_00018_amd/csrc/sa_step.hpp",
-                  "paper_2408_00018_amd/csrc/sa_level_common.hpp", "paper_2408_00018_amd/csrc/sa_mlp_net.hpp",
-                  "paper_2408_00018_amd/build.py"]
+# Instruction counters of one level launch (rocprofv3 --pmc SQ_INSTS_VALU
+# SQ_INSTS_VALU_TRANS_F32, wave-instructions per dispatch, same sources):
+# with the live launch time they give the lane-operation issue rate, set
+# against the probe's full-grid FP32 FMA rate and v_sin_f32 rate.
+COUNTERS_MEASURED = {"sources_sha256_16": "847196abcce54231", "insts_valu": 6.375e6, "insts_trans": 5.12e5,
+                     "fma_rate": 5.625e13, "trans_rate": 1.824e13}
+KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_level_kernel.hpp",
+                  "paper_2408_00018_amd/csrc/sa_device.hpp", "paper_2408_00018_amd/csrc/sa_internal.hpp",
+                  "paper_2408_00018_amd/csrc/sa_step.hpp", "paper_2408_00018_amd/csrc/sa_level_common.hpp",
+                  "paper_2408_00018_amd/csrc/sa_mlp_net.hpp", "paper_2408_00018_amd/build.py"]
 
 
-def measured_traffic_bytes():
+def kernel_sources_hash():
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic_bytes():
     t = TRAFFIC_MEASURED
-    if h.hexdigest()[:16] != t["sources_sha256_16"]:
+    if kernel_sources_hash() != t["sources_sha256_16"]:
         return None
     return round((t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0)
+
+
+def counter_issue_fractions(avg_launch_s):
+    """Measured VALU and transcendental lane-op issue rates of the level
+    kernel over the probe's rates, or None once the sources have changed."""
+    c = COUNTERS_MEASURED
+    if kernel_sources_hash() != c["sources_sha256_16"]:
+        return None
+    valu = c["insts_valu"] * 64 / avg_launch_s
+    trans = c["insts_trans"] * 64 / avg_launch_s
+    return {"valu_lane_ops_per_s": float(f"{valu:.4g}"), "valu_issue_frac": round(valu / c["fma_rate"], 4),
+            "trans_lane_ops_per_s": float(f"{trans:.4g}"), "trans_issue_frac": round(trans / c["trans_rate"], 4)}
 
 
 def parse():
@@ -92,6 +118,11 @@ def parse():
     p.add_argument("--probe", action="store_true", help="also measure VALU issue rates")
     p.add_argument("--no-ttt", action="store_true", help="skip the time-to-target comparison")
     p.add_argument("--no-extra", action="store_true", help="skip the large-n and batched throughput figures")
+    p.add_argument("--only-extra", action="store_true",
+                   help="run only the other workloads' throughput figures (no bench line; for counter passes)")
+    p.add_argument("--learned-levels", type=int, default=0,
+                   help="only run this many learned-mixture levels of the bench workload (untrained network; "
+                        "for counter passes)")
     p.add_argument("--ttt-seeds", type=int, default=10, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--exchange-sweep", action="store_true",
                    help="bench workload with the winner broadcast every level, every 10 levels and never")
@@ -260,13 +291,15 @@ def extra_workloads():
     """Throughput of the other workloads, one timed run each after a warm-up
     run (graph-replayed levels, HIP events on the library's stream): the
     n = 512 Rastrigin and n = 1024 Ackley runs (131072 chains, 1000 levels x
-    64 steps, shifted), and 1024 batched problems (n ~ U{2..256}, 500 levels
+    64 steps, shifted), the n = 100 Griewank run (65536 chains, 200 levels x
+    100 steps; non-separable: every move re-evaluates f in full), and 1024
+    batched problems (n ~ U{2..256}, 500 levels
     x 64 steps, chains per problem and waves per workgroup from the
     autotuner)."""
     import torch
     from paper_2408_00018_amd import sa
     out = {}
-    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32()):
+    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32(), W.griewank_n100_fp32()):
         sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
                             seed=wl.seed, precision=sa.FP32, graph=True)
         with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
@@ -305,6 +338,27 @@ def extra_workloads():
                            "autotune_s": round(tune_s, 2)}
     print(f"[extra] batched: {out['batched_1024']}", file=sys.stderr, flush=True)
     return out
+
+
+def learned_levels(wl, levels):
+    """`levels` learned-mixture levels (eps = 0.1, untrained network from
+    learned.init_params) of the bench workload, graph-replayed: device ms per
+    level (used to take counters of the learned level kernel)."""
+    import torch
+    from paper_2408_00018_amd import learned as Lp
+    from paper_2408_00018_amd import sa
+    sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
+                        precision=sa.FP32, graph=True, learned=True)
+    with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+        ann.set_proposal(Lp.init_params(0), 0.1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ann.stream)
+        ann.run()
+        e1.record(ann.stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+    return {"levels": levels, "ms_per_level": round(ms / levels, 4),
+            "moves_per_s": float(f"{wl.chains * wl.steps * levels / (ms * 1e-3):.4g}")}
 
 
 def us_per_level(wl, chains, steps, levels=100):
@@ -460,6 +514,12 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30, "copies": 3}), flush=True)
         return
     wl = W.schwefel_n100_fp32()
+    if args.only_extra:
+        print(json.dumps({"other_workloads": extra_workloads()}), flush=True)
+        return
+    if args.learned_levels:
+        print(json.dumps({"learned_levels": learned_levels(wl, args.learned_levels)}), flush=True)
+        return
     sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
                         precision=sa.FP32, graph=True)
     ann = sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched)
@@ -492,7 +552,7 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_SLOTS_PER_S / 1e12, 3),
                 "unit": "Tslot/s", "frac": round(achieved / PEAK_SLOTS_PER_S, 4), "traffic": measured_traffic_bytes(),
                 "kernel": "level_kernel<float,Schwefel,uniform box,radius>", "slots_per_move": round(SLOTS, 2),
-                "avg_launch_us": round(avg_launch_s * 1e6, 3)}
+                "avg_launch_us": round(avg_launch_s * 1e6, 3), "counters": counter_issue_fractions(avg_launch_s)}
     out = {
         "metric": "SA moves/s (Schwefel n=100)",
         "value": float(f"{value:.6g}"),

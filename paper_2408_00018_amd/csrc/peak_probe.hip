@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sa_device.hpp"
+
 namespace {
 
 constexpr int kChains = 16;
@@ -93,7 +95,8 @@ __global__ void __launch_bounds__(256) probe_kernel(int kind, int iters, uint32_
 }
 
 // One hardware transcendental per element: 0 sin(2 pi t), 1 cos(2 pi t) (the
-// instructions take revolutions), 2 sqrt(t), 3 2^t.
+// instructions take revolutions), 2 sqrt(t), 3 2^t; and 4 e^t - 1 as the FP32
+// Ackley increment computes it (sa::expm1_f32).
 __global__ void __launch_bounds__(256) accuracy_kernel(int op, const float *in, float *out, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -104,7 +107,8 @@ __global__ void __launch_bounds__(256) accuracy_kernel(int op, const float *in, 
     case 0: r = __builtin_amdgcn_sinf(t); break;
     case 1: r = __builtin_amdgcn_cosf(t); break;
     case 2: r = __builtin_amdgcn_sqrtf(t); break;
-    default: r = __builtin_amdgcn_exp2f(t); break;
+    case 3: r = __builtin_amdgcn_exp2f(t); break;
+    default: r = sa::expm1_f32(t); break;
     }
     out[i] = r;
 }
@@ -118,7 +122,7 @@ extern "C" {
 // the instructions' error against an FP64 evaluation of the same inputs.
 int sa_peak_accuracy(int op, const float *in, float *out, uint32_t n)
 {
-    if (op < 0 || op > 3 || !in || !out) return -1;
+    if (op < 0 || op > 4 || !in || !out) return -1;
     if (n == 0) return 0;
     hipLaunchKernelGGL(accuracy_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, op, in, out, n);
     if (hipGetLastError() != hipSuccess) return -3;

@@ -83,6 +83,26 @@ __device__ __forceinline__ float hw_cos_rev(float t) { return __builtin_amdgcn_c
 __device__ __forceinline__ float hw_exp2(float t) { return __builtin_amdgcn_exp2f(t); }
 __device__ __forceinline__ float hw_log2(float t) { return __builtin_amdgcn_logf(t); }
 
+// e^x - 1 in FP32 (Ackley's increment): for |x| <= 1/2 the Taylor polynomial
+// through x^9/9! in Horner form (truncation below 2^-26 relative, a few ulps
+// of rounding), beyond it 2^(x log2 e) - 1 on the hardware exponential
+// (|e^x - 1| >= 0.39 there, so the subtraction costs at most two bits).  Both
+// forms are evaluated and one selected, so the lanes of a wave do not split.
+__device__ __forceinline__ float expm1_f32(float x)
+{
+    float p = fmaf(x, 1.0f / 362880.0f, 1.0f / 40320.0f);
+    p = fmaf(x, p, 1.0f / 5040.0f);
+    p = fmaf(x, p, 1.0f / 720.0f);
+    p = fmaf(x, p, 1.0f / 120.0f);
+    p = fmaf(x, p, 1.0f / 24.0f);
+    p = fmaf(x, p, 1.0f / 6.0f);
+    p = fmaf(x, p, 0.5f);
+    p = fmaf(x, p, 1.0f);
+    const float small = x * p;
+    const float large = hw_exp2(x * 1.44269504088896341f) - 1.0f;
+    return fabsf(x) <= 0.5f ? small : large;
+}
+
 constexpr float kInv2Pi = 0.159154943091895335768883763372514362f;
 constexpr float kInv4Pi2 = 0.0253302959105844428049187623077562f;  // 1 / (4 pi^2)
 constexpr float kLog2e = 1.44269504088896340735992468100189214f;

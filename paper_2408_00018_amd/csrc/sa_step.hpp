@@ -199,8 +199,8 @@ template <> struct Cost<float, kAckley> {
         s2n_ = s2 + ds2;
         qn_ = hw_sqrt(s1n_ * inv_n);
         const float den = qn_ + q;
-        const float da = den > 0.0f ? (-0.2f * (ds1 * inv_n)) / den : 0.0f;
-        df_ = -20.0f * ea * expm1f(da) - eb * expm1f(ds2 * inv_n);
+        const float da = den > 0.0f ? (-0.2f * (ds1 * inv_n)) * __builtin_amdgcn_rcpf(den) : 0.0f;
+        df_ = -20.0f * ea * expm1_f32(da) - eb * expm1_f32(ds2 * inv_n);
         return df_;
     }
     __device__ bool step(float xd, float xn, float sh, float k, float nl2T, float inv_n)

@@ -20,6 +20,10 @@ E_TRIG = 2.0 ** -19
 E_TRIG_WIDE = 2.0 ** -17
 E_SQRT = 2.0 ** -22
 E_EXP2 = 2.0 ** -21
+# Relative error of the FP32 e^x - 1 of the Ackley increment (polynomial for
+# |x| <= 1/2, hardware exponential minus one beyond); the Ackley floor below
+# allows 36 and 68 of 2^-24 on its two terms.
+E_EXPM1 = 2.0 ** -20
 
 
 def f32(v):

@@ -1,6 +1,7 @@
 """Error of the gfx950 FP32 transcendental instructions the kernels use
-(v_sin_f32 and v_cos_f32 on revolutions, v_sqrt_f32, v_exp_f32), measured
-against FP64 evaluations of the same FP32 inputs.
+(v_sin_f32 and v_cos_f32 on revolutions, v_sqrt_f32, v_exp_f32), and of the
+FP32 e^x - 1 of the Ackley increment built on them, measured against FP64
+evaluations of the same FP32 inputs.
 
 The per-move tolerances of the FP32 parity tests take the sine/cosine error
 as an absolute bound (parity_util.E_TRIG, for arguments up to 64
@@ -93,3 +94,22 @@ def test_exp2_relative_error(probe):
     say(f"[trig] exp2: max relative error {err:.3e} ({err / 2 ** -24:.2f} x 2^-24); E_EXP2 = {P.E_EXP2:.3e}")
     assert err <= P.E_EXP2
     assert math.isfinite(err)
+
+
+def test_expm1_relative_error(probe):
+    """The Ackley increment's e^x - 1: polynomial for |x| <= 1/2, hardware
+    exponential minus one beyond; relative error against FP64 expm1 over the
+    arguments the increment takes (|x| up to ~7 for the Gaussian-term
+    exponent at small n, tiny ones near the end of a run)."""
+    rng = np.random.default_rng(7)
+    x = np.concatenate([rng.uniform(-0.5, 0.5, 1 << 20), rng.uniform(-8, 3, 1 << 20),
+                        np.sign(rng.uniform(-1, 1, 1 << 18)) * np.exp(rng.uniform(-40, -1, 1 << 18))])
+    x = x.astype(np.float32)
+    x = x[x != 0]
+    ref = np.expm1(x.astype(np.float64))
+    rel = np.abs(probe(4, x) - ref) / np.abs(ref)
+    small = np.abs(x) <= 0.5
+    es, el = rel[small].max(), rel[~small].max()
+    say(f"[trig] expm1_f32: max relative error {es:.3e} (|x| <= 1/2, {es / 2 ** -24:.2f} x 2^-24), "
+        f"{el:.3e} beyond ({el / 2 ** -24:.2f} x 2^-24); E_EXPM1 = {P.E_EXPM1:.3e}")
+    assert es <= P.E_EXPM1 and el <= P.E_EXPM1
