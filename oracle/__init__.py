@@ -86,6 +86,8 @@ def lib():
         L.orc_sa_run_v.restype = _i
         L.orc_sos_uniform.argtypes = [_u64, _u32, _u32, _u32]
         L.orc_sos_uniform.restype = _d
+        L.orc_set_net_kind.argtypes = [_i]
+        L.orc_set_net_kind.restype = None
         L.orc_replay_level.argtypes = [_i, _u32, _p, _p, _p, _u64, _u32, _u32, _d, _d, _i, _u32, _p, _u32, _u32,
                                        _p, _p, _p, _p, _p, _p, _p]
         L.orc_replay_level.restype = _i
@@ -315,6 +317,14 @@ def replay_level(func, lower, upper, shift=None, *, seed, steps, T, level, x_sta
 # ---------------------------------------------------------------------------
 MLP_HIDDEN = 128
 MLP_INPUTS = 6
+# Network kinds: relu + Cauchy output + log-magnitude history features, or the
+# written configuration (GELU + Gaussian output + raw history features).
+NET_RELU_CAUCHY, NET_GELU_GAUSS = 0, 1
+
+
+def set_net_kind(kind: int):
+    """Kind of the proposal network every network function below uses."""
+    lib().orc_set_net_kind(int(kind))
 
 
 def mlp_nparam() -> int:

@@ -387,8 +387,27 @@ static struct {
     double tau;
 } capture_sink;
 
-/* History feature of the learned proposal's input: sign(h) ln(1 + 2^24 |h|) / 16. */
-double orc_hist_feature(double h) { return copysign(log(1.0 + ldexp(fabs(h), 24)) / 16.0, h); }
+/* Kind of the proposal network (orc_set_net_kind):
+ *   ORC_NET_RELU_CAUCHY  relu hidden activations, a Cauchy distribution over
+ *                        the scaled displacement, history features entered as
+ *                        sign(h) ln(1 + 2^24 |h|) / 16;
+ *   ORC_NET_GELU_GAUSS   the written learned-proposal configuration: GELU
+ *                        (exact erf form), a Gaussian distribution (mean, log
+ *                        standard deviation), the last accepted scaled
+ *                        displacements entered as they are. */
+#define ORC_NET_RELU_CAUCHY 0
+#define ORC_NET_GELU_GAUSS 1
+static int orc_net_kind = ORC_NET_RELU_CAUCHY;
+
+void orc_set_net_kind(int kind) { orc_net_kind = kind == ORC_NET_GELU_GAUSS ? kind : ORC_NET_RELU_CAUCHY; }
+
+/* History feature of the learned proposal's input: sign(h) ln(1 + 2^24 |h|) / 16
+ * (ORC_NET_RELU_CAUCHY), or h itself (ORC_NET_GELU_GAUSS). */
+double orc_hist_feature(double h)
+{
+    if (orc_net_kind == ORC_NET_GELU_GAUSS) return h;
+    return copysign(log(1.0 + ldexp(fabs(h), 24)) / 16.0, h);
+}
 
 static void capture_move(const orc_problem *p, double T, uint32_t d, double xd, double xn, double hist[4])
 {
@@ -773,10 +792,25 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
 
 uint32_t orc_mlp_nparam(void) { return ORC_NPARAM; }
 
-double orc_act(double a) { return a > 0.0 ? a : 0.0; }
+#define ORC_SQRT1_2 0.70710678118654752440
+#define ORC_INV_SQRT_2PI 0.39894228040143267794
+#define ORC_LN_SQRT_2PI 0.91893853320467274178
 
-/* Derivative of relu, taken as 0 at a = 0. */
-double orc_act_grad(double a) { return a > 0.0 ? 1.0 : 0.0; }
+/* Hidden activation: relu, or GELU a Phi(a) = a (1 + erf(a / sqrt 2)) / 2. */
+double orc_act(double a)
+{
+    if (orc_net_kind == ORC_NET_GELU_GAUSS) return 0.5 * a * (1.0 + erf(a * ORC_SQRT1_2));
+    return a > 0.0 ? a : 0.0;
+}
+
+/* Derivative of the activation: relu's taken as 0 at a = 0; GELU's
+ * Phi(a) + a phi(a). */
+double orc_act_grad(double a)
+{
+    if (orc_net_kind == ORC_NET_GELU_GAUSS)
+        return 0.5 * (1.0 + erf(a * ORC_SQRT1_2)) + a * ORC_INV_SQRT_2PI * exp(-0.5 * a * a);
+    return a > 0.0 ? 1.0 : 0.0;
+}
 
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3;
@@ -841,11 +875,19 @@ double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, 
         const double mu = o[0], s = o[1];
         const double e = delta[r] - mu;
         const double r = e * exp(-s); /* standardised residual */
-        const double q = 1.0 + r * r;
-        loss += (s + ORC_LN_PI + log(q)) * inv_b;
+        double dmu, ds;
+        if (orc_net_kind == ORC_NET_GELU_GAUSS) {
+            /* Gaussian NLL: s + ln sqrt(2 pi) + r^2 / 2 */
+            loss += (s + ORC_LN_SQRT_2PI + 0.5 * r * r) * inv_b;
+            dmu = -r * exp(-s) * inv_b;
+            ds = (1.0 - r * r) * inv_b;
+        } else {
+            const double q = 1.0 + r * r;
+            loss += (s + ORC_LN_PI + log(q)) * inv_b;
+            dmu = -2.0 * r * exp(-s) / q * inv_b;
+            ds = (1.0 - 2.0 * r * r / q) * inv_b;
+        }
         if (!grad) continue;
-        const double dmu = -2.0 * r * exp(-s) / q * inv_b;
-        const double ds = (1.0 - 2.0 * r * r / q) * inv_b;
         double dh2[ORC_H], da2[ORC_H], dh1[ORC_H], da1[ORC_H];
         gb3[0] += dmu;
         gb3[1] += ds;
@@ -904,7 +946,8 @@ void orc_mlp_forward_bound(const double *params, const double *z, double *out2, 
         for (int i = 0; i < ORC_H; ++i) t += fabs(m.W2[i * ORC_H + j]) * fabs(orc_act(a1[i]));
         prop[j] = t;
     }
-    const double u = ldexp(1.0, -9);
+    /* GELU's slope stays below 1.13 (relu's below 1) */
+    const double u = ldexp(1.0, -9) * (orc_net_kind == ORC_NET_GELU_GAUSS ? 1.13 : 1.0);
     for (int k = 0; k < 2; ++k) {
         double t = 0.0;
         for (int j = 0; j < ORC_H; ++j) t += fabs(m.W3[j * 2 + k]) * (fabs(orc_act(a2[j])) + prop[j]);
@@ -928,6 +971,12 @@ double orc_learn_draw(uint64_t seed, uint32_t problem, uint32_t level, uint32_t 
 {
     uint32_t r[4];
     learn_block(seed, problem, level, chain, step, r);
+    if (orc_net_kind == ORC_NET_GELU_GAUSS) {
+        /* standard normal by Box-Muller on words 0 and 2: the radius from
+         * U = 1 - U0 in (0, 1], the angle from U2 */
+        const double u = 1.0 - orc_uniform(r[0]);
+        return sqrt(-2.0 * log(u)) * cos(2.0 * ORC_PI * orc_uniform(r[2]));
+    }
     return tan(ORC_PI * (orc_uniform(r[0]) - 0.5));
 }
 
@@ -939,10 +988,12 @@ double orc_learn_mix(uint64_t seed, uint32_t problem, uint32_t level, uint32_t c
 }
 
 /* Log density of the proposal, in scaled units: the Cauchy density with
- * location mu and scale e^s at delta. */
+ * location mu and scale e^s at delta, or the Gaussian one with mean mu and
+ * standard deviation e^s. */
 double orc_proposal_logpdf(double delta, double mu, double s)
 {
     const double r = (delta - mu) * exp(-s);
+    if (orc_net_kind == ORC_NET_GELU_GAUSS) return -s - ORC_LN_SQRT_2PI - 0.5 * r * r;
     return -s - ORC_LN_PI - log(1.0 + r * r);
 }
 
@@ -982,6 +1033,43 @@ static double bf16_relu_err(double a, double e)
     return fmax(fabs(hi - v), fabs(v - lo));
 }
 
+/* GELU kind: the device evaluates a (1 + erf(a / sqrt 2)) / 2 in FP32 (erf to
+ * a few ulps, three roundings): its deviation from the exact value, below. */
+static double gelu_dev_err(double a) { return fabs(orc_act(a)) * ldexp(1.0, -20) + fabs(a) * ldexp(1.0, -22); }
+
+/* BF16 value of the activation of the FP32 accumulator holding a. */
+static double bf16_act(double a)
+{
+    if (orc_net_kind == ORC_NET_GELU_GAUSS) return (double)bf16_round((float)orc_act(a));
+    return bf16_relu(a);
+}
+
+/* FP32 value at or below (dir < 0) / at or above (dir > 0) v. */
+static float f32_dir(double v, int dir)
+{
+    float f = (float)v;
+    if (dir < 0 && (double)f > v) f = nextafterf(f, -INFINITY);
+    if (dir > 0 && (double)f < v) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+/* Largest |w - bf16_act(a)| over the BF16 activations w the device can
+ * produce from an accumulator within [a - e, a + e]: GELU falls to its
+ * minimum at a = -0.7518 and rises after it, and the device's GELU adds its
+ * own FP32 error before the rounding to BF16 (which keeps order). */
+static double bf16_act_err(double a, double e)
+{
+    if (orc_net_kind != ORC_NET_GELU_GAUSS) return bf16_relu_err(a, e);
+    const double c = -0.751791524693564457;
+    const double lo = a - e, hi = a + e, g1 = orc_act(lo), g2 = orc_act(hi);
+    double gmin = fmin(g1, g2), gmax = fmax(g1, g2);
+    if (lo < c && c < hi) gmin = fmin(gmin, orc_act(c));
+    const double eg = fmax(gelu_dev_err(lo), gelu_dev_err(hi));
+    const double v = bf16_act(a);
+    const double wlo = bf16_round(f32_dir(gmin - eg, -1)), whi = bf16_round(f32_dir(gmax + eg, 1));
+    return fmax(fabs(whi - v), fabs(v - wlo));
+}
+
 /* FP32 accumulation of k terms in any order: |error| <= gamma_k * sum |terms|,
  * gamma_k = k u / (1 - k u), u = 2^-24; doubled for the MFMA's internal
  * summation order. */
@@ -1018,8 +1106,8 @@ void orc_mlp_forward_device(const double *params, const double *z, const double 
             k += t != 0.0 ? 2 : 0;
         }
         const double e = prop + acc_bound(k, sa);
-        h1[j] = bf16_relu(a);
-        e1[j] = bf16_relu_err(a, e);
+        h1[j] = bf16_act(a);
+        e1[j] = bf16_act_err(a, e);
     }
     for (int j = 0; j < ORC_H; ++j) {
         const double b = (double)(float)m.b2[j];
@@ -1034,8 +1122,8 @@ void orc_mlp_forward_device(const double *params, const double *z, const double 
         }
         /* activations that may differ enlarge the accumulated magnitudes too */
         const double e = prop + acc_bound(k, sa + prop);
-        h2[j] = bf16_relu(a);
-        e2[j] = bf16_relu_err(a, e);
+        h2[j] = bf16_act(a);
+        e2[j] = bf16_act_err(a, e);
     }
     for (int k = 0; k < 2; ++k) {
         const double b = (double)(float)m.b3[k];

@@ -30,6 +30,7 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
                      double *log_xold, double *log_xnew, double *log_df, uint8_t *log_acc, double *x_final,
                      double *f_final);
 uint32_t orc_mlp_nparam(void);
+void orc_set_net_kind(int kind);
 void orc_mlp_forward(const double *params, const double *z, double *out2, double *a1_out, double *a2_out);
 double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, const double *delta, double *grad);
 void orc_adam_step(double *params, const double *grad, double *m, double *v, uint32_t nparam, uint32_t t, double lr,
@@ -167,7 +168,11 @@ int main(void)
     const uint32_t dims[3] = {1, 2, 7};
     for (int func = 0; func < 6; ++func)
         for (int k = 0; k < 3; ++k) runs(func, dims[k]);
-    network();
+    for (int kind = 0; kind < 2; ++kind) {
+        orc_set_net_kind(kind);
+        network();
+    }
+    orc_set_net_kind(0);
     printf("ok\n");
     return 0;
 }
