@@ -64,6 +64,16 @@
  *     sa_trace and sa_move_log synchronise that stream.
  *   - Errors: a negative sa_status; sa_last_error() describes the last error
  *     of the calling thread.  No call aborts the process.
+ *   - Fault injection, for tests of callers' error paths: with the
+ *     environment variable SA_FAULT=alloc every call that would allocate
+ *     device memory (sa_create, sa_batch_create without a workspace,
+ *     sa_mlp_create, sa_nm_polish without a workspace) returns SA_ERR_NOMEM
+ *     once its arguments are validated, before it touches the device; with
+ *     SA_FAULT=launch every call that would enqueue kernels (sa_run, sa_reset,
+ *     sa_set_proposal, sa_run_static, sa_nm_polish, sa_batch_run,
+ *     sa_batch_reset, sa_mlp_grad, sa_mlp_train, sa_mlp_infer) returns
+ *     SA_ERR_DEVICE before enqueuing anything and leaves its context as it
+ *     was.  The variable is read at every call; other values do nothing.
  *   - Execution: sa_run enqueues one kernel launch per level and one that
  *     publishes the last level; each level's launch reduces the previous
  *     level's per-workgroup candidates to the winner on the device.  There is
@@ -288,6 +298,28 @@ sa_status sa_set_start(sa_ctx *ctx, uint32_t level, const double *x);
  */
 sa_status sa_set_proposal(sa_ctx *ctx, const float *params, float eps);
 
+/* Kinds of proposal network (the learned-proposal configuration that names
+ * GELU and a Gaussian output beside the relu/Cauchy network above):
+ *   SA_NET_RELU_CAUCHY  as described above (the default);
+ *   SA_NET_GELU_GAUSS   GELU hidden activations, x Phi(x) (Phi the standard
+ *                       normal distribution function; FP32 on the device, by
+ *                       the rational approximation 26.2.17 of Abramowitz and
+ *                       Stegun, then rounded to BF16), a Gaussian over the
+ *                       scaled displacement with mean mu and standard
+ *                       deviation exp(s) (t = sqrt(-2 ln(1 - U0)) cos(2 pi U2)
+ *                       from words 0 and 2 of the learned block, Box-Muller),
+ *                       the history's scaled displacements entered as they
+ *                       are, and the temperature feature ln T (tau = 1). */
+#define SA_NET_RELU_CAUCHY 0
+#define SA_NET_GELU_GAUSS 1
+
+/* Select the kind of network the context's learned levels evaluate and the
+ * features its captures record (history form, temperature feature); the
+ * parameters set by sa_set_proposal are read under the kind in force when a
+ * level runs.  SA_ERR_INVALID for an unknown kind; SA_ERR_STATE while
+ * capturing.  Synchronises. */
+sa_status sa_set_network_kind(sa_ctx *ctx, int kind);
+
 /* Record every accepted move of the following plain levels into `records`
  * (device memory, capacity x 7 floats: the six network features at the old
  * state -- (x_d - l_d)/(u_d - l_d), ln(tau T), the history features of the
@@ -506,6 +538,12 @@ sa_status sa_mlp_grad(sa_mlp *m, const float *records, uint64_t nrec, const uint
  * loss_trace: `steps` host floats (each minibatch's mean loss) or NULL. */
 sa_status sa_mlp_train(sa_mlp *m, const float *records, uint64_t nrec, uint32_t batch, uint32_t steps, float lr,
                        uint64_t seed, float *loss_trace);
+
+/* Network kind (SA_NET_*) the trainer's forward pass, loss and inference use:
+ * SA_NET_GELU_GAUSS trains GELU activations under the mean Gaussian negative
+ * log-likelihood s + ln sqrt(2 pi) + ((d - mu)/exp(s))^2 / 2.  Default
+ * SA_NET_RELU_CAUCHY.  SA_ERR_INVALID for an unknown kind. */
+sa_status sa_mlp_set_kind(sa_mlp *m, int kind);
 
 /* Evaluate the network at the current parameters for `rows` feature vectors
  * Z (device, rows x 6 floats) into out (device, rows x 2 floats: mu, s),

@@ -416,16 +416,20 @@ def feature_tau(func, n):
 
 
 def sa_run_capture(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, level_begin=0,
-                   x_start=None, radius_frac=0.1, move_rule=MOVE_RADIUS, problem=0, capacity=1 << 20):
+                   x_start=None, radius_frac=0.1, move_rule=MOVE_RADIUS, problem=0, capacity=1 << 20, tau=None):
     """Synchronous run over levels [level_begin, level_begin+levels) that
-    records every accepted move; returns (records float32 [k, 7], count)."""
+    records every accepted move, with the temperature feature ln(tau T)
+    (tau = feature_tau(func, n) unless given; 1 for the Gaussian network
+    kind's ln T) and the history features of the network kind in force;
+    returns (records float32 [k, 7], count)."""
     lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
     n = lo.size
     xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
     rec = np.zeros((capacity, 7), dtype=np.float32)
     cnt = ctypes.c_uint64()
     rc = lib().orc_sa_run_capture(func, n, _ptr(lo), _ptr(hi), _ptr(s), seed, problem, chains, steps, T0, alpha,
-                                  radius_frac, move_rule, level_begin, levels, _ptr(xs), feature_tau(func, n),
+                                  radius_frac, move_rule, level_begin, levels, _ptr(xs),
+                                  feature_tau(func, n) if tau is None else float(tau),
                                   _ptr(rec), capacity, ctypes.byref(cnt))
     if rc != 0:
         raise RuntimeError(f"orc_sa_run_capture failed: {rc}")

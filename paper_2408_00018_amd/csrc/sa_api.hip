@@ -243,6 +243,7 @@ struct sa_ctx {
     uint32_t first_level = 0;  // first level of the current run (the start level, or 0)
     bool fp64 = false;
     bool learned = false;  // a proposal network is set
+    int net_kind = SA_NET_RELU_CAUCHY;  // kind of the proposal network (and of captured features)
     bool capturing = false;  // accepted moves are being recorded
     sa::LevelArgs<float> a32{};
     sa::LevelArgs<double> a64{};
@@ -301,11 +302,18 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.cap_capacity = 0;
     a.gcoef = reinterpret_cast<const float *>(w + l.gcoef);
     a.cscale = (float)(3.14159265358979323846 / (double)c->prob.n);
+    a.net_kind = c->net_kind;
 }
 
 // Temperature feature of the proposal network: ln(tau T), tau = n for the
 // objectives normalised by n (Schwefel, Ackley), 1 for Rastrigin.
+// The Gaussian network kind takes ln T itself (tau = 1).
 double feature_tau(const sa_problem &p) { return p.func == SA_RASTRIGIN ? 1.0 : (double)p.n; }
+
+double feature_temperature_scale(const sa_ctx *c)
+{
+    return c->net_kind == SA_NET_GELU_GAUSS ? 1.0 : feature_tau(c->prob);
+}
 
 // Box/shift values of coordinate i in the run's precision: (l, u, rho, s).
 void coord_values(const sa_ctx *c, uint32_t i, double out[4])
@@ -329,7 +337,7 @@ sa_status upload_tables(sa_ctx *c, const Staging &hs)
 {
     const Layout &l = c->pl.lay;
     const uint32_t n = c->prob.n, L = c->cfg.levels;
-    const double tau = feature_tau(c->prob);
+    const double tau = feature_temperature_scale(c);
     double t = c->cfg.T0;
     for (uint32_t k = 0; k < L; ++k) {
         hs.T[k] = t;
@@ -402,7 +410,9 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
     const uint32_t lg0 = c->cfg.log_level, lg1 = c->cfg.log_chains ? c->cfg.log_level + c->cfg.log_levels : 0;
     for (uint32_t k = first; k < first + count; ++k) {
         const bool log = k >= lg0 && k < lg1;
-        const int mode = c->learned ? (log ? sa::kModeLearnLog : sa::kModeLearn)
+        const bool gauss = c->net_kind == SA_NET_GELU_GAUSS;
+        const int mode = c->learned ? (log ? (gauss ? sa::kModeLearnLogG : sa::kModeLearnLog)
+                                           : (gauss ? sa::kModeLearnG : sa::kModeLearn))
                                     : (log ? sa::kModeLog : (c->capturing ? sa::kModeCapture : sa::kModePlain));
         uint32_t g = 0;
         hipError_t e;
@@ -507,6 +517,7 @@ sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, 
     *out = nullptr;
     sa_status st = validate(prob, cfg);
     if (st != SA_OK) return st;
+    if (!workspace) SA_FAULT_CHECK(sa::kFaultAlloc);
 
     int dev = 0;
     SA_HIP(hipGetDevice(&dev));
@@ -587,6 +598,7 @@ sa_status sa_run(sa_ctx *c, uint32_t levels)
     const uint32_t count = levels ? levels : L - c->next_level;
     if (count > L - c->next_level)
         return fail(SA_ERR_STATE, "%u levels requested, %u remain", count, L - c->next_level);
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     const uint32_t first = c->next_level;
     if (c->cfg.flags & SA_FLAG_GRAPH) {
         const auto key = std::make_tuple(first, count, c->groups);
@@ -629,6 +641,7 @@ sa_status sa_reset(sa_ctx *c, uint64_t seed)
 {
     sa::g_last_error.clear();
     if (!c) return fail(SA_ERR_INVALID, "null context");
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     if (seed != c->seed) {
         // Captured graphs hold the seed in their kernel arguments.
         drop_graphs(c);
@@ -774,6 +787,7 @@ sa_status sa_set_proposal(sa_ctx *c, const float *params, float eps)
     }
     if (!(eps >= 0.0f && eps <= 1.0f)) return fail(SA_ERR_INVALID, "eps must lie in [0, 1]");
     if (c->capturing) return fail(SA_ERR_STATE, "capture records plain runs; stop it (sa_capture(NULL)) first");
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     for (uint32_t i = 0; i < sa::mlp::kNumParams; ++i)
         if (!std::isfinite(params[i])) return fail(SA_ERR_INVALID, "parameter %u is not finite", i);
     const Layout &l = c->pl.lay;
@@ -785,6 +799,29 @@ sa_status sa_set_proposal(sa_ctx *c, const float *params, float eps)
     drop_graphs(c);
     c->a32.eps = eps;
     c->learned = true;
+    return SA_OK;
+}
+
+sa_status sa_set_network_kind(sa_ctx *c, int kind)
+{
+    sa::g_last_error.clear();
+    if (!c) return fail(SA_ERR_INVALID, "null context");
+    if (kind != SA_NET_RELU_CAUCHY && kind != SA_NET_GELU_GAUSS) return fail(SA_ERR_INVALID, "unknown network kind %d", kind);
+    if (c->capturing) return fail(SA_ERR_STATE, "the network kind fixes the captured features; stop the capture first");
+    if (kind == c->net_kind) return SA_OK;
+    c->net_kind = kind;
+    c->a32.net_kind = c->a64.net_kind = kind;
+    const uint32_t L = c->cfg.levels;
+    const double tau = feature_temperature_scale(c);
+    std::vector<float> featT(L);
+    double t = c->cfg.T0;
+    for (uint32_t k = 0; k < L; ++k) {
+        featT[k] = (float)std::log(tau * t);
+        t = t * c->cfg.alpha;
+    }
+    SA_HIP(hipMemcpyAsync(c->ws + c->pl.lay.featT, featT.data(), L * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    SA_HIP(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
     return SA_OK;
 }
 
@@ -891,6 +928,7 @@ extern "C" sa_status sa_run_static(const sa_problem *prob, const sa_config *cfg,
     if (prob->n > kStaticMaxN) return fail(SA_ERR_UNSUPPORTED, "sa_run_static: n = %u exceeds %u", prob->n, kStaticMaxN);
     if (cfg->levels > kStaticMaxLevels)
         return fail(SA_ERR_UNSUPPORTED, "sa_run_static: %u levels exceed %u", cfg->levels, kStaticMaxLevels);
+    SA_FAULT_CHECK(sa::kFaultLaunch);
 
     int dev = 0;
     SA_HIP(hipGetDevice(&dev));

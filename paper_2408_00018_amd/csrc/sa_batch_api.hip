@@ -350,6 +350,7 @@ sa_status sa_batch_create(const sa_problem *probs, uint32_t nprob, const uint32_
     if (!out) return fail(SA_ERR_INVALID, "out must not be NULL");
     *out = nullptr;
     if (sa_status st = validate_batch(probs, nprob, chains, cfg); st != SA_OK) return st;
+    if (!workspace) SA_FAULT_CHECK(sa::kFaultAlloc);
     int dev = 0;
     SA_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
@@ -425,6 +426,7 @@ sa_status sa_batch_run(sa_batch *b, uint32_t levels)
     const uint32_t count = levels ? levels : L - b->next_level;
     if (count > L - b->next_level)
         return fail(SA_ERR_STATE, "%u levels requested, %u remain", count, L - b->next_level);
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     const uint32_t first = b->next_level;
     if (b->cfg.flags & SA_FLAG_GRAPH) {
         const auto key = std::make_pair(first, count);
@@ -460,6 +462,7 @@ sa_status sa_batch_reset(sa_batch *b, uint64_t seed)
 {
     sa::g_last_error.clear();
     if (!b) return fail(SA_ERR_INVALID, "null batch");
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     if (seed != b->seed) {
         drop_batch_graphs(b);
         b->seed = seed;

@@ -7,6 +7,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <string>
 
 #include "../../include/sa.h"
@@ -31,6 +33,32 @@ inline sa_status fail(sa_status st, const char *fmt, ...)
     g_last_error = buf;
     return st;
 }
+
+// Fault injection for tests of the error paths, from the environment
+// variable SA_FAULT (read at every call):
+//   "alloc"   every call that would allocate device memory fails with
+//             SA_ERR_NOMEM once its arguments are validated, before it
+//             touches the device;
+//   "launch"  every call that would enqueue kernels fails with SA_ERR_DEVICE
+//             before it enqueues anything, leaving the context as it was.
+// Any other value, or none, injects nothing.
+enum Fault { kFaultAlloc = 0, kFaultLaunch = 1 };
+
+inline sa_status injected_fault(Fault f)
+{
+    const char *v = std::getenv("SA_FAULT");
+    if (!v) return SA_OK;
+    if (f == kFaultAlloc && std::strcmp(v, "alloc") == 0)
+        return fail(SA_ERR_NOMEM, "device allocation refused (SA_FAULT=alloc)");
+    if (f == kFaultLaunch && std::strcmp(v, "launch") == 0)
+        return fail(SA_ERR_DEVICE, "kernel launch refused (SA_FAULT=launch)");
+    return SA_OK;
+}
+
+#define SA_FAULT_CHECK(kind)                                            \
+    do {                                                                \
+        if (sa_status st_ = sa::injected_fault(kind); st_ != SA_OK) return st_; \
+    } while (0)
 
 #define SA_HIP(call)                                                                                  \
     do {                                                                                              \

@@ -76,6 +76,7 @@ template <typename R> struct LevelArgs {
     const float *featT;         // per level: ln(tau T_k), the network's temperature feature
     const unsigned char *net;   // packed network (global memory), learned modes
     float eps;                  // probability of a plain move in the learned mixture
+    int net_kind;               // mlp::NetKind of the proposal network (capture: its history features)
     float *cap_rec;             // captured records, 7 floats each
     unsigned long long *cap_count;  // accepted moves seen by the capture
     uint64_t cap_capacity;      // records cap_rec holds
@@ -92,6 +93,8 @@ enum LevelMode : int {
     kModeCapture = 2,   // record every accepted move (features, scaled displacement)
     kModeLearn = 3,     // learned-proposal mixture (FP32, radius moves)
     kModeLearnLog = 4,  // learned mixture with the move log
+    kModeLearnG = 5,    // learned mixture, Gaussian network kind (GELU)
+    kModeLearnLogG = 6, // the same with the move log
 };
 
 // Host-side launchers.  A level launch runs one level and publishes one

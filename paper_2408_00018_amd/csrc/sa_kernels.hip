@@ -59,7 +59,7 @@ static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, uint32_t pre
 {
     auto kern = level_kernel<R, F, TABLE, MODE, MOVE, UNSHIFTED>;
     const size_t lds =
-        level_lds_bytes(a.n, a.wg, sizeof(R), TABLE, MODE == kModeLearn || MODE == kModeLearnLog);
+        level_lds_bytes(a.n, a.wg, sizeof(R), TABLE, MODE >= kModeLearn);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)a.wg, lds);
     if (e != hipSuccess) return e;
@@ -88,6 +88,8 @@ static hipError_t launch_mode(int mode, const LevelArgs<R> &a, uint32_t level, u
     if constexpr (sizeof(R) == sizeof(float) && MOVE == SA_MOVE_RADIUS) {
         if (mode == kModeLearn) return launch_one<R, F, TABLE, kModeLearn, MOVE>(a, level, prev, groups, s);
         if (mode == kModeLearnLog) return launch_one<R, F, TABLE, kModeLearnLog, MOVE>(a, level, prev, groups, s);
+        if (mode == kModeLearnG) return launch_one<R, F, TABLE, kModeLearnG, MOVE>(a, level, prev, groups, s);
+        if (mode == kModeLearnLogG) return launch_one<R, F, TABLE, kModeLearnLogG, MOVE>(a, level, prev, groups, s);
     }
     return hipErrorInvalidValue;
 }

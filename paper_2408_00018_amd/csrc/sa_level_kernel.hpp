@@ -106,8 +106,9 @@ __global__ void __launch_bounds__(256)
     constexpr bool BEST = (VAR & kVarBest) != 0;
     static_assert(VAR == 0 || (!UNSHIFTED && (MODE == kModePlain || MODE == kModeLog)),
                   "exchange variants run plain or logged moves on the general kernel");
-    constexpr bool LOG = MODE == kModeLog || MODE == kModeLearnLog;
-    constexpr bool LEARN = MODE == kModeLearn || MODE == kModeLearnLog;
+    constexpr bool LOG = MODE == kModeLog || MODE == kModeLearnLog || MODE == kModeLearnLogG;
+    constexpr bool LEARN = MODE == kModeLearn || MODE == kModeLearnLog || MODE == kModeLearnG || MODE == kModeLearnLogG;
+    constexpr int KIND = (MODE == kModeLearnG || MODE == kModeLearnLogG) ? mlp::kNetGeluGauss : mlp::kNetReluCauchy;
     constexpr bool CAPTURE = MODE == kModeCapture;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Slot<R> wave_slot[4];
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(256)
         };
         if constexpr (LEARN) {
             float h[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            accepted += run_learned_steps<F>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3,
+            accepted += run_learned_steps<F, KIND>(xs, WG, tid, cost, coordf, logf, n, a.steps, level, chain, ctr3,
                                              kTagLearn | (a.problem << 8), k0, k1, nl2T, a.inv_n, featT, a.eps,
                                              net_lds, h);
         } else if constexpr (CAPTURE) {
@@ -277,10 +278,9 @@ __global__ void __launch_bounds__(256)
                         float *rec = a.cap_rec + slot * 7u;
                         rec[0] = (float)z0;
                         rec[1] = featT;
-                        rec[2] = (float)hist_feature(hist[0]);
-                        rec[3] = (float)hist_feature(hist[1]);
-                        rec[4] = (float)hist_feature(hist[2]);
-                        rec[5] = (float)hist_feature(hist[3]);
+                        const bool raw = a.net_kind == mlp::kNetGeluGauss;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) rec[2 + k] = raw ? (float)hist[k] : (float)hist_feature(hist[k]);
                         rec[6] = (float)dl;
                     }
                 }

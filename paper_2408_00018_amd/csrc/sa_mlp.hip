@@ -1,10 +1,11 @@
 // Training of the learned proposal network on gfx950 (sa_mlp_* in
 // include/sa.h).
 //
-// Network (per chosen coordinate): z (6 features) -> 128 (relu) -> 128
-// (relu) -> 2 outputs (location and log scale of a Cauchy distribution over
-// the coordinate's scaled displacement); loss = Cauchy negative
-// log-likelihood of accepted displacements.  Master parameters and Adam
+// Network (per chosen coordinate): z (6 features) -> 128 (act) -> 128
+// (act) -> 2 outputs (location and log scale of a distribution over the
+// coordinate's scaled displacement); loss = negative log-likelihood of
+// accepted displacements.  Two kinds (NetKind): relu with a Cauchy
+// distribution, GELU with a Gaussian one.  Master parameters and Adam
 // moments are FP32; the three weight matrices are used in BF16.  The
 // 128x128 layer and its two backward products run on BF16 MFMA
 // (v_mfma_f32_16x16x32_bf16, FP32 accumulate); the 6-wide input layer and
@@ -40,11 +41,11 @@ enum Epilogue { kEpiStore = 0, kEpiBiasAct = 1, kEpiActBwd = 2 };
 // tile; M, N multiples of 16, K a multiple of 32.  Epilogues:
 //   kEpiStore     C = acc
 //   kEpiBiasAct  C = acc + bias[n] (pre-activation), H = act(C)
-//   kEpiActBwd   C = acc * relu'(aux(m, n))
+//   kEpiActBwd   C = acc * act'(aux(m, n))
 template <int EPI>
 __global__ void __launch_bounds__(256)
     gemm_bf16(int M, int N, int K, const uint16_t *A, int am, int ak, const uint16_t *B, int bk, int bn, float *C,
-              int ldc, const float *bias, const float *aux, float *H)
+              int ldc, const float *bias, const float *aux, float *H, int kind)
 {
     const int lane = threadIdx.x & 63;
     const int tile = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -69,9 +70,9 @@ __global__ void __launch_bounds__(256)
         float v = acc[j];
         if (EPI == kEpiBiasAct) {
             v += bias[c];
-            H[(size_t)r * ldc + c] = bf16_bits_to_f32(f32_to_bf16_bits(act(v)));
+            H[(size_t)r * ldc + c] = bf16_bits_to_f32(f32_to_bf16_bits(act(v, kind)));
         }
-        if (EPI == kEpiActBwd) v *= act_grad(aux[(size_t)r * ldc + c]);
+        if (EPI == kEpiActBwd) v *= act_grad(aux[(size_t)r * ldc + c], kind);
         C[(size_t)r * ldc + c] = v;
     }
 }
@@ -89,7 +90,7 @@ __global__ void sample_index(uint32_t *idx, uint32_t batch, uint64_t nrec, uint3
 
 // Layer 1 (VALU): gather the minibatch, a1 = z W1 + b1, h1 = act(a1) in BF16.
 __global__ void layer1_forward(const float *records, const uint32_t *idx, uint32_t batch, const uint16_t *W1b,
-                               const float *b1, float *Z, float *delta, float *A1, uint16_t *H1b)
+                               const float *b1, float *Z, float *delta, float *A1, uint16_t *H1b, int kind)
 {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= batch * kHidden) return;
@@ -99,7 +100,7 @@ __global__ void layer1_forward(const float *records, const uint32_t *idx, uint32
 #pragma unroll
     for (int i = 0; i < kInputs; ++i) a = fmaf(rec[i], bf16_bits_to_f32(W1b[i * kHidden + j]), a);
     A1[(size_t)r * kHidden + j] = a;
-    H1b[(size_t)r * kHidden + j] = f32_to_bf16_bits(act(a));
+    H1b[(size_t)r * kHidden + j] = f32_to_bf16_bits(act(a, kind));
     if (j < kInputs) Z[(size_t)r * kInputs + j] = rec[j];
     if (j == kInputs) delta[r] = rec[kInputs];
 }
@@ -108,7 +109,7 @@ __global__ void layer1_forward(const float *records, const uint32_t *idx, uint32
 // the gradient back into layer 2's pre-activation (FP32 and BF16).
 __global__ void __launch_bounds__(256) layer3_loss(const float *H2, const float *A2, const uint16_t *W3b,
                                                    const float *b3, const float *delta, uint32_t batch, float inv_b,
-                                                   float *loss_r, float *dO, float *dA2, uint16_t *dA2b)
+                                                   float *loss_r, float *dO, float *dA2, uint16_t *dA2b, int kind)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -127,16 +128,25 @@ __global__ void __launch_bounds__(256) layer3_loss(const float *H2, const float 
     const float mu = o0 + b3[0], s = o1 + b3[1];
     const float is = expf(-s);
     const float rr = (delta[r] - mu) * is;  // standardised residual
-    const float q = 1.0f + rr * rr;
-    const float dmu = -2.0f * rr * is / q * inv_b, ds = (1.0f - 2.0f * rr * rr / q) * inv_b;
+    float dmu, ds, lr;
+    if (kind == kNetGeluGauss) {  // s + ln sqrt(2 pi) + r^2 / 2
+        dmu = -rr * is * inv_b;
+        ds = (1.0f - rr * rr) * inv_b;
+        lr = s + 0.918938533204672742f + 0.5f * rr * rr;
+    } else {  // s + ln pi + ln(1 + r^2)
+        const float q = 1.0f + rr * rr;
+        dmu = -2.0f * rr * is / q * inv_b;
+        ds = (1.0f - 2.0f * rr * rr / q) * inv_b;
+        lr = s + 1.14472988584940017f + logf(q);
+    }
     if (lane == 0) {
-        loss_r[r] = s + 1.14472988584940017f + logf(q);  // + ln pi
+        loss_r[r] = lr;
         dO[2 * r + 0] = dmu;
         dO[2 * r + 1] = ds;
     }
     for (uint32_t j = lane; j < kHidden; j += 64) {
         const float dh = bf16_bits_to_f32(W3b[2 * j + 0]) * dmu + bf16_bits_to_f32(W3b[2 * j + 1]) * ds;
-        const float da = dh * act_grad(A2[(size_t)r * kHidden + j]);
+        const float da = dh * act_grad(A2[(size_t)r * kHidden + j], kind);
         dA2[(size_t)r * kHidden + j] = da;
         dA2b[(size_t)r * kHidden + j] = f32_to_bf16_bits(da);
     }
@@ -242,6 +252,7 @@ __global__ void pack_net(const float *theta, unsigned char *net)
 
 // (mu, s) for `rows` feature vectors Z[rows][6], one chain per lane as in the
 // annealing kernels.
+template <int KIND>
 __global__ void __launch_bounds__(256) infer_rows(const unsigned char *net, const float *Z, uint32_t rows, float *out)
 {
     __shared__ __align__(16) unsigned char lds[kNetBytes];
@@ -253,7 +264,7 @@ __global__ void __launch_bounds__(256) infer_rows(const unsigned char *net, cons
 #pragma unroll
     for (int i = 0; i < kInputs; ++i) z[i] = live ? Z[(size_t)r * kInputs + i] : 0.0f;
     float mu, s;
-    net_forward(lds, z, mu, s);
+    net_forward<KIND>(lds, z, mu, s);
     if (live) {
         out[2 * (size_t)r + 0] = mu;
         out[2 * (size_t)r + 1] = s;
@@ -280,6 +291,7 @@ struct sa_mlp {
     unsigned char *net;  // packed copy for inference
     float *partial;      // chunk partial sums of the small gradients
     uint32_t t = 0;  // Adam steps taken
+    int kind = kNetReluCauchy;
 };
 
 namespace {
@@ -316,22 +328,22 @@ sa_status mlp_grad_pass(sa_mlp *p, const float *records, uint32_t batch)
     const dim3 blk(256);
     const float inv_b = 1.0f / (float)batch;
     hipLaunchKernelGGL(layer1_forward, dim3((batch * kHidden + 255) / 256), blk, 0, p->stream, records, p->idx,
-                       batch, p->W1b, p->theta + kOffB1, p->Z, p->delta, p->A1, p->H1b);
+                       batch, p->W1b, p->theta + kOffB1, p->Z, p->delta, p->A1, p->H1b, p->kind);
     // a2 = h1 W2 + b2, h2 = act(a2)
     const int tiles_bh = (int)(batch / 16) * (kHidden / 16);
     hipLaunchKernelGGL((gemm_bf16<kEpiBiasAct>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
                        kHidden, p->H1b, kHidden, 1, p->W2b, kHidden, 1, p->A2, kHidden, p->theta + kOffB2,
-                       (const float *)nullptr, p->H2);
+                       (const float *)nullptr, p->H2, p->kind);
     hipLaunchKernelGGL(layer3_loss, dim3((batch + 3) / 4), blk, 0, p->stream, p->H2, p->A2, p->W3b,
-                       p->theta + kOffB3, p->delta, batch, inv_b, p->loss_r, p->dO, p->dA2, p->dA2b);
+                       p->theta + kOffB3, p->delta, batch, inv_b, p->loss_r, p->dO, p->dA2, p->dA2b, p->kind);
     // dW2 = h1^T da2  (M = N = 128, K = batch)
     hipLaunchKernelGGL((gemm_bf16<kEpiStore>), dim3((64 + 3) / 4), blk, 0, p->stream, kHidden, kHidden, (int)batch,
                        p->H1b, 1, kHidden, p->dA2b, kHidden, 1, p->g + kOffW2, kHidden, (const float *)nullptr,
-                       (const float *)nullptr, (float *)nullptr);
-    // da1 = (da2 W2^T) * relu'(a1)
+                       (const float *)nullptr, (float *)nullptr, p->kind);
+    // da1 = (da2 W2^T) * act'(a1)
     hipLaunchKernelGGL((gemm_bf16<kEpiActBwd>), dim3((tiles_bh + 3) / 4), blk, 0, p->stream, (int)batch, kHidden,
                        kHidden, p->dA2b, kHidden, 1, p->W2b, 1, kHidden, p->dA1, kHidden, (const float *)nullptr,
-                       p->A1, (float *)nullptr);
+                       p->A1, (float *)nullptr, p->kind);
     const uint32_t chunks = (batch + kGradChunk - 1) / kGradChunk;
     hipLaunchKernelGGL(small_grads_partial, dim3((kSmallGrads + 255) / 256, chunks), blk, 0, p->stream, p->Z,
                        p->dA1, p->dA2, p->H2, p->dO, batch, p->partial);
@@ -361,6 +373,7 @@ sa_status sa_mlp_create(uint32_t max_batch, void *stream, sa_mlp **out)
     *out = nullptr;
     if (max_batch == 0 || max_batch % 32 || max_batch > (1u << 20))
         return fail(SA_ERR_INVALID, "max_batch must be a multiple of 32 in [32, 2^20]");
+    SA_FAULT_CHECK(sa::kFaultAlloc);
     sa_mlp *p = new (std::nothrow) sa_mlp;
     if (!p) return fail(SA_ERR_NOMEM, "host allocation failed");
     p->stream = reinterpret_cast<hipStream_t>(stream);
@@ -404,6 +417,7 @@ sa_status sa_mlp_grad(sa_mlp *p, const float *records, uint64_t nrec, const uint
         return fail(SA_ERR_INVALID, "batch must be a multiple of 32 and at most max_batch");
     for (uint32_t r = 0; r < batch; ++r)
         if (idx[r] >= nrec) return fail(SA_ERR_INVALID, "index %u out of range", r);
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     SA_HIP(hipMemcpyAsync(p->idx, idx, batch * sizeof(uint32_t), hipMemcpyHostToDevice, p->stream));
     if (sa_status st = mlp_grad_pass(p, records, batch); st != SA_OK) return st;
     SA_HIP(hipStreamSynchronize(p->stream));
@@ -421,6 +435,7 @@ sa_status sa_mlp_train(sa_mlp *p, const float *records, uint64_t nrec, uint32_t 
     if (batch == 0 || batch % 32 || batch > p->max_batch)
         return fail(SA_ERR_INVALID, "batch must be a multiple of 32 and at most max_batch");
     if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(SA_ERR_INVALID, "lr must be finite and > 0");
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     const float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
     std::vector<float> trace(loss_trace ? steps : 0);
     for (uint32_t s = 0; s < steps; ++s) {
@@ -444,10 +459,25 @@ sa_status sa_mlp_infer(sa_mlp *p, const float *Z, uint32_t rows, float *out)
     sa::g_last_error.clear();
     if (!p || !Z || !out) return fail(SA_ERR_INVALID, "null argument");
     if (rows == 0) return SA_OK;
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     hipError_t e = sa::launch_pack_net(p->theta, p->net, p->stream);
     if (e != hipSuccess) return fail(SA_ERR_DEVICE, "pack launch: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(infer_rows, dim3((rows + 255) / 256), dim3(256), 0, p->stream, p->net, Z, rows, out);
+    if (p->kind == kNetGeluGauss)
+        hipLaunchKernelGGL(infer_rows<kNetGeluGauss>, dim3((rows + 255) / 256), dim3(256), 0, p->stream, p->net, Z,
+                           rows, out);
+    else
+        hipLaunchKernelGGL(infer_rows<kNetReluCauchy>, dim3((rows + 255) / 256), dim3(256), 0, p->stream, p->net, Z,
+                           rows, out);
     SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
+sa_status sa_mlp_set_kind(sa_mlp *p, int kind)
+{
+    sa::g_last_error.clear();
+    if (!p) return fail(SA_ERR_INVALID, "null trainer");
+    if (kind != SA_NET_RELU_CAUCHY && kind != SA_NET_GELU_GAUSS) return fail(SA_ERR_INVALID, "unknown network kind %d", kind);
+    p->kind = kind;
     return SA_OK;
 }
 

@@ -23,10 +23,58 @@ constexpr uint32_t kOffB3 = kOffW3 + kHidden * 2;
 constexpr uint32_t kNumParams = kOffB3 + 2;
 static_assert(kNumParams == 17666, "parameter count");
 
-// Hidden activation: relu, with derivative 0 at 0.
-__host__ __device__ __forceinline__ float act(float a) { return fmaxf(a, 0.0f); }
+// Network kinds (include/sa.h SA_NET_*): relu hidden activations with a
+// Cauchy distribution over the scaled displacement and log-magnitude history
+// features, or GELU activations with a Gaussian distribution (mean, log
+// standard deviation) and the history's scaled displacements as they are.
+enum NetKind : int { kNetReluCauchy = 0, kNetGeluGauss = 1 };
 
-__host__ __device__ __forceinline__ float act_grad(float a) { return a > 0.0f ? 1.0f : 0.0f; }
+// Standard normal density phi(x) and the upper tail 1 - Phi(|x|) by the
+// rational approximation 26.2.17 of Abramowitz and Stegun (Handbook of
+// Mathematical Functions, 1964): 1 - Phi(x) = phi(x) (b1 t + ... + b5 t^5),
+// t = 1 / (1 + p x), x >= 0, absolute error below 7.5e-8; FP32 with the
+// hardware reciprocal and base-2 exponential.
+__device__ __forceinline__ float normal_pdf(float x)
+{
+    return 0.398942280401432678f * __builtin_amdgcn_exp2f((x * x) * -0.721347520444481703f);
+}
+
+__device__ __forceinline__ float normal_upper_tail(float ax, float pdf)
+{
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.2316419f, ax, 1.0f));
+    float q = fmaf(t, 1.330274429f, -1.821255978f);
+    q = fmaf(t, q, 1.781477937f);
+    q = fmaf(t, q, -0.356563782f);
+    q = fmaf(t, q, 0.319381530f);
+    return pdf * (t * q);
+}
+
+// Phi(a) for any a.
+__device__ __forceinline__ float normal_cdf(float a)
+{
+    const float ax = fminf(fabsf(a), 16.0f);
+    const float tail = normal_upper_tail(ax, normal_pdf(ax));
+    return a >= 0.0f ? 1.0f - tail : tail;
+}
+
+// Hidden activation of a kind: relu (derivative 0 at 0), or GELU
+// a Phi(a) with derivative Phi(a) + a phi(a).
+__device__ __forceinline__ float act(float a, int kind = kNetReluCauchy)
+{
+    if (kind == kNetGeluGauss) return a * normal_cdf(a);
+    return fmaxf(a, 0.0f);
+}
+
+__device__ __forceinline__ float act_grad(float a, int kind = kNetReluCauchy)
+{
+    if (kind == kNetGeluGauss) {
+        const float ax = fminf(fabsf(a), 16.0f);
+        const float pdf = normal_pdf(ax);
+        const float tail = normal_upper_tail(ax, pdf);
+        return (a >= 0.0f ? 1.0f - tail : tail) + a * pdf;
+    }
+    return a > 0.0f ? 1.0f : 0.0f;
+}
 
 // FP32 <-> BF16 (round to nearest even; NaN stays NaN).
 __host__ __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f)

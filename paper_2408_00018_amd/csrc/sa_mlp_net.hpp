@@ -4,7 +4,8 @@
 //
 // The 64 lanes of a wave each bring one feature vector (their chain's chosen
 // coordinate).  The wave evaluates the transposed network
-//     H1^T = relu(W1^T Z^T + b1),  H2^T = relu(W2^T H1^T + b2),  O^T = W3^T H2^T + b3
+//     H1^T = act(W1^T Z^T + b1),  H2^T = act(W2^T H1^T + b2),  O^T = W3^T H2^T + b3
+// (act = relu, or GELU for the Gaussian network kind)
 // on v_mfma_f32_16x16x32_bf16 in four column tiles of 16 chains, so that the
 // accumulator layout of one layer (lane l holds rows 4(l/16)+j, j<4, of column
 // l%16) is already the B-operand layout of the next: the K index of a layer's
@@ -94,13 +95,29 @@ __device__ __forceinline__ uint32_t relu_pack(float a, float b)
     return __builtin_bit_cast(uint32_t, m);
 }
 
+// Two FP32 pre-activations as a word of two BF16 GELU values (GELU in FP32,
+// then one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t gelu_pack(float a, float b)
+{
+    const bf16x2 h = __builtin_convertvector(float2v{act(a, kNetGeluGauss), act(b, kNetGeluGauss)}, bf16x2);
+    return __builtin_bit_cast(uint32_t, h);
+}
+
+template <int KIND> __device__ __forceinline__ uint32_t act_pack(float a, float b)
+{
+    if constexpr (KIND == kNetGeluGauss) return gelu_pack(a, b);
+    else return relu_pack(a, b);
+}
+
 __device__ __forceinline__ bf16x8 words(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3)
 {
     return __builtin_bit_cast(bf16x8, u32x4{w0, w1, w2, w3});
 }
 
 // (mu, s) of this lane's feature vector z[0..5].  Every lane of the wave must
-// call it (the products are wave-wide).  `net` is the packed network in LDS.
+// call it (the products are wave-wide).  `net` is the packed network in LDS;
+// KIND selects the hidden activation (NetKind).
+template <int KIND = kNetReluCauchy>
 __device__ __forceinline__ void net_forward(const unsigned char *net, const float (&z)[kInputs], float &mu, float &s)
 {
     const uint32_t lane = threadIdx.x & 63u, g = lane >> 4, col = lane & 15u;
@@ -131,8 +148,8 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
             const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1[ct], bias, 0, 0, 0);
-            h1[ct][rt >> 1][(rt & 1) * 2 + 0] = relu_pack(acc[0], acc[1]);
-            h1[ct][rt >> 1][(rt & 1) * 2 + 1] = relu_pack(acc[2], acc[3]);
+            h1[ct][rt >> 1][(rt & 1) * 2 + 0] = act_pack<KIND>(acc[0], acc[1]);
+            h1[ct][rt >> 1][(rt & 1) * 2 + 1] = act_pack<KIND>(acc[2], acc[3]);
         }
     }
 
@@ -152,8 +169,8 @@ __device__ __forceinline__ void net_forward(const unsigned char *net, const floa
         }
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) {
-            h2[ct][rt >> 1][(rt & 1) * 2 + 0] = relu_pack(acc[ct][0], acc[ct][1]);
-            h2[ct][rt >> 1][(rt & 1) * 2 + 1] = relu_pack(acc[ct][2], acc[ct][3]);
+            h2[ct][rt >> 1][(rt & 1) * 2 + 0] = act_pack<KIND>(acc[ct][0], acc[ct][1]);
+            h2[ct][rt >> 1][(rt & 1) * 2 + 1] = act_pack<KIND>(acc[ct][2], acc[ct][3]);
         }
     }
 

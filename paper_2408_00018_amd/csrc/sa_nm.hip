@@ -420,6 +420,7 @@ sa_status sa_nm_polish(const sa_problem *prob, const double *x0, uint32_t starts
     const uint32_t log_steps = cfg->log_steps ? cfg->maxiter : 0;
     const NmLayout l = nm_layout(n, starts, log_steps, prob->shift != nullptr);
     const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    SA_FAULT_CHECK(sa::kFaultLaunch);
     unsigned char *ws = static_cast<unsigned char *>(workspace);
     bool own = false;
     if (ws) {
@@ -428,6 +429,7 @@ sa_status sa_nm_polish(const sa_problem *prob, const double *x0, uint32_t starts
         if (reinterpret_cast<uintptr_t>(ws) % sa::kAlign)
             return fail(SA_ERR_INVALID, "workspace must be %zu-byte aligned", sa::kAlign);
     } else {
+        SA_FAULT_CHECK(sa::kFaultAlloc);
         hipError_t e = hipMalloc(reinterpret_cast<void **>(&ws), l.total);
         if (e != hipSuccess) return fail(SA_ERR_NOMEM, "hipMalloc(%zu): %s", l.total, hipGetErrorString(e));
         own = true;

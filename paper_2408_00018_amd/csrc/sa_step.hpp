@@ -633,10 +633,12 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
 //   d from wd; a plain move with probability eps (U(q1) < eps): the radius
 //   neighbour from w1 and the Metropolis test on w2, as in run_steps;
 //   otherwise the network gives (mu, s) at the features of x_d, the scaled
-//   displacement is dl = mu + e^s t with t = tan(pi (U(q0) - 1/2)) (a standard
-//   Cauchy draw by inversion), x'_d = x_d + dl (u_d - l_d); a proposal
-//   outside [l_d, u_d] is rejected; otherwise the network is evaluated again
-//   at x'_d (same history) and the move is taken iff
+//   displacement is dl = mu + e^s t with t a standard draw of the network's
+//   distribution -- Cauchy: t = tan(pi (U(q0) - 1/2)) by inversion; Gaussian:
+//   t = sqrt(-2 ln(1 - U(q0))) cos(2 pi U(q2)) (Box-Muller) --,
+//   x'_d = x_d + dl (u_d - l_d); a proposal outside [l_d, u_d] is rejected;
+//   otherwise the network is evaluated again at x'_d (same history) and the
+//   move is taken iff
 //       U(w2) < exp(-df/T + ln q(x | x') - ln q(x' | x))
 //   (Metropolis-Hastings.  For a fixed history each component, and so their
 //   state-independent mixture, is reversible with respect to exp(-f/T); an
@@ -644,10 +646,11 @@ __device__ __forceinline__ uint32_t run_steps(R *xs, uint32_t stride, uint32_t l
 //   is adaptive and the invariance holds only approximately.)
 // h holds the history features of the chain's last four accepted scaled
 // displacements (most recent first); every accepted move, plain or learned,
-// pushes hist_feature((x'_d - x_d)/(u_d - l_d)).
+// pushes the feature of (x'_d - x_d)/(u_d - l_d): hist_feature of it for the
+// Cauchy kind, the value itself for the Gaussian kind.
 // All lanes of the wave run every step (the network runs on wave-wide MFMA).
 // ---------------------------------------------------------------------------
-template <int F, typename CoordFn, typename LogFn>
+template <int F, int KIND, typename CoordFn, typename LogFn>
 __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride, uint32_t lane_off,
                                                       Cost<float, F> &cost, const CoordFn &coordf, const LogFn &logf,
                                                       uint32_t n, uint32_t steps, uint32_t level, uint32_t chain,
@@ -672,20 +675,29 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
 
         float z[mlp::kInputs] = {(xd - c.lo) * inv_w, featT, h[0], h[1], h[2], h[3]};
         float mu, s;
-        mlp::net_forward(net, z, mu, s);
-        // tan(pi a) = sin(2 pi a/2) / cos(2 pi a/2) on the revolution-based units
-        const float half = 0.5f * (u24f(q.w0) - 0.5f);
-        const float t = hw_sin_rev(half) / hw_cos_rev(half);
+        mlp::net_forward<KIND>(net, z, mu, s);
+        float t;
+        if constexpr (KIND == mlp::kNetGeluGauss) {
+            // 1 - U(q0) lies in [2^-24, 1]: the logarithm is finite
+            const float rad = __builtin_sqrtf(-2.0f * kLn2 * hw_log2(1.0f - u24f(q.w0)));
+            t = rad * hw_cos_rev(u24f(q.w2));
+        } else {
+            // tan(pi a) = sin(2 pi a/2) / cos(2 pi a/2) on the revolution-based units
+            const float half = 0.5f * (u24f(q.w0) - 0.5f);
+            t = hw_sin_rev(half) / hw_cos_rev(half);
+        }
         const float dl = fmaf(hw_exp2(kLog2e * s), t, mu);
         const float xl = fmaf(dl, w, xd);
         const bool inbox = xl >= c.lo && xl <= c.hi;
         z[0] = inbox ? (xl - c.lo) * inv_w : 0.5f;
         float mu2, s2;
-        mlp::net_forward(net, z, mu2, s2);
-        // ln q(x | x') - ln q(x' | x) for Cauchy densities; the forward
-        // standardised residual is t
+        mlp::net_forward<KIND>(net, z, mu2, s2);
+        // ln q(x | x') - ln q(x' | x); the forward standardised residual is t,
+        // the reverse one -(dl + mu2) e^-s2
         const float e2 = (dl + mu2) * hw_exp2(-kLog2e * s2);
-        const float lq = (s - s2) + kLn2 * (hw_log2(fmaf(t, t, 1.0f)) - hw_log2(fmaf(e2, e2, 1.0f)));
+        float lq;
+        if constexpr (KIND == mlp::kNetGeluGauss) lq = (s - s2) + 0.5f * (t * t - e2 * e2);
+        else lq = (s - s2) + kLn2 * (hw_log2(fmaf(t, t, 1.0f)) - hw_log2(fmaf(e2, e2, 1.0f)));
 
         const float xp = neighbour<SA_MOVE_RADIUS>(xd, c, u24f(w1));
         const float xn = plain ? xp : xl;
@@ -700,7 +712,8 @@ __device__ __forceinline__ uint32_t run_learned_steps(float *xs, uint32_t stride
             h[3] = h[2];
             h[2] = h[1];
             h[1] = h[0];
-            h[0] = hist_feature((xn - xd) * inv_w);
+            const float hs = (xn - xd) * inv_w;
+            h[0] = KIND == mlp::kNetGeluGauss ? hs : hist_feature(hs);
         }
         accepted += take ? 1u : 0u;
     }

@@ -6,8 +6,11 @@ paper's moves are the plain radius/resample neighbours).
    displacement) across the whole temperature range, the same number from
    every captured level (acceptance falls by orders of magnitude as T drops,
    so levels with fewer accepted moves are repeated to the quota).
-2. ``train``: Adam on the Cauchy negative log-likelihood of those records,
-   on the GPU (``MLPTrainer``).
+2. ``train``: Adam on the negative log-likelihood of those records (Cauchy
+   for the relu network, Gaussian for the GELU one), on the GPU
+   (``MLPTrainer``).  ``collect_runs`` captures every accepted move of whole
+   runs over successive seeds instead (the learned-proposal configuration
+   that trains the GELU/Gaussian network on small-problem runs).
 3. ``time_to_target``: run a schedule with plain or learned moves and report
    the first level whose record is within ``target`` of f*, with its device
    time.
@@ -41,17 +44,19 @@ def init_params(seed: int = 0, sigma0: float = 0.01) -> np.ndarray:
     return p.astype(np.float32)
 
 
-def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, per_level: int = 2000):
+def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, per_level: int = 2000,
+            kind: int = sa.NET_RELU_CAUCHY):
     """Run `schedule` (plain moves) and capture the accepted moves of every
     `every`-th level: the first `per_level` of each, or all of them repeated
-    up to `per_level` when there are fewer.  Returns a float32 CUDA tensor
-    [N, 7]."""
+    up to `per_level` when there are fewer; features of network kind `kind`.
+    Returns a float32 CUDA tensor [N, 7]."""
     import torch
     nlev = (schedule.levels + every - 1) // every
     rec = torch.empty((nlev * per_level, 7), dtype=torch.float32, device="cuda")
     off = 0
     sched = sa.Schedule(**{**schedule.__dict__, "graph": False, "learned": False, "log_chains": 0})
     with sa.Annealer(func, lower, upper, shift, schedule=sched) as ann:
+        ann.set_network_kind(kind)
         level = 0
         while level < sched.levels:
             ann.capture(rec[off:off + per_level])
@@ -71,11 +76,36 @@ def collect(func, lower, upper, shift, schedule: sa.Schedule, every: int = 4, pe
     return rec[:off]
 
 
+def collect_runs(func, lower, upper, shift, schedule: sa.Schedule, records: int, kind: int = sa.NET_RELU_CAUCHY,
+                 first_seed: Optional[int] = None, max_runs: int = 1000):
+    """Capture every accepted move of whole plain runs of `schedule`, seed
+    after seed (from `first_seed`, default the schedule's), until `records`
+    are stored (the last run's surplus is dropped).  Returns (float32 CUDA
+    tensor [records, 7], runs used)."""
+    import torch
+    rec = torch.empty((records, 7), dtype=torch.float32, device="cuda")
+    off, runs = 0, 0
+    seed = schedule.seed if first_seed is None else first_seed
+    while off < records and runs < max_runs:
+        sched = sa.Schedule(**{**schedule.__dict__, "graph": False, "learned": False, "log_chains": 0, "seed": seed})
+        with sa.Annealer(func, lower, upper, shift, schedule=sched) as ann:
+            ann.set_network_kind(kind)
+            ann.capture(rec[off:])
+            ann.run()
+            off += min(ann.capture_count(), records - off)
+            ann.capture(None)
+        seed += 1
+        runs += 1
+    return rec[:off], runs
+
+
 def train(records, steps: int = 6000, batch: int = 1024, lr: float = 1e-3, seed: int = 0,
-          params: Optional[np.ndarray] = None):
-    """Train the proposal network on `records`; returns (params, loss trace)."""
+          params: Optional[np.ndarray] = None, kind: int = sa.NET_RELU_CAUCHY):
+    """Train the proposal network of kind `kind` on `records`; returns
+    (params, loss trace)."""
     tr = sa.MLPTrainer(max_batch=batch)
     try:
+        tr.set_kind(kind)
         tr.set_params(init_params(seed) if params is None else params)
         trace = tr.train(records, batch=batch, steps=steps, lr=lr, seed=seed)
         return tr.params(), trace
@@ -95,7 +125,7 @@ class TargetResult:
 
 def time_to_target(func, lower, upper, shift, schedule: sa.Schedule, f_star: float, target: float = 1e-4, *,
                    params=None, eps: float = 0.1, start_level: int = 0, x_start=None, chunk: int = 100,
-                   learn_from: int = 0):
+                   learn_from: int = 0, kind: int = sa.NET_RELU_CAUCHY):
     """Run levels in chunks until the record is within `target` of f_star or
     the schedule ends.  With `params`, levels from `learn_from` on use the
     learned mixture and earlier ones the plain moves.  The time to the hit is
@@ -105,6 +135,8 @@ def time_to_target(func, lower, upper, shift, schedule: sa.Schedule, f_star: flo
     sched = sa.Schedule(**{**schedule.__dict__, "trace_x": False, "graph": False, "learned": params is not None,
                            "log_chains": 0})
     with sa.Annealer(func, lower, upper, shift, schedule=sched) as ann:
+        if params is not None:
+            ann.set_network_kind(kind)
         if start_level:
             ann.set_start(start_level, x_start)
         learning = False

@@ -23,6 +23,7 @@ FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8
 FLAG_SOS, FLAG_BEST_SEEN = 0x10, 0x20  # exchange variants
+NET_RELU_CAUCHY, NET_GELU_GAUSS = 0, 1  # proposal network kinds
 EXCHANGE_NEVER = 0xFFFFFFFF
 
 SA_OK = 0
@@ -30,7 +31,8 @@ STATUS_NAMES = {0: "SA_OK", -1: "SA_ERR_INVALID", -2: "SA_ERR_NOMEM", -3: "SA_ER
                 -5: "SA_ERR_UNSUPPORTED"}
 
 EXPORTED = ["sa_workspace_bytes", "sa_create", "sa_run", "sa_reset", "sa_levels_done", "sa_best", "sa_trace",
-            "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_capture", "sa_capture_count", "sa_layout",
+            "sa_move_log", "sa_set_start", "sa_set_proposal", "sa_set_network_kind", "sa_capture", "sa_capture_count",
+            "sa_layout",
             "sa_destroy", "sa_last_error", "sa_run_static", "sa_nm_workspace_bytes", "sa_nm_polish",
             "sa_candidates"]
 
@@ -101,6 +103,8 @@ def load_library():
     L.sa_set_start.restype = st
     L.sa_set_proposal.argtypes = [vp, vp, ctypes.c_float]
     L.sa_set_proposal.restype = st
+    L.sa_set_network_kind.argtypes = [vp, ctypes.c_int]
+    L.sa_set_network_kind.restype = st
     L.sa_capture.argtypes = [vp, vp, u64]
     L.sa_capture.restype = st
     L.sa_capture_count.argtypes = [vp, ctypes.POINTER(u64)]
@@ -299,6 +303,11 @@ class Annealer:
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == MLP_PARAMS
         _check(load_library().sa_set_proposal(self._ctx, p.ctypes.data, eps))
+
+    def set_network_kind(self, kind: int):
+        """Kind of network (NET_RELU_CAUCHY or NET_GELU_GAUSS) the learned
+        levels evaluate and captures record features for."""
+        _check(load_library().sa_set_network_kind(self._ctx, int(kind)))
 
     def capture(self, records):
         """Record accepted moves of later plain levels into ``records`` (a
@@ -578,7 +587,7 @@ class BatchAnnealer:
 # ---------------------------------------------------------------------------
 MLP_PARAMS = 17666
 EXPORTED_MLP = ["sa_mlp_create", "sa_mlp_set_params", "sa_mlp_get_params", "sa_mlp_grad", "sa_mlp_train",
-                "sa_mlp_infer", "sa_mlp_destroy"]
+                "sa_mlp_infer", "sa_mlp_set_kind", "sa_mlp_destroy"]
 EXPORTED = EXPORTED + EXPORTED_MLP
 
 
@@ -598,6 +607,8 @@ def _mlp_lib():
         L.sa_mlp_train.restype = st
         L.sa_mlp_infer.argtypes = [vp, vp, u32, vp]
         L.sa_mlp_infer.restype = st
+        L.sa_mlp_set_kind.argtypes = [vp, ctypes.c_int]
+        L.sa_mlp_set_kind.restype = st
         L.sa_mlp_destroy.argtypes = [vp]
         L.sa_mlp_destroy.restype = None
         L._mlp_bound = True
@@ -620,6 +631,11 @@ class MLPTrainer:
         p = np.ascontiguousarray(params, dtype=np.float32)
         assert p.size == MLP_PARAMS
         _check(_mlp_lib().sa_mlp_set_params(self._h, p.ctypes.data))
+
+    def set_kind(self, kind: int):
+        """Network kind (NET_RELU_CAUCHY or NET_GELU_GAUSS) of the forward
+        pass, the loss and inference."""
+        _check(_mlp_lib().sa_mlp_set_kind(self._h, int(kind)))
 
     def params(self):
         p = np.zeros(MLP_PARAMS, dtype=np.float32)

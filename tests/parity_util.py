@@ -15,15 +15,20 @@ U32 = 2.0 ** -24  # FP32 unit roundoff
 # Error bounds of the FP32 hardware transcendentals, checked against FP64 on
 # the GPU by tests/test_gpu_trig.py: absolute for sine/cosine on arguments up
 # to 64 revolutions (E_TRIG) and up to 256 (E_TRIG_WIDE, Griewank's
-# cos(y/sqrt(i)) at |y| up to 1200), relative for sqrt and 2^t.
-E_TRIG = 2.0 ** -19
-E_TRIG_WIDE = 2.0 ** -17
+# cos(y/sqrt(i)) at |y| up to 1200), relative for sqrt and 2^t.  The
+# sine/cosine bounds are the measured maximum (2.10 x 2^-24 at every range)
+# with a margin of 1.9 (E_TRIG) and 3.8 (E_TRIG_WIDE).
+E_TRIG = 2.0 ** -21
+E_TRIG_WIDE = 2.0 ** -20
 E_SQRT = 2.0 ** -22
 E_EXP2 = 2.0 ** -21
 # Relative error of the FP32 e^x - 1 of the Ackley increment (polynomial for
 # |x| <= 1/2, hardware exponential minus one beyond); the Ackley floor below
 # allows 36 and 68 of 2^-24 on its two terms.
 E_EXPM1 = 2.0 ** -20
+# v_log_f32, relative, over (0, 1] (the Box-Muller radius of the Gaussian
+# proposal network; tests/test_gpu_trig.py)
+E_LOG2 = 2.0 ** -21
 
 
 def f32(v):
@@ -110,7 +115,9 @@ def eval_err32(func, x, shift):
 def df_floor(func, n, x, xn, d, shift):
     """Absolute error floor of an FP32 cost increment, from the rounding of its
     inputs and the hardware transcendental error (the relative 1e-5 is added
-    on top).  x, xn: FP64 copies of the FP32 states before/after the move.
+    on top): twice a first-order bound (the factor 2 covers the second-order
+    terms the bound leaves out).  x, xn: FP64 copies of the FP32 states
+    before/after the move.
     Non-separable families: the increment is the difference of two full FP32
     evaluations (the carried cost is the last one, or the FP64 start value
     rounded to FP32), so the floor is the sum of their error bounds, doubled
@@ -123,12 +130,12 @@ def df_floor(func, n, x, xn, d, shift):
         def t(v):
             a = abs(v)
             return a * (math.sqrt(a) * 4 * U32 + E_TRIG) + a * 2 * U32
-        return 4.0 * (t(y) + t(yn)) / n
+        return 2.0 * (t(y) + t(yn)) / n
     if func == O.RASTRIGIN:
         dl, sg = abs(yn - y), abs(yn + y)
         ddl = U32 * (abs(y) + abs(yn) + dl)
         dsg = U32 * (abs(y) + abs(yn) + sg)
-        return 4.0 * (sg * ddl + dl * dsg + dl * sg * 2 * U32 + 20 * (math.pi * (ddl + dsg) + 2 * E_TRIG)
+        return 2.0 * (sg * ddl + dl * dsg + dl * sg * 2 * U32 + 20 * (math.pi * (ddl + dsg) + 2 * E_TRIG)
                       + 40 * U32)
     # Ackley, increment formed from the two sums (S1 = sum y^2, S2 = sum cos 2 pi y):
     # errors of dS1 = dl sg and dS2 = -2 sin(pi sg) sin(pi dl), plus the FP32
@@ -152,7 +159,7 @@ def df_floor(func, n, x, xn, d, shift):
     da = 0.2 * (ds1 / n) / den
     term_a = 20.0 * ea * da * (6.4 * q * U32 + 36 * U32) + 20.0 * ea * 0.2 * e_ds1 / (n * den)
     term_b = eb * (ds2 / n) * 68 * U32 + eb * e_ds2 / n
-    return 4.0 * (term_a + term_b)
+    return 2.0 * (term_a + term_b)
 
 
 def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
@@ -327,11 +334,25 @@ def bf16_matrices(params):
     return p.astype(np.float64)
 
 
+def gauss_draw_error(seed, problem, level, chain, step):
+    """Bound on the FP32 Box-Muller draw's error (the Gaussian network kind):
+    t = sqrt(-2 ln(1 - U0)) cos(2 pi U2), with ln from the hardware log2
+    (relative E_LOG2, then two roundings), the hardware square root (E_SQRT)
+    and cosine (absolute E_TRIG), and the final product's rounding."""
+    w = O.philox4x32_10([step, level, chain, 3 | (problem << 8)], [seed & 0xFFFFFFFF, seed >> 32])
+    u0, u2 = O.uniform(w[0]), O.uniform(w[2])
+    rad = math.sqrt(-2.0 * math.log(1.0 - u0))
+    cv = abs(math.cos(2.0 * math.pi * u2))
+    drad = rad * (0.5 * (E_LOG2 + 3 * U32) + E_SQRT)
+    return rad * E_TRIG + cv * drad + 2 * U32 * rad
+
+
 def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, featT, eps32, params64, radius_frac,
-                        x_start, moves, final_f, chain_ids, problem=0):
+                        x_start, moves, final_f, chain_ids, problem=0, kind=O.NET_RELU_CAUCHY):
     """Replay the logged moves of a learned-mixture level against the oracle's
     learned move (oracle.learned_propose / oracle.learned_accept with the
-    network under the device's stated precision, NET_DEVICE, and its bounds).
+    network under the device's stated precision, NET_DEVICE, and its bounds),
+    for network kind `kind` (the relu/Cauchy network or the GELU/Gaussian one).
 
     Each move: the coordinate and the plain/learned choice are bit-exact; a
     plain move is checked as in check_fp32_level; a learned move's proposal
@@ -341,6 +362,17 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
     wherever those bounds (and the FP32 increment's) cannot flip it.  The
     chain state and history follow the GPU's own accepted moves.  Returns
     statistics."""
+    O.set_net_kind(kind)
+    try:
+        return _check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, featT, eps32, params64,
+                                    radius_frac, x_start, moves, final_f, chain_ids, problem, kind)
+    finally:
+        O.set_net_kind(O.NET_RELU_CAUCHY)
+
+
+def _check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, featT, eps32, params64, radius_frac,
+                         x_start, moves, final_f, chain_ids, problem, kind):
+    gauss = kind == O.NET_GELU_GAUSS
     stats = dict(moves=0, learned=0, outside=0, ambiguous=0, max_dl_excess=0.0, max_rel_excess=0.0)
     nd = O.NET_DEVICE
     for j, c in enumerate(chain_ids):
@@ -384,11 +416,16 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                 dl_gpu = (x_new - x_old) / w
                 # rounding of x' = x + dl w and of the logged positions, in dl units
                 ddl = 4 * U32 * (abs(x_old) + abs(x_new)) / w
-                # network bounds on mu and s (e^s within e^{+-bs}); the hardware
-                # sin/cos quotient for t (relative error growing like |t| towards
-                # the poles); FP32 rounding of the draw and the fused multiply-add
-                tol_dl = (bmu + sig * abs(t) * (math.expm1(bs) + 2.0 ** -18)
-                          + sig * 2.0 ** -18 * (1 + abs(t) + t * t) + 4 * U32 * abs(dl_ref) + ddl)
+                # network bounds on mu and s (e^s within e^{+-bs}); the draw t's
+                # FP32 error -- Cauchy: the hardware sin/cos quotient (relative
+                # error growing like |t| towards the poles); Gaussian: the
+                # Box-Muller bound --; FP32 rounding of the fused multiply-add
+                if gauss:
+                    dt = gauss_draw_error(seed, problem, level, c, s)
+                else:
+                    dt = 2.0 ** -18 * (1 + abs(t) + t * t)
+                tol_dl = (bmu + sig * abs(t) * (math.expm1(bs) + 2.0 ** -18) + sig * dt + 4 * U32 * abs(dl_ref)
+                          + ddl)
                 err = abs(dl_gpu - dl_ref)
                 stats["max_dl_excess"] = max(stats["max_dl_excess"], err / tol_dl)
                 assert err <= tol_dl, (level, c, s, dl_gpu, dl_ref, tol_dl)
@@ -406,14 +443,18 @@ def check_learned_level(func, n, lower32, upper32, shift32, seed, level, T, feat
                     assert abs(m["df"] - df_ref) <= tol, (level, c, s, float(m["df"]), df_ref)
                     stats["max_rel_excess"] = max(stats["max_rel_excess"], abs(m["df"] - df_ref) / tol)
                     mu2, s2, bmu2, bs2 = det["mu2"], det["s2"], det["b_mu2"], det["b_s2"]
-                    # first-order sensitivity of the two Cauchy log densities to
-                    # their location and log scale (and to dl's rounding)
+                    # first-order sensitivity of the two log densities to their
+                    # location and log scale (and to dl's rounding)
                     e1 = (dl_gpu - mu) * math.exp(-sl)
                     e2 = (-dl_gpu - mu2) * math.exp(-s2)
-                    tol_lq = (2 * abs(e1) * math.exp(-sl) / (1 + e1 * e1) * (bmu + ddl)
-                              + abs(1 - 2 * e1 * e1 / (1 + e1 * e1)) * bs
-                              + 2 * abs(e2) * math.exp(-s2) / (1 + e2 * e2) * (bmu2 + ddl)
-                              + abs(1 - 2 * e2 * e2 / (1 + e2 * e2)) * bs2)
+                    if gauss:  # ln q = -s - r^2/2 + const: d/dmu = r e^-s, d/ds = r^2 - 1
+                        tol_lq = (abs(e1) * math.exp(-sl) * (bmu + ddl) + abs(e1 * e1 - 1) * bs
+                                  + abs(e2) * math.exp(-s2) * (bmu2 + ddl) + abs(e2 * e2 - 1) * bs2)
+                    else:
+                        tol_lq = (2 * abs(e1) * math.exp(-sl) / (1 + e1 * e1) * (bmu + ddl)
+                                  + abs(1 - 2 * e1 * e1 / (1 + e1 * e1)) * bs
+                                  + 2 * abs(e2) * math.exp(-s2) / (1 + e2 * e2) * (bmu2 + ddl)
+                                  + abs(1 - 2 * e2 * e2 / (1 + e2 * e2)) * bs2)
                     r = det["log_ratio"]
                     tol_r = 2 * tol_lq + tol / T + 2.0 ** -16 * (1 + abs(r))
                     u2 = det["u2"]

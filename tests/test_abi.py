@@ -206,3 +206,69 @@ def test_exchange_variant_flags(S):
         S.workspace_bytes(S.GRIEWANK, np.full(8, -600.0), np.full(8, 600.0), None,
                           S.Schedule(**{**base.__dict__, "best_seen": True}))
     assert e.value.status == -5
+
+
+def test_network_kind_constants_and_null_handles(S):
+    """SA_NET_* in the header equal the binding's constants; the kind setters
+    reject null handles before touching a device."""
+    text = open(HEADER).read()
+    consts = dict(re.findall(r"#define (SA_NET_\w+) (\d+)", text))
+    assert consts == {"SA_NET_RELU_CAUCHY": str(S.NET_RELU_CAUCHY), "SA_NET_GELU_GAUSS": str(S.NET_GELU_GAUSS)}
+    L = S.load_library()
+    S._mlp_lib()
+    assert L.sa_set_network_kind(None, S.NET_GELU_GAUSS) == -1
+    assert L.sa_mlp_set_kind(None, S.NET_GELU_GAUSS) == -1
+
+
+def test_fault_injection_hook(S, monkeypatch):
+    """SA_FAULT=alloc|launch: a call that would allocate device memory fails
+    with SA_ERR_NOMEM, one that would launch kernels with SA_ERR_DEVICE, once
+    its arguments are validated and before it touches the device (so these
+    run without a GPU); invalid arguments are still reported first; other
+    values inject nothing."""
+    L = S.load_library()
+    S._mlp_lib()
+    S._batch_lib()
+    by = ctypes.byref
+    lo, hi = np.full(8, -500.0), np.full(8, 500.0)
+    p, keep = S._problem_struct(S.SCHWEFEL, lo, hi, None)
+    cfg = S.Schedule(chains=256, levels=4, steps=8, T0=1.0, alpha=0.9).to_c()
+    bad = S.Schedule(chains=100, levels=4, steps=8, T0=1.0, alpha=0.9).to_c()
+    arr, keep2 = S._problem_array([(S.SCHWEFEL, lo, hi, None)] * 3)
+    chains = np.full(3, 64, dtype=np.uint32)
+    bcfg = S.BatchSchedule(levels=2, steps=4, T0=1.0, alpha=0.9).to_c()
+    ncfg = S.NMConfig(100, 0, 1e-12, 1e-10)
+    x0 = np.zeros((1, 8))
+    x, f = np.zeros(8), np.zeros(1)
+    it, ev = np.zeros(1, dtype=np.uint32), np.zeros(1, dtype=np.uint32)
+    h = ctypes.c_void_p()
+
+    def nm(ws=None, ws_bytes=0):
+        return L.sa_nm_polish(by(p), x0.ctypes.data, 1, by(ncfg), None, ws, ws_bytes, x.ctypes.data, f.ctypes.data,
+                              it.ctypes.data, ev.ctypes.data, None)
+
+    monkeypatch.setenv("SA_FAULT", "alloc")
+    assert L.sa_create(by(p), by(bad), None, None, 0, by(h)) == -1
+    assert L.sa_create(by(p), by(cfg), None, None, 0, by(h)) == -2 and h.value is None
+    assert "SA_FAULT=alloc" in L.sa_last_error().decode()
+    assert L.sa_batch_create(arr, 3, chains.ctypes.data, by(bcfg), None, None, 0, by(h)) == -2
+    assert L.sa_mlp_create(64, None, by(h)) == -2 and h.value is None
+    assert nm() == -2
+    monkeypatch.setenv("SA_FAULT", "launch")
+    need = ctypes.c_size_t()
+    assert L.sa_nm_workspace_bytes(by(p), 1, by(ncfg), by(need)) == 0
+    host = np.zeros(need.value + 256, dtype=np.uint8)  # never touched: the fault comes first
+    base = host.ctypes.data
+    aligned = base + (-base) % 256
+    assert nm(aligned, need.value) == -3
+    assert "SA_FAULT=launch" in L.sa_last_error().decode()
+    lvl = ctypes.c_uint32()
+    fr = ctypes.c_double()
+    assert L.sa_run_static(by(p), by(cfg), None, x.ctypes.data, by(fr), by(lvl)) == -3
+    assert "SA_FAULT=launch" in L.sa_last_error().decode()
+    monkeypatch.setenv("SA_FAULT", "something-else")
+    st = L.sa_create(by(p), by(cfg), None, None, 0, by(h))
+    assert st in (0, -3) and "SA_FAULT" not in L.sa_last_error().decode()  # -3: no device here
+    if st == 0:
+        L.sa_destroy(h)
+    del keep, keep2

@@ -1,7 +1,8 @@
 """Error of the gfx950 FP32 transcendental instructions the kernels use
-(v_sin_f32 and v_cos_f32 on revolutions, v_sqrt_f32, v_exp_f32), and of the
-FP32 e^x - 1 of the Ackley increment built on them, measured against FP64
-evaluations of the same FP32 inputs.
+(v_sin_f32 and v_cos_f32 on revolutions, v_sqrt_f32, v_exp_f32, v_log_f32),
+of the FP32 e^x - 1 of the Ackley increment and of the FP32 GELU of the
+Gaussian proposal network built on them, measured against FP64 evaluations
+of the same FP32 inputs.
 
 The per-move tolerances of the FP32 parity tests take the sine/cosine error
 as an absolute bound (parity_util.E_TRIG, for arguments up to 64
@@ -18,7 +19,9 @@ import sys
 
 import numpy as np
 import pytest
+from scipy import special
 
+import oracle as O
 import parity_util as P
 
 pytestmark = pytest.mark.gpu
@@ -113,3 +116,47 @@ def test_expm1_relative_error(probe):
     say(f"[trig] expm1_f32: max relative error {es:.3e} (|x| <= 1/2, {es / 2 ** -24:.2f} x 2^-24), "
         f"{el:.3e} beyond ({el / 2 ** -24:.2f} x 2^-24); E_EXPM1 = {P.E_EXPM1:.3e}")
     assert es <= P.E_EXPM1 and el <= P.E_EXPM1
+
+
+def test_log2_relative_error(probe):
+    """v_log_f32 over (0, 1]: the Box-Muller radius of the Gaussian proposal
+    takes log2(1 - U) for U on the 2^-24 grid, every one of which is tried
+    (the results near 1 are tiny, so the error is taken relative)."""
+    k = np.arange(1, 1 << 24, dtype=np.float64)
+    x = (1.0 - k * 2.0 ** -24).astype(np.float32)
+    rng = np.random.default_rng(8)
+    x = np.concatenate([x, rng.uniform(1e-7, 1.0, 1 << 20).astype(np.float32)])
+    ref = np.log2(x.astype(np.float64))
+    err = np.max(np.abs(probe(7, x) - ref) / np.abs(ref))
+    say(f"[trig] log2: max relative error {err:.3e} ({err / 2 ** -24:.2f} x 2^-24) over 1 - U and (0, 1); "
+        f"E_LOG2 = {P.E_LOG2:.3e}")
+    assert err <= P.E_LOG2
+
+
+def test_gelu_within_the_oracle_device_bound(probe):
+    """The device GELU (FP32, Abramowitz-Stegun 26.2.17 for the normal
+    distribution function) against the exact x Phi(x) in FP64: within the
+    deviation the oracle's device-precision network bound allows
+    (|gelu(a)| 2^-20 + |a| 2^-22), over the pre-activations a network sees;
+    its derivative within 2^-20 + 2^-22 |a| absolute."""
+    rng = np.random.default_rng(9)
+    a = np.concatenate([np.linspace(-12, 12, 1 << 20), rng.normal(0, 2, 1 << 20),
+                        np.sign(rng.uniform(-1, 1, 1 << 16)) * np.exp(rng.uniform(-30, 2, 1 << 16))]).astype(np.float32)
+    a64 = a.astype(np.float64)
+    cdf = 0.5 * (1.0 + special.erf(a64 / math.sqrt(2.0)))
+    ref = a64 * cdf
+    dref = cdf + a64 * np.exp(-0.5 * a64 * a64) / math.sqrt(2.0 * math.pi)
+    # the same allowance as the oracle's device-precision model, checked there
+    O.set_net_kind(O.NET_GELU_GAUSS)
+    try:
+        assert all(abs(O.act(v) - r) <= 1e-15 * (1 + abs(r)) for v, r in zip(a64[::4099], ref[::4099]))
+    finally:
+        O.set_net_kind(O.NET_RELU_CAUCHY)
+    err = np.abs(probe(5, a) - ref)
+    allow = np.abs(ref) * 2.0 ** -20 + np.abs(a64) * 2.0 ** -22
+    derr = np.abs(probe(6, a) - dref)
+    dallow = 2.0 ** -20 + np.abs(a64) * 2.0 ** -22
+    say(f"[trig] gelu: max err/allowance {np.max(err / allow):.3f}, max abs err {err.max():.3e}; "
+        f"derivative max err/allowance {np.max(derr / dallow):.3f}")
+    assert np.all(err <= allow)
+    assert np.all(derr <= dallow)
