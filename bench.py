@@ -66,13 +66,13 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "847196abcce54231", "fetch_kib": 168.955, "fetch_scale": 2.0,
+TRAFFIC_MEASURED = {"sources_sha256_16": "cc2842ddd2fdffc6", "fetch_kib": 168.954, "fetch_scale": 2.0,
                     "write_kib": 120.592, "write_scale": 1.0}
 # Instruction counters of one level launch (rocprofv3 --pmc SQ_INSTS_VALU
 # SQ_INSTS_VALU_TRANS_F32, wave-instructions per dispatch, same sources):
 # with the live launch time they give the lane-operation issue rate, set
 # against the probe's full-grid FP32 FMA rate and v_sin_f32 rate.
-COUNTERS_MEASURED = {"sources_sha256_16": "847196abcce54231", "insts_valu": 6.375e6, "insts_trans": 5.12e5,
+COUNTERS_MEASURED = {"sources_sha256_16": "cc2842ddd2fdffc6", "insts_valu": 6.375e6, "insts_trans": 5.12e5,
                      "fma_rate": 5.625e13, "trans_rate": 1.824e13}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_level_kernel.hpp",
                   "paper_2408_00018_amd/csrc/sa_device.hpp", "paper_2408_00018_amd/csrc/sa_internal.hpp",
@@ -123,11 +123,14 @@ def parse():
     p.add_argument("--learned-levels", type=int, default=0,
                    help="only run this many learned-mixture levels of the bench workload (untrained network; "
                         "for counter passes)")
+    p.add_argument("--gauss", action="store_true",
+                   help="with --learned-levels: the GELU/Gaussian network kind instead of relu/Cauchy")
     p.add_argument("--ttt-seeds", type=int, default=10, help="seeds per arm of the time-to-target comparison")
     p.add_argument("--exchange-sweep", action="store_true",
                    help="bench workload with the winner broadcast every level, every 10 levels and never")
-    p.add_argument("--paper-tables", action="store_true",
-                   help="the paper's V2/V1 setting: Schwefel n=8..512, 16384 chains, T0=1000, rho=0.99, 1146 levels")
+    p.add_argument("--no-paper-tables", action="store_true",
+                   help="skip the paper's V2/V1 setting (Schwefel n=8..512, 16384 chains, T0=1000, rho=0.99, "
+                        "1146 levels) and the V0 sample")
     p.add_argument("--wave-sweep", action="store_true",
                    help="cost of a wave's move at 1, 2 and 3 waves per SIMD (Schwefel n=40)")
     p.add_argument("--level-sweep", action="store_true",
@@ -166,6 +169,7 @@ def cpu_baseline(wl, levels):
                       T0=wl.T0, alpha=wl.alpha, levels=nlev, radius_frac=wl.radius_frac, keep_x_best=False)
         return time.perf_counter() - t0
 
+    v0 = v0_sample(oracle)
     dt1 = timed(1, levels)
     all_levels = 4 * levels
     dtn = timed(threads, all_levels)
@@ -177,7 +181,35 @@ def cpu_baseline(wl, levels):
     return {"value": per_level * all_levels / dtn, "unit": "moves/s", "cores": threads, "kind": "oracle",
             "sample": f"first {all_levels} of {wl.levels} levels, all {wl.chains} chains x {wl.steps} steps, FP64, "
                       f"{threads} threads over the chains of each level, {dtn:.1f} s",
-            "single_thread": single, "usable_cpus": usable, "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+            "single_thread": single, "usable_cpus": usable, "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "v0": v0}
+
+
+PAPER_LEVELS = math.ceil(math.log(0.01 / 1000.0) / math.log(0.99))  # T_k > T_min = 0.01 for k < 1146
+PAPER_CHAINS, PAPER_STEPS = 16384, 100
+PAPER_NS = (8, 16, 32, 64, 128, 256, 512)
+
+
+def v0_sample(oracle):
+    """The paper's sequential version V0 (Sec. 4.1) at its comparison setting:
+    one chain performing the same number of moves as the parallel versions
+    (16384 chains x 1146 levels x 100 steps = 1.8776e9), here the FP64 oracle
+    on one thread.  Timed on a sample -- one level of 16384 x 100 moves of the
+    single chain at T0 = 1000 (whole-interval resampling moves, normalized
+    Schwefel on +-500) for each n -- and scaled to the full move count."""
+    total = PAPER_CHAINS * PAPER_LEVELS * PAPER_STEPS
+    oracle.set_threads(1)
+    rows = []
+    for n in PAPER_NS:
+        lo, hi = np.full(n, -500.0), np.full(n, 500.0)
+        t0 = time.perf_counter()
+        oracle.sa_run(W.SCHWEFEL, lo, hi, None, seed=1, chains=1, steps=PAPER_CHAINS * PAPER_STEPS, T0=1000.0,
+                      alpha=0.99, levels=1, move_rule=oracle.MOVE_RESAMPLE, keep_x_best=False)
+        dt = time.perf_counter() - t0
+        rate = PAPER_CHAINS * PAPER_STEPS / dt
+        rows.append({"n": n, "moves_per_s": float(f"{rate:.4g}"), "seconds_for_all_moves": round(total / rate, 2)})
+    return {"moves": total, "sample": f"one level of {PAPER_CHAINS * PAPER_STEPS} moves per n, FP64, one thread",
+            "rows": rows}
 
 
 def probe_rates():
@@ -207,6 +239,9 @@ def probe_rates():
     return {"rates_many_waves": rates, "by_waves_per_simd": occ}
 
 
+WRITTEN_CAP = 1000  # levels the written-configuration arms may run past their first learned level
+
+
 def time_to_target_report(wl, seeds):
     """Learned vs plain proposal: time until the record is within 1e-4 of f*.
 
@@ -223,6 +258,15 @@ def time_to_target_report(wl, seeds):
     whose thermal gap n T / 2 is at most the target, the learned mixture from
     there on.  Each arm runs `seeds` seeds; the summary gives hit fractions,
     median times and the learned / plain ratios of median times.
+
+    The learned-proposal configuration as written (GELU/Gaussian network,
+    ln T and raw history features, trained on every accepted move of n = 4
+    Schwefel runs in FP64 -- 256 chains, T0 10, alpha 0.99, 200 levels x 50
+    steps -- seed after seed until 10^7 records; 6000 Adam steps, minibatch
+    4096) runs as two more arms, 'written' in the final-approach regime and
+    'written_late' (from the same switch level as 'learned_late') in the full
+    one, each capped at WRITTEN_CAP levels past its first learned level (its
+    step costs ~3x the relu network's).
     """
     import torch
     from paper_2408_00018_amd import learned as Lp
@@ -241,6 +285,20 @@ def time_to_target_report(wl, seeds):
     out["train"] = {"steps": 6000, "batch": 4096, "loss_first": float(trace[:20].mean()),
                     "loss_last": float(trace[-50:].mean()), "seconds": round(t2 - t1, 3)}
     del rec
+    t3 = time.perf_counter()
+    cfg1 = W.schwefel_n4_fp64()
+    col1 = sa.Schedule(chains=cfg1.chains, levels=cfg1.levels, steps=cfg1.steps, T0=cfg1.T0, alpha=cfg1.alpha,
+                       seed=cfg1.seed, precision=sa.FP64)
+    rec1, runs1 = Lp.collect_runs(cfg1.func, cfg1.lower, cfg1.upper, cfg1.shift, col1, records=10_000_000,
+                                  kind=sa.NET_GELU_GAUSS)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    params_w, trace_w = Lp.train(rec1, steps=6000, batch=4096, lr=1e-3, seed=0, kind=sa.NET_GELU_GAUSS)
+    t5 = time.perf_counter()
+    out["written"] = {"records": int(rec1.shape[0]), "runs": runs1, "collect_seconds": round(t4 - t3, 3),
+                      "loss_first": float(trace_w[:20].mean()), "loss_last": float(trace_w[-50:].mean()),
+                      "train_seconds": round(t5 - t4, 3), "cap_levels": WRITTEN_CAP}
+    del rec1
     rng = np.random.default_rng(7)
     x0 = W.SCHWEFEL_X_STAR + rng.uniform(-2, 2, wl.n)
     # 'learned_late': plain moves until the thermal gap n T / 2 has fallen to the
@@ -249,18 +307,23 @@ def time_to_target_report(wl, seeds):
     out["learned_late_from_level"] = k_late
     for regime, start in (("full", 0), ("final_approach", 3000)):
         res = {}
-        arms = [("plain", None, 0, sa.MOVE_RADIUS), ("plain_resample", None, 0, sa.MOVE_RESAMPLE),
-                ("learned", params, 0, sa.MOVE_RADIUS)]
+        relu, gauss = sa.NET_RELU_CAUCHY, sa.NET_GELU_GAUSS
+        arms = [("plain", None, 0, sa.MOVE_RADIUS, relu, levels),
+                ("plain_resample", None, 0, sa.MOVE_RESAMPLE, relu, levels),
+                ("learned", params, 0, sa.MOVE_RADIUS, relu, levels)]
         if start == 0:
-            arms.append(("learned_late", params, k_late, sa.MOVE_RADIUS))
-        for arm, p, learn_from, move in arms:
+            arms.append(("learned_late", params, k_late, sa.MOVE_RADIUS, relu, levels))
+            arms.append(("written_late", params_w, k_late, sa.MOVE_RADIUS, gauss, k_late + WRITTEN_CAP))
+        else:
+            arms.append(("written", params_w, 0, sa.MOVE_RADIUS, gauss, start + WRITTEN_CAP))
+        for arm, p, learn_from, move, kind, cap in arms:
             runs = []
             for seed in range(1, seeds + 1):
-                sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
+                sched = sa.Schedule(chains=wl.chains, levels=cap, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
                                     seed=seed, precision=sa.FP32, move=move)
                 r = Lp.time_to_target(wl.func, wl.lower, wl.upper, wl.shift, sched, W.SCHWEFEL_F_STAR, 1e-4,
                                       params=p, eps=0.1, start_level=start, x_start=x0 if start else None,
-                                      learn_from=learn_from)
+                                      learn_from=learn_from, kind=kind)
                 runs.append({"seed": seed, "hit": r.hit, "level": r.level, "seconds": r.seconds,
                              "levels_run": r.levels_run, "ms_per_level": round(r.ms_per_level, 4),
                              "final_gap": r.final_gap})
@@ -275,7 +338,7 @@ def time_to_target_report(wl, seeds):
         # learned / plain speedups: median seconds to the target of each plain
         # arm that hits it, over that of each learned arm
         for pa in ("plain", "plain_resample"):
-            for la in ("learned", "learned_late"):
+            for la in ("learned", "learned_late", "written", "written_late"):
                 if la in summary and summary[pa]["median_seconds"] and summary[la]["median_seconds"]:
                     summary[f"speedup_{la}_vs_{pa}"] = summary[pa]["median_seconds"] / summary[la]["median_seconds"]
         if "learned_late" in summary and summary["learned"]["median_seconds"] and \
@@ -340,16 +403,18 @@ def extra_workloads():
     return out
 
 
-def learned_levels(wl, levels):
+def learned_levels(wl, levels, kind=0):
     """`levels` learned-mixture levels (eps = 0.1, untrained network from
-    learned.init_params) of the bench workload, graph-replayed: device ms per
-    level (used to take counters of the learned level kernel)."""
+    learned.init_params, network kind `kind`) of the bench workload,
+    graph-replayed: device ms per level (used to take counters of the learned
+    level kernel)."""
     import torch
     from paper_2408_00018_amd import learned as Lp
     from paper_2408_00018_amd import sa
     sched = sa.Schedule(chains=wl.chains, levels=levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
                         precision=sa.FP32, graph=True, learned=True)
     with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
+        ann.set_network_kind(kind)
         ann.set_proposal(Lp.init_params(0), 0.1)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(ann.stream)
@@ -357,7 +422,7 @@ def learned_levels(wl, levels):
         e1.record(ann.stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
-    return {"levels": levels, "ms_per_level": round(ms / levels, 4),
+    return {"levels": levels, "kind": "gelu_gauss" if kind else "relu_cauchy", "ms_per_level": round(ms / levels, 4),
             "moves_per_s": float(f"{wl.chains * wl.steps * levels / (ms * 1e-3):.4g}")}
 
 
@@ -440,9 +505,9 @@ def paper_tables(seed=1):
     record."""
     import torch
     from paper_2408_00018_amd import sa
-    levels = math.ceil(math.log(0.01 / 1000.0) / math.log(0.99))  # T_k > T_min for k < levels
-    out = {"levels": levels, "steps": 100, "chains": 16384, "T0": 1000.0, "alpha": 0.99, "rows": []}
-    for n in (8, 16, 32, 64, 128, 256, 512):
+    levels = PAPER_LEVELS
+    out = {"levels": levels, "steps": PAPER_STEPS, "chains": PAPER_CHAINS, "T0": 1000.0, "alpha": 0.99, "rows": []}
+    for n in PAPER_NS:
         lo, hi = np.full(n, -500.0), np.full(n, 500.0)
         x_star = np.full(n, W.SCHWEFEL_X_STAR)
         for name, k, move in (("V2", 1, sa.MOVE_RADIUS), ("V1", 0, sa.MOVE_RADIUS), ("V2", 1, sa.MOVE_RESAMPLE),
@@ -518,7 +583,8 @@ def main():
         print(json.dumps({"other_workloads": extra_workloads()}), flush=True)
         return
     if args.learned_levels:
-        print(json.dumps({"learned_levels": learned_levels(wl, args.learned_levels)}), flush=True)
+        print(json.dumps({"learned_levels": learned_levels(wl, args.learned_levels, 1 if args.gauss else 0)}),
+              flush=True)
         return
     sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=wl.seed,
                         precision=sa.FP32, graph=True)
@@ -581,10 +647,15 @@ def main():
         out["wave_sweep"] = wave_sweep()
     if args.exchange_sweep:
         out["exchange_sweep"] = exchange_sweep(wl)
-    if args.paper_tables:
+    if not args.no_paper_tables:
         out["paper_tables"] = paper_tables()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_levels)
+        if "paper_tables" in out:
+            # speedups over V0 as the paper's Table 2 gives them (its V0: one CPU core)
+            v0 = {r["n"]: r["seconds_for_all_moves"] for r in out["cpu_baseline"]["v0"]["rows"]}
+            for r in out["paper_tables"]["rows"]:
+                r["speedup_vs_v0"] = round(v0[r["n"]] / r["seconds"], 1)
     if not args.no_extra:
         try:
             out["other_workloads"] = extra_workloads()

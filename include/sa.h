@@ -225,11 +225,16 @@ typedef struct {
 
 typedef struct sa_ctx sa_ctx;
 
-/* Bytes of device workspace sa_create needs for this problem and config. */
+/* Bytes of device workspace sa_create needs for this problem and config:
+ * the states of the parallel chains of Sec. 2.2, their per-level
+ * candidates and records (Sec. 2.2.2), and the level tables. */
 sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_t *bytes);
 
 /*
- * Create a context for one problem on the current HIP device.
+ * Create a context for one problem on the current HIP device: the
+ * box-constrained minimisation of Sec. 1 with the schedule parameters of the
+ * algorithm of Sec. 2.1 (T0, rho, N steps per level) and the chain count of
+ * the parallel versions (Sec. 2.2).
  *   stream:    hipStream_t to enqueue on (NULL = the null stream); not owned.
  *   workspace: device memory of at least sa_workspace_bytes bytes, 256-byte
  *              aligned, owned by the caller and kept alive until sa_destroy;
@@ -239,32 +244,41 @@ sa_status sa_workspace_bytes(const sa_problem *prob, const sa_config *cfg, size_
 sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, void *workspace,
                     size_t ws_bytes, sa_ctx **out);
 
-/* Enqueue the next `levels` levels (0 = all remaining).  SA_ERR_STATE if the
- * run already finished or `levels` passes cfg->levels. */
+/* Enqueue the next `levels` levels (0 = all remaining): at each, every
+ * chain runs N steps of Sec. 2.1 (Steps 2-4) at T_k = T0 rho^k, then the
+ * level's best state is exchanged per cfg->exchange (Sec. 2.2.2; 1 = the
+ * synchronous scheme, never = the asynchronous one of Sec. 2.2.1).
+ * SA_ERR_STATE if the run already finished or `levels` passes cfg->levels. */
 sa_status sa_run(sa_ctx *ctx, uint32_t levels);
 
-/* Restart at level 0 with an empty record and a new seed (enqueued). */
+/* Restart at level 0 (Sec. 2.1 Step 1: new random starts) with an empty
+ * record and a new seed (enqueued). */
 sa_status sa_reset(sa_ctx *ctx, uint64_t seed);
 
 /* Levels enqueued so far. */
 sa_status sa_levels_done(const sa_ctx *ctx, uint32_t *levels);
 
-/* Record after the enqueued levels (synchronises).  x_out: n doubles;
+/* Record after the enqueued levels: the best point found, the method's
+ * result (Sec. 2.1, Sec. 2.2.2) (synchronises).  x_out: n doubles;
  * f_out: f(x_rec) in FP64 arithmetic; level_found: level that set it.
  * SA_ERR_STATE before the first level has run.  Any output may be NULL. */
 sa_status sa_best(sa_ctx *ctx, double *x_out, double *f_out, uint32_t *level_found);
 
-/* Per-level records of levels [first, first + count) (synchronises).
- * x_best: count * n doubles or NULL; needs SA_FLAG_TRACE_X. */
+/* Per-level records of levels [first, first + count): each level's
+ * exchanged state and the record so far, the data of the convergence curves
+ * of Sec. 4.1 (synchronises).  x_best: count * n doubles or NULL; needs
+ * SA_FLAG_TRACE_X. */
 sa_status sa_trace(sa_ctx *ctx, uint32_t first, uint32_t count, sa_level *out, double *x_best);
 
-/* Logged moves (synchronises).  moves: log_levels * log_chains * steps
+/* Logged moves, every step of Sec. 2.1 Steps 2-3 of the logged chains (for
+ * verification; synchronises).  moves: log_levels * log_chains * steps
  * records, index ((level - log_level) * log_chains + chain) * steps + step;
  * final_f: log_levels * chains doubles, index (level - log_level) * chains +
  * chain.  Either may be NULL. */
 sa_status sa_move_log(sa_ctx *ctx, sa_move_rec *moves, double *final_f);
 
 /* Start the run at `level` (1 <= level < cfg->levels) with every chain at x
+ * -- the state the exchange of Sec. 2.2.2 broadcasts at a level's start --
  * (n doubles inside the box; FP32 runs round them to FP32, kept inside the
  * inward-rounded box), instead of the random starts of level 0: the levels
  * before `level` are skipped and the record starts empty.  With an exchange
@@ -335,12 +349,14 @@ sa_status sa_capture(sa_ctx *ctx, float *records, uint64_t capacity);
  * records stored are min(count, capacity). */
 sa_status sa_capture_count(sa_ctx *ctx, uint64_t *count);
 
-/* Layout the context launches with: lanes per workgroup, overlay table slots
+/* Layout the context launches with (the blocks and threads of Sec. 3.3 on
+ * this device): lanes per workgroup, overlay table slots
  * per chain (0 = dense per-chain state), and chain tiles (chains / workgroup).
  * Any output may be NULL. */
 sa_status sa_layout(const sa_ctx *ctx, uint32_t *workgroup, uint32_t *overlay_slots, uint32_t *tiles);
 
-/* Release the context and any memory the library allocated. */
+/* Release the context and any memory the library allocated (no passage of
+ * the paper: resource ownership). */
 void sa_destroy(sa_ctx *ctx);
 
 /*
@@ -396,16 +412,19 @@ typedef struct sa_batch sa_batch;
 sa_status sa_batch_workspace_bytes(const sa_problem *probs, uint32_t nprob, const uint32_t *chains,
                                    const sa_batch_config *cfg, size_t *bytes);
 
-/* Create a batch (same stream/workspace conventions as sa_create).  probs:
- * nprob host problems; chains: nprob chain counts (see sa_batch_autotune). */
+/* Create a batch of independent problems of Sec. 1, each annealed by the
+ * synchronous scheme of Sec. 2.2.2 (same stream/workspace conventions as
+ * sa_create).  probs: nprob host problems; chains: nprob chain counts (see
+ * sa_batch_autotune). */
 sa_status sa_batch_create(const sa_problem *probs, uint32_t nprob, const uint32_t *chains,
                           const sa_batch_config *cfg, void *stream, void *workspace, size_t ws_bytes,
                           sa_batch **out);
 
-/* Enqueue the next `levels` levels of every problem (0 = all remaining). */
+/* Enqueue the next `levels` levels of every problem (0 = all remaining), as
+ * sa_run for each. */
 sa_status sa_batch_run(sa_batch *b, uint32_t levels);
 
-/* Restart every problem at level 0 with a new seed (enqueued). */
+/* Restart every problem at level 0 with a new seed (enqueued), as sa_reset. */
 sa_status sa_batch_reset(sa_batch *b, uint64_t seed);
 
 /* Record of problem p (synchronises), as sa_best. */
@@ -425,15 +444,33 @@ sa_status sa_batch_move_log(sa_batch *b, sa_move_rec *moves, double *final_f);
 sa_status sa_batch_layout(const sa_batch *b, uint32_t *tiles, uint32_t *groups, uint32_t *waves_per_group,
                           uint32_t *lds_bytes);
 
+/* Clock of the batched levels (measurement of how long each problem's
+ * tiles wait for the level's slowest problem; no passage of the paper: the
+ * batch has no counterpart there).  For levels [first_level, first_level +
+ * levels) of later runs, every 64-chain tile records the device wall clock
+ * when its wave starts the level and when it has published its candidate:
+ * ticks (device memory, 8-byte aligned, levels x tiles x 2 uint64, index
+ * ((level - first_level) * tiles + tile) * 2 + {0 = start, 1 = end}; tiles
+ * as sa_batch_layout reports, tile t of problem p being the t - (first tile
+ * of p)-th 64-chain group of p, tiles numbered problem by problem).
+ * *ticks_per_s (may be NULL) returns the clock's rate.  ticks = NULL stops
+ * recording.  Drops captured graphs (their launches hold the arguments).
+ * SA_ERR_INVALID for levels outside the schedule. */
+sa_status sa_batch_clock(sa_batch *b, uint64_t *ticks, uint32_t first_level, uint32_t levels, uint64_t *ticks_per_s);
+
 void sa_batch_destroy(sa_batch *b);
 
 /*
  * Autotuner: pick chains per problem and tiles per workgroup by measurement
- * on the current device.  Candidates: uniform chain counts 64..1024 and
+ * on the current device (the chain-count question the paper studies by
+ * sweeping the number of launched threads, Sec. 4.1, answered per problem).  Candidates: uniform chain counts 64..1024 and
  * counts proportional to each problem's dimension (64..1024, multiples of
  * 64), each with 1, 2 and 4 tiles per workgroup.  Each candidate runs
- * `trial_levels` levels of cfg's schedule twice (the second timed with HIP
- * events).  The choice is the candidate with the fewest total chains whose
+ * `trial_levels` levels of cfg's schedule twice with graph-replayed levels
+ * (SA_FLAG_GRAPH; the first pass captures the graphs); the second pass is
+ * timed with HIP events from level 1 on (level 0's random starts cost a full
+ * evaluation per chain, which later levels do not pay; with trial_levels = 1
+ * level 0 is timed).  The choice is the candidate with the fewest total chains whose
  * moves/s is within 5% of the best measured.  Writes nprob chain counts to
  * chains_out, the tiles per workgroup to *waves_per_group_out and the chosen
  * candidate's moves/s to *moves_per_s_out (any may be NULL except
@@ -443,7 +480,6 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
                             uint32_t trial_levels, uint32_t *chains_out, uint32_t *waves_per_group_out,
                             double *moves_per_s_out);
 
-/* Description of the calling thread's last error ("" if none). */
 /* ------------------------------------------------------------------------
  * Nelder-Mead polish (the paper's hybrid strategy: a local minimizer started
  * where the annealing stopped, Sec. 4.2, hybrid results table).  The paper
@@ -495,6 +531,7 @@ sa_status sa_nm_polish(const sa_problem *prob, const double *x0, uint32_t starts
 sa_status sa_candidates(sa_ctx *ctx, uint32_t k, double *x_out, double *f_out, uint32_t *chains_out,
                         uint32_t *available);
 
+/* Description of the calling thread's last error ("" if none). */
 const char *sa_last_error(void);
 
 /* ------------------------------------------------------------------------
