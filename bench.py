@@ -123,6 +123,8 @@ def parse():
     p.add_argument("--learned-levels", type=int, default=0,
                    help="only run this many learned-mixture levels of the bench workload (untrained network; "
                         "for counter passes)")
+    p.add_argument("--train-steps", type=int, default=0,
+                   help="only collect the time-to-target records and run this many training steps (for profiles)")
     p.add_argument("--gauss", action="store_true",
                    help="with --learned-levels: the GELU/Gaussian network kind instead of relu/Cauchy")
     p.add_argument("--ttt-seeds", type=int, default=10, help="seeds per arm of the time-to-target comparison")
@@ -394,13 +396,78 @@ def extra_workloads():
         e1.record(b._stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
+        idle = batch_idle(b, chains, first=100, levels=50)
     moves = float(np.sum(chains.astype(np.float64))) * bs.steps * bs.levels
     out["batched_1024"] = {"moves_per_s": float(f"{moves / (ms * 1e-3):.4g}"), "ms_per_run": round(ms, 3),
                            "problems": len(probs), "total_chains": int(np.sum(chains)),
                            "chains_per_problem": sorted({int(c) for c in chains}), "waves_per_group": wpg,
-                           "autotune_s": round(tune_s, 2)}
+                           "autotune_s": round(tune_s, 2), "idle": idle}
     print(f"[extra] batched: {out['batched_1024']}", file=sys.stderr, flush=True)
     return out
+
+
+def train_only(wl, steps, kind=0):
+    """The time-to-target comparison's collection (relu kind) and `steps`
+    Adam steps at minibatch 4096 on it, timed (for the training kernels'
+    profiles)."""
+    import torch
+    from paper_2408_00018_amd import learned as Lp
+    from paper_2408_00018_amd import sa
+    col = sa.Schedule(chains=4096, levels=4000, steps=wl.steps, T0=wl.T0, alpha=wl.alpha, seed=1001,
+                      precision=sa.FP32)
+    rec = Lp.collect(wl.func, wl.lower, wl.upper, wl.shift, col, every=8, per_level=20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, trace = Lp.train(rec, steps=steps, batch=4096, lr=1e-3, seed=0, kind=kind)
+    dt = time.perf_counter() - t0
+    return {"records": int(rec.shape[0]), "steps": steps, "seconds": round(dt, 4),
+            "us_per_step": round(1e6 * dt / steps, 2), "loss_first": float(trace[:20].mean()),
+            "loss_last": float(trace[-20:].mean())}
+
+
+def batch_idle(b, chains, first, levels):
+    """Where a batched level's time goes, from the device wall clock of every
+    64-chain tile (sa_batch_clock) over levels [first, first + levels) of one
+    more run.  Per level: `idle_fraction` = 1 - (sum of the tiles' busy times)
+    / (peak number of tiles running at once x level span): the share of the
+    level's wave slots left empty while the level waits for its last tiles
+    (what a launch that let problems run ahead could fill); `problem_wait` =
+    1 - mean over problems of (end of its last tile - level start) / level
+    span: the share of the level a problem's results wait for the slowest
+    problem; `peak_tiles` and `tile_us` = concurrency and mean busy time of a
+    tile; `gap_us` = mean time from the last tile end of a level to the first
+    tile start of the next (launch and hand-off).  Means over the levels."""
+    import torch
+    tiles = b.layout()["tiles"]
+    ticks = torch.zeros((levels, tiles, 2), dtype=torch.int64, device="cuda")
+    rate = b.clock(ticks, first, levels)
+    b.reset(4)
+    b.run()
+    torch.cuda.synchronize()
+    b.clock(None)
+    t = ticks.cpu().numpy().astype(np.float64) / rate
+    owner = np.repeat(np.arange(len(chains)), np.asarray(chains) // 64)
+    idle, wait, peak, tile_s, spans, gaps = [], [], [], [], [], []
+    for k in range(levels):
+        start, end = t[k, :, 0].min(), t[k, :, 1].max()
+        span = end - start
+        busy = t[k, :, 1] - t[k, :, 0]
+        ev = np.concatenate([np.stack([t[k, :, 0], np.ones(tiles)], 1), np.stack([t[k, :, 1], -np.ones(tiles)], 1)])
+        ev = ev[np.lexsort((ev[:, 1], ev[:, 0]))]  # ends before starts at equal times
+        pk = float(np.max(np.cumsum(ev[:, 1])))
+        idle.append(1.0 - busy.sum() / (pk * span))
+        p_end = np.zeros(len(chains))
+        np.maximum.at(p_end, owner, t[k, :, 1])
+        wait.append(1.0 - np.mean(p_end - start) / span)
+        peak.append(pk)
+        tile_s.append(busy.mean())
+        spans.append(span)
+        if k + 1 < levels:
+            gaps.append(t[k + 1, :, 0].min() - end)
+    return {"levels": [first, first + levels], "idle_fraction": round(float(np.mean(idle)), 4),
+            "problem_wait": round(float(np.mean(wait)), 4), "peak_tiles": int(round(np.mean(peak))),
+            "tile_us": round(1e6 * float(np.mean(tile_s)), 2), "level_span_us": round(1e6 * float(np.mean(spans)), 2),
+            "gap_us": round(1e6 * float(np.mean(gaps)), 2)}
 
 
 def learned_levels(wl, levels, kind=0):
@@ -581,6 +648,9 @@ def main():
     wl = W.schwefel_n100_fp32()
     if args.only_extra:
         print(json.dumps({"other_workloads": extra_workloads()}), flush=True)
+        return
+    if args.train_steps:
+        print(json.dumps({"train": train_only(wl, args.train_steps, 1 if args.gauss else 0)}), flush=True)
         return
     if args.learned_levels:
         print(json.dumps({"learned_levels": learned_levels(wl, args.learned_levels, 1 if args.gauss else 0)}),

@@ -208,7 +208,7 @@ typedef struct {
     double f_best;      /* full re-evaluation of the winner (FP64 arithmetic) */
     double f_rec;       /* lowest f_best so far */
     uint64_t accepts;   /* accepted moves over all chains */
-    uint64_t t_ticks;   /* device constant-clock stamp when the level finished */
+    uint64_t t_ns;      /* when the level's record was written, in ns of the device's constant clock */
 } sa_level;
 
 /* One logged move (sa_move_log).  In FP32 runs the values are the FP32

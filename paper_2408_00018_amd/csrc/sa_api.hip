@@ -229,6 +229,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
 
 struct sa_ctx {
     int device = 0;
+    int clock_khz = 0;  // rate of the device's constant clock
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;
     sa_problem prob{};
@@ -531,6 +532,7 @@ sa_status sa_create(const sa_problem *prob, const sa_config *cfg, void *stream, 
     sa_ctx *c = new (std::nothrow) sa_ctx;
     if (!c) return fail(SA_ERR_NOMEM, "host allocation failed");
     c->device = dev;
+    if (hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) c->clock_khz = 0;
     c->stream = reinterpret_cast<hipStream_t>(stream);
     c->cfg = *cfg;
     c->seed = cfg->seed;
@@ -700,9 +702,11 @@ sa_status sa_trace(sa_ctx *c, uint32_t first, uint32_t count, sa_level *out, dou
         return fail(SA_ERR_STATE, "x_best trace needs SA_FLAG_TRACE_X");
     SA_HIP(hipStreamSynchronize(c->stream));
     const Layout &l = c->pl.lay;
-    if (out)
+    if (out) {
         SA_HIP(hipMemcpy(out, c->ws + l.trace + (size_t)first * sizeof(sa_level), count * sizeof(sa_level),
                          hipMemcpyDeviceToHost));
+        sa::stamps_to_ns(out, count, c->clock_khz);
+    }
     if (x_best) {
         const size_t n = c->prob.n, m = n * count;
         if (c->fp64) {

@@ -112,7 +112,7 @@ __device__ void batch_adopt(const BatchArgs<R> &a, const BatchProblem &P, uint32
             t.f_best = ws.ff;
             t.f_rec = improved ? ws.ff : rec_prev;
             t.accepts = gacc;
-            t.t_ticks = wall_clock64();
+            t.t_ns = wall_clock64();  // ticks here; sa_batch_trace converts them to ns
             a.trace[(size_t)p * a.levels + lvl] = t;
         }
     }
@@ -190,6 +190,7 @@ __global__ void __launch_bounds__(256) batch_level_kernel(const BatchArgs<R> a, 
     const uint32_t slot = blockIdx.x * a.waves_per_group + wave;
     const uint32_t tile = __builtin_amdgcn_readfirstlane(a.wg_tile[slot]);
     if (tile == 0xFFFFFFFFu) return;
+    const uint64_t t_start = wall_clock64();
     const uint32_t p = __builtin_amdgcn_readfirstlane(a.tile_prob[tile]);
     const BatchProblem P = a.probs[p];
     // The level's constants are loaded before the hand-off (latency overlap).
@@ -207,6 +208,11 @@ __global__ void __launch_bounds__(256) batch_level_kernel(const BatchArgs<R> a, 
     case kSchwefel: batch_tile<R, kSchwefel, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
     case kRastrigin: batch_tile<R, kRastrigin, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
     default: batch_tile<R, kAckley, MOVE, LOG>(a, P, p, tile, xs, xw, tab, level, start, T, nl2T); break;
+    }
+    if (a.clock && level - a.clock_level < a.clock_levels && lane == 0) {
+        uint64_t *c = a.clock + ((size_t)(level - a.clock_level) * a.ntiles + tile) * 2u;
+        c[0] = t_start;
+        c[1] = wall_clock64();
     }
 }
 

@@ -190,6 +190,7 @@ sa_status plan_batch(const sa_problem *probs, uint32_t nprob, const uint32_t *ch
 
 struct sa_batch {
     int device = 0;
+    int clock_khz = 0;  // rate of the device's constant clock
     hipStream_t stream = nullptr;
     hipStream_t capture = nullptr;
     sa_batch_config cfg{};
@@ -200,6 +201,8 @@ struct sa_batch {
     bool fp64 = false;
     uint32_t next_level = 0;
     uint64_t seed = 0;
+    uint64_t *clock = nullptr;  // caller's tile clock log (sa_batch_clock)
+    uint32_t clock_level = 0, clock_levels = 0;
     sa::BatchArgs<float> a32{};
     sa::BatchArgs<double> a64{};
     struct Graph {
@@ -246,6 +249,9 @@ template <typename R> void fill_batch_args(sa_batch *b, sa::BatchArgs<R> &a)
     a.log_chains = b->cfg.log_chains;
     a.log_level = b->cfg.log_level;
     a.log_levels = b->cfg.log_chains ? b->cfg.log_levels : 0;
+    a.clock = b->clock;
+    a.clock_level = b->clock_level;
+    a.clock_levels = b->clock ? b->clock_levels : 0;
 }
 
 template <typename R> sa_status upload_table(sa_batch *b)
@@ -362,6 +368,7 @@ sa_status sa_batch_create(const sa_problem *probs, uint32_t nprob, const uint32_
     sa_batch *b = new (std::nothrow) sa_batch;
     if (!b) return fail(SA_ERR_NOMEM, "host allocation failed");
     b->device = dev;
+    if (hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) b->clock_khz = 0;
     b->stream = reinterpret_cast<hipStream_t>(stream);
     b->cfg = *cfg;
     b->seed = cfg->seed;
@@ -515,9 +522,11 @@ sa_status sa_batch_trace(sa_batch *b, uint32_t prob, uint32_t first, uint32_t co
     if (x_best && !(b->cfg.flags & SA_FLAG_TRACE_X))
         return fail(SA_ERR_STATE, "x_best trace needs SA_FLAG_TRACE_X");
     SA_HIP(hipStreamSynchronize(b->stream));
-    if (out)
+    if (out) {
         SA_HIP(hipMemcpy(out, b->ws + b->pl.lay.trace + ((size_t)prob * b->cfg.levels + first) * sizeof(sa_level),
                          count * sizeof(sa_level), hipMemcpyDeviceToHost));
+        sa::stamps_to_ns(out, count, b->clock_khz);
+    }
     if (x_best) {
         const sa::BatchProblem &P = b->pl.probs[prob];
         const size_t base = (size_t)b->cfg.levels * P.x_off + (size_t)first * P.n, m = (size_t)count * P.n;
@@ -563,6 +572,32 @@ sa_status sa_batch_layout(const sa_batch *b, uint32_t *tiles, uint32_t *groups, 
     return SA_OK;
 }
 
+sa_status sa_batch_clock(sa_batch *b, uint64_t *ticks, uint32_t first_level, uint32_t levels,
+                         uint64_t *ticks_per_s)
+{
+    sa::g_last_error.clear();
+    if (!b) return fail(SA_ERR_INVALID, "null batch");
+    if (ticks && (levels == 0 || first_level >= b->cfg.levels || levels > b->cfg.levels - first_level))
+        return fail(SA_ERR_INVALID, "clocked levels [%u, %u + %u) must lie inside the %u levels", first_level,
+                    first_level, levels, b->cfg.levels);
+    if (ticks && reinterpret_cast<uintptr_t>(ticks) % sizeof(uint64_t))
+        return fail(SA_ERR_INVALID, "ticks must be 8-byte aligned");
+    if (ticks_per_s) {
+        int khz = 0;
+        SA_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+        *ticks_per_s = (uint64_t)khz * 1000u;
+    }
+    drop_batch_graphs(b);  // captured launches hold the arguments
+    b->clock = ticks;
+    b->clock_level = ticks ? first_level : 0;
+    b->clock_levels = ticks ? levels : 0;
+    if (b->fp64)
+        fill_batch_args<double>(b, b->a64);
+    else
+        fill_batch_args<float>(b, b->a32);
+    return SA_OK;
+}
+
 void sa_batch_destroy(sa_batch *b)
 {
     if (!b) return;
@@ -597,10 +632,15 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
         }
         cands.push_back(std::move(v));
     }
+    // Candidates run as production runs do (graph-replayed levels); the timed
+    // window leaves out level 0, whose random starts cost a full evaluation
+    // per chain, and each candidate's graphs are captured in an untimed pass
+    // over the same chunks first.
     sa_batch_config tc = *cfg;
     tc.levels = std::min(trial_levels, cfg->levels);
-    tc.flags = 0;
+    tc.flags = SA_FLAG_GRAPH;
     tc.log_chains = 0;
+    const uint32_t head = tc.levels > 1 ? 1u : 0u;  // untimed leading levels of each pass
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     SA_HIP(hipEventCreate(&e0));
@@ -623,11 +663,13 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
                 (void)hipEventDestroy(e1);
                 return st;
             }
-            st = sa_batch_run(b, 0);
-            if (st == SA_OK) st = sa_batch_reset(b, tc.seed);
-            if (st == SA_OK && hipEventRecord(e0, s) != hipSuccess) st = fail(SA_ERR_DEVICE, "event record");
-            if (st == SA_OK) st = sa_batch_run(b, 0);
-            if (st == SA_OK && hipEventRecord(e1, s) != hipSuccess) st = fail(SA_ERR_DEVICE, "event record");
+            for (int pass = 0; pass < 2 && st == SA_OK; ++pass) {
+                if (pass) st = sa_batch_reset(b, tc.seed);
+                if (st == SA_OK && head) st = sa_batch_run(b, head);
+                if (st == SA_OK && pass && hipEventRecord(e0, s) != hipSuccess) st = fail(SA_ERR_DEVICE, "event record");
+                if (st == SA_OK) st = sa_batch_run(b, 0);
+                if (st == SA_OK && pass && hipEventRecord(e1, s) != hipSuccess) st = fail(SA_ERR_DEVICE, "event record");
+            }
             if (st == SA_OK && hipEventSynchronize(e1) != hipSuccess) st = fail(SA_ERR_DEVICE, "event sync");
             float ms = 0.0f;
             if (st == SA_OK) (void)hipEventElapsedTime(&ms, e0, e1);
@@ -639,7 +681,7 @@ sa_status sa_batch_autotune(const sa_problem *probs, uint32_t nprob, const sa_ba
             }
             uint64_t chains = 0;
             for (uint32_t c : cands[ci]) chains += c;
-            const double moves = (double)chains * tc.steps * tc.levels;
+            const double moves = (double)chains * tc.steps * (tc.levels - head);
             res.push_back(Result{ci, wpg, ms > 0.0f ? moves / (ms * 1e-3) : 0.0, chains});
         }
     }

@@ -66,6 +66,14 @@ inline sa_status injected_fault(Fault f)
         if (e_ != hipSuccess) return sa::fail(SA_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Convert the kernels' constant-clock stamps (ticks of `khz` kHz) in the
+// per-level records to nanoseconds, in place.
+inline void stamps_to_ns(sa_level *rec, uint32_t count, int khz)
+{
+    for (uint32_t k = 0; k < count; ++k)
+        rec[k].t_ns = khz > 0 ? (uint64_t)((unsigned __int128)rec[k].t_ns * 1000000u / (unsigned)khz) : 0;
+}
+
 // Families whose cost is a sum of per-coordinate terms (a move updates it
 // incrementally); the others are re-evaluated in full at every move.
 inline bool separable(uint32_t func) { return func <= SA_ACKLEY; }

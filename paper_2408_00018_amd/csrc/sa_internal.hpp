@@ -178,6 +178,8 @@ template <typename R> struct BatchArgs {
     sa_move_rec *log;           // move log of one problem, or nullptr
     double *log_final;          // per-chain final cost of that problem at logged levels
     uint32_t log_problem, log_chains, log_level, log_levels;
+    uint64_t *clock;            // per tile and clocked level: start and end wall-clock ticks, or nullptr
+    uint32_t clock_level, clock_levels;
 };
 
 // Bytes of LDS one wave of a batched launch needs for dimension n.

@@ -148,7 +148,7 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
             t.f_best = ws.ff;
             t.f_rec = improved ? ws.ff : rec_prev;
             t.accepts = gacc;
-            t.t_ticks = wall_clock64();
+            t.t_ns = wall_clock64();  // ticks here; sa_trace converts them to ns
             a.trace[lvl] = t;
         }
     }

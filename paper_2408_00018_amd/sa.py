@@ -58,7 +58,7 @@ class Config(ctypes.Structure):
 
 LEVEL_DTYPE = np.dtype([("win_chain", np.uint32), ("reserved", np.uint32), ("f_win", np.float64),
                         ("f_best", np.float64), ("f_rec", np.float64), ("accepts", np.uint64),
-                        ("t_ticks", np.uint64)])
+                        ("t_ns", np.uint64)])
 MOVE_DTYPE = np.dtype([("d", np.uint32), ("accept", np.uint32), ("x_old", np.float64), ("x_new", np.float64),
                        ("df", np.float64)])
 
@@ -390,7 +390,8 @@ class Annealer:
 # Batched runs (sa_batch_* in include/sa.h)
 # ---------------------------------------------------------------------------
 EXPORTED_BATCH = ["sa_batch_workspace_bytes", "sa_batch_create", "sa_batch_run", "sa_batch_reset", "sa_batch_best",
-                  "sa_batch_trace", "sa_batch_move_log", "sa_batch_layout", "sa_batch_destroy", "sa_batch_autotune"]
+                  "sa_batch_trace", "sa_batch_move_log", "sa_batch_layout", "sa_batch_destroy", "sa_batch_autotune",
+                  "sa_batch_clock"]
 EXPORTED = EXPORTED + EXPORTED_BATCH
 
 
@@ -451,6 +452,8 @@ def _bind_batch(L):
     L.sa_batch_destroy.restype = None
     L.sa_batch_autotune.argtypes = [P, u32, C, vp, u32, vp, vp, vp]
     L.sa_batch_autotune.restype = st
+    L.sa_batch_clock.argtypes = [vp, vp, u32, u32, vp]
+    L.sa_batch_clock.restype = st
 
 
 def _batch_lib():
@@ -562,6 +565,19 @@ class BatchAnnealer:
         v = [ctypes.c_uint32() for _ in range(4)]
         _check(_batch_lib().sa_batch_layout(self._h, *[ctypes.byref(x) for x in v]))
         return dict(tiles=v[0].value, groups=v[1].value, waves_per_group=v[2].value, lds_bytes=v[3].value)
+
+    def clock(self, ticks, first_level: int = 0, levels: int = 0) -> int:
+        """Record each tile's start and end wall-clock ticks of levels
+        [first_level, first_level + levels) of later runs into ``ticks`` (an
+        int64 CUDA tensor [levels, tiles, 2]); None stops.  Returns the clock's
+        ticks per second."""
+        rate = ctypes.c_uint64()
+        ptr = None
+        if ticks is not None:
+            assert ticks.is_cuda and ticks.element_size() == 8 and ticks.numel() >= levels * self.layout()["tiles"] * 2
+            ptr = ctypes.c_void_p(ticks.data_ptr())
+        _check(_batch_lib().sa_batch_clock(self._h, ptr, first_level, levels, ctypes.byref(rate)))
+        return rate.value
 
     def close(self):
         if getattr(self, "_h", None):

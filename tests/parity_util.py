@@ -309,7 +309,7 @@ def check_record(wl, g):
     sh = None if wl.shift is None else (f32(wl.shift) if wl.precision == 0 else np.asarray(wl.shift))
     fr = O.f(wl.func, g["x_rec"], sh)
     assert abs(g["f_rec"] - fr) <= 1e-11 * max(1.0, abs(fr))
-    assert np.all(np.diff(rec["t_ticks"].astype(np.int64)) >= 0)
+    assert np.all(np.diff(rec["t_ns"].astype(np.int64)) >= 0)
 
 
 def learned_params(seed, scale=0.1, mu0=0.0, sigma0=0.05):

@@ -155,6 +155,35 @@ def test_fp32_batch_full_size(S):
         check_record(w, g[p])
 
 
+def test_clock_log_is_consistent_and_changes_nothing(S):
+    """sa_batch_clock: every tile of every clocked level records a start
+    before its end, tiles of one level overlap the level's span and levels
+    follow one another; levels outside the window stay unwritten; the run's
+    records are bit-identical to an unclocked run's."""
+    import torch
+    probs, chains, _ = make_batch(30, seed=19, nmax=128, precision=W.FP32, chains_choices=(64, 128, 256))
+    kw = dict(levels=8, steps=32, T0=10.0, alpha=0.9, seed=5, precision=S.FP32, trace_x=True, graph=True)
+    plain, _ = run_batch(S, probs, chains, S.BatchSchedule(**kw))
+    cols = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    with S.BatchAnnealer(probs, chains, schedule=S.BatchSchedule(**kw)) as b:
+        tiles = b.layout()["tiles"]
+        assert tiles == int(np.sum(chains)) // 64
+        ticks = torch.full((4, tiles, 2), -1, dtype=torch.int64, device="cuda")
+        rate = b.clock(ticks, 2, 3)  # levels 2, 3, 4 into the first three planes
+        b.run()
+        recs = [b.trace(p, 0, 8, with_x=True) for p in range(len(probs))]
+    t = ticks.cpu().numpy()
+    say(f"[gpu batch] clock rate {rate} ticks/s, level spans "
+        f"{[(int(t[k, :, 1].max() - t[k, :, 0].min())) for k in range(3)]}")
+    assert rate > 0
+    assert np.all(t[3] == -1)
+    assert np.all(t[:3, :, 0] > 0) and np.all(t[:3, :, 1] >= t[:3, :, 0])
+    for k in range(2):
+        assert t[k + 1, :, 0].min() >= t[k, :, 1].max()  # level k+1 starts after level k ends
+    for (rec, xb), g in zip(recs, plain):
+        assert np.array_equal(rec[cols], g["rec"][cols]) and np.array_equal(xb, g["xb"])
+
+
 def test_autotune_picks_a_valid_layout(S):
     probs, _, _ = make_batch(64, seed=17, nmax=256, precision=W.FP32)
     sched = S.BatchSchedule(levels=3, steps=16, T0=10.0, alpha=0.9, seed=0, precision=S.FP32)
