@@ -200,6 +200,16 @@ typedef struct {
 #define SA_FLAG_SOS 0x10u
 #define SA_FLAG_BEST_SEEN 0x20u
 
+/* SA_FLAG_ELITIST: an exchange broadcasts the record -- the lowest full
+ * re-evaluation of a level winner so far, the first of equal ones, with that
+ * full evaluation as the chains' start cost -- instead of the last level's
+ * winner (the paper's exchange broadcasts the winner, Sec. 2.2.2; keeping the
+ * best point found as the next start is its elitist reading).  The trace's
+ * winner fields and x_best still describe each level's winner.  Any state
+ * layout and family; not with SA_FLAG_SOS (whose keep test compares a chain
+ * with the winner): SA_ERR_UNSUPPORTED; not a flag of sa_batch_config. */
+#define SA_FLAG_ELITIST 0x40u
+
 /* Per-level record returned by sa_trace. */
 typedef struct {
     uint32_t win_chain; /* chain index of the level winner */

@@ -212,7 +212,7 @@ def set_threads(threads: int):
     lib().orc_set_threads(int(threads))
 
 
-VARIANT_SOS, VARIANT_BEST_SEEN = 1, 2
+VARIANT_SOS, VARIANT_BEST_SEEN, VARIANT_ELITIST = 1, 2, 4
 
 
 def sos_uniform(seed, problem, level, chain) -> float:
@@ -223,7 +223,7 @@ def sos_uniform(seed, problem, level, chain) -> float:
 def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
            move_rule=MOVE_RADIUS, exchange=True, problem=0, level_begin=0, x_start=None, chain_x=None,
            chain_cost=None, record=None, keep_x_best=True, final_f=False, sos=False, best_seen=False,
-           f_win_prev=None, kept=False):
+           f_win_prev=None, kept=False, elitist=False):
     """Run levels [level_begin, level_begin+levels) of the multi-chain SA.
 
     ``exchange``: levels between broadcasts of the winner -- 1 or True: every
@@ -238,11 +238,14 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
     final state in the argmin, broadcast and record.  ``f_win_prev``: the
     winner cost of level level_begin - 1 (sos runs that start past level 0).
     ``kept``: also return, for the last level, which chains kept their state.
+    ``elitist``: an exchange broadcasts the record instead of the last
+    level's winner (with ``x_start`` the record's state when resuming).
     Returns a dict of per-level outputs and the record."""
     lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
     n = lo.size
     period = 1 if exchange is True else 0 if exchange is False else int(exchange)
-    variant = (VARIANT_SOS if sos else 0) | (VARIANT_BEST_SEEN if best_seen else 0)
+    variant = ((VARIANT_SOS if sos else 0) | (VARIANT_BEST_SEEN if best_seen else 0)
+               | (VARIANT_ELITIST if elitist else 0))
     xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
     cx = cc = None
     if period != 1 or sos:

@@ -81,9 +81,16 @@
  *     first state of lowest carried cost among its start state and its states
  *     after each accepted move) stands in for its final state in the level's
  *     argmin, broadcast and record; a chain that continues on its own state
- *     continues from its final state. */
+ *     continues from its final state.
+ *   ORC_VARIANT_ELITIST: the state broadcast at an exchange is the record
+ *     (the lowest fully re-evaluated level winner so far, the first of equal
+ *     ones) instead of the last level's winner (Sec. 2.2.2 broadcasts the
+ *     winner; keeping the best point found as the next start is the elitist
+ *     reading of the same exchange).  Not defined together with
+ *     ORC_VARIANT_SOS, whose keep test compares against the winner. */
 #define ORC_VARIANT_SOS 1u
 #define ORC_VARIANT_BEST_SEEN 2u
+#define ORC_VARIANT_ELITIST 4u
 
 #define ORC_MOVE_RADIUS 0
 #define ORC_MOVE_RESAMPLE 1
@@ -581,7 +588,9 @@ int orc_sa_run_v(int func, uint32_t n, const double *lower, const double *upper,
     if (n == 0 || chains == 0) return -1;
     if ((exchange != 1 || (variant & ORC_VARIANT_SOS)) && (!chain_x || !chain_cost)) return -1;
     if ((variant & ORC_VARIANT_SOS) && level_begin > 0 && !f_win_io) return -1;
+    if ((variant & ORC_VARIANT_SOS) && (variant & ORC_VARIANT_ELITIST)) return -1;
     if (exchange && level_begin > 0 && !x_start) return -1;
+    if ((variant & ORC_VARIANT_ELITIST) && !x_rec) return -1;
     orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
     /* the capture sink appends in chain order: one thread while it is set */
     uint32_t nt = capture_sink.rec ? 1u : (uint32_t)orc_threads;
@@ -659,7 +668,9 @@ int orc_sa_run_v(int func, uint32_t n, const double *lower, const double *upper,
             *rec_level_io = level;
             memcpy(x_rec, bx, sizeof(double) * n);
         }
-        if (x_start) memmove(x_start, bx, sizeof(double) * n);
+        /* the next exchange broadcasts the winner, or the record (elitist) */
+        if (x_start) memmove(x_start, (variant & ORC_VARIANT_ELITIST) && isfinite(*f_rec_io) ? x_rec : bx,
+                             sizeof(double) * n);
         if (win_chain) win_chain[k] = best_chain;
         if (f_win) f_win[k] = best_f;
         f_win_prev = best_f;

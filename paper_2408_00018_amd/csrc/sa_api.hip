@@ -89,7 +89,8 @@ bool pick_overlay(uint32_t n, uint32_t chains, uint32_t steps, size_t real_size,
 constexpr uint32_t kNoStart = 0xFFFFFFFFu;
 
 struct Layout {
-    size_t table, T, inv_T, featT, x_best, slots, slot_x, x_rec, rec, rec_level, trace, trace_x, log, log_final;
+    size_t table, T, inv_T, featT, x_best, slots, slot_x, x_rec, rec, rec_level, elite_x, elite_f, trace, trace_x, log,
+        log_final;
     size_t x_start, theta, net, cap_count, chain_x, chain_cost, gcoef, total;
 };
 
@@ -111,9 +112,11 @@ sa_status validate(const sa_problem *p, const sa_config *c)
                                              c->radius_frac);
         st != SA_OK)
         return st;
-    if (c->flags &
-        ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_SOS | SA_FLAG_BEST_SEEN))
+    if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_SOS |
+                     SA_FLAG_BEST_SEEN | SA_FLAG_ELITIST))
         return fail(SA_ERR_INVALID, "unknown flag bits");
+    if ((c->flags & SA_FLAG_ELITIST) && (c->flags & SA_FLAG_SOS))
+        return fail(SA_ERR_UNSUPPORTED, "the stochastic exchange compares chains with the winner; not with SA_FLAG_ELITIST");
     if ((c->flags & (SA_FLAG_SOS | SA_FLAG_BEST_SEEN)) &&
         ((c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)) || !sa::separable(p->func)))
         return fail(SA_ERR_UNSUPPORTED,
@@ -208,6 +211,8 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     l.x_rec = take(n * R);
     l.rec = take(2 * sizeof(double));
     l.rec_level = take(sizeof(uint32_t));
+    l.elite_x = take((c->flags & SA_FLAG_ELITIST) ? 2 * n * R : 0);
+    l.elite_f = take(6 * sizeof(double));
     l.trace = take(L * sizeof(sa_level));
     l.trace_x = take((c->flags & SA_FLAG_TRACE_X) ? L * n * R : 0);
     const size_t log_moves = c->log_chains ? (size_t)c->log_levels * c->log_chains * c->steps : 0;
@@ -282,6 +287,9 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.x_rec = reinterpret_cast<R *>(w + l.x_rec);
     a.rec = reinterpret_cast<double *>(w + l.rec);
     a.rec_level = reinterpret_cast<uint32_t *>(w + l.rec_level);
+    a.elitist = (c->cfg.flags & SA_FLAG_ELITIST) ? 1u : 0u;
+    a.elite_x = a.elitist ? reinterpret_cast<R *>(w + l.elite_x) : nullptr;
+    a.elite_f = reinterpret_cast<double *>(w + l.elite_f);
     a.exchange = c->cfg.exchange <= 1 ? 1u : c->cfg.exchange == SA_EXCHANGE_NEVER ? 0u : c->cfg.exchange;
     const bool own_state = a.exchange != 1 || (c->cfg.flags & SA_FLAG_SOS);
     a.chain_x = own_state ? reinterpret_cast<R *>(w + l.chain_x) : nullptr;
@@ -451,7 +459,8 @@ void drop_graphs(sa_ctx *c)
 sa_status enqueue_reset(sa_ctx *c)
 {
     hipError_t e = sa::launch_reset(reinterpret_cast<double *>(c->ws + c->pl.lay.rec),
-                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level), c->stream);
+                                    reinterpret_cast<uint32_t *>(c->ws + c->pl.lay.rec_level),
+                                    reinterpret_cast<double *>(c->ws + c->pl.lay.elite_f), c->stream);
     if (e != hipSuccess) return fail(SA_ERR_DEVICE, "reset launch: %s", hipGetErrorString(e));
     c->groups = 0;
     c->next_level = 0;

@@ -57,6 +57,14 @@ template <typename R> struct LevelArgs {
     R *x_rec;            // n
     double *rec;         // {f_rec}
     uint32_t *rec_level;
+    // Elitist exchange: the broadcast state is the record.  The record after
+    // level m is mirrored in elite_x[(m & 1) n ..] and elite_f[3 (m & 1) ..]
+    // (f, s1, s2 of its full evaluation), so that every workgroup of the next
+    // launch reads the one the launch before wrote while workgroup 0 writes
+    // the other.
+    uint32_t elitist;
+    R *elite_x;          // 2 x n
+    double *elite_f;     // 2 x 3
     // Exchange period (Sec. 2.2): level L > 0 starts from the broadcast winner
     // when exchange > 0 and L % exchange == 0 (exchange = 1: every level);
     // otherwise every chain continues from its own state and carried cost.
@@ -108,7 +116,7 @@ hipError_t launch_level_f64(int func, bool table, int mode, const LevelArgs<doub
 hipError_t launch_finalize_f32(const LevelArgs<float> &a, uint32_t level, uint32_t groups, hipStream_t s);
 hipError_t launch_finalize_f64(const LevelArgs<double> &a, uint32_t level, uint32_t groups, hipStream_t s);
 // Reset the record (a kernel, so it can be captured in a graph).
-hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s);
+hipError_t launch_reset(double *rec, uint32_t *rec_level, double *elite_f, hipStream_t s);
 
 // Dynamic LDS bytes of a level launch (learn: the packed network as well).
 size_t level_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn);

@@ -39,11 +39,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(const LevelArgs<R> a, con
     adopt_winner<R>(a, level, groups, reinterpret_cast<R *>(lds_raw), sh_start, true, wave_slot, wave_acc);
 }
 
-__global__ void reset_kernel(double *rec, uint32_t *rec_level)
+__global__ void reset_kernel(double *rec, uint32_t *rec_level, double *elite_f)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         rec[0] = __builtin_inf();
         *rec_level = 0xFFFFFFFFu;
+        elite_f[0] = __builtin_inf();
+        elite_f[3] = __builtin_inf();
     }
 }
 
@@ -141,9 +143,9 @@ hipError_t launch_finalize_f64(const LevelArgs<double> &a, uint32_t level, uint3
     return hipGetLastError();
 }
 
-hipError_t launch_reset(double *rec, uint32_t *rec_level, hipStream_t s)
+hipError_t launch_reset(double *rec, uint32_t *rec_level, double *elite_f, hipStream_t s)
 {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, rec, rec_level);
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, rec, rec_level, elite_f);
     return hipGetLastError();
 }
 

@@ -69,8 +69,11 @@ __device__ Full full_eval_wg(const LevelArgs<R> &a, const R *tab, const R *x, do
 // Reduce the candidates level `lvl` published (`groups` of them) to the
 // level's winner: lowest carried cost, ties to the lowest chain.  Every
 // workgroup that calls this gets the same winner; its state goes to xw and
-// its full re-evaluation to start.  With `publish` the workgroup also writes
-// the level's trace entry, the record and the broadcast state.  win_f
+// its full re-evaluation to start -- or, for an elitist run, the record's
+// (the winner if it improves the record after level lvl - 1, else that
+// record, read from the mirror the previous launch wrote).  With `publish`
+// the workgroup also writes the level's trace entry, the record, the
+// winner's state and the record's mirror for the next launch.  win_f
 // (optional, LDS) gets the winner's carried cost.
 // ---------------------------------------------------------------------------
 template <typename R>
@@ -120,20 +123,32 @@ __device__ void adopt_winner(const LevelArgs<R> &a, uint32_t lvl, uint32_t group
     const size_t w = base + gj;
     const Slot<R> ws = a.slots[w];
     const bool improved = publish && ws.ff < rec_prev;
+    // elitist: the record after level lvl - 1 (mirror (lvl + 1) & 1; +inf
+    // after a reset) and the one after level lvl (mirror lvl & 1)
+    const uint32_t e_in = (lvl + 1u) & 1u, e_out = lvl & 1u;
+    const bool elite_keeps = a.elitist && !(ws.ff < a.elite_f[3 * e_in]);
     for (uint32_t i = tid; i < n; i += WG) {
         const R v = a.slot_x[w * n + i];
-        xw[i] = v;
+        const R e = elite_keeps ? a.elite_x[(size_t)e_in * n + i] : v;
+        xw[i] = e;
         if (publish) {
             a.x_best[i] = v;
             if (a.trace_x) a.trace_x[(size_t)lvl * n + i] = v;
             if (improved) a.x_rec[i] = v;
+            if (a.elitist) a.elite_x[(size_t)e_out * n + i] = e;
         }
     }
     if (tid == 0) {
-        start[0] = ws.ff;
-        start[1] = ws.s1;
-        start[2] = ws.s2;
+        const double *ef = a.elite_f + 3 * e_in;
+        start[0] = elite_keeps ? ef[0] : ws.ff;
+        start[1] = elite_keeps ? ef[1] : ws.s1;
+        start[2] = elite_keeps ? ef[2] : ws.s2;
         if (win_f) *win_f = (double)gf;
+        if (publish && a.elitist) {
+            a.elite_f[3 * e_out + 0] = start[0];
+            a.elite_f[3 * e_out + 1] = start[1];
+            a.elite_f[3 * e_out + 2] = start[2];
+        }
     }
     if (publish) {
         if (tid == 0) {

@@ -272,3 +272,18 @@ def test_fault_injection_hook(S, monkeypatch):
     if st == 0:
         L.sa_destroy(h)
     del keep, keep2
+
+
+def test_elitist_flag(S):
+    """SA_FLAG_ELITIST: accepted on every layout (two mirrors of the record
+    state in the workspace), refused with the stochastic exchange."""
+    lo, hi = np.full(100, -500.0), np.full(100, 500.0)
+    base = S.Schedule(chains=65536, levels=10, steps=100, T0=10.0, alpha=0.99)
+    plain = S.workspace_bytes(S.SCHWEFEL, lo, hi, None, base)
+    el = S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "elitist": True}))
+    assert el > plain
+    for kw in (dict(overlay=True), dict(best_seen=True), dict(exchange=3)):
+        S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "elitist": True, **kw}))
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "elitist": True, "sos": True}))
+    assert e.value.status == -5

@@ -1,6 +1,7 @@
 """GPU parity of the exchange variants (Sec. 2.2: the minimum operator read as
 a deterministic crossover; a stochastic crossover beside it; the best-seen
-state in place of the final state) against the FP64 oracle.
+state in place of the final state; the record broadcast in place of the
+winner) against the FP64 oracle.
 
 - FP64 runs follow the oracle's trajectory exactly (winners, accepted-move
   counts, broadcast states, costs to 1e-12), with the stochastic exchange,
@@ -49,7 +50,7 @@ def run(S, wl, chunks=None, **kw):
     sched = S.Schedule(**d)
     say(f"[gpu variants] {wl.name} n={wl.n} chains={sched.chains} levels={sched.levels} steps={sched.steps} "
         f"prec={sched.precision} exchange={sched.exchange} sos={sched.sos} best_seen={sched.best_seen} "
-        f"move={sched.move} chunks={chunks} graph={sched.graph} log={sched.log_chains}")
+        f"elitist={sched.elitist} move={sched.move} chunks={chunks} graph={sched.graph} log={sched.log_chains}")
     with S.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as a:
         for c in (chunks or [0]):
             a.run(c)
@@ -110,7 +111,14 @@ def sos_keeps(d, u, T_prev):
     return u < p, abs(u - p) <= margin
 
 
-def replay(wl, g, exchange, sos, best, chains):
+def elite_state(g, level):
+    """The record after `level` as an elitist run broadcasts it: the first
+    level winner of lowest full re-evaluation up to that level."""
+    fb = g["rec"]["f_best"][:level + 1]
+    return g["xb"][int(np.argmin(fb))]
+
+
+def replay(wl, g, exchange, sos, best, chains, elitist=False):
     """Per-move replay of a logged FP32 variant run from level 0; each chain
     from the start it chose.  Returns (moves replayed, ambiguous decisions)."""
     lo32, hi32 = box32(wl.lower, wl.upper)
@@ -131,7 +139,7 @@ def replay(wl, g, exchange, sos, best, chains):
             elif not exch:
                 starts = [(state[c], err[c], True)]
             elif not sos:
-                starts = [(xb[level - 1], None, False)]
+                starts = [(elite_state(g, level - 1) if elitist else xb[level - 1], None, False)]
             else:
                 T_prev = O.temperature(wl.T0, wl.alpha, level - 1)
                 u = O.sos_uniform(wl.seed, 0, level, c)
@@ -216,3 +224,56 @@ def test_variants_rejected_where_unsupported(S):
     with pytest.raises(S.SAError) as e:
         run(S, g, best_seen=True)
     assert e.value.status == -5
+
+
+ELITIST_CASES = [
+    # func, n, chains, levels, steps, box, exchange, best, move, chunks, T0
+    (W.SCHWEFEL, 4, 256, 12, 30, "canonical", 1, False, O.MOVE_RADIUS, None, 200.0),
+    (W.RASTRIGIN, 6, 512, 10, 20, "shifted", 3, False, O.MOVE_RADIUS, [4, 0], 40.0),
+    (W.ACKLEY, 5, 256, 9, 25, "uneven", 1, True, O.MOVE_RESAMPLE, [2, 0], 40.0),
+    (W.GRIEWANK, 7, 256, 9, 20, "shifted", 1, False, O.MOVE_RADIUS, None, 20.0),
+]
+
+
+@pytest.mark.parametrize("func,n,chains,levels,steps,box,exchange,best,move,chunks,T0", ELITIST_CASES)
+def test_fp64_elitist_trajectory_equals_oracle(S, func, n, chains, levels, steps, box, exchange, best, move, chunks,
+                                               T0):
+    """SA_FLAG_ELITIST in FP64: the trajectory equals the oracle's elitist run
+    (winners, accepted moves, winner states, costs to 1e-12) -- dense layout,
+    a periodic exchange, the best-seen reduction, a non-separable family --
+    with levels whose winner does not improve the record (where broadcasting
+    the winner would differ)."""
+    wl = problem(func, n, box, 3100 + 10 * func + n, chains=chains, levels=levels, steps=steps, precision=W.FP64,
+                 T0=T0, alpha=0.9)
+    g = run(S, wl, chunks=chunks, exchange=exchange, best_seen=best, move=move, elitist=True)
+    o = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, seed=wl.seed, chains=chains, steps=steps, T0=wl.T0,
+                 alpha=wl.alpha, levels=levels, radius_frac=wl.radius_frac, move_rule=move, exchange=exchange,
+                 best_seen=best, elitist=True)
+    fb = o["f_best"]
+    if not best:  # (a best-seen winner never trails the record it started from)
+        assert np.sum(fb[1:] >= np.minimum.accumulate(fb)[:-1]) >= 2  # some winners leave the record alone
+    assert np.array_equal(g["rec"]["win_chain"], o["win_chain"])
+    assert np.array_equal(g["rec"]["accepts"], o["accepts"])
+    np.testing.assert_allclose(g["xb"], o["x_best"], rtol=1e-12, atol=1e-12)
+    for k in ("f_win", "f_best", "f_rec"):
+        np.testing.assert_allclose(g["rec"][k], o[k], rtol=1e-12, atol=1e-12)
+    assert g["rec_level"] == o["rec_level"]
+
+
+def test_fp32_elitist_levels_replay_against_oracle(S):
+    """FP32 elitist run: every logged move replayed against the oracle from
+    the record state each level broadcasts; whole, chunked and graph-captured
+    runs agree bit for bit."""
+    wl = W.random_problem(W.RASTRIGIN, 8, seed=91).with_(chains=256, levels=6, steps=24, T0=40.0, alpha=0.9)
+    g = run(S, wl, elitist=True, log_chains=256, log_level=0, log_levels=6)
+    moves, amb = replay(wl, g, 1, False, False, range(256), elitist=True)
+    check_record(wl, g)
+    fb = g["rec"]["f_best"]
+    kept = int(np.sum(fb[1:-1] >= np.minimum.accumulate(fb)[:-2]))
+    say(f"[fp32 elitist parity] {moves} moves, {amb} ambiguous; {kept} broadcasts kept the record")
+    assert kept >= 1
+    keys = ["win_chain", "accepts", "f_win", "f_best", "f_rec"]
+    whole = run(S, wl, elitist=True)
+    for other in (run(S, wl, chunks=[2, 1, 0], elitist=True), run(S, wl, graph=True, chunks=[3, 0], elitist=True)):
+        assert np.array_equal(other["rec"][keys], whole["rec"][keys])
+        assert np.array_equal(other["xb"], whole["xb"])

@@ -14,6 +14,10 @@ else starts from the winner.
 - Each chain's next level replays (orc_replay_level, one chain at a time)
   from its own previous state if it kept it and from the winner otherwise,
   to its logged final cost.
+Elitist exchange (the record broadcast instead of the level winner):
+- Each level equals one plain level whose broadcast state is the record
+  after the level before, the record tracked from the plain levels.
+- Without exchanges it is the asynchronous run.
 Best-seen reduction:
 - Near zero temperature (only downhill moves) it equals the final-state run.
 - The level winner's state is one of the states its chain visited (replayed
@@ -23,6 +27,7 @@ Best-seen reduction:
 import math
 
 import numpy as np
+import pytest
 
 import oracle as O
 import workloads as W
@@ -135,3 +140,52 @@ def test_best_seen_winner_is_the_lowest_visited_state():
     assert any(np.array_equal(o["x_best"][0], v) for v in visited[w])
     assert o["f_best"][0] <= best_visit + 1e-9
     assert o["f_best"][0] <= fs["f_best"][0] + 1e-9
+
+
+def _elitist_cases():
+    # T0 at which level winners often come out worse than the record
+    return [(W.SCHWEFEL, 6, "canonical", 1, 200.0), (W.RASTRIGIN, 5, "shifted", 1, 40.0),
+            (W.ACKLEY, 4, "canonical", 2, 40.0)]
+
+
+@pytest.mark.parametrize("func,n,box,exchange,T0", _elitist_cases())
+def test_elitist_is_the_plain_run_restarted_from_the_record(func, n, box, exchange, T0):
+    """The elitist exchange composed from plain runs: level k of an elitist
+    run equals one plain level k whose broadcast state is the record after
+    level k - 1 (the lowest re-evaluated winner so far, the first of equal
+    ones), with every chain's own state carried between exchanges.  The
+    record is tracked here from the plain levels' f_best, so broadcasting the
+    winner instead, or moving the record on a tie, fails at the levels whose
+    winner does not improve it (the test requires some)."""
+    wl = W.random_problem(func, n, seed=600 + n, shifted=(box == "shifted"))
+    kw = dict(seed=7, chains=64, steps=12, T0=T0, alpha=0.9, radius_frac=wl.radius_frac)
+    levels = 14
+    el = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, levels=levels, exchange=exchange, elitist=True, **kw)
+    x_rec, f_rec, rec_level = np.zeros(n), math.inf, 0
+    x_start = None
+    cx = cc = None
+    not_improving = 0
+    for k in range(levels):
+        r = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, levels=1, level_begin=k, exchange=exchange,
+                     x_start=x_start, chain_x=cx, chain_cost=cc, record=(x_rec, f_rec, rec_level), **kw)
+        for key in ("win_chain", "f_win", "f_best", "f_rec", "accepts"):
+            assert np.array_equal(r[key], el[key][k:k + 1]), (k, key)
+        assert np.array_equal(r["x_best"], el["x_best"][k:k + 1])
+        fb = float(r["f_best"][0])
+        if fb < f_rec:
+            x_rec, f_rec, rec_level = r["x_best"][0].copy(), fb, k
+        else:
+            not_improving += 1
+        x_start = x_rec.copy()
+        cx, cc = r.get("chain_x"), r.get("chain_cost")
+    assert not_improving >= 3, not_improving
+    assert np.array_equal(el["x_rec"], x_rec) and el["f_rec_final"] == f_rec
+
+
+def test_elitist_without_exchange_is_the_asynchronous_run():
+    wl = W.random_problem(W.RASTRIGIN, 5, seed=77)
+    kw = dict(seed=3, chains=64, steps=10, T0=5.0, alpha=0.9, levels=8, exchange=0, radius_frac=wl.radius_frac)
+    a = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, **kw)
+    b = O.sa_run(wl.func, wl.lower, wl.upper, wl.shift, elitist=True, **kw)
+    for key in ("win_chain", "f_win", "f_best", "f_rec", "accepts"):
+        assert np.array_equal(a[key], b[key])
