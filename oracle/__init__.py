@@ -212,7 +212,7 @@ def set_threads(threads: int):
     lib().orc_set_threads(int(threads))
 
 
-VARIANT_SOS, VARIANT_BEST_SEEN, VARIANT_ELITIST = 1, 2, 4
+VARIANT_SOS, VARIANT_BEST_SEEN, VARIANT_ELITIST, VARIANT_FULL = 1, 2, 4, 8
 
 
 def sos_uniform(seed, problem, level, chain) -> float:
@@ -223,7 +223,7 @@ def sos_uniform(seed, problem, level, chain) -> float:
 def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, levels, radius_frac=0.1,
            move_rule=MOVE_RADIUS, exchange=True, problem=0, level_begin=0, x_start=None, chain_x=None,
            chain_cost=None, record=None, keep_x_best=True, final_f=False, sos=False, best_seen=False,
-           f_win_prev=None, kept=False, elitist=False):
+           f_win_prev=None, kept=False, elitist=False, full_eval=False):
     """Run levels [level_begin, level_begin+levels) of the multi-chain SA.
 
     ``exchange``: levels between broadcasts of the winner -- 1 or True: every
@@ -240,12 +240,14 @@ def sa_run(func, lower, upper, shift=None, *, seed, chains, steps, T0, alpha, le
     ``kept``: also return, for the last level, which chains kept their state.
     ``elitist``: an exchange broadcasts the record instead of the last
     level's winner (with ``x_start`` the record's state when resuming).
+    ``full_eval``: every move's cost is f evaluated in full at the moved
+    state instead of the separable families' increment.
     Returns a dict of per-level outputs and the record."""
     lo, hi, s = _f64(lower), _f64(upper), _f64(shift)
     n = lo.size
     period = 1 if exchange is True else 0 if exchange is False else int(exchange)
     variant = ((VARIANT_SOS if sos else 0) | (VARIANT_BEST_SEEN if best_seen else 0)
-               | (VARIANT_ELITIST if elitist else 0))
+               | (VARIANT_ELITIST if elitist else 0) | (VARIANT_FULL if full_eval else 0))
     xs = np.zeros(n) if x_start is None else _f64(x_start).copy()
     cx = cc = None
     if period != 1 or sos:

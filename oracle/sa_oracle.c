@@ -91,6 +91,11 @@
 #define ORC_VARIANT_SOS 1u
 #define ORC_VARIANT_BEST_SEEN 2u
 #define ORC_VARIANT_ELITIST 4u
+/*   ORC_VARIANT_FULL: every move's cost is f evaluated in full at the moved
+ *     state (Sec. 2.1 Step 3 compares f(x1) with f(x0); the paper's kernel
+ *     evaluates f(x1) whole), not the separable families' increment of the
+ *     changed term.  Non-separable families are evaluated in full anyway. */
+#define ORC_VARIANT_FULL 8u
 
 #define ORC_MOVE_RADIUS 0
 #define ORC_MOVE_RESAMPLE 1
@@ -383,6 +388,7 @@ typedef struct {
     uint32_t steps;
     double radius_frac;
     int move_rule;
+    int full_eval; /* re-evaluate f in full at every move (ORC_VARIANT_FULL) */
 } orc_problem;
 
 /* Capture sink: while set (orc_sa_run_capture), every accepted move appends
@@ -449,7 +455,16 @@ static uint64_t run_chain(const orc_problem *p, uint32_t level, uint32_t chain, 
         double xd = x[d];
         double xn = orc_neighbour(p->move_rule, xd, p->lower[d], p->upper[d], p->radius_frac, u1);
         orc_cost cn;
-        double df = cost_delta(p->func, p->n, c, x, p->shift, d, xn, &cn);
+        double df;
+        if (p->full_eval) {
+            /* the move's cost from scratch: f at x with x_d replaced */
+            x[d] = xn;
+            cost_full(p->func, p->n, x, p->shift, &cn);
+            x[d] = xd;
+            df = cn.f - c->f;
+        } else {
+            df = cost_delta(p->func, p->n, c, x, p->shift, d, xn, &cn);
+        }
         if (orc_accept(df, T, u2)) {
             if (capture_sink.rec) capture_move(p, T, d, xd, xn, hist);
             x[d] = xn;
@@ -591,7 +606,8 @@ int orc_sa_run_v(int func, uint32_t n, const double *lower, const double *upper,
     if ((variant & ORC_VARIANT_SOS) && (variant & ORC_VARIANT_ELITIST)) return -1;
     if (exchange && level_begin > 0 && !x_start) return -1;
     if ((variant & ORC_VARIANT_ELITIST) && !x_rec) return -1;
-    orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule};
+    orc_problem p = {func, n, lower, upper, shift, seed, problem, steps, radius_frac, move_rule,
+                     (variant & ORC_VARIANT_FULL) != 0};
     /* the capture sink appends in chain order: one thread while it is set */
     uint32_t nt = capture_sink.rec ? 1u : (uint32_t)orc_threads;
     if (nt > chains) nt = chains;
