@@ -66,13 +66,13 @@ PEAK_SLOTS_PER_S = 157.3e12 / 2.0
 # device copy (FETCH_SIZE reads 0.5x the bytes moved, WRITE_SIZE 1.0x); see
 # profiles/level_kernel_schwefel_n100_fp32.md.  Valid only for the kernel
 # sources it was measured on (hash below); otherwise reported as null.
-TRAFFIC_MEASURED = {"sources_sha256_16": "cc2842ddd2fdffc6", "fetch_kib": 168.954, "fetch_scale": 2.0,
+TRAFFIC_MEASURED = {"sources_sha256_16": "514386df92a4c560", "fetch_kib": 174.960, "fetch_scale": 2.0,
                     "write_kib": 120.592, "write_scale": 1.0}
 # Instruction counters of one level launch (rocprofv3 --pmc SQ_INSTS_VALU
 # SQ_INSTS_VALU_TRANS_F32, wave-instructions per dispatch, same sources):
 # with the live launch time they give the lane-operation issue rate, set
 # against the probe's full-grid FP32 FMA rate and v_sin_f32 rate.
-COUNTERS_MEASURED = {"sources_sha256_16": "cc2842ddd2fdffc6", "insts_valu": 6.375e6, "insts_trans": 5.12e5,
+COUNTERS_MEASURED = {"sources_sha256_16": "514386df92a4c560", "insts_valu": 6.379e6, "insts_trans": 5.12e5,
                      "fma_rate": 5.625e13, "trans_rate": 1.824e13}
 KERNEL_SOURCES = ["paper_2408_00018_amd/csrc/sa_kernels.hip", "paper_2408_00018_amd/csrc/sa_level_kernel.hpp",
                   "paper_2408_00018_amd/csrc/sa_device.hpp", "paper_2408_00018_amd/csrc/sa_internal.hpp",
@@ -357,16 +357,19 @@ def extra_workloads():
     run (graph-replayed levels, HIP events on the library's stream): the
     n = 512 Rastrigin and n = 1024 Ackley runs (131072 chains, 1000 levels x
     64 steps, shifted), the n = 100 Griewank run (65536 chains, 200 levels x
-    100 steps; non-separable: every move re-evaluates f in full), and 1024
+    100 steps; non-separable: every move re-evaluates f in full), the n = 100
+    Schwefel run with a full evaluation of f per move as the paper's kernel
+    does (SA_FLAG_FULL_EVAL) instead of the increment, and 1024
     batched problems (n ~ U{2..256}, 500 levels
     x 64 steps, chains per problem and waves per workgroup from the
     autotuner)."""
     import torch
     from paper_2408_00018_amd import sa
     out = {}
-    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32(), W.griewank_n100_fp32()):
+    full_eval = W.schwefel_n100_fp32().with_(name="schwefel_n100_fp32_full_eval")
+    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32(), W.griewank_n100_fp32(), full_eval):
         sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
-                            seed=wl.seed, precision=sa.FP32, graph=True)
+                            seed=wl.seed, precision=sa.FP32, graph=True, full_eval=wl is full_eval)
         with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:
             ann.run()
             ann.reset(wl.seed)

@@ -210,6 +210,20 @@ typedef struct {
  * with the winner): SA_ERR_UNSUPPORTED; not a flag of sa_batch_config. */
 #define SA_FLAG_ELITIST 0x40u
 
+/* SA_FLAG_FULL_EVAL: every move of a separable family (Schwefel, Rastrigin,
+ * Ackley) takes its cost increment as f(x') - f(x) with f(x') evaluated in
+ * full -- the paper's kernel evaluates f at every neighbour (Sec. 3.3, the
+ * synchronous kernel) -- instead of the O(1) increment of the one changed
+ * term; each move then reads all n coordinates.  FP64 runs give the same
+ * trajectory up to rounding; FP32 runs evaluate the cancellation-free forms
+ * (Rastrigin as sum y^2 + 20 sin^2(pi y), Ackley through expm1) on the
+ * hardware transcendentals.  The non-separable families always evaluate in
+ * full, so the flag changes nothing for them.  Dense state layout, plain or
+ * logged moves: not with SA_FLAG_LEARNED, SA_FLAG_OVERLAY, SA_FLAG_SOS,
+ * SA_FLAG_BEST_SEEN or sa_capture (SA_ERR_UNSUPPORTED); not a flag of
+ * sa_batch_config. */
+#define SA_FLAG_FULL_EVAL 0x80u
+
 /* Per-level record returned by sa_trace. */
 typedef struct {
     uint32_t win_chain; /* chain index of the level winner */

@@ -42,6 +42,13 @@ int variant_of(const sa_config *c)
     return ((c->flags & SA_FLAG_SOS) ? sa::kVarSos : 0) | ((c->flags & SA_FLAG_BEST_SEEN) ? sa::kVarBest : 0);
 }
 
+// Whether every move evaluates f in full (the non-separable families always;
+// the separable ones under SA_FLAG_FULL_EVAL) rather than by its increment.
+bool full_eval(const sa_problem *p, const sa_config *c)
+{
+    return !sa::separable(p->func) || (c->flags & SA_FLAG_FULL_EVAL);
+}
+
 // Dynamic LDS of a dense level launch (learned: the packed network too;
 // best-seen: its accept bits and replay lists).
 size_t dense_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool learn, int var, uint32_t steps)
@@ -113,12 +120,12 @@ sa_status validate(const sa_problem *p, const sa_config *c)
         st != SA_OK)
         return st;
     if (c->flags & ~(SA_FLAG_TRACE_X | SA_FLAG_GRAPH | SA_FLAG_LEARNED | SA_FLAG_OVERLAY | SA_FLAG_SOS |
-                     SA_FLAG_BEST_SEEN | SA_FLAG_ELITIST))
+                     SA_FLAG_BEST_SEEN | SA_FLAG_ELITIST | SA_FLAG_FULL_EVAL))
         return fail(SA_ERR_INVALID, "unknown flag bits");
     if ((c->flags & SA_FLAG_ELITIST) && (c->flags & SA_FLAG_SOS))
         return fail(SA_ERR_UNSUPPORTED, "the stochastic exchange compares chains with the winner; not with SA_FLAG_ELITIST");
-    if ((c->flags & (SA_FLAG_SOS | SA_FLAG_BEST_SEEN)) &&
-        ((c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)) || !sa::separable(p->func)))
+    const bool full = full_eval(p, c);
+    if ((c->flags & (SA_FLAG_SOS | SA_FLAG_BEST_SEEN)) && ((c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)) || full))
         return fail(SA_ERR_UNSUPPORTED,
                     "the exchange variants run plain or logged moves of the separable families on the dense layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->flags & SA_FLAG_OVERLAY))
@@ -129,8 +136,10 @@ sa_status validate(const sa_problem *p, const sa_config *c)
         return fail(SA_ERR_UNSUPPORTED, "an exchange period other than 1 needs the dense state layout");
     if ((c->flags & SA_FLAG_LEARNED) && (c->precision != SA_FP32 || c->move != SA_MOVE_RADIUS))
         return fail(SA_ERR_UNSUPPORTED, "the learned proposal runs in FP32 with the radius move as its plain part");
-    if (!sa::separable(p->func) && (c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)))
-        return fail(SA_ERR_UNSUPPORTED, "the non-separable families run plain or logged moves on the dense layout");
+    if (full && (c->flags & (SA_FLAG_LEARNED | SA_FLAG_OVERLAY)))
+        return fail(SA_ERR_UNSUPPORTED,
+                    "full evaluation per move (the non-separable families, SA_FLAG_FULL_EVAL) runs plain or logged "
+                    "moves on the dense layout");
     if (c->log_chains) {
         if (c->log_chains > c->chains) return fail(SA_ERR_INVALID, "log_chains exceeds chains");
         if (c->log_levels == 0 || c->log_level >= c->levels || c->log_levels > c->levels - c->log_level)
@@ -176,7 +185,7 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     // operations per move; measured at n = 512: 1.7x faster than the dense
     // layout with 131072 chains, 2.8x slower with 16384, where both put 256
     // waves in flight).
-    if (!learn && !periodic && !var && sa::separable(p->func)) {
+    if (!learn && !periodic && !var && !full_eval(p, c)) {
         uint32_t ov_wg = 0, ov_slots = 0;
         const bool ov_fits = pick_overlay(p->n, c->chains, c->steps, pl.real, pl.table, lds_limit, &ov_wg, &ov_slots);
         const uint64_t ov_flight =
@@ -310,7 +319,10 @@ template <typename R> void fill_args(sa_ctx *c, sa::LevelArgs<R> &a)
     a.cap_count = reinterpret_cast<unsigned long long *>(w + l.cap_count);
     a.cap_capacity = 0;
     a.gcoef = reinterpret_cast<const float *>(w + l.gcoef);
-    a.cscale = (float)(3.14159265358979323846 / (double)c->prob.n);
+    const double dn = (double)c->prob.n;
+    a.cscale = (float)(c->prob.func == SA_SCHWEFEL  ? -1.0 / dn
+                       : c->prob.func == SA_ACKLEY ? 1.0 / dn
+                                                   : 3.14159265358979323846 / dn);
     a.net_kind = c->net_kind;
 }
 
@@ -428,7 +440,7 @@ sa_status enqueue_levels(sa_ctx *c, uint32_t first, uint32_t count, hipStream_t 
         if (const int var = variant_of(&c->cfg))
             e = c->fp64 ? sa::launch_variant_level_f64(c->prob.func, c->pl.table, var, log, c->a64, k, *groups, &g, s)
                         : sa::launch_variant_level_f32(c->prob.func, c->pl.table, var, log, c->a32, k, *groups, &g, s);
-        else if (!sa::separable(c->prob.func))
+        else if (full_eval(&c->prob, &c->cfg))
             e = c->fp64 ? sa::launch_coupled_level_f64(c->prob.func, c->pl.table, log, c->a64, k, *groups, &g, s)
                         : sa::launch_coupled_level_f32(c->prob.func, c->pl.table, log, c->a32, k, *groups, &g, s);
         else if (c->pl.overlay)
@@ -847,8 +859,8 @@ sa_status sa_capture(sa_ctx *c, float *records, uint64_t capacity)
         return fail(SA_ERR_INVALID, "records must be float-aligned");
     if (records && c->learned) return fail(SA_ERR_STATE, "capture records plain runs; clear the proposal first");
     if (records && c->pl.overlay) return fail(SA_ERR_UNSUPPORTED, "capture runs on the dense state layout");
-    if (records && !sa::separable(c->prob.func))
-        return fail(SA_ERR_UNSUPPORTED, "capture records moves of the separable families");
+    if (records && full_eval(&c->prob, &c->cfg))
+        return fail(SA_ERR_UNSUPPORTED, "capture records incremental moves of the separable families");
     if (records && variant_of(&c->cfg)) return fail(SA_ERR_UNSUPPORTED, "capture records plain-exchange runs");
     drop_graphs(c);
     c->a32.cap_rec = records;

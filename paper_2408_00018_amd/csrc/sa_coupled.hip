@@ -2,7 +2,9 @@
 // (Appendix: Test 8 Griewank, Test 10 Levy-Montalvo, Test 14 generalized
 // Rosenbrock).  No cost term belongs to one coordinate alone, so every move
 // evaluates f(x') in full, as the paper's kernel does for every function
-// (Sec. 3.3, synchronous kernel listing: f at the neighbour each step).
+// (Sec. 3.3, synchronous kernel: f at the neighbour each step).  The same
+// kernel runs the separable families (Schwefel, Rastrigin, Ackley) with that
+// full evaluation when a run asks for it instead of their increment.
 //
 // Layout and level structure as the separable level kernel: one chain per
 // lane, a tile's states in LDS as x[d][lane] (coordinate-major), one launch
@@ -13,6 +15,10 @@
 // restores x_d if the move is rejected.
 //
 // Forms (y = x - s):
+//   Schwefel        -(1/n) sum y_i sin(sqrt|y_i|)
+//   Rastrigin       sum y_i^2 + 20 sin^2(pi y_i)   (= 10 n + sum y_i^2 - 10 cos(2 pi y_i))
+//   Ackley          -20 expm1(-0.2 sqrt(S1/n)) - e expm1(-2 D/n),
+//                   S1 = sum y_i^2, D = sum sin^2(pi y_i)  (sum cos(2 pi y_i) = n - 2 D)
 //   Griewank        1 + sum y_i^2 / 4000 - prod cos(y_i / sqrt(i))
 //   Levy-Montalvo   (pi/n) [10 sin^2(pi w_1) + sum_{i<n} (w_i - 1)^2
 //                   (1 + 10 sin^2(pi w_{i+1})) + (w_n - 1)^2],  w = 1 + (y + 1)/4
@@ -22,9 +28,11 @@
 // (the forms above), whose stated minima (0 at the origin, 0 at (1,...,1))
 // they then have.
 // FP64 runs evaluate the definitions term by term in coordinate order, as a
-// plain sequential evaluation does.  FP32 runs use the hardware
-// transcendentals: cos(y/sqrt(i)) = cos_rev(y c_i) with c_i = 1/(2 pi sqrt(i))
-// from a per-coordinate table, and sin^2(pi w) = sin_rev((w - 1)/2)^2.
+// plain sequential evaluation does (the separable families in their printed
+// forms).  FP32 runs use the hardware transcendentals: cos(y/sqrt(i)) =
+// cos_rev(y c_i) with c_i = 1/(2 pi sqrt(i)) from a per-coordinate table,
+// sin^2(pi w) = sin_rev((w - 1)/2)^2, sin(sqrt|y|) = sin_rev(sqrt(|y|/(4 pi^2))),
+// and the separable families in the cancellation-free forms above.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -42,9 +50,15 @@ namespace sa {
 // FP64 full evaluation of a coupled function, definition order; y(i) returns
 // shifted coordinate i.
 // ---------------------------------------------------------------------------
+template <int F> constexpr bool kSeparable = F == kSchwefel || F == kRastrigin || F == kAckley;
+
 template <int F, typename YFn> __device__ double coupled_f64(uint32_t n, const YFn &y)
 {
-    if constexpr (F == kGriewank) {
+    if constexpr (kSeparable<F>) {
+        FullAcc<F> acc;
+        for (uint32_t i = 0; i < n; ++i) acc.add(y(i));
+        return acc.finish(n).f;
+    } else if constexpr (F == kGriewank) {
         double sum = 0.0, prod = 1.0;
         for (uint32_t i = 0; i < n; ++i) {
             const double v = y(i);
@@ -113,14 +127,43 @@ template <typename T> __device__ __forceinline__ T wave_prod(T v)
 // FP32 full evaluation of one chain's column (coordinate i at col[i * STRIDE],
 // STRIDE = 0: the run-time `stride`).  sh(i) returns coordinate i's shift;
 // gco: Griewank's c_i = 1/(2 pi sqrt(i+1)), FP32, wave-uniform loads;
-// scale: Levy-Montalvo's pi/n rounded to FP32.
+// scale, rounded to FP32: Levy-Montalvo's pi/n, Schwefel's -1/n, Ackley's 1/n.
 // ---------------------------------------------------------------------------
 template <int F, uint32_t STRIDE, typename ShFn>
 __device__ __forceinline__ float coupled_f32(const float *col, uint32_t stride, uint32_t n, const ShFn &sh,
                                              const float *__restrict__ gco, float scale)
 {
     const uint32_t st = STRIDE ? STRIDE : stride;
-    if constexpr (F == kGriewank) {
+    if constexpr (F == kSchwefel) {
+        float acc = 0.0f;
+#pragma unroll 4
+        for (uint32_t i = 0; i < n; ++i) {
+            const float y = col[i * st] - sh(i);
+            acc = fmaf(y, hw_sin_rev(hw_sqrt(fabsf(y) * kInv4Pi2)), acc);
+        }
+        return acc * scale;
+    } else if constexpr (F == kRastrigin) {
+        float acc = 0.0f;
+#pragma unroll 4
+        for (uint32_t i = 0; i < n; ++i) {
+            const float y = col[i * st] - sh(i);
+            const float sp = hw_sin_rev(0.5f * y);
+            acc = fmaf(y, y, fmaf(20.0f * sp, sp, acc));
+        }
+        return acc;
+    } else if constexpr (F == kAckley) {
+        float s1 = 0.0f, dd = 0.0f;
+#pragma unroll 4
+        for (uint32_t i = 0; i < n; ++i) {
+            const float y = col[i * st] - sh(i);
+            const float sp = hw_sin_rev(0.5f * y);
+            s1 = fmaf(y, y, s1);
+            dd = fmaf(sp, sp, dd);
+        }
+        const float ea = expm1_f32(-0.2f * hw_sqrt(s1 * scale));
+        const float eb = expm1_f32(-2.0f * (dd * scale));
+        return fmaf(-20.0f, ea, -(float)kE * eb);
+    } else if constexpr (F == kGriewank) {
         float s = 0.0f, p = 1.0f;
 #pragma unroll 4
         for (uint32_t i = 0; i < n; ++i) {
@@ -163,8 +206,8 @@ __device__ __forceinline__ float coupled_f32(const float *col, uint32_t stride, 
 // ---------------------------------------------------------------------------
 // Full FP64 evaluation of a state in LDS (x[i * stride]) by the workgroup:
 // FP64 runs in definition order on one lane; FP32 runs split over the first
-// wave (Griewank: a sum and a product; the others: a sum of per-coordinate
-// terms).  Contains workgroup barriers.
+// wave (Griewank: a sum and a product; Ackley: its two sums; the others: a
+// sum of per-coordinate terms).  Contains workgroup barriers.
 // ---------------------------------------------------------------------------
 template <typename R, int F, bool TABLE>
 __device__ double coupled_full_wg(const LevelArgs<R> &a, const R *tab, const R *x, double *part, uint32_t stride = 1)
@@ -175,7 +218,13 @@ __device__ double coupled_full_wg(const LevelArgs<R> &a, const R *tab, const R *
         if (tid == 0) part[0] = coupled_f64<F>(n, y);
     } else if (tid < 64) {
         double v;
-        if constexpr (F == kGriewank) {
+        if constexpr (kSeparable<F>) {
+            FullAcc<F> acc;
+            for (uint32_t i = tid; i < n; i += 64) acc.add(y(i));
+            acc.a = wave_sum_d(acc.a);
+            acc.b = wave_sum_d(acc.b);
+            v = acc.finish(n).f;
+        } else if constexpr (F == kGriewank) {
             double s = 0.0, p = 1.0;
             for (uint32_t i = tid; i < n; i += 64) {
                 const double yi = y(i);
@@ -444,6 +493,9 @@ static hipError_t dispatch(int func, bool table, bool log, const LevelArgs<R> &a
                            uint32_t *groups, hipStream_t s)
 {
     switch (func) {
+    case kSchwefel: return dispatch_f<R, kSchwefel>(table, log, a, level, prev, groups, s);
+    case kRastrigin: return dispatch_f<R, kRastrigin>(table, log, a, level, prev, groups, s);
+    case kAckley: return dispatch_f<R, kAckley>(table, log, a, level, prev, groups, s);
     case kGriewank: return dispatch_f<R, kGriewank>(table, log, a, level, prev, groups, s);
     case kLevyMontalvo: return dispatch_f<R, kLevyMontalvo>(table, log, a, level, prev, groups, s);
     case kRosenbrock: return dispatch_f<R, kRosenbrock>(table, log, a, level, prev, groups, s);

@@ -88,8 +88,9 @@ template <typename R> struct LevelArgs {
     float *cap_rec;             // captured records, 7 floats each
     unsigned long long *cap_count;  // accepted moves seen by the capture
     uint64_t cap_capacity;      // records cap_rec holds
-    // Non-separable families: Griewank's c_i = 1/(2 pi sqrt(i+1)) (n FP32
-    // values, FP32 runs) and Levy-Montalvo's pi/n in FP32.
+    // Full-evaluation kernel, FP32 runs: Griewank's c_i = 1/(2 pi sqrt(i+1))
+    // (n values) and the family's scale (Levy-Montalvo pi/n, Schwefel -1/n,
+    // Ackley 1/n).
     const float *gcoef;
     float cscale;
 };
@@ -141,8 +142,9 @@ hipError_t launch_variant_level_f64(int func, bool table, int var, bool log, con
 // replay lists as well).
 size_t variant_lds_bytes(uint32_t n, uint32_t wg, size_t real_size, bool table, bool best_seen, uint32_t steps);
 
-// Level launches for the non-separable families (full re-evaluation per
-// move; dense state layout; plain and logged moves).
+// Level launches with a full re-evaluation per move: the non-separable
+// families, and the separable ones when a run asks for it (dense state
+// layout; plain and logged moves).
 hipError_t launch_coupled_level_f32(int func, bool table, bool log, const LevelArgs<float> &a, uint32_t level,
                                     uint32_t prev_groups, uint32_t *groups, hipStream_t s);
 hipError_t launch_coupled_level_f64(int func, bool table, bool log, const LevelArgs<double> &a, uint32_t level,

@@ -23,6 +23,7 @@ FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8
 FLAG_SOS, FLAG_BEST_SEEN, FLAG_ELITIST = 0x10, 0x20, 0x40  # exchange variants
+FLAG_FULL_EVAL = 0x80  # separable families: f evaluated in full at every move
 NET_RELU_CAUCHY, NET_GELU_GAUSS = 0, 1  # proposal network kinds
 EXCHANGE_NEVER = 0xFFFFFFFF
 
@@ -159,12 +160,13 @@ class Schedule:
     sos: bool = False        # stochastic exchange (SA_FLAG_SOS)
     best_seen: bool = False  # best-seen reduction (SA_FLAG_BEST_SEEN)
     elitist: bool = False    # broadcast the record instead of the winner (SA_FLAG_ELITIST)
+    full_eval: bool = False  # full evaluation of f per move instead of the increment (SA_FLAG_FULL_EVAL)
 
     def to_c(self) -> Config:
         flags = ((FLAG_TRACE_X if self.trace_x else 0) | (FLAG_GRAPH if self.graph else 0) |
                  (FLAG_LEARNED if self.learned else 0) | (FLAG_OVERLAY if self.overlay else 0) |
                  (FLAG_SOS if self.sos else 0) | (FLAG_BEST_SEEN if self.best_seen else 0) |
-                 (FLAG_ELITIST if self.elitist else 0))
+                 (FLAG_ELITIST if self.elitist else 0) | (FLAG_FULL_EVAL if self.full_eval else 0))
         return Config(self.seed, self.chains, self.levels, self.steps, self.precision, self.move, flags, self.T0,
                       self.alpha, self.radius_frac, self.log_chains, self.log_level, self.log_levels,
                       EXCHANGE_NEVER if self.exchange == 0 else self.exchange)

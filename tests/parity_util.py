@@ -51,8 +51,12 @@ COUPLED = (O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK)
 
 def eval_err32(func, x, shift):
     """First-order bound on the absolute error of the FP32 full evaluation of
-    a non-separable family at state x (FP64 copy of the FP32 state), following
-    the kernel's operation order: y = x - s rounded, then per coordinate
+    the full-evaluation kernel at state x (FP64 copy of the FP32 state),
+    following its operation order: y = x - s rounded, then per coordinate
+      Schwefel     acc = fma(y, sin_rev(sqrt(|y| fl(1/(4 pi^2)))), acc); f = acc fl(-1/n)
+      Rastrigin    S = sin_rev(y/2); acc = fma(y, y, fma(20 S, S, acc))
+      Ackley       S = sin_rev(y/2); s1 = fma(y, y, s1); D = fma(S, S, D);
+                   f = fma(-20, expm1(-0.2 sqrt(s1 fl(1/n))), -fl(e) expm1(-2 D fl(1/n)))
       Griewank     s += y^2 (fma); p *= cos_rev(y c_i), c_i = fl(1/(2 pi sqrt(i)));
                    f = fma(s, fl(1/4000), 1) - p
       Levy         h = fma(y, 1/8, 1/8) = v/2; S = sin_rev(h);
@@ -60,12 +64,46 @@ def eval_err32(func, x, shift):
       Rosenbrock   t = fma(-a, a, b); acc = fma(100 t, t, acc); acc = fma(u, u, acc)
     Every rounding contributes U32 times the magnitude of its result, the
     hardware sine/cosine E_TRIG (E_TRIG_WIDE past 64 revolutions) absolutely,
-    and errors propagate through first derivatives.  Sums of n roundings are
-    bounded by n U32 times the sum of the magnitudes."""
+    sqrt E_SQRT and e^x - 1 E_EXPM1 relatively, and errors propagate through
+    first derivatives.  Sums of n roundings are bounded by n U32 times the sum
+    of the magnitudes."""
     x = np.asarray(x, dtype=np.float64)
     n = x.size
     y = x - (0.0 if shift is None else np.asarray(shift, dtype=np.float64))
     dy = U32 * np.abs(y) if shift is not None else np.zeros(n)
+    ay = np.abs(y)
+    if func == O.SCHWEFEL:
+        r = np.sqrt(ay / (4 * np.pi ** 2))  # the sine's argument in revolutions
+        S = np.sin(2 * np.pi * r)
+        rel_r = E_SQRT + 0.5 * (2 * U32 + np.divide(dy, ay, out=np.zeros(n), where=ay > 0))
+        dS = E_TRIG + 2 * np.pi * r * np.abs(np.cos(2 * np.pi * r)) * rel_r
+        h = np.abs(y * S)
+        f = -float(np.sum(y * S)) / n
+        return (float(np.sum(np.abs(S) * dy + ay * dS)) + n * U32 * float(np.sum(h))) / n + 2 * U32 * abs(f)
+    if func in (O.RASTRIGIN, O.ACKLEY):
+        S = np.sin(np.pi * y)
+        dS = np.pi * np.abs(np.cos(np.pi * y)) * dy + E_TRIG
+        if func == O.RASTRIGIN:
+            g = y * y + 20 * S * S
+            dg = 2 * ay * dy + 40 * np.abs(S) * dS + 20 * S * S * U32
+            return float(np.sum(dg)) + 2 * n * U32 * float(np.sum(g))
+        s1, D = float(np.sum(y * y)), float(np.sum(S * S))
+        ds1 = float(np.sum(2 * ay * dy)) + n * U32 * s1
+        dD = float(np.sum(2 * np.abs(S) * dS)) + n * U32 * D
+        u = s1 / n
+        du = ds1 / n + 2 * U32 * u
+        q = math.sqrt(u)
+        dq = (min(du / (2 * q), math.sqrt(du)) if q > 0 else math.sqrt(du)) + E_SQRT * q
+        a = -0.2 * q
+        da = 0.2 * dq + 2 * U32 * 0.2 * q
+        ea = math.expm1(a)
+        dea = math.exp(a) * da + E_EXPM1 * abs(ea)
+        b = -2 * D / n
+        db = 2 * dD / n + 2 * U32 * abs(b)
+        eb = math.expm1(b)
+        deb = math.exp(b) * db + E_EXPM1 * abs(eb)
+        f = -20 * ea - math.e * eb
+        return 20 * dea + math.e * deb + 2 * U32 * math.e * abs(eb) + U32 * abs(f)
     if func == O.GRIEWANK:
         idx = np.arange(1, n + 1, dtype=np.float64)
         th = y / np.sqrt(idx)
@@ -112,17 +150,18 @@ def eval_err32(func, x, shift):
     return float(np.sum(dterms)) + 2 * (n + 1) * U32 * float(np.sum(terms))
 
 
-def df_floor(func, n, x, xn, d, shift):
+def df_floor(func, n, x, xn, d, shift, full=False):
     """Absolute error floor of an FP32 cost increment, from the rounding of its
     inputs and the hardware transcendental error (the relative 1e-5 is added
     on top): twice a first-order bound (the factor 2 covers the second-order
     terms the bound leaves out).  x, xn: FP64 copies of the FP32 states
     before/after the move.
-    Non-separable families: the increment is the difference of two full FP32
+    Non-separable families, and every family with `full` (a run under
+    SA_FLAG_FULL_EVAL): the increment is the difference of two full FP32
     evaluations (the carried cost is the last one, or the FP64 start value
     rounded to FP32), so the floor is the sum of their error bounds, doubled
     for the first-order analysis."""
-    if func in COUPLED:
+    if func in COUPLED or full:
         return 2.0 * (eval_err32(func, x, shift) + eval_err32(func, xn, shift))
     s = 0.0 if shift is None else shift[d]
     y, yn = x[d] - s, xn[d] - s
@@ -163,7 +202,7 @@ def df_floor(func, n, x, xn, d, shift):
 
 
 def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_rule, radius_frac, x_start, moves,
-                     final_f, chain_ids, rel=1e-5, problem=0, start_err=None, best_seen=False):
+                     final_f, chain_ids, rel=1e-5, problem=0, start_err=None, best_seen=False, full=False):
     """Replay the logged moves of `chain_ids` at one level against the oracle.
 
     x_start: the level's start state (the previous level's broadcast winner,
@@ -175,7 +214,8 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
     lowest cost it carried during the level, start included), which must match
     the lowest FP64 cost of the states it visited within the same bound;
     stats["visited"][c] lists those states and stats["f_last"][c] bounds
-    the final state's FP64 cost."""
+    the final state's FP64 cost.  full: the increments are differences of full
+    FP32 evaluations (SA_FLAG_FULL_EVAL)."""
     stats = dict(moves=0, max_rel_excess=0.0, decision_mismatch=0, ambiguous=0, max_df_err=0.0, f_err={},
                  x_final={}, visited={}, f_last={})
     for j, c in enumerate(chain_ids):
@@ -197,7 +237,7 @@ def check_fp32_level(func, n, lower32, upper32, shift32, seed, level, T, move_ru
             xn = x.copy()
             xn[d_ref] = m["x_new"]
             df_ref = O.f(func, xn, shift32) - O.f(func, x, shift32)
-            floor = df_floor(func, n, x, xn, d_ref, shift32)
+            floor = df_floor(func, n, x, xn, d_ref, shift32, full)
             err = abs(m["df"] - df_ref)
             tol = rel * abs(df_ref) + floor
             stats["max_df_err"] = max(stats["max_df_err"], err)
@@ -260,7 +300,7 @@ def fp32_init_state(wl, chain, problem=0):
     return x.astype(np.float64)
 
 
-def check_fp32_run(wl, g, log_level, chain_ids=None, problem=0, move_rule=O.MOVE_RADIUS, say=print):
+def check_fp32_run(wl, g, log_level, chain_ids=None, problem=0, move_rule=O.MOVE_RADIUS, say=print, full=False):
     """Per-move replay of a logged FP32 run (moves, final costs, per-level
     trace and broadcast states in g) against the oracle, plus the level
     argmin and the full re-evaluation of each broadcast."""
@@ -285,7 +325,7 @@ def check_fp32_run(wl, g, log_level, chain_ids=None, problem=0, move_rule=O.MOVE
         for c in chain_ids:
             x_start = fp32_init_state(wl, c, problem) if level == 0 else xb[level - 1]
             st = check_fp32_level(wl.func, wl.n, lo32, hi32, sh32, wl.seed, level, T, move_rule, wl.radius_frac,
-                                  x_start, moves[k, c:c + 1], final_f[k], [c], problem=problem)
+                                  x_start, moves[k, c:c + 1], final_f[k], [c], problem=problem, full=full)
             totals["moves"] += st["moves"]
             totals["ambiguous"] += st["ambiguous"]
             totals["max_rel_excess"] = max(totals["max_rel_excess"], st["max_rel_excess"])

@@ -287,3 +287,25 @@ def test_elitist_flag(S):
     with pytest.raises(S.SAError) as e:
         S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "elitist": True, "sos": True}))
     assert e.value.status == -5
+
+
+def test_full_eval_flag(S):
+    """SA_FLAG_FULL_EVAL: the header's value; accepted for plain and logged
+    moves on the dense layout (any exchange period, elitist too), refused with
+    the layouts and variants that assume the increment, and where the dense
+    state does not fit in LDS."""
+    text = open(os.path.join(ROOT, "include", "sa.h")).read()
+    assert int(re.search(r"#define SA_FLAG_FULL_EVAL (0x[0-9a-f]+)u", text).group(1), 16) == S.FLAG_FULL_EVAL
+    lo, hi = np.full(100, -500.0), np.full(100, 500.0)
+    base = S.Schedule(chains=65536, levels=10, steps=100, T0=10.0, alpha=0.99)
+    for kw in (dict(), dict(exchange=3), dict(exchange=0), dict(elitist=True), dict(precision=S.FP64),
+               dict(log_chains=64, log_level=0, log_levels=1)):
+        S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "full_eval": True, **kw}))
+    for kw in (dict(overlay=True), dict(best_seen=True), dict(sos=True), dict(learned=True)):
+        with pytest.raises(S.SAError) as e:
+            S.workspace_bytes(S.SCHWEFEL, lo, hi, None, S.Schedule(**{**base.__dict__, "full_eval": True, **kw}))
+        assert e.value.status == -5
+    big = S.Schedule(**{**base.__dict__, "full_eval": True})
+    with pytest.raises(S.SAError) as e:
+        S.workspace_bytes(S.SCHWEFEL, np.full(1024, -500.0), np.full(1024, 500.0), None, big)
+    assert e.value.status == -5

@@ -191,3 +191,24 @@ def test_fp64_start_state_with_exchange_period(S):
     np.testing.assert_allclose(rec["f_best"], o["f_best"], rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(xb, o["x_best"], rtol=1e-12, atol=1e-12)
     assert lvl == o["rec_level"] and abs(f_rec - o["f_rec_final"]) <= 1e-12
+
+
+def test_fp32_carried_cost_drift_over_an_asynchronous_run(S):
+    """The bench shape with no exchange (500 levels x 100 steps, 65536
+    chains, FP32): each chain carries its cost incrementally through all
+    50000 steps, and each level's winner is ranked by that carried cost.
+    Every level's record holds both the winner's carried cost (f_win) and the
+    full FP64 re-evaluation of its state (f_best); their difference is the
+    drift the carried cost has gathered.  Each accepted move adds at most one
+    increment's error (below 1e-4 here) and one FP32 rounding of the sum
+    (ulp(419) / 2 = 1.5e-5); over ~1.5e4 accepted moves the errors largely
+    cancel.  The test prints the drift and bounds it by 1e-2 -- far below the
+    spread of the level winners' costs in the asynchronous run, so the
+    ranking of the winners is not what decides its (poor) result."""
+    wl = W.schwefel_n100_fp32()
+    g = run(S, wl, exchange=0)
+    drift = np.abs(g["rec"]["f_win"] - g["rec"]["f_best"])
+    spread = np.ptp(g["rec"]["f_best"][-50:])
+    say(f"[fp32 drift] asynchronous run: max |f_win - f_best| {drift.max():.3e} (last level {drift[-1]:.3e}), "
+        f"spread of the last 50 winners' costs {spread:.3e}")
+    assert drift.max() < 1e-2

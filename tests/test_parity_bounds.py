@@ -1,9 +1,11 @@
-"""CPU checks of the FP32 error bounds the GPU parity tests use for the
-non-separable families (parity_util.eval_err32).
+"""CPU checks of the FP32 error bounds the GPU parity tests use for the full
+evaluation per move: the non-separable families, and the separable ones
+under SA_FLAG_FULL_EVAL (parity_util.eval_err32).
 
 The FP32 evaluation is emulated in numpy float32 in the kernels' operation
 order, with the hardware sine/cosine replaced by the FP64 value of the same
-FP32 revolution argument rounded to FP32 (an error below E_TRIG).  The bound
+FP32 revolution argument rounded to FP32 (an error below E_TRIG), and the
+hardware square root and 2^x by the correctly rounded FP32 values.  The bound
 must cover the emulation's error against the FP64 definition on random
 states, and must not be vacuous (a small fraction of the cost's scale).
 """
@@ -32,6 +34,39 @@ def emulate32(func, x, shift):
     def hw_sin_rev(t):
         return F32(np.sin(2 * np.pi * (np.float64(t) - np.round(np.float64(t)))))
 
+    def hw_sqrt(t):
+        return F32(np.sqrt(np.float64(t)))
+
+    def expm1_32(t):  # the kernels' FP32 e^t - 1
+        if abs(t) <= 0.5:
+            p = F32(1.0 / 362880.0)
+            for k in (40320.0, 5040.0, 720.0, 120.0, 24.0, 6.0, 2.0, 1.0):
+                p = fma(t, p, F32(1.0 / k))
+            return F32(t * p)
+        return F32(F32(np.exp2(np.float64(F32(t * F32(1.4426950408889634))))) - F32(1))
+
+    if func == O.SCHWEFEL:
+        acc = F32(0)
+        k = F32(1.0 / (4 * np.pi ** 2))
+        for i in range(n):
+            acc = fma(y[i], hw_sin_rev(hw_sqrt(F32(abs(y[i]) * k))), acc)
+        return float(F32(acc * F32(-1.0 / n)))
+    if func == O.RASTRIGIN:
+        acc = F32(0)
+        for i in range(n):
+            sp = hw_sin_rev(F32(0.5) * y[i])
+            acc = fma(y[i], y[i], fma(F32(F32(20) * sp), sp, acc))
+        return float(acc)
+    if func == O.ACKLEY:
+        s1, dd = F32(0), F32(0)
+        for i in range(n):
+            sp = hw_sin_rev(F32(0.5) * y[i])
+            s1 = fma(y[i], y[i], s1)
+            dd = fma(sp, sp, dd)
+        inv_n = F32(1.0 / n)
+        ea = expm1_32(F32(F32(-0.2) * hw_sqrt(F32(s1 * inv_n))))
+        eb = expm1_32(F32(F32(-2) * F32(dd * inv_n)))
+        return float(fma(F32(-20), ea, F32(-F32(np.e) * eb)))
     if func == O.GRIEWANK:
         c = (1.0 / (2 * np.pi * np.sqrt(np.arange(1, n + 1, dtype=np.float64)))).astype(np.float32)
         s, p = F32(0), F32(1)
@@ -63,7 +98,7 @@ def emulate32(func, x, shift):
     return float(acc)
 
 
-@pytest.mark.parametrize("func", [O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK])
+@pytest.mark.parametrize("func", [O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK, O.SCHWEFEL, O.RASTRIGIN, O.ACKLEY])
 @pytest.mark.parametrize("n,shifted", [(1, False), (2, True), (17, False), (100, True), (100, False)])
 def test_fp32_evaluation_within_bound(func, n, shifted):
     half = W.HALF_BOX[func]
@@ -74,15 +109,19 @@ def test_fp32_evaluation_within_bound(func, n, shifted):
         # states across the box, and near the minimiser (where the increments are small)
         scale = half if trial % 2 == 0 else half * 1e-3
         centre = (0.0 if shift is None else shift) + (1.0 if func == O.ROSENBROCK else
-                                                      -1.0 if func == O.LEVY_MONTALVO else 0.0)
+                                                      -1.0 if func == O.LEVY_MONTALVO else
+                                                      420.968746 if func == O.SCHWEFEL else 0.0)
         x = np.clip(centre + rng.uniform(-scale, scale, n), -half, half).astype(np.float32).astype(np.float64)
         exact = O.f(func, x, shift)
         err = abs(emulate32(func, x, shift) - exact)
         bound = eval_err32(func, x, shift)
         assert err <= bound, (trial, err, bound)
         worst = max(worst, err / bound if bound > 0 else 0.0)
-        # not vacuous: far below the cost's own scale
-        assert bound <= 1e-4 * max(1.0, abs(exact)) + (2e-3 if func == O.GRIEWANK else 0.0)
+        # not vacuous: far below the cost's own scale (Schwefel: that of its
+        # terms, -y sin(sqrt|y|)/n, which cancel in the sum)
+        size = max(1.0, abs(exact), float(np.mean(np.abs(x - (0.0 if shift is None else shift))))
+                   if func == O.SCHWEFEL else 0.0)
+        assert bound <= 1e-4 * size + (2e-3 if func == O.GRIEWANK else 0.0)
     print(f"func {func} n {n}: max err/bound {worst:.3f}")
 
 
