@@ -25,6 +25,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5
+SHEKEL5, SHEKEL7, SHEKEL10, FOXHOLES, LANGERMAN = 6, 7, 8, 9, 10  # centre families (Tests 18, 19, 11)
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 
 CFLAGS = ["-O2", "-shared", "-fPIC", "-fno-fast-math", "-ffp-contract=off", "-std=c11"]

@@ -59,6 +59,11 @@
 #define ORC_GRIEWANK 3
 #define ORC_LEVY_MONTALVO 4
 #define ORC_ROSENBROCK 5
+#define ORC_SHEKEL5 6
+#define ORC_SHEKEL7 7
+#define ORC_SHEKEL10 8
+#define ORC_FOXHOLES 9
+#define ORC_LANGERMAN 10
 
 #define ORC_TAG_MOVE 0u
 #define ORC_TAG_INIT 1u
@@ -217,6 +222,49 @@ static double y_at(const double *x, const double *s, uint32_t i, uint32_t d, dou
 }
 
 /*
+ * Tables of the centre families (Appendix: Test 18 Shekel, Test 19 modified
+ * Shekel foxholes, Test 11 modified Langerman), as printed there: row i is
+ * centre a_i, c_i its offset (Shekel, foxholes) or weight (Langerman).  The
+ * Langerman problem takes the first five rows of the foxholes tables, as its
+ * own printed tables are.
+ */
+static const double orc_shekel_c[10] = {0.1, 0.2, 0.2, 0.4, 0.4, 0.6, 0.3, 0.7, 0.5, 0.5};
+static const double orc_shekel_a[10][4] = {{4.0, 4.0, 4.0, 4.0}, {1.0, 1.0, 1.0, 1.0}, {8.0, 8.0, 8.0, 8.0}, {6.0, 6.0, 6.0, 6.0}, {3.0, 7.0, 3.0, 7.0}, {2.0, 9.0, 2.0, 9.0}, {5.0, 5.0, 3.0, 3.0}, {8.0, 1.0, 8.0, 1.0}, {6.0, 2.0, 6.0, 2.0}, {7.0, 3.6, 7.0, 3.6}};
+static const double orc_fox_c[30] = {0.806, 0.517, 0.1, 0.908, 0.965, 0.669, 0.524, 0.902, 0.531, 0.876, 0.462, 0.491, 0.463, 0.714, 0.352, 0.869, 0.813, 0.811, 0.828, 0.964, 0.789, 0.36, 0.369, 0.992, 0.332, 0.817, 0.632, 0.883, 0.608, 0.326};
+static const double orc_fox_a[30][10] = {
+    {9.681, 0.667, 4.783, 9.095, 3.517, 9.325, 6.544, 0.211, 5.122, 2.02},
+    {9.4, 2.041, 3.788, 7.931, 2.882, 2.672, 3.568, 1.284, 7.033, 7.374},
+    {8.025, 9.152, 5.114, 7.621, 4.564, 4.711, 2.996, 6.126, 0.734, 4.982},
+    {2.196, 0.415, 5.649, 6.979, 9.51, 9.166, 6.304, 6.054, 9.377, 1.426},
+    {8.074, 8.777, 3.467, 1.863, 6.708, 6.349, 4.534, 0.276, 7.633, 1.567},
+    {7.65, 5.658, 0.72, 2.764, 3.278, 5.283, 7.474, 6.274, 1.409, 8.208},
+    {1.256, 3.605, 8.623, 6.905, 4.584, 8.133, 6.071, 6.888, 4.187, 5.448},
+    {8.314, 2.261, 4.224, 1.781, 4.124, 0.932, 8.129, 8.658, 1.208, 5.762},
+    {0.226, 8.858, 1.42, 0.945, 1.622, 4.698, 6.228, 9.096, 0.972, 7.637},
+    {7.305, 2.228, 1.242, 5.928, 9.133, 1.826, 4.06, 5.204, 8.713, 8.247},
+    {0.652, 7.027, 0.508, 4.876, 8.807, 4.632, 5.808, 6.937, 3.291, 7.016},
+    {2.699, 3.516, 5.874, 4.119, 4.461, 7.496, 8.817, 0.69, 6.593, 9.789},
+    {8.327, 3.897, 2.017, 9.57, 9.825, 1.15, 1.395, 3.885, 6.354, 0.109},
+    {2.132, 7.006, 7.136, 2.641, 1.882, 5.943, 7.273, 7.691, 2.88, 0.564},
+    {4.707, 5.579, 4.08, 0.581, 9.698, 8.542, 8.077, 8.515, 9.231, 4.67},
+    {8.304, 7.559, 8.567, 0.322, 7.128, 8.392, 1.472, 8.524, 2.277, 7.826},
+    {8.632, 4.409, 4.832, 5.768, 7.05, 6.715, 1.711, 4.323, 4.405, 4.591},
+    {4.887, 9.112, 0.17, 8.967, 9.693, 9.867, 7.508, 7.77, 8.382, 6.74},
+    {2.44, 6.686, 4.299, 1.007, 7.008, 1.427, 9.398, 8.48, 9.95, 1.675},
+    {6.306, 8.583, 6.084, 1.138, 4.35, 3.134, 7.853, 6.061, 7.457, 2.258},
+    {0.652, 2.343, 1.37, 0.821, 1.31, 1.063, 0.689, 8.819, 8.833, 9.07},
+    {5.558, 1.272, 5.756, 9.857, 2.279, 2.764, 1.284, 1.677, 1.244, 1.234},
+    {3.352, 7.549, 9.817, 9.437, 8.687, 4.167, 2.57, 6.54, 0.228, 0.027},
+    {8.798, 0.88, 2.37, 0.168, 1.701, 3.68, 1.231, 2.39, 2.499, 0.064},
+    {1.46, 8.057, 1.336, 7.217, 7.914, 3.615, 9.981, 9.198, 5.292, 1.224},
+    {0.432, 8.645, 8.774, 0.249, 8.081, 7.461, 4.416, 0.652, 4.002, 4.644},
+    {0.679, 2.8, 5.523, 3.049, 2.968, 7.225, 6.73, 4.199, 9.614, 9.229},
+    {4.263, 1.074, 7.286, 5.599, 8.291, 5.2, 9.214, 8.272, 4.398, 4.506},
+    {9.496, 4.83, 3.15, 8.27, 5.079, 1.231, 5.731, 9.494, 1.883, 9.732},
+    {4.138, 2.562, 2.532, 9.661, 5.611, 5.5, 6.886, 2.341, 9.699, 6.5},
+};
+
+/*
  * The non-separable families, evaluated in full (the paper's move evaluates
  * f(x1) in full, Sec. 3.3).  Coordinate d may be replaced by xdn (d >= n:
  * none).  Sums and products run over the coordinates in order 1..n.
@@ -231,6 +279,13 @@ static double y_at(const double *x, const double *s, uint32_t i, uint32_t d, dou
  *     sum_{i<n} [100 (y_{i+1} - y_i^2)^2 + (1 - y_i)^2].  The printed form has
  *     (y_{i+1} - y_i)^2; the named function (De Jong's second) squares y_i,
  *     and both have the stated minimum 0 at (1, ..., 1).
+ *   The centre families, n = 4 for Shekel and n <= 10 otherwise (the tables'
+ *   width), centres in table order, coordinates in order:
+ *     Shekel with m = 5, 7, 10 (Test 18) and the modified foxholes (Test 19,
+ *     m = 30): -sum_{i<m} 1 / (sum_j (y_j - a_ij)^2 + c_i);
+ *     modified Langerman (Test 11, m = 5):
+ *     -sum_{i<m} c_i exp(-(1/pi) sum_j (y_j - a_ij)^2) cos(pi sum_j (y_j - a_ij)^2).
+ *   Other n: NaN.
  */
 static double f_coupled(int func, uint32_t n, const double *x, const double *s, uint32_t d, double xdn)
 {
@@ -263,6 +318,27 @@ static double f_coupled(int func, uint32_t n, const double *x, const double *s, 
             acc += 100.0 * (b - a * a) * (b - a * a) + (1.0 - a) * (1.0 - a);
         }
         return acc;
+    }
+    if (func >= ORC_SHEKEL5 && func <= ORC_LANGERMAN) {
+        /* squared distance to each centre a_i over the n coordinates, then
+         * Shekel / foxholes: -sum_i 1 / (|y - a_i|^2 + c_i);
+         * Langerman:         -sum_i c_i exp(-|y - a_i|^2 / pi) cos(pi |y - a_i|^2). */
+        const int shekel = func <= ORC_SHEKEL10;
+        const uint32_t m = func == ORC_SHEKEL5 ? 5 : func == ORC_SHEKEL7 ? 7 : func == ORC_SHEKEL10 ? 10
+                         : func == ORC_FOXHOLES ? 30 : 5;
+        if (shekel ? n != 4 : n > 10) return NAN;
+        double acc = 0.0;
+        for (uint32_t i = 0; i < m; ++i) {
+            const double *a = shekel ? orc_shekel_a[i] : orc_fox_a[i];
+            const double c = shekel ? orc_shekel_c[i] : orc_fox_c[i];
+            double dd = 0.0;
+            for (uint32_t j = 0; j < n; ++j) {
+                const double t = y_at(x, s, j, d, xdn) - a[j];
+                dd += t * t;
+            }
+            acc += func == ORC_LANGERMAN ? c * exp(-dd / ORC_PI) * cos(ORC_PI * dd) : 1.0 / (dd + c);
+        }
+        return -acc;
     }
     return NAN;
 }
