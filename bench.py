@@ -359,7 +359,9 @@ def extra_workloads():
     64 steps, shifted), the n = 100 Griewank run (65536 chains, 200 levels x
     100 steps; non-separable: every move re-evaluates f in full), the n = 100
     Schwefel run with a full evaluation of f per move as the paper's kernel
-    does (SA_FLAG_FULL_EVAL) instead of the increment, and 1024
+    does (SA_FLAG_FULL_EVAL) instead of the increment, the Shekel (m = 10,
+    n = 4) and foxholes (n = 5) runs (65536 chains, 200 levels x 100 steps;
+    centre families, evaluated in full per move), and 1024
     batched problems (n ~ U{2..256}, 500 levels
     x 64 steps, chains per problem and waves per workgroup from the
     autotuner)."""
@@ -367,7 +369,8 @@ def extra_workloads():
     from paper_2408_00018_amd import sa
     out = {}
     full_eval = W.schwefel_n100_fp32().with_(name="schwefel_n100_fp32_full_eval")
-    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32(), W.griewank_n100_fp32(), full_eval):
+    for wl in (W.rastrigin_n512_fp32(), W.ackley_n1024_fp32(), W.griewank_n100_fp32(), full_eval,
+               W.shekel10_n4_fp32(), W.foxholes_n5_fp32()):
         sched = sa.Schedule(chains=wl.chains, levels=wl.levels, steps=wl.steps, T0=wl.T0, alpha=wl.alpha,
                             seed=wl.seed, precision=sa.FP32, graph=True, full_eval=wl is full_eval)
         with sa.Annealer(wl.func, wl.lower, wl.upper, wl.shift, schedule=sched) as ann:

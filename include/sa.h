@@ -46,9 +46,18 @@
  *                     w_i = 1 + (y_i + 1)/4                   (Appendix, Test 10)
  *   SA_ROSENBROCK f = sum_{i<n} [100 (y_{i+1} - y_i^2)^2 + (1 - y_i)^2]
  *                                                             (Appendix, Test 14)
+ *   Centre families, d_i = sum_j (y_j - a_ij)^2 over the appendix's tables of
+ *   centres a_i and constants c_i, centres in table order:
+ *   SA_SHEKEL5, SA_SHEKEL7, SA_SHEKEL10  f = -sum_{i<m} 1 / (d_i + c_i),
+ *                     m = 5, 7, 10; n = 4                     (Appendix, Test 18)
+ *   SA_FOXHOLES   f = -sum_{i<30} 1 / (d_i + c_i), n <= 10  (Appendix, Test 19)
+ *   SA_LANGERMAN  f = -sum_{i<5} c_i exp(-d_i / pi) cos(pi d_i), n <= 10, the
+ *                     first five centres and constants of the foxholes
+ *                     tables                                  (Appendix, Test 11)
+ *   Other n for these: SA_ERR_INVALID.
  * The first three are sums of per-coordinate terms (Ackley through its two
  * sums), so a move updates the cost by the changed coordinate's terms; the
- * other three are not, and every move evaluates f(x') in full, as the paper's
+ * others are not, and every move evaluates f(x') in full, as the paper's
  * kernel does for every function (Sec. 3.3).  The printed Griewank form puts
  * the product inside the sum and the printed Rosenbrock form squares
  * (y_{i+1} - y_i); the forms above are the named functions, with the stated
@@ -114,7 +123,12 @@ typedef enum {
     SA_ACKLEY = 2,
     SA_GRIEWANK = 3,      /* non-separable: every move re-evaluates f in full */
     SA_LEVY_MONTALVO = 4, /* non-separable */
-    SA_ROSENBROCK = 5     /* non-separable */
+    SA_ROSENBROCK = 5,    /* non-separable */
+    SA_SHEKEL5 = 6,       /* non-separable centre families */
+    SA_SHEKEL7 = 7,
+    SA_SHEKEL10 = 8,
+    SA_FOXHOLES = 9,
+    SA_LANGERMAN = 10
 } sa_func;
 typedef enum { SA_FP32 = 0, SA_FP64 = 1 } sa_precision;
 typedef enum { SA_MOVE_RADIUS = 0, SA_MOVE_RESAMPLE = 1 } sa_move;

@@ -73,6 +73,8 @@ def lib():
         L.orc_ackley_from_sums.restype = _d
         L.orc_f.argtypes = [_i, _u32, _p, _p]
         L.orc_f.restype = _d
+        L.orc_centres.argtypes = [_i, _p, _p]
+        L.orc_centres.restype = _u32
         L.orc_accept.argtypes = [_d, _d, _d]
         L.orc_accept.restype = _i
         L.orc_neighbour.argtypes = [_i, _d, _d, _d, _d, _d]
@@ -181,6 +183,15 @@ def f(func, x, shift=None):
     x = _f64(x)
     s = _f64(shift)
     return lib().orc_f(func, x.size, _ptr(x), _ptr(s))
+
+
+def centres(func):
+    """(a [m, 10], c [m]) of a centre family's table (Shekel's last six
+    coordinates zero); None for another function."""
+    a = np.zeros((30, 10))
+    c = np.zeros(30)
+    m = lib().orc_centres(func, _ptr(a), _ptr(c))
+    return (a[:m], c[:m]) if m else None
 
 
 def schwefel_term(y):

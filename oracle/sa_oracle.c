@@ -226,7 +226,8 @@ static double y_at(const double *x, const double *s, uint32_t i, uint32_t d, dou
  * Shekel foxholes, Test 11 modified Langerman), as printed there: row i is
  * centre a_i, c_i its offset (Shekel, foxholes) or weight (Langerman).  The
  * Langerman problem takes the first five rows of the foxholes tables, as its
- * own printed tables are.
+ * own printed tables are.  Parity unpinned for columns 6-10 of the foxholes
+ * table: the appendix prints minima at n = 2 and 5 only.
  */
 static const double orc_shekel_c[10] = {0.1, 0.2, 0.2, 0.4, 0.4, 0.6, 0.3, 0.7, 0.5, 0.5};
 static const double orc_shekel_a[10][4] = {{4.0, 4.0, 4.0, 4.0}, {1.0, 1.0, 1.0, 1.0}, {8.0, 8.0, 8.0, 8.0}, {6.0, 6.0, 6.0, 6.0}, {3.0, 7.0, 3.0, 7.0}, {2.0, 9.0, 2.0, 9.0}, {5.0, 5.0, 3.0, 3.0}, {8.0, 1.0, 8.0, 1.0}, {6.0, 2.0, 6.0, 2.0}, {7.0, 3.6, 7.0, 3.6}};
@@ -341,6 +342,23 @@ static double f_coupled(int func, uint32_t n, const double *x, const double *s, 
         return -acc;
     }
     return NAN;
+}
+
+/* Table of a centre family: writes its m centres (10 coordinates each,
+ * Shekel's last six zero) to a[m][10] and constants to c[m] when they are
+ * not NULL; returns m, or 0 for another function id. */
+uint32_t orc_centres(int func, double *a, double *c)
+{
+    if (func < ORC_SHEKEL5 || func > ORC_LANGERMAN) return 0;
+    const int shekel = func <= ORC_SHEKEL10;
+    const uint32_t m = func == ORC_SHEKEL5 ? 5 : func == ORC_SHEKEL7 ? 7 : func == ORC_SHEKEL10 ? 10
+                     : func == ORC_FOXHOLES ? 30 : 5;
+    for (uint32_t i = 0; i < m; ++i) {
+        for (uint32_t j = 0; j < 10; ++j)
+            if (a) a[i * 10 + j] = shekel ? (j < 4 ? orc_shekel_a[i][j] : 0.0) : orc_fox_a[i][j];
+        if (c) c[i] = shekel ? orc_shekel_c[i] : orc_fox_c[i];
+    }
+    return m;
 }
 
 /* Full evaluation, summing the coordinates in order 0..n-1. */

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(256) probe_kernel(int kind, int iters, uint32_
 // instructions take revolutions), 2 sqrt(t), 3 2^t; 4 e^t - 1 as the FP32
 // Ackley increment computes it (sa::expm1_f32); 5 the FP32 GELU of the
 // Gaussian proposal network and 6 its derivative (sa::mlp::act, act_grad);
-// 7 log2(t) (v_log_f32).
+// 7 log2(t) (v_log_f32); 8 1/t (v_rcp_f32, the centre families' terms).
 __global__ void __launch_bounds__(256) accuracy_kernel(int op, const float *in, float *out, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -114,7 +114,8 @@ __global__ void __launch_bounds__(256) accuracy_kernel(int op, const float *in, 
     case 4: r = sa::expm1_f32(t); break;
     case 5: r = sa::mlp::act(t, sa::mlp::kNetGeluGauss); break;
     case 6: r = sa::mlp::act_grad(t, sa::mlp::kNetGeluGauss); break;
-    default: r = __builtin_amdgcn_logf(t); break;
+    case 7: r = __builtin_amdgcn_logf(t); break;
+    default: r = __builtin_amdgcn_rcpf(t); break;
     }
     out[i] = r;
 }
@@ -128,7 +129,7 @@ extern "C" {
 // the instructions' error against an FP64 evaluation of the same inputs.
 int sa_peak_accuracy(int op, const float *in, float *out, uint32_t n)
 {
-    if (op < 0 || op > 7 || !in || !out) return -1;
+    if (op < 0 || op > 8 || !in || !out) return -1;
     if (n == 0) return 0;
     hipLaunchKernelGGL(accuracy_kernel, dim3((n + 255) / 256), dim3(256), 0, 0, op, in, out, n);
     if (hipGetLastError() != hipSuccess) return -3;

@@ -23,6 +23,8 @@
 //   Levy-Montalvo   (pi/n) [10 sin^2(pi w_1) + sum_{i<n} (w_i - 1)^2
 //                   (1 + 10 sin^2(pi w_{i+1})) + (w_n - 1)^2],  w = 1 + (y + 1)/4
 //   Rosenbrock      sum_{i<n} [100 (y_{i+1} - y_i^2)^2 + (1 - y_i)^2]
+//   Shekel (m = 5, 7, 10), foxholes, Langerman: sums over table centres
+//                   (sa_centres.hpp), Appendix Tests 18, 19, 11
 // The printed Griewank puts the product inside the sum and the printed
 // Rosenbrock squares (y_{i+1} - y_i); both are read as the named functions
 // (the forms above), whose stated minima (0 at the origin, 0 at (1,...,1))
@@ -43,6 +45,7 @@
 #include "sa_internal.hpp"
 #include "sa_step.hpp"
 #include "sa_level_common.hpp"
+#include "sa_centres.hpp"
 
 namespace sa {
 
@@ -78,6 +81,17 @@ template <int F, typename YFn> __device__ double coupled_f64(uint32_t n, const Y
         }
         acc += (w0 - 1.0) * (w0 - 1.0);
         return kPi / (double)n * acc;
+    } else if constexpr (kCentreFamily<F>) {
+        double acc = 0.0;
+        for (uint32_t i = 0; i < kCentres<F>; ++i) {
+            double d = 0.0;
+            for (uint32_t j = 0; j < n; ++j) {
+                const double t = y(j) - centre_a64<F>(i, j);
+                d += t * t;
+            }
+            acc += centre_term64<F>(i, d);
+        }
+        return -acc;
     } else {
         double acc = 0.0;
         for (uint32_t i = 0; i + 1 < n; ++i) {
@@ -85,6 +99,22 @@ template <int F, typename YFn> __device__ double coupled_f64(uint32_t n, const Y
             acc += 100.0 * (b - a * a) * (b - a * a) + (1.0 - a) * (1.0 - a);
         }
         return acc;
+    }
+}
+
+// FP32 term i of a centre family from its squared distance d: 1/(d + c_i) on
+// the hardware reciprocal, or Langerman's c_i e^(-d/pi) cos(pi d) with
+// cos(pi d) = cos_rev(d/2) taken on the argument reduced to [-1/2, 1/2]
+// revolutions (exact: d/2 minus its nearest integer).
+template <int F> __device__ __forceinline__ float centre_term32(uint32_t i, float d)
+{
+    if constexpr (F == kLangerman) {
+        constexpr float kNegLog2eOverPi = (float)(-1.44269504088896340736 / 3.14159265358979323846);
+        const float h = 0.5f * d;
+        const float r = h - __builtin_rintf(h);
+        return centre_c32<F>(i) * hw_exp2(d * kNegLog2eOverPi) * hw_cos_rev(r);
+    } else {
+        return __builtin_amdgcn_rcpf(d + centre_c32<F>(i));
     }
 }
 
@@ -187,6 +217,26 @@ __device__ __forceinline__ float coupled_f32(const float *col, uint32_t stride, 
         }
         acc = fmaf(vp, vp, acc);
         return acc * scale;
+    } else if constexpr (kCentreFamily<F>) {
+        // the chain's coordinates in registers (n <= 4 for Shekel, <= 10
+        // otherwise), then the centres in table order
+        constexpr uint32_t J = kShekelTable<F> ? 4u : 10u;
+        float yv[J];
+#pragma unroll
+        for (uint32_t j = 0; j < J; ++j) yv[j] = j < n ? col[j * st] - sh(j) : 0.0f;
+        float acc = 0.0f;
+        for (uint32_t i = 0; i < kCentres<F>; ++i) {
+            float d = 0.0f;
+#pragma unroll
+            for (uint32_t j = 0; j < J; ++j) {
+                if (j < n) {
+                    const float t = yv[j] - centre_a32<F>(i, j);
+                    d = fmaf(t, t, d);
+                }
+            }
+            acc += centre_term32<F>(i, d);
+        }
+        return -acc;
     } else {
         float acc = 0.0f;
         float a = col[0] - sh(0);
@@ -224,6 +274,18 @@ __device__ double coupled_full_wg(const LevelArgs<R> &a, const R *tab, const R *
             acc.a = wave_sum_d(acc.a);
             acc.b = wave_sum_d(acc.b);
             v = acc.finish(n).f;
+        } else if constexpr (kCentreFamily<F>) {
+            // lanes over the centres
+            double s = 0.0;
+            for (uint32_t i = tid; i < kCentres<F>; i += 64) {
+                double d = 0.0;
+                for (uint32_t j = 0; j < n; ++j) {
+                    const double t = y(j) - centre_a64<F>(i, j);
+                    d += t * t;
+                }
+                s += centre_term64<F>(i, d);
+            }
+            v = -wave_sum_d(s);
         } else if constexpr (F == kGriewank) {
             double s = 0.0, p = 1.0;
             for (uint32_t i = tid; i < n; i += 64) {
@@ -499,6 +561,11 @@ static hipError_t dispatch(int func, bool table, bool log, const LevelArgs<R> &a
     case kGriewank: return dispatch_f<R, kGriewank>(table, log, a, level, prev, groups, s);
     case kLevyMontalvo: return dispatch_f<R, kLevyMontalvo>(table, log, a, level, prev, groups, s);
     case kRosenbrock: return dispatch_f<R, kRosenbrock>(table, log, a, level, prev, groups, s);
+    case kShekel5: return dispatch_f<R, kShekel5>(table, log, a, level, prev, groups, s);
+    case kShekel7: return dispatch_f<R, kShekel7>(table, log, a, level, prev, groups, s);
+    case kShekel10: return dispatch_f<R, kShekel10>(table, log, a, level, prev, groups, s);
+    case kFoxholes: return dispatch_f<R, kFoxholes>(table, log, a, level, prev, groups, s);
+    case kLangerman: return dispatch_f<R, kLangerman>(table, log, a, level, prev, groups, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -82,8 +82,13 @@ inline bool separable(uint32_t func) { return func <= SA_ACKLEY; }
 inline sa_status validate_problem(const sa_problem *p, uint32_t index)
 {
     if (!p) return fail(SA_ERR_INVALID, "problem %u is NULL", index);
-    if (p->func > SA_ROSENBROCK) return fail(SA_ERR_INVALID, "problem %u: unknown function id %u", index, p->func);
+    if (p->func > SA_LANGERMAN) return fail(SA_ERR_INVALID, "problem %u: unknown function id %u", index, p->func);
     if (p->n == 0) return fail(SA_ERR_INVALID, "problem %u: dimension n must be >= 1", index);
+    if (p->func >= SA_SHEKEL5 && p->func <= SA_SHEKEL10 && p->n != 4)
+        return fail(SA_ERR_INVALID, "problem %u: the Shekel functions take n = 4 (got %u)", index, p->n);
+    if ((p->func == SA_FOXHOLES || p->func == SA_LANGERMAN) && p->n > 10)
+        return fail(SA_ERR_INVALID, "problem %u: the foxholes and Langerman tables hold n <= 10 (got %u)", index,
+                    p->n);
     if (!p->lower || !p->upper) return fail(SA_ERR_INVALID, "problem %u: lower/upper must not be NULL", index);
     for (uint32_t i = 0; i < p->n; ++i) {
         if (!std::isfinite(p->lower[i]) || !std::isfinite(p->upper[i]))

@@ -36,6 +36,7 @@
 #include <cstring>
 #include <vector>
 
+#include "sa_centres.hpp"
 #include "sa_host.hpp"
 
 namespace {
@@ -47,7 +48,7 @@ constexpr double kE = 2.71828182845904523536;
 constexpr uint32_t kLanes = 64;
 
 struct NmArgs {
-    uint32_t func, n, maxiter, log_steps;
+    uint32_t func, n, maxiter, log_steps, nterms;
     double ftol, xtol;
     const double *lower, *upper, *shift;  // n each (shift may be null)
     const double *x0;                     // starts x n
@@ -69,7 +70,18 @@ template <int F>
 __device__ double nm_eval(const NmArgs &a, const double *x, double *t0, double *t1, double *bcast)
 {
     const uint32_t lane = threadIdx.x, n = a.n;
-    for (uint32_t i = lane; i < n; i += kLanes) {
+    if constexpr (sa::kCentreFamily<F>) {
+        // centre families: term i (one per table centre) on lane i
+        for (uint32_t i = lane; i < sa::kCentres<F>; i += kLanes) {
+            double d = 0.0;
+            for (uint32_t j = 0; j < n; ++j) {
+                const double t = y_of(a, x, j) - sa::centre_a64<F>(i, j);
+                d += t * t;
+            }
+            t0[i] = sa::centre_term64<F>(i, d);
+        }
+    }
+    for (uint32_t i = lane; i < (sa::kCentreFamily<F> ? 0u : n); i += kLanes) {
         const double y = y_of(a, x, i);
         if constexpr (F == SA_SCHWEFEL) {
             t0[i] = y * sin(sqrt(fabs(y)));
@@ -123,6 +135,10 @@ __device__ double nm_eval(const NmArgs &a, const double *x, double *t0, double *
                 prod *= t1[i];
             }
             v = 1.0 + sum - prod;
+        } else if constexpr (sa::kCentreFamily<F>) {
+            double acc = 0.0;
+            for (uint32_t i = 0; i < sa::kCentres<F>; ++i) acc += t0[i];
+            v = -acc;
         } else if constexpr (F == SA_LEVY_MONTALVO) {
             const double sp = sin(kPi * t1[0]);
             double acc = 10.0 * sp * sp;
@@ -199,9 +215,9 @@ __global__ void __launch_bounds__(64) nm_kernel(const NmArgs a)
     double *xm = lds;        // n
     double *xr = xm + n;     // n
     double *xt = xr + n;     // n
-    double *t0 = xt + n;     // n
-    double *t1 = t0 + n;     // n
-    double *fv = t1 + n;     // n + 1 vertex costs
+    double *t0 = xt + n;     // terms (nm_terms(n))
+    double *t1 = t0 + a.nterms;
+    double *fv = t1 + a.nterms;  // n + 1 vertex costs
     double *bc = fv + m;     // 1
     double *V = a.V + (size_t)k * m * n;
     const double *x0 = a.x0 + (size_t)k * n;
@@ -329,7 +345,10 @@ __global__ void __launch_bounds__(64) nm_kernel(const NmArgs a)
     }
 }
 
-size_t nm_lds_bytes(uint32_t n) { return (6 * (size_t)n + 2) * sizeof(double); }
+// Per-term scratch (t0, t1): one entry per coordinate, or per centre of the
+// centre families (at most 30).
+uint32_t nm_terms(uint32_t n) { return std::max<uint32_t>(n, 30u); }
+size_t nm_lds_bytes(uint32_t n) { return (4 * (size_t)n + 2 * (size_t)nm_terms(n) + 2) * sizeof(double); }
 
 struct NmLayout {
     size_t lower, upper, shift, x0, V, x_out, f_out, iters, evals, steps, total;
@@ -384,7 +403,12 @@ hipError_t launch(const NmArgs &a, uint32_t starts, hipStream_t s)
     case SA_ACKLEY: return launch_f<SA_ACKLEY>(a, starts, s);
     case SA_GRIEWANK: return launch_f<SA_GRIEWANK>(a, starts, s);
     case SA_LEVY_MONTALVO: return launch_f<SA_LEVY_MONTALVO>(a, starts, s);
-    default: return launch_f<SA_ROSENBROCK>(a, starts, s);
+    case SA_ROSENBROCK: return launch_f<SA_ROSENBROCK>(a, starts, s);
+    case SA_SHEKEL5: return launch_f<SA_SHEKEL5>(a, starts, s);
+    case SA_SHEKEL7: return launch_f<SA_SHEKEL7>(a, starts, s);
+    case SA_SHEKEL10: return launch_f<SA_SHEKEL10>(a, starts, s);
+    case SA_FOXHOLES: return launch_f<SA_FOXHOLES>(a, starts, s);
+    default: return launch_f<SA_LANGERMAN>(a, starts, s);
     }
 }
 
@@ -454,6 +478,7 @@ sa_status sa_nm_polish(const sa_problem *prob, const double *x0, uint32_t starts
     NmArgs a{};
     a.func = prob->func;
     a.n = n;
+    a.nterms = nm_terms(n);
     a.maxiter = cfg->maxiter;
     a.log_steps = log_steps;
     a.ftol = cfg->ftol;

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libsa_hip.so")
 
 SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5  # non-separable: full re-evaluation per move
+SHEKEL5, SHEKEL7, SHEKEL10, FOXHOLES, LANGERMAN = 6, 7, 8, 9, 10  # centre families (non-separable)
 FP32, FP64 = 0, 1
 MOVE_RADIUS, MOVE_RESAMPLE = 0, 1
 FLAG_TRACE_X, FLAG_GRAPH, FLAG_LEARNED, FLAG_OVERLAY = 0x1, 0x2, 0x4, 0x8

@@ -29,6 +29,9 @@ E_EXPM1 = 2.0 ** -20
 # v_log_f32, relative, over (0, 1] (the Box-Muller radius of the Gaussian
 # proposal network; tests/test_gpu_trig.py)
 E_LOG2 = 2.0 ** -21
+# v_rcp_f32, relative (the centre families' 1/(d + c); documented as 1 ulp,
+# checked by tests/test_gpu_trig.py)
+E_RCP = 2.0 ** -22
 
 
 def f32(v):
@@ -46,7 +49,8 @@ def box32(lower, upper):
     return l32.astype(np.float64), h32.astype(np.float64)
 
 
-COUPLED = (O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK)
+CENTRE_FAMILIES = (O.SHEKEL5, O.SHEKEL7, O.SHEKEL10, O.FOXHOLES, O.LANGERMAN)
+COUPLED = (O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK) + CENTRE_FAMILIES
 
 
 def eval_err32(func, x, shift):
@@ -62,7 +66,11 @@ def eval_err32(func, x, shift):
       Levy         h = fma(y, 1/8, 1/8) = v/2; S = sin_rev(h);
                    acc = fma(v_prev^2, fma(10 S, S, 1), acc); f = acc fl(pi/n)
       Rosenbrock   t = fma(-a, a, b); acc = fma(100 t, t, acc); acc = fma(u, u, acc)
-    Every rounding contributes U32 times the magnitude of its result, the
+      centres      per centre i: t = y - fl(a_ij); d = fma(t, t, d) over j; then
+                   Shekel/foxholes  acc += rcp(d + fl(c_i));
+                   Langerman        acc += fl(c_i) exp2(d fl(-log2(e)/pi)) cos_rev(d/2 - rint(d/2));
+                   f = -acc
+    (v_rcp_f32 relative error E_RCP.)  Every rounding contributes U32 times the magnitude of its result, the
     hardware sine/cosine E_TRIG (E_TRIG_WIDE past 64 revolutions) absolutely,
     sqrt E_SQRT and e^x - 1 E_EXPM1 relatively, and errors propagate through
     first derivatives.  Sums of n roundings are bounded by n U32 times the sum
@@ -104,6 +112,29 @@ def eval_err32(func, x, shift):
         deb = math.exp(b) * db + E_EXPM1 * abs(eb)
         f = -20 * ea - math.e * eb
         return 20 * dea + math.e * deb + 2 * U32 * math.e * abs(eb) + U32 * abs(f)
+    if func in CENTRE_FAMILIES:
+        A, C = O.centres(func)
+        A = A[:, :n]
+        T = y[None, :] - A
+        dT = dy[None, :] + U32 * np.abs(A) + U32 * np.abs(T)
+        D = np.sum(T * T, axis=1)
+        dD = np.sum(2 * np.abs(T) * dT, axis=1) + n * U32 * D
+        if func == O.LANGERMAN:
+            K = math.log2(math.e) / math.pi
+            e = np.exp(-D / math.pi)
+            cs = np.cos(math.pi * D)
+            de = e * (math.log(2) * (K * dD + 2 * U32 * K * D) + E_EXP2)
+            dcs = math.pi * dD + E_TRIG
+            term = C * e * cs
+            dterm = C * (de * np.abs(cs) + e * dcs) + U32 * C * e * np.abs(cs) + 2 * U32 * np.abs(term)
+        else:
+            u = D + C
+            r = 1.0 / u
+            du = dD + U32 * C + U32 * u
+            term = r
+            dterm = r * r * du + E_RCP * r
+        m = C.size
+        return float(np.sum(dterm)) + m * U32 * float(np.sum(np.abs(term)))
     if func == O.GRIEWANK:
         idx = np.arange(1, n + 1, dtype=np.float64)
         th = y / np.sqrt(idx)

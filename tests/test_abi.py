@@ -88,7 +88,14 @@ def test_invalid_problems_are_rejected(S):
     wl = W.schwefel_n4_fp64()
     sched = S.Schedule(chains=64, levels=2, steps=2, T0=1.0, alpha=0.9)
     with pytest.raises(S.SAError):
-        S.workspace_bytes(9, wl.lower, wl.upper, None, sched)
+        S.workspace_bytes(11, wl.lower, wl.upper, None, sched)
+    # the centre families' tables fix n = 4 (Shekel) and n <= 10
+    for func, n in ((S.SHEKEL5, 3), (S.SHEKEL10, 5), (S.FOXHOLES, 11), (S.LANGERMAN, 11)):
+        with pytest.raises(S.SAError) as e:
+            S.workspace_bytes(func, np.zeros(n), np.full(n, 10.0), None, sched)
+        assert e.value.status == -1
+    for func, n in ((S.SHEKEL7, 4), (S.FOXHOLES, 10), (S.LANGERMAN, 1)):
+        S.workspace_bytes(func, np.zeros(n), np.full(n, 10.0), None, sched)
     with pytest.raises(S.SAError):
         S.workspace_bytes(0, wl.upper, wl.lower, None, sched)
     with pytest.raises(S.SAError):
@@ -178,7 +185,7 @@ def test_non_separable_families(S):
         S.workspace_bytes(W.ROSENBROCK, lo, hi, None, sched)
     assert e.value.status == -5
     with pytest.raises(S.SAError) as e:
-        S.workspace_bytes(6, lo[:4], hi[:4], None, sched)
+        S.workspace_bytes(11, lo[:4], hi[:4], None, sched)
     assert e.value.status == -1
     bs = S.BatchSchedule(levels=2, steps=2, T0=1.0, alpha=0.9)
     with pytest.raises(S.SAError) as e:

@@ -133,6 +133,20 @@ def test_log2_relative_error(probe):
     assert err <= P.E_LOG2
 
 
+def test_rcp_relative_error(probe):
+    """v_rcp_f32 over the arguments the centre families give it (d + c with
+    c >= 0.1 and d up to a few thousand), log-uniform, and every FP32 value
+    of one binade: within E_RCP relative."""
+    rng = np.random.default_rng(9)
+    x = np.exp(rng.uniform(np.log(0.05), np.log(4096.0), 1 << 22)).astype(np.float32)
+    one = (1.0 + np.arange(1 << 23, dtype=np.float64) * 2.0 ** -23).astype(np.float32)
+    x = np.concatenate([x, one])
+    ref = 1.0 / x.astype(np.float64)
+    err = np.max(np.abs(probe(8, x) - ref) / ref)
+    say(f"[trig] rcp: max relative error {err:.3e} ({err / 2 ** -24:.2f} x 2^-24); E_RCP = {P.E_RCP:.3e}")
+    assert err <= P.E_RCP
+
+
 def test_gelu_within_the_oracle_device_bound(probe):
     """The device GELU (FP32, Abramowitz-Stegun 26.2.17 for the normal
     distribution function) against the exact x Phi(x) in FP64: within the

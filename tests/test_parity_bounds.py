@@ -45,6 +45,24 @@ def emulate32(func, x, shift):
             return F32(t * p)
         return F32(F32(np.exp2(np.float64(F32(t * F32(1.4426950408889634))))) - F32(1))
 
+    if func in (O.SHEKEL5, O.SHEKEL7, O.SHEKEL10, O.FOXHOLES, O.LANGERMAN):
+        A, C = O.centres(func)
+        A32, C32 = A.astype(np.float32), C.astype(np.float32)
+        acc = F32(0)
+        for i in range(C.size):
+            d = F32(0)
+            for j in range(n):
+                t = F32(y[j] - A32[i, j])
+                d = fma(t, t, d)
+            if func == O.LANGERMAN:
+                h = F32(F32(0.5) * d)
+                r = F32(h - F32(np.rint(h)))
+                e = F32(np.exp2(np.float64(F32(d * F32(-np.log2(np.e) / np.pi)))))
+                term = F32(F32(C32[i] * e) * hw_cos_rev(r))
+            else:
+                term = F32(1.0 / np.float64(F32(d + C32[i])))
+            acc = F32(acc + term)
+        return float(-acc)
     if func == O.SCHWEFEL:
         acc = F32(0)
         k = F32(1.0 / (4 * np.pi ** 2))
@@ -96,6 +114,33 @@ def emulate32(func, x, shift):
         acc = fma(u, u, acc)
         a = b
     return float(acc)
+
+
+@pytest.mark.parametrize("func,n,shifted", [(O.SHEKEL5, 4, False), (O.SHEKEL7, 4, True), (O.SHEKEL10, 4, False),
+                                            (O.FOXHOLES, 2, False), (O.FOXHOLES, 5, True), (O.FOXHOLES, 10, False),
+                                            (O.LANGERMAN, 2, False), (O.LANGERMAN, 5, True),
+                                            (O.LANGERMAN, 10, False)])
+def test_fp32_centre_evaluation_within_bound(func, n, shifted):
+    """The centre families on their boxes, near their table centres (where
+    the terms peak) and across the box."""
+    lo, hi = W.CENTRE_BOX[func]
+    A, _ = O.centres(func)
+    rng = np.random.default_rng(100 * func + n)
+    worst = 0.0
+    for trial in range(24):
+        shift = rng.uniform(-0.5, 0.5, n).astype(np.float32).astype(np.float64) if shifted else None
+        if trial % 2:
+            x = A[rng.integers(A.shape[0]), :n] + rng.uniform(-0.05, 0.05, n) + (0.0 if shift is None else shift)
+        else:
+            x = rng.uniform(lo, hi, n)
+        x = np.clip(x, lo, hi).astype(np.float32).astype(np.float64)
+        exact = O.f(func, x, shift)
+        err = abs(emulate32(func, x, shift) - exact)
+        bound = eval_err32(func, x, shift)
+        assert err <= bound, (trial, err, bound)
+        worst = max(worst, err / bound if bound > 0 else 0.0)
+        assert bound <= 1e-4 * max(1.0, abs(exact))
+    print(f"func {func} n {n}: max err/bound {worst:.3f}")
 
 
 @pytest.mark.parametrize("func", [O.GRIEWANK, O.LEVY_MONTALVO, O.ROSENBROCK, O.SCHWEFEL, O.RASTRIGIN, O.ACKLEY])

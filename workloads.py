@@ -31,6 +31,9 @@ SCHWEFEL, RASTRIGIN, ACKLEY = 0, 1, 2
 # Non-separable families (Appendix: Test 8 Griewank, Test 10 Levy-Montalvo,
 # Test 14 generalized Rosenbrock): every move re-evaluates the whole cost.
 GRIEWANK, LEVY_MONTALVO, ROSENBROCK = 3, 4, 5
+# Centre families (Appendix: Test 18 Shekel, m = 5, 7, 10, n = 4; Test 19
+# modified Shekel foxholes and Test 11 modified Langerman, n <= 10).
+SHEKEL5, SHEKEL7, SHEKEL10, FOXHOLES, LANGERMAN = 6, 7, 8, 9, 10
 FP32, FP64 = 0, 1
 
 # Half-width of each family's canonical box [-h, h]^n: the paper's boxes for
@@ -39,6 +42,10 @@ FP32, FP64 = 0, 1
 # annealing workloads here (500 and 32.768).
 HALF_BOX = {SCHWEFEL: 500.0, RASTRIGIN: 5.12, ACKLEY: 32.768, GRIEWANK: 600.0, LEVY_MONTALVO: 10.0,
             ROSENBROCK: 2.048}
+# The centre families' boxes as the paper gives them: [0, 10] (Shekel,
+# Langerman) and [-5, 15] (foxholes) in every coordinate.
+CENTRE_BOX = {SHEKEL5: (0.0, 10.0), SHEKEL7: (0.0, 10.0), SHEKEL10: (0.0, 10.0), FOXHOLES: (-5.0, 15.0),
+              LANGERMAN: (0.0, 10.0)}
 
 # Closed-form minimum of the normalized Schwefel function (Sec. 4.1): the
 # paper prints x_i* = 420.968746 and f* = -418.982887 (tests/golden/paper_values.txt);
@@ -125,11 +132,30 @@ def griewank_n100_fp32() -> Workload:
                     T0=10.0, alpha=0.97, seed=5, precision=FP32, f_star=0.0, x_star=np.zeros(100))
 
 
+def shekel10_n4_fp32() -> Workload:
+    """Shekel with m = 10 (Appendix, Test 18; F18_c), box [0, 10]^4; f* and
+    x* as printed there."""
+    lo, hi = np.zeros(4), np.full(4, 10.0)
+    return Workload("shekel10_n4_fp32", SHEKEL10, 4, lo, hi, None, chains=65536, levels=200, steps=100, T0=1.0,
+                    alpha=0.97, seed=6, precision=FP32, f_star=-10.5364, x_star=np.full(4, 4.0))
+
+
+def foxholes_n5_fp32() -> Workload:
+    """Modified Shekel foxholes at n = 5 (Appendix, Test 19; F19_b), box
+    [-5, 15]^5; f* and x* as printed there."""
+    lo, hi = np.full(5, -5.0), np.full(5, 15.0)
+    return Workload("foxholes_n5_fp32", FOXHOLES, 5, lo, hi, None, chains=65536, levels=200, steps=100, T0=1.0,
+                    alpha=0.97, seed=7, precision=FP32, f_star=-10.4056,
+                    x_star=np.array([8.025, 9.152, 5.114, 7.621, 4.564]))
+
+
 def random_problem(func: int, n: int, seed: int, shifted: bool = True) -> Workload:
     """A small random problem of one of the families, for parity tests:
     canonical box, optional inner shift, random FP32 schedule."""
-    half = HALF_BOX[func]
-    lo, hi = _box(n, half)
+    if func in CENTRE_BOX:
+        lo, hi = np.full(n, CENTRE_BOX[func][0]), np.full(n, CENTRE_BOX[func][1])
+    else:
+        lo, hi = _box(n, HALF_BOX[func])
     rng = np.random.default_rng(seed)
     s = inner_shift(lo, hi, rng) if shifted else None
     return Workload(f"random_f{func}_n{n}_s{seed}", func, n, lo, hi, s, chains=256, levels=8, steps=32, T0=10.0,
