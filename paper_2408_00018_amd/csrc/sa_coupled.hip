@@ -153,6 +153,33 @@ template <typename T> __device__ __forceinline__ T wave_prod(T v)
     return v;
 }
 
+// FP32 evaluation of a centre family at one chain's column, J >= n columns:
+// the coordinates in registers, then the centres in table order, fully
+// unrolled so every table entry is an instruction constant (no scalar-load
+// round trip per coefficient) and the centres' independent distance sums
+// interleave; columns j >= n are computed and then dropped by a select, so
+// d is the same as a sum over j < n.
+template <int F, uint32_t J, typename ShFn>
+__device__ __forceinline__ float centre_f32(const float *col, uint32_t st, uint32_t n, const ShFn &sh)
+{
+    float yv[J];
+#pragma unroll
+    for (uint32_t j = 0; j < J; ++j) yv[j] = j < n ? col[j * st] - sh(j) : 0.0f;
+    float acc = 0.0f;
+#pragma unroll
+    for (uint32_t i = 0; i < kCentres<F>; ++i) {
+        float d = 0.0f;
+#pragma unroll
+        for (uint32_t j = 0; j < J; ++j) {
+            const float t = yv[j] - centre_a32<F>(i, j);
+            const float dn = fmaf(t, t, d);
+            d = j < n ? dn : d;
+        }
+        acc += centre_term32<F>(i, d);
+    }
+    return -acc;
+}
+
 // ---------------------------------------------------------------------------
 // FP32 full evaluation of one chain's column (coordinate i at col[i * STRIDE],
 // STRIDE = 0: the run-time `stride`).  sh(i) returns coordinate i's shift;
@@ -218,25 +245,11 @@ __device__ __forceinline__ float coupled_f32(const float *col, uint32_t stride, 
         acc = fmaf(vp, vp, acc);
         return acc * scale;
     } else if constexpr (kCentreFamily<F>) {
-        // the chain's coordinates in registers (n <= 4 for Shekel, <= 10
-        // otherwise), then the centres in table order
-        constexpr uint32_t J = kShekelTable<F> ? 4u : 10u;
-        float yv[J];
-#pragma unroll
-        for (uint32_t j = 0; j < J; ++j) yv[j] = j < n ? col[j * st] - sh(j) : 0.0f;
-        float acc = 0.0f;
-        for (uint32_t i = 0; i < kCentres<F>; ++i) {
-            float d = 0.0f;
-#pragma unroll
-            for (uint32_t j = 0; j < J; ++j) {
-                if (j < n) {
-                    const float t = yv[j] - centre_a32<F>(i, j);
-                    d = fmaf(t, t, d);
-                }
-            }
-            acc += centre_term32<F>(i, d);
-        }
-        return -acc;
+        // compile-time column counts, chosen by n (wave-uniform)
+        if constexpr (kShekelTable<F>) return centre_f32<F, 4>(col, st, n, sh);
+        else if (n <= 2) return centre_f32<F, 2>(col, st, n, sh);
+        else if (n <= 5) return centre_f32<F, 5>(col, st, n, sh);
+        else return centre_f32<F, 10>(col, st, n, sh);
     } else {
         float acc = 0.0f;
         float a = col[0] - sh(0);
