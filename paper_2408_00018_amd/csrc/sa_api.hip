@@ -164,7 +164,10 @@ sa_status plan(const sa_problem *p, const sa_config *c, size_t lds_limit, Plan *
     pl.real = c->precision == SA_FP64 ? sizeof(double) : sizeof(float);
     const bool learn = (c->flags & SA_FLAG_LEARNED) != 0;
     const int var = variant_of(c);
-    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, var, c->steps, lds_limit);
+    // FP32 Griewank runs also stage their n cosine factors in LDS
+    const size_t coef_lds = p->func == SA_GRIEWANK && c->precision == SA_FP32 ? p->n * sizeof(float) : 0;
+    pl.wg = pick_wg(p->n, c->chains, pl.real, pl.table, learn, var, c->steps,
+                    coef_lds < lds_limit ? lds_limit - coef_lds : 0);
     // Waves a layout keeps in flight on the device: its workgroups per CU (LDS
     // and the 32-wave limit) times the CUs, capped by its tiles.  The plan
     // counts the 256 CUs of the target device rather than querying it, so the

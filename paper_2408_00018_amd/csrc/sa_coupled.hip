@@ -367,7 +367,7 @@ __device__ __forceinline__ uint32_t run_full_steps(R *xs, uint32_t stride, uint3
 // shift, a broadcast at every level (the shift subtraction is left out:
 // x - 0 is x exactly).
 // LDS: xs[n][WG] tile states | xw[n] level start | xb[n] workgroup best |
-//      tab[n][4] per-coordinate box/shift (TABLE only)
+//      tab[n][4] per-coordinate box/shift (TABLE only) | gco[n] (FP32 Griewank)
 // ---------------------------------------------------------------------------
 template <typename R, int F, bool TABLE, int MODE, int MOVE, bool UNSHIFTED>
 __global__ void __launch_bounds__(256)
@@ -386,9 +386,17 @@ __global__ void __launch_bounds__(256)
     R *xw = xs + (size_t)n * WG;
     R *xb = xw + n;
     R *tab = xb + n;
+    // FP32 Griewank: the n factors c_i staged in LDS after the table (read
+    // from global memory in the step loop they cost a load round trip per
+    // four coordinates)
+    float *gco = reinterpret_cast<float *>(tab + (TABLE ? 4 * (size_t)n : 0));
+    constexpr bool kStageGco = F == kGriewank && sizeof(R) == sizeof(float);
 
     const double T = a.T[level];
     const float nl2T = -kLog2e * a.inv_T[level];
+    if (kStageGco) {
+        for (uint32_t i = tid; i < n; i += WG) gco[i] = a.gcoef[i];
+    }
     if (TABLE) {
         for (uint32_t i = tid; i < 4 * n; i += WG) tab[i] = a.table[i];
     }
@@ -469,8 +477,8 @@ __global__ void __launch_bounds__(256)
         };
         const auto evalf = [&]() -> R {
             if constexpr (sizeof(R) == sizeof(float)) {
-                if (WG == 256) return coupled_f32<F, 256>(xs + tid, 256, n, shf, a.gcoef, a.cscale);
-                return coupled_f32<F, 0>(xs + tid, WG, n, shf, a.gcoef, a.cscale);
+                if (WG == 256) return coupled_f32<F, 256>(xs + tid, 256, n, shf, gco, a.cscale);
+                return coupled_f32<F, 0>(xs + tid, WG, n, shf, gco, a.cscale);
             } else {
                 return coupled_f64<F>(n, [&](uint32_t i) { return xs[i * WG + tid] - coordf(i).sh; });
             }
@@ -529,7 +537,8 @@ static hipError_t launch_one(const LevelArgs<R> &a, uint32_t level, uint32_t pre
                              hipStream_t s)
 {
     auto kern = coupled_level_kernel<R, F, TABLE, MODE, MOVE, UNSHIFTED>;
-    const size_t lds = level_lds_bytes(a.n, a.wg, sizeof(R), TABLE, false);
+    const size_t lds = level_lds_bytes(a.n, a.wg, sizeof(R), TABLE, false) +
+                       (F == kGriewank && sizeof(R) == sizeof(float) ? (size_t)a.n * sizeof(float) : 0);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)a.wg, lds);
     if (e != hipSuccess) return e;
