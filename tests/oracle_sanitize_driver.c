@@ -30,6 +30,7 @@ int orc_replay_level(int func, uint32_t n, const double *lower, const double *up
                      double *log_xold, double *log_xnew, double *log_df, uint8_t *log_acc, double *x_final,
                      double *f_final);
 uint32_t orc_mlp_nparam(void);
+uint32_t orc_centres(int func, double *a, double *c);
 void orc_set_net_kind(int kind);
 void orc_mlp_forward(const double *params, const double *z, double *out2, double *a1_out, double *a2_out);
 double orc_mlp_loss_grad(const double *params, uint32_t batch, const double *Z, const double *delta, double *grad);
@@ -47,7 +48,7 @@ int orc_nelder_mead(int func, uint32_t n, const double *lower, const double *upp
                     const double *x0, uint32_t maxiter, double ftol, double xtol, double *x_out, double *f_out,
                     uint32_t *iters_out, uint32_t *evals_out, uint8_t *step_log, double *gap_log);
 
-static const double half_box[6] = {500.0, 5.12, 32.768, 600.0, 10.0, 2.048};
+static const double half_box[11] = {500.0, 5.12, 32.768, 600.0, 10.0, 2.048, 10.0, 10.0, 10.0, 15.0, 10.0};
 
 static void fail(const char *what, int rc)
 {
@@ -166,8 +167,18 @@ int main(void)
     uint32_t ctr[4] = {1, 2, 3, 4}, key[2] = {5, 6}, out[4];
     orc_philox4x32_10(ctr, key, out);
     const uint32_t dims[3] = {1, 2, 7};
-    for (int func = 0; func < 6; ++func)
+    for (int func = 0; func < 11; ++func) {
+        if (func >= 6 && func <= 8) {
+            runs(func, 4); /* Shekel: n = 4 only */
+            continue;
+        }
         for (int k = 0; k < 3; ++k) runs(func, dims[k]);
+    }
+    {
+        double a[30 * 10], c[30];
+        for (int func = 0; func < 12; ++func) (void)orc_centres(func, a, c);
+        (void)orc_centres(9, NULL, NULL);
+    }
     for (int kind = 0; kind < 2; ++kind) {
         orc_set_net_kind(kind);
         network();
