@@ -114,7 +114,7 @@ typedef enum {
     SA_ERR_NOMEM = -2,       /* device or host allocation failed */
     SA_ERR_DEVICE = -3,      /* a HIP call failed */
     SA_ERR_STATE = -4,       /* call not valid in the context's state */
-    SA_ERR_UNSUPPORTED = -5  /* valid request this build does not support */
+    SA_ERR_UNSUPPORTED = -5  /* valid request the library does not support */
 } sa_status;
 
 typedef enum {

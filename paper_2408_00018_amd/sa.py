@@ -73,12 +73,12 @@ class NMConfig(ctypes.Structure):
 
 
 def load_library():
-    """Load libsa_hip.so (built by ``__graft_entry__.build()``); raise if absent."""
+    """Load libsa_hip.so (built by ``python -m paper_2408_00018_amd.build``); raise if absent."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2408_00018_amd.build first")
     # torch ships the HIP runtime this process uses; load it first so the
     # library binds to the same libamdhip64.
     import torch  # noqa: F401
