@@ -74,18 +74,30 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
             // two LDS round trips overlap
             const Coord<R> c = coord<R, TABLE>(a, tab, d);
             uint32_t h = slot_of(d, K);
+            // the home slot's key and value and the start-state fallback are
+            // read together (one LDS round trip when the home slot decides,
+            // the common case); a collision continues the probe
+            const uint32_t key0 = keys[h * WG + tid];
+            const R val0 = vals[h * WG + tid];
+            const R base0 = level != 0 ? xw[d] : R(0);
             R xd;
-            for (;;) {
-                const uint32_t key = keys[h * WG + tid];
-                if (key == d) {
-                    xd = vals[h * WG + tid];
-                    break;
+            if (key0 == d) {
+                xd = val0;
+            } else if (key0 == kEmptyKey) {
+                xd = level != 0 ? base0 : start_coord<R, TABLE>(a, tab, xw, level, chain, d);
+            } else {
+                for (;;) {
+                    h = h + 1u == K ? 0u : h + 1u;
+                    const uint32_t key = keys[h * WG + tid];
+                    if (key == d) {
+                        xd = vals[h * WG + tid];
+                        break;
+                    }
+                    if (key == kEmptyKey) {
+                        xd = level != 0 ? base0 : start_coord<R, TABLE>(a, tab, xw, level, chain, d);
+                        break;
+                    }
                 }
-                if (key == kEmptyKey) {
-                    xd = start_coord<R, TABLE>(a, tab, xw, level, chain, d);
-                    break;
-                }
-                h = h + 1u == K ? 0u : h + 1u;
             }
             const R xn = neighbour_w<MOVE>(xd, c, w1);
             R df;
