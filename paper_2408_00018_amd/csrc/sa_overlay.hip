@@ -80,25 +80,27 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
             const uint32_t key0 = keys[h * WG + tid];
             const R val0 = vals[h * WG + tid];
             const R base0 = level != 0 ? xw[d] : R(0);
-            R xd;
-            if (key0 == d) {
-                xd = val0;
-            } else if (key0 == kEmptyKey) {
-                xd = level != 0 ? base0 : start_coord<R, TABLE>(a, tab, xw, level, chain, d);
-            } else {
+            // kh, vh: key and value of the slot the probe ends on (vh is not
+            // read for an empty slot; an empty slot's value is never used)
+            uint32_t kh = key0;
+            R vh = val0;
+            R xd = key0 == d ? val0 : base0;
+            if (key0 != d && key0 != kEmptyKey) {
                 for (;;) {
                     h = h + 1u == K ? 0u : h + 1u;
-                    const uint32_t key = keys[h * WG + tid];
-                    if (key == d) {
-                        xd = vals[h * WG + tid];
+                    kh = keys[h * WG + tid];
+                    if (kh == d) {
+                        vh = vals[h * WG + tid];
+                        xd = vh;
                         break;
                     }
-                    if (key == kEmptyKey) {
-                        xd = level != 0 ? base0 : start_coord<R, TABLE>(a, tab, xw, level, chain, d);
+                    if (kh == kEmptyKey) {
+                        xd = base0;
                         break;
                     }
                 }
             }
+            if (level == 0 && kh == kEmptyKey) xd = start_coord<R, TABLE>(a, tab, xw, level, chain, d);
             const R xn = neighbour_w<MOVE>(xd, c, w1);
             R df;
             bool take;
@@ -110,10 +112,9 @@ __device__ __forceinline__ uint32_t run_overlay_steps(const LevelArgs<R> &a, con
                 take = metropolis_w(df, w2, T, nl2T);
             }
             logf(step, d, take, xd, xn, df);
-            if (take) {
-                keys[h * WG + tid] = (uint16_t)d;
-                vals[h * WG + tid] = xn;
-            }
+            // the slot's new contents, or its old ones: no branch on the decision
+            keys[h * WG + tid] = (uint16_t)(take ? d : kh);
+            vals[h * WG + tid] = take ? xn : vh;
             cost.commit(take, a.inv_n);
             accepted += take ? 1u : 0u;
         }
