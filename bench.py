@@ -402,12 +402,23 @@ def extra_workloads():
         e1.record(b._stream)
         e1.synchronize()
         ms = e0.elapsed_time(e1)
+        # per-family hit rates of the timed run's records (f* = Schwefel's
+        # minimum, 0 for Rastrigin and Ackley; every shift keeps the minimiser
+        # inside its box)
+        names = {W.SCHWEFEL: "schwefel", W.RASTRIGIN: "rastrigin", W.ACKLEY: "ackley"}
+        gaps = {}
+        for p_i, (func, _, _, _) in enumerate(probs):
+            _, f_rec, _ = b.best(p_i)
+            gaps.setdefault(names[func], []).append(f_rec - (W.SCHWEFEL_F_STAR if func == W.SCHWEFEL else 0.0))
+        families = {k: {"problems": len(v), "hit_1e-4": round(float(np.mean(np.array(v) < 1e-4)), 4),
+                        "hit_1e-2": round(float(np.mean(np.array(v) < 1e-2)), 4),
+                        "median_gap": float(f"{np.median(v):.4g}")} for k, v in sorted(gaps.items())}
         idle = batch_idle(b, chains, first=100, levels=50)
     moves = float(np.sum(chains.astype(np.float64))) * bs.steps * bs.levels
     out["batched_1024"] = {"moves_per_s": float(f"{moves / (ms * 1e-3):.4g}"), "ms_per_run": round(ms, 3),
                            "problems": len(probs), "total_chains": int(np.sum(chains)),
                            "chains_per_problem": sorted({int(c) for c in chains}), "waves_per_group": wpg,
-                           "autotune_s": round(tune_s, 2), "idle": idle}
+                           "autotune_s": round(tune_s, 2), "families": families, "idle": idle}
     print(f"[extra] batched: {out['batched_1024']}", file=sys.stderr, flush=True)
     return out
 
